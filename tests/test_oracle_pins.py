@@ -1,0 +1,261 @@
+"""Pins of the oracle against what the paper and mathematics fix (CPU only).
+
+- worked example: constants, grid values, codes and reconstruction of a
+  4-point field re-derived here from the closed forms of Sec. 3.2 (Eq. 8-12)
+  with 60-digit mpmath (no value lies near a rounding tie);
+- annihilation: the one-layer Lorenzo predictor of Sec. 4.1 predicts every
+  interior point of g(y,x)+h(z,x)+k(z,y) exactly (mixed third difference);
+- the initialised perceptron (end of Sec. 4.2) equals Lorenzo on any field;
+- the PW_REL bound with sign and zero preserved holds on every point, the
+  decoder rebuilds the encoder's grid field, and the zero < positive <
+  negative grid ranges are disjoint (Sec. 3.2, factor inequality);
+- error paths: non-finite input, bad arguments, grid overflow.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2309_09778_amd import synth
+
+mpmath.mp.dps = 60
+
+
+def mp_log2(v):
+    return mpmath.log(mpmath.mpf(v), 2)
+
+
+def mp_rint(v):
+    return int(mpmath.nint(v))
+
+
+def test_worked_example_closed_forms():
+    # x = [0, 1, 2, -4] (FP32), eps = 1e-2, block 4, untrained network.
+    x = np.array([0.0, 1.0, 2.0, -4.0], dtype=np.float32)
+    eps = 1e-2
+    c = O.consts(x, eps)
+    one_eps = mpmath.mpf(1.0 + eps)  # 1 + eps as the FP64 sum the method forms
+    b_a = mp_log2(one_eps)                                    # Eq. 8
+    eps0 = mpmath.mpf(2) ** -126                              # smallest FP32 normal
+    fp, amax, amin = 1, 4, 1                                  # Eq. 9: factor_pos = min |x|
+    fn = (amax + eps0) * fp * one_eps ** 2 / (amin - eps0)    # Eq. 10
+    assert abs(c["b_a"] - float(b_a)) <= 4 * math.ulp(float(b_a))
+    assert abs(c["Ln"] - float(mp_log2(fn))) < 1e-14
+    assert c["Lp"] == 0.0
+    r = 1 / (2 * b_a)
+    assert c["p_zero"] == mp_rint((mp_log2(eps0 * fp)) * r) == -4389        # Eq. 12
+    assert c["b_sign"] == mp_rint(mp_log2(amax * fp) * r) == 70
+    assert c["n_lo"] == mp_rint(mp_log2(amin * fn) * r) == 71
+    assert c["delta"] == 0
+    p_expect = [-4389, mp_rint(mp_log2(1) * r), mp_rint(mp_log2(2) * r),
+                mp_rint(mp_log2(4 * fn) * r)]
+    assert p_expect == [-4389, 0, 35, 140]
+    m = O.mlp_init(1, 2)
+    out = O.compress(x, eps, 4, m, O.MODE_PLAIN)
+    assert out["p"].tolist() == p_expect
+    # Algorithm 1: error = prediction - actual; 1-D Lorenzo = previous value,
+    # first point predicted as 0; code = error + 2^15.
+    preds = [0, -4389, 0, 35]
+    assert out["codes"].tolist() == [pr - p + 32768 for pr, p in zip(preds, p_expect)]
+    assert out["codes"].tolist() == [37157, 28379, 32733, 32663]
+    assert out["counts"].tolist() == [0] and out["raw"].size == 0
+    xh, p2 = O.decompress(out["codes"], out["raw"], out["consts"], x.shape, np.float32, 4, m)
+    w = 2 * b_a
+    lnf = mp_log2(fn)
+    exp_xh = [0.0, 1.0, float(np.float32(float(mpmath.power(2, 35 * w)))),
+              -float(np.float32(float(mpmath.power(2, 140 * w - lnf))))]
+    assert xh.tolist() == exp_xh
+    assert xh.tolist() == [0.0, 1.0, 2.006763458251953, -3.974494695663452]
+    assert p2.tolist() == p_expect
+
+
+def _annihilated_field_3d(shape, seed):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    g = rng.integers(-5000, 5000, size=(ny, nx))
+    h = rng.integers(-5000, 5000, size=(nz, nx))
+    k = rng.integers(-5000, 5000, size=(nz, ny))
+    return (g[None, :, :] + h[:, None, :] + k[:, :, None]).astype(np.int32)
+
+
+def stream_positions(shape, B):
+    """Block-major stream position of every C-order point (sort by block
+    raster key, then local raster key)."""
+    co = np.unravel_index(np.arange(int(np.prod(shape))), shape)
+    keys = [c % B for c in co[::-1]] + [c // B for c in co[::-1]]
+    order = np.lexsort(keys)
+    pos = np.empty(order.size, dtype=np.int64)
+    pos[order] = np.arange(order.size)
+    return pos
+
+
+@pytest.mark.parametrize("shape,B", [((9, 10, 11), 4), ((16, 16, 16), 8), ((5, 7, 13), 8)])
+def test_lorenzo_annihilates_mixed_third_difference(shape, B):
+    p = _annihilated_field_3d(shape, 11)
+    pos = stream_positions(shape, B)
+    zz, yy, xx = np.unravel_index(np.arange(p.size), shape)
+    interior = (zz > 0) & (yy > 0) & (xx > 0)
+    for use_net, model in ((False, None), (True, O.mlp_init(3, 16, seed=3))):
+        codes = O.encode_p(p, B, model, use_net=use_net)
+        assert np.all(codes[pos[interior]] == 32768)
+        # a plain linear ramp is predicted exactly on every face too (2-D and
+        # 1-D Lorenzo are exact on planes and lines away from the origin)
+    ramp = (np.add.outer(np.add.outer(3 * np.arange(shape[0]), -7 * np.arange(shape[1])),
+                         11 * np.arange(shape[2]))).astype(np.int32)
+    codes = O.encode_p(ramp, B, None, use_net=False)
+    faces = ((zz > 0).astype(int) + (yy > 0) + (xx > 0)) >= 2
+    assert np.all(codes[pos[faces]] == 32768)
+
+
+def test_lorenzo_annihilates_2d_sum():
+    rng = np.random.default_rng(5)
+    a, b = rng.integers(-9000, 9000, 17), rng.integers(-9000, 9000, 23)
+    p = (a[:, None] + b[None, :]).astype(np.int32)
+    codes = O.encode_p(p, 8, None, use_net=False)
+    # stream order for 2-D: recompute positions by sorting block/local keys
+    yy, xx = np.meshgrid(np.arange(17), np.arange(23), indexing="ij")
+    key = sorted(zip((yy // 8).ravel(), (xx // 8).ravel(), (yy % 8).ravel(), (xx % 8).ravel(),
+                     yy.ravel(), xx.ravel()))
+    for pos, (_, _, _, _, y, x) in enumerate(key):
+        if y > 0 and x > 0:
+            assert codes[pos] == 32768
+
+
+def test_untrained_network_equals_lorenzo():
+    for shape, seed in (((24, 20, 18), 1), ((40, 36), 2), ((300,), 3)):
+        x = synth.gaussian_bumps(shape, seed=seed, zero_frac=0.01) if len(shape) == 3 else \
+            synth.lognormal_grf(shape, seed=seed, decades=6, neg_frac=0.1, zero_frac=0.01)
+        m = O.mlp_init(len(shape), 16, seed=9)
+        a = O.compress(x, 1e-2, 8, m, O.MODE_PLAIN)
+        b = O.compress(x, 1e-2, 8, None, O.MODE_LORENZO)
+        assert np.array_equal(a["codes"], b["codes"])
+        assert np.array_equal(a["raw"], b["raw"])
+
+
+def _check_invariants(x, eps, B, model, independent=False):
+    out = O.compress(x, eps, B, model, O.MODE_PLAIN, independent=independent)
+    c = out["consts"]
+    xh, p = O.decompress(out["codes"], out["raw"], c, x.shape, x.dtype, B, model, O.MODE_PLAIN,
+                         independent=independent)
+    assert np.array_equal(p, out["p"]), "decoder grid field differs from the encoder's"
+    xd, hd = x.astype(np.float64), xh.astype(np.float64)
+    zero = xd == 0
+    assert np.all(hd[zero] == 0)
+    nz = ~zero
+    assert np.all(np.signbit(hd[nz]) == np.signbit(xd[nz]))
+    assert np.all(np.abs(xd[nz] - hd[nz]) <= eps * np.abs(xd[nz]))
+    # raw points are exact; counts add up
+    assert out["raw"].size == int(out["counts"].sum()) == int((out["codes"] == 0).sum())
+    # disjoint grid ranges: zero < positive <= b_sign < negative
+    P = out["p"]
+    assert np.all(P[zero] == c["p_zero"])
+    assert np.all((P[x > 0] > c["p_zero"]) & (P[x > 0] <= c["b_sign"]))
+    assert np.all(P[x < 0] > c["b_sign"])
+    return out, xh
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("eps", [1e-1, 1e-2, 1e-3, 1e-4])
+def test_bound_and_grid_invariants_3d(dtype, eps):
+    x = synth.lognormal_grf((20, 24, 28), seed=17, decades=8, neg_frac=0.1, zero_frac=0.005,
+                            dtype=dtype)
+    _check_invariants(x, eps, 8, O.mlp_init(3, 16, seed=2))
+
+
+def test_bound_with_trained_network_and_independent_blocks():
+    x = synth.gaussian_bumps((32, 32, 32), seed=4, zero_frac=0.01)
+    init = O.mlp_init(3, 16, seed=1)
+    c = O.consts(x, 1e-2)
+    model, idx, ntr, nva = O.train_rule(O.transform_field(x, c), c, 8, init, rho=0.1, seed=5)
+    for indep in (False, True):
+        _check_invariants(x, 1e-2, 8, model, independent=indep)
+
+
+def test_subnormals_and_extreme_range_f64():
+    rng = np.random.default_rng(8)
+    x = (rng.standard_normal(4000) * 10.0 ** rng.uniform(-300, 300, 4000)).astype(np.float64)
+    x[::97] = 0.0
+    x[5] = 5e-324 * 7
+    x[6] = -2.5e-310
+    x = x.reshape(10, 20, 20)
+    _check_invariants(x, 1e-3, 8, O.mlp_init(3, 8, seed=2))
+
+
+def test_subnormals_f32():
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal(3000) * 10.0 ** rng.uniform(-44, 38, 3000)).astype(np.float32)
+    x[::50] = 0
+    _check_invariants(x.reshape(30, 100), 1e-2, 16, O.mlp_init(2, 16, seed=2))
+
+
+def test_monotone_grid_within_sign():
+    x = np.sort(np.abs(synth.lognormal_grf((4096,), seed=2, decades=10, neg_frac=0.0,
+                                           zero_frac=0.0)))
+    c = O.consts(x, 1e-3)
+    p = O.transform_field(x, c)
+    assert np.all(np.diff(p.astype(np.int64)) >= 0)
+    pn = O.transform_field(-x, c)
+    assert np.all(np.diff(pn.astype(np.int64)) >= 0)
+
+
+@pytest.mark.parametrize("shape,B", [((1,), 2), ((7,), 4), ((3, 5), 2), ((9, 1, 17), 8),
+                                     ((64,), 64), ((1, 1, 1), 8)])
+def test_edge_shapes_round_trip(shape, B):
+    x = synth.lognormal_grf(shape, seed=3, decades=4, neg_frac=0.3, zero_frac=0.1)
+    m = O.mlp_init(len(shape), 4, seed=1) if len(shape) > 1 else O.mlp_init(1, 2)
+    _check_invariants(x, 1e-2, B, m)
+    _check_invariants(x, 1e-2, B, m, independent=True)
+
+
+def test_all_zero_and_constant_fields():
+    z = np.zeros((5, 6, 7), dtype=np.float32)
+    out, xh = _check_invariants(z, 1e-2, 4, O.mlp_init(3, 4))
+    assert np.all(xh == 0)
+    k = np.full((5, 6, 7), -3.5, dtype=np.float32)
+    out, xh = _check_invariants(k, 1e-2, 4, O.mlp_init(3, 4))
+    # every point after the first is predicted exactly (Lorenzo of a constant)
+    assert np.sum(out["codes"] != 32768) <= 1 + 4 * 2 * 2
+
+
+def test_stream_positions_match_sorted_block_order():
+    shape, B = (10, 7, 13), 4
+    x = synth.lognormal_grf(shape, seed=1, decades=3, neg_frac=0.2, zero_frac=0.0)
+    c = O.consts(x, 1e-2)
+    pos = O.codes_at(x, c, B, np.arange(x.size), None, O.MODE_LORENZO)["pos"]
+    zz, yy, xx = np.unravel_index(np.arange(x.size), shape)
+    order = np.lexsort((xx % B, yy % B, zz % B, xx // B, yy // B, zz // B))
+    expect = np.empty(x.size, dtype=np.int64)
+    expect[order] = np.arange(x.size)
+    assert np.array_equal(pos.astype(np.int64), expect)
+
+
+def test_codes_at_matches_full_compress():
+    x = synth.lognormal_grf((18, 19, 21), seed=6, decades=8, neg_frac=0.1, zero_frac=0.01)
+    m = O.mlp_init(3, 16, seed=4)
+    full = O.compress(x, 1e-3, 8, m)
+    pt = O.codes_at(x, full["consts"], 8, np.arange(x.size), m)
+    assert np.array_equal(full["codes"][pt["pos"].astype(np.int64)], pt["codes"])
+    assert np.array_equal(full["p"].ravel(), pt["p"])
+
+
+def test_error_paths():
+    x = np.ones((4, 4), dtype=np.float32)
+    x[1, 1] = np.nan
+    with pytest.raises(O.OracleError) as e:
+        O.compress(x, 1e-2, 4, None, O.MODE_LORENZO)
+    assert e.value.status == O.ENONFINITE
+    y = np.ones((4, 4), dtype=np.float32)
+    for eps in (0.0, 1.0, -1e-3, 1e-17):
+        with pytest.raises(O.OracleError) as e:
+            O.compress(y, eps, 4, None, O.MODE_LORENZO)
+        assert e.value.status == O.EINVAL
+    with pytest.raises(O.OracleError) as e:
+        O.compress(y, 1e-2, 1, None, O.MODE_LORENZO)
+    assert e.value.status == O.EINVAL
+    # grid value beyond 2^30: huge range at a tiny bound
+    z = np.array([1e-300, 1e300], dtype=np.float64)
+    with pytest.raises(O.OracleError) as e:
+        O.compress(z, 1e-9, 2, None, O.MODE_LORENZO)
+    assert e.value.status == O.ERANGE
