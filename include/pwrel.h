@@ -1,0 +1,214 @@
+/*
+ * pwrel -- perceptron-predicted point-wise relative (PW_REL) lossy compressor
+ * for AMD Instinct MI355X (gfx950), after Chen & Li, arXiv 2309.09778.
+ *
+ * C ABI.  Every pointer named d_* is a device pointer on the context's GPU;
+ * every other pointer is host memory.  Streams are passed as `void *` holding
+ * a hipStream_t (NULL = the device's null stream).  Fields are dense C-order
+ * arrays: dims[0] is the slowest axis, dims[ndim-1] the fastest.
+ *
+ * Error behaviour: every entry point returns PWREL_OK (0) or a negative
+ * pwrel_status; nothing is thrown across the ABI.  The message of the last
+ * failure on a context is available from pwrel_last_error().  On failure the
+ * contents of output buffers are unspecified and *out_size is not written.
+ * Argument errors are reported before any GPU work is queued.
+ *
+ * Ownership: the caller owns every field, stream and output buffer.  The
+ * context owns its device workspace (grown on demand, freed by
+ * pwrel_destroy); a context must not be used from two threads at once.
+ */
+#ifndef PWREL_H
+#define PWREL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { PWREL_F32 = 0, PWREL_F64 = 1 } pwrel_dtype;
+
+typedef enum {
+    PWREL_OK = 0,
+    PWREL_EINVAL = -1,     /* bad argument (dims, ndim, dtype, bound, block size, model) */
+    PWREL_ERANGE = -2,     /* a grid value would leave +-2^30 (bound too tight for the range) */
+    PWREL_ENONFINITE = -3, /* the field holds NaN or Inf */
+    PWREL_ENOSPC = -4,     /* output capacity too small */
+    PWREL_ECORRUPT = -5,   /* stream header or sections inconsistent */
+    PWREL_EHIP = -6,       /* a HIP runtime call failed */
+    PWREL_ENOMEM = -7      /* device or host allocation failed */
+} pwrel_status;
+
+#define PWREL_MAX_HIDDEN 32
+#define PWREL_MAX_INPUTS 6
+#define PWREL_HEADER_BYTES 512
+#define PWREL_MAGIC 0x4C455750u /* "PWEL" little-endian */
+#define PWREL_VERSION 1u
+
+/*
+ * The three-layer perceptron (Sec. 4.2, Fig. 3).  Inputs are the K = 2^ndim - 2
+ * neighbour differences u_k = n_{k+2} - n_1 of grid values on the prediction
+ * surface (n_1 = previous point along the fastest axis; neighbour o steps back
+ * by one along axis ndim-1-i for every set bit i of o); hidden layer of
+ * `hidden` leaky-ReLU units with slope `alpha`; one linear output y.  The
+ * prediction is n_1 + rint(clamp(y, -2^30, 2^30)).
+ *
+ * precision 0: evaluated in FP32 on the vector ALUs in a fixed order with
+ *   explicit fused multiply-adds: z_j = fma(w1[j][K-1], u_{K-1}, ... fma(w1[j][0],
+ *   u_0, b1[j])), h_j = z_j < 0 ? z_j * alpha : z_j, y = fma(v[H-1], h_{H-1},
+ *   ... fma(v[0], h_0, b2)).  Bit-identical to the CPU oracle.
+ * precision 1: inputs, w1, hidden activations and v rounded to bfloat16 and
+ *   multiplied on the matrix cores with FP32 accumulation (b1, b2 in FP32).
+ *   Encoder and decoder run the same instruction sequence, so streams are
+ *   self-consistent; the bound is enforced by the quantizer either way.
+ */
+typedef struct {
+    int32_t hidden;    /* H, 2..32 */
+    int32_t inputs;    /* K = 2^ndim - 2 */
+    float alpha;       /* leaky-ReLU slope */
+    float w1[PWREL_MAX_HIDDEN][PWREL_MAX_INPUTS];
+    float b1[PWREL_MAX_HIDDEN];
+    float v[PWREL_MAX_HIDDEN];
+    float b2;
+    int32_t precision; /* 0 = FP32 vector ALU, 1 = BF16 matrix cores */
+} pwrel_mlp;
+
+/* Compression options; pass NULL for the defaults (all zero except use_net = 1). */
+typedef struct {
+    int32_t use_net;            /* 0: one-layer Lorenzo everywhere; 1: network where all
+                                   neighbours exist (needs a model) */
+    int32_t judge;              /* 1: per block keep the network only if its code entropy is
+                                   strictly below Lorenzo's (flag per block in the stream) */
+    int32_t independent_blocks; /* 0: the prediction surface crosses block faces (halo mode);
+                                   1: neighbours outside the block count as missing, so every
+                                   block decodes on its own (Sec. 4.4.2) */
+    int32_t reserved;
+} pwrel_options;
+
+/*
+ * Stream header (first PWREL_HEADER_BYTES of every stream, little-endian).
+ * Sections follow at the stated byte offsets, each 256-byte aligned:
+ *   model  : pwrel_mlp                      (if flags & PWREL_HF_NET)
+ *   bflags : uint8  [nblocks], 1 = network  (if flags & PWREL_HF_JUDGE)
+ *   counts : uint32 [nblocks]   code-0 points per block
+ *   codes  : uint16 [n]         block-major: blocks in raster order, points in
+ *                               local raster order; code = e + 2^15 with
+ *                               e = prediction - grid value, 0 = balance point
+ *   raw    : dtype  [n_raw]     input values of the code-0 points, same order
+ */
+#define PWREL_HF_NET 1
+#define PWREL_HF_JUDGE 2
+#define PWREL_HF_INDEPENDENT 4
+typedef struct {
+    uint32_t magic, version;
+    int32_t dtype, ndim;
+    uint64_t dims[3];
+    int32_t block, flags;
+    double eps;   /* relative bound b_r */
+    double eps0;  /* stand-in magnitude of zero */
+    double b_a;   /* log2(1 + eps), Eq. 8 */
+    double w;     /* grid step 2 b_a */
+    double r;     /* 1 / w */
+    double Lp;    /* log2 factor_pos, Eq. 9 */
+    double Ln;    /* log2 factor_neg, Eq. 10 */
+    double d0;    /* log-domain image of zero, Eq. 12 */
+    int64_t p_zero, b_sign, n_lo, delta; /* grid thresholds and negative offset */
+    uint64_t n, nblocks, n_raw;
+    uint64_t off_model, off_bflags, off_counts, off_codes, off_raw, total_size;
+    double abs_min, abs_max;
+    uint64_t n_zero, n_neg;
+    int32_t status; /* device-side status of the producing call (0 = ok) */
+    int32_t pad0;
+} pwrel_header;
+
+typedef struct pwrel_ctx pwrel_ctx;
+
+/* Create a context on HIP device `device` (allocates a small workspace). */
+int pwrel_create(pwrel_ctx **out, int device);
+void pwrel_destroy(pwrel_ctx *ctx);
+const char *pwrel_last_error(const pwrel_ctx *ctx);
+const char *pwrel_status_string(int status);
+
+/* Limits on block_size: 1-D 2..4096, 2-D 2..64, 3-D 2..16. */
+int pwrel_check_args(const uint64_t *dims, int ndim, int dtype, double rel_error_bound,
+                     int block_size);
+
+/* Upper bound of the stream size in bytes (0 if the arguments are invalid). */
+uint64_t pwrel_compress_bound(const uint64_t *dims, int ndim, int dtype, int block_size);
+
+/*
+ * Compress (Algorithm 1 with the transform of Sec. 3.2, the predictor of
+ * Sec. 4.1/4.2 fed with grid-snapped actual values per Sec. 4.4.1, and the
+ * 2^16-code quantizer with balance points).  Every point of the result
+ * decompresses to x^ with |x - x^| <= eps |x|, the sign of x, and x^ = 0
+ * exactly where x = 0.  model may be NULL when opt->use_net = 0.  Writes the
+ * stream to d_out (capacity out_capacity bytes) and its length to *out_size;
+ * synchronises `stream` once to learn that length.
+ */
+int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                   int dtype, double rel_error_bound, int block_size, const pwrel_mlp *model,
+                   const pwrel_options *opt, void *d_out, uint64_t out_capacity,
+                   uint64_t *out_size, void *stream);
+
+/*
+ * Decompress a stream (Sec. 5): blocks in dependency order (block levels in
+ * halo mode, all at once with independent blocks), grid values rebuilt from the
+ * same prediction, x^ = exact inverse transform rounded to dtype; code-0 points
+ * take their raw value.  dims/ndim/dtype must match the header.  Synchronises
+ * `stream` once to read the header.
+ */
+int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d_field,
+                     const uint64_t *dims, int ndim, int dtype, void *stream);
+
+/* Validate a header held in host memory (no GPU work). */
+int pwrel_read_header(const void *buf, uint64_t size, pwrel_header *out);
+
+/*
+ * Inspection entry points (same kernels as the codec):
+ *  pwrel_transform   - statistics, constants and grid value of every point
+ *                      (Sec. 3.2, Eq. 6-12); header constants to *hdr_out.
+ *  pwrel_encode_grid - prediction and codes of a given int32 grid field with
+ *                      every point taken as verified (Sec. 4.1/4.2, Algorithm 1);
+ *                      codes in stream order.
+ *  pwrel_detmath     - the device's deterministic log2/exp2 on n doubles.
+ */
+int pwrel_transform(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                    int dtype, double rel_error_bound, int32_t *d_p, pwrel_header *hdr_out,
+                    void *stream);
+int pwrel_encode_grid(pwrel_ctx *ctx, const int32_t *d_p, const uint64_t *dims, int ndim,
+                      int block_size, const pwrel_mlp *model, const pwrel_options *opt,
+                      uint16_t *d_codes, void *stream);
+int pwrel_detmath(pwrel_ctx *ctx, const double *d_x, double *d_log2, double *d_exp2, uint64_t n,
+                  void *stream);
+
+/*
+ * Histogram (65536 bins, host output) of n codes held on the device (e.g. the
+ * codes section of a stream), and the size in bits of those codes under a
+ * Huffman code built from the histogram (Sec. 4.1: the coding stage after
+ * quantisation; used for the ratio report).  pwrel_histogram synchronises.
+ */
+int pwrel_histogram(pwrel_ctx *ctx, const uint16_t *d_codes, uint64_t n, uint64_t *hist65536,
+                    void *stream);
+uint64_t pwrel_huffman_bits(const uint64_t *hist65536, uint32_t *max_len_out);
+
+/*
+ * Device time per phase of the last pwrel_compress / pwrel_decompress on this
+ * context, in milliseconds, from HIP events recorded on the caller's stream
+ * while profiling is enabled (off by default; enabling adds no host sync).
+ * Phases: 0 statistics + constants, 1 fused compression kernel,
+ * 2 scan + raw scatter + header, 3 decoder scan, 4 decoder block levels.
+ * Returns the number of phases written (<= n).
+ */
+#define PWREL_NUM_PHASES 5
+int pwrel_set_profiling(pwrel_ctx *ctx, int enable);
+int pwrel_phase_times(pwrel_ctx *ctx, double *ms, int n);
+
+/* Network that reproduces Lorenzo exactly (end of Sec. 4.2). */
+int pwrel_mlp_init(pwrel_mlp *out, int ndim, int hidden, float alpha, uint64_t seed);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWREL_H */

@@ -419,7 +419,7 @@ typedef struct {
 
 static int geom_init(geom *g, const uint64_t *dims, int ndim, int B)
 {
-    if (ndim < 1 || ndim > 3 || B < 2 || B > 64)
+    if (ndim < 1 || ndim > 3 || B < 2 || B > 4096)
         return OR_EINVAL;
     int64_t bd = 1;
     for (int d = 0; d < ndim; ++d)

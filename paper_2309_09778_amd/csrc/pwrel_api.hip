@@ -1,0 +1,738 @@
+// C ABI of the PW_REL perceptron compressor (see include/pwrel.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "pwrel_internal.h"
+
+using namespace pwrel;
+
+struct pwrel_ctx {
+    int device = 0;
+    int num_cus = 256;
+    Workspace ws;
+    uint32_t *counts_scratch = nullptr;  // per-block counts for pwrel_encode_grid
+    size_t counts_scratch_cap = 0;
+    std::string err;
+    int profiling = 0;
+    hipEvent_t ev[8] = {};
+    bool ev_ok = false;
+    double phase_ms[PWREL_NUM_PHASES] = {};
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        if (prev != dev)
+            (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+int fail(pwrel_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    return code;
+}
+
+int hip_fail(pwrel_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, PWREL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+uint64_t align256(uint64_t v) { return (v + 255u) & ~uint64_t(255u); }
+
+int max_block(int ndim) { return ndim == 1 ? 4096 : (ndim == 2 ? 64 : 16); }
+
+bool make_geom(const uint64_t *dims, int ndim, int dtype, int B, Geom &g)
+{
+    if (!dims || ndim < 1 || ndim > 3 || B < 2 || B > max_block(ndim))
+        return false;
+    if (dtype != PWREL_F32 && dtype != PWREL_F64)
+        return false;
+    g.D = ndim;
+    g.B = B;
+    g.dtype = dtype;
+    g.N = 1;
+    g.nblocks = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int src = d - (3 - ndim);
+        const uint64_t nd = src >= 0 ? dims[src] : 1;
+        if (nd < 1 || nd > (uint64_t(1) << 40))
+            return false;
+        g.n[d] = (long long)nd;
+        g.bd[d] = src >= 0 ? B : 1;
+        g.nb[d] = (g.n[d] + g.bd[d] - 1) / g.bd[d];
+        if (g.N > (1LL << 42) / g.n[d])
+            return false;
+        g.N *= g.n[d];
+        g.nblocks *= g.nb[d];
+    }
+    return true;
+}
+
+struct Layout {
+    uint64_t off[5];  // model, bflags, counts, codes, raw
+};
+
+Layout layout_for(const Geom &g, int flags)
+{
+    Layout L;
+    uint64_t o = PWREL_HEADER_BYTES;
+    L.off[0] = o;
+    if (flags & PWREL_HF_NET)
+        o = align256(o + sizeof(pwrel_mlp));
+    L.off[1] = o;
+    if (flags & PWREL_HF_JUDGE)
+        o = align256(o + (uint64_t)g.nblocks);
+    L.off[2] = o;
+    o = align256(o + 4ull * (uint64_t)g.nblocks);
+    L.off[3] = o;
+    o = align256(o + 2ull * (uint64_t)g.N);
+    L.off[4] = o;
+    return L;
+}
+
+int check_model(pwrel_ctx *ctx, const pwrel_mlp *m, int ndim)
+{
+    if (!m)
+        return fail(ctx, PWREL_EINVAL, "model is NULL but use_net is set");
+    if (m->hidden < 2 || m->hidden > PWREL_MAX_HIDDEN)
+        return fail(ctx, PWREL_EINVAL, "model hidden width must be 2..32");
+    if (m->inputs != (1 << ndim) - 2)
+        return fail(ctx, PWREL_EINVAL, "model inputs must equal 2^ndim - 2");
+    if (m->precision != 0)
+        return fail(ctx, PWREL_EINVAL, "this build evaluates FP32 networks (precision 0) only");
+    auto bad = [](float v) { return !std::isfinite(v) || std::fabs(v) > 65536.0f; };
+    if (bad(m->alpha) || bad(m->b2))
+        return fail(ctx, PWREL_EINVAL, "model weights must be finite and below 2^16");
+    for (int j = 0; j < m->hidden; ++j) {
+        if (bad(m->b1[j]) || bad(m->v[j]))
+            return fail(ctx, PWREL_EINVAL, "model weights must be finite and below 2^16");
+        for (int k = 0; k < m->inputs; ++k)
+            if (bad(m->w1[j][k]))
+                return fail(ctx, PWREL_EINVAL, "model weights must be finite and below 2^16");
+    }
+    return PWREL_OK;
+}
+
+template <typename P>
+hipError_t grow(P *&ptr, size_t &cap, size_t need)
+{
+    if (need <= cap && ptr)
+        return hipSuccess;
+    if (ptr)
+        (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    const hipError_t e = hipMalloc(reinterpret_cast<void **>(&ptr), need * sizeof(P));
+    if (e == hipSuccess)
+        cap = need;
+    return e;
+}
+
+int ensure_scan(pwrel_ctx *ctx, const Geom &g)
+{
+    hipError_t e = grow(ctx->ws.offsets, ctx->ws.offsets_cap, (size_t)g.nblocks);
+    if (e == hipSuccess)
+        e = grow(ctx->ws.partials, ctx->ws.partials_cap,
+                 (size_t)((g.nblocks + kScanChunk - 1) / kScanChunk));
+    if (e != hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
+    return PWREL_OK;
+}
+
+int finish_status(pwrel_ctx *ctx, int st)
+{
+    switch (st) {
+    case PWREL_OK:
+        return PWREL_OK;
+    case PWREL_ERANGE:
+        return fail(ctx, st, "a grid value leaves +-2^30: the bound is too tight for the range");
+    case PWREL_ENONFINITE:
+        return fail(ctx, st, "the field holds NaN or Inf");
+    case PWREL_ENOSPC:
+        return fail(ctx, st, "output capacity too small");
+    case PWREL_ECORRUPT:
+        return fail(ctx, st, "stream is corrupt");
+    default:
+        return fail(ctx, st, "device reported status " + std::to_string(st));
+    }
+}
+
+// Profiling marks: record event `i` on the stream when profiling is on.
+void mark(pwrel_ctx *ctx, int i, hipStream_t s)
+{
+    if (ctx->profiling && ctx->ev_ok)
+        (void)hipEventRecord(ctx->ev[i], s);
+}
+
+// After a synchronize: phase p = time from mark a to mark b.
+void collect(pwrel_ctx *ctx, const int (*spans)[3], int n)
+{
+    if (!(ctx->profiling && ctx->ev_ok))
+        return;
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ctx->ev[spans[i][1]], ctx->ev[spans[i][2]]) == hipSuccess)
+            ctx->phase_ms[spans[i][0]] = ms;
+    }
+}
+
+uint64_t splitmix64(uint64_t s)
+{
+    uint64_t z = s + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pwrel_status_string(int status)
+{
+    switch (status) {
+    case PWREL_OK: return "ok";
+    case PWREL_EINVAL: return "invalid argument";
+    case PWREL_ERANGE: return "grid value out of range";
+    case PWREL_ENONFINITE: return "non-finite input";
+    case PWREL_ENOSPC: return "output capacity too small";
+    case PWREL_ECORRUPT: return "corrupt stream";
+    case PWREL_EHIP: return "HIP runtime error";
+    case PWREL_ENOMEM: return "out of memory";
+    default: return "unknown status";
+    }
+}
+
+int pwrel_check_args(const uint64_t *dims, int ndim, int dtype, double eps, int block_size)
+{
+    Geom g;
+    if (!make_geom(dims, ndim, dtype, block_size, g))
+        return PWREL_EINVAL;
+    if (!(eps > 0.0 && eps < 1.0) || !(1.0 + eps > 1.0))
+        return PWREL_EINVAL;
+    return PWREL_OK;
+}
+
+uint64_t pwrel_compress_bound(const uint64_t *dims, int ndim, int dtype, int block_size)
+{
+    Geom g;
+    if (!make_geom(dims, ndim, dtype, block_size, g))
+        return 0;
+    const Layout L = layout_for(g, PWREL_HF_NET | PWREL_HF_JUDGE);
+    return L.off[4] + (uint64_t)g.N * (dtype == PWREL_F32 ? 4u : 8u);
+}
+
+int pwrel_create(pwrel_ctx **out, int device)
+{
+    if (!out)
+        return PWREL_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return PWREL_EINVAL;
+    pwrel_ctx *ctx = new (std::nothrow) pwrel_ctx();
+    if (!ctx)
+        return PWREL_ENOMEM;
+    ctx->device = device;
+    DeviceGuard guard(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->num_cus = prop.multiProcessorCount;
+    Workspace &ws = ctx->ws;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&ws.stats), kStatParts * sizeof(DevStats));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.consts), sizeof(DevConsts));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.status), 256);
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.hist), 65536 * sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.n_raw), 256);
+    if (e != hipSuccess) {
+        pwrel_destroy(ctx);
+        return PWREL_ENOMEM;
+    }
+    *out = ctx;
+    return PWREL_OK;
+}
+
+void pwrel_destroy(pwrel_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    DeviceGuard guard(ctx->device);
+    Workspace &ws = ctx->ws;
+    void *ptrs[] = {ws.stats, ws.consts, ws.status, ws.hist, ws.n_raw, ws.offsets, ws.partials,
+                    ws.pgrid, ctx->counts_scratch};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    if (ctx->ev_ok)
+        for (hipEvent_t &e : ctx->ev)
+            (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char *pwrel_last_error(const pwrel_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : "no context";
+}
+
+int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                   int dtype, double eps, int block_size, const pwrel_mlp *model,
+                   const pwrel_options *opt_in, void *d_out, uint64_t out_capacity,
+                   uint64_t *out_size, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    pwrel_options opt{1, 0, 0, 0};
+    if (opt_in)
+        opt = *opt_in;
+    if (pwrel_check_args(dims, ndim, dtype, eps, block_size) != PWREL_OK)
+        return fail(ctx, PWREL_EINVAL, "bad dims/ndim/dtype/bound/block size");
+    if (!d_field || !d_out || !out_size)
+        return fail(ctx, PWREL_EINVAL, "NULL field, output or size pointer");
+    if (opt.judge)
+        return fail(ctx, PWREL_EINVAL, "per-block judge needs the matrix-core network path");
+    if (opt.use_net) {
+        const int st = check_model(ctx, model, ndim);
+        if (st)
+            return st;
+    }
+    Geom g;
+    make_geom(dims, ndim, dtype, block_size, g);
+    Tile tile;
+    if (!tile_for(g, tile))
+        return fail(ctx, PWREL_EINVAL, "block too large for the LDS tile");
+    const int flags = (opt.use_net ? PWREL_HF_NET : 0) | (opt.judge ? PWREL_HF_JUDGE : 0) |
+                      (opt.independent_blocks ? PWREL_HF_INDEPENDENT : 0);
+    const Layout L = layout_for(g, flags);
+    if (out_capacity < L.off[4])
+        return fail(ctx, PWREL_ENOSPC, "output capacity below header + codes");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int st = ensure_scan(ctx, g);
+    if (st)
+        return st;
+    unsigned char *out = static_cast<unsigned char *>(d_out);
+    uint16_t *codes = reinterpret_cast<uint16_t *>(out + L.off[3]);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(out + L.off[2]);
+    uint8_t *bflags = (flags & PWREL_HF_JUDGE) ? out + L.off[1] : nullptr;
+    const unsigned tsize = dtype == PWREL_F32 ? 4u : 8u;
+    hipError_t e;
+    if ((e = launch_reset(ctx->ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "reset");
+    mark(ctx, 0, s);
+    if ((e = launch_stats(d_field, g, ctx->ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "stats");
+    if ((e = launch_consts(g, eps, ctx->ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "consts");
+    mark(ctx, 1, s);
+    if ((e = launch_compress(d_field, nullptr, g, tile, model, opt, ctx->ws, codes, counts,
+                             bflags, ctx->num_cus, s)) != hipSuccess)
+        return hip_fail(ctx, e, "compress");
+    mark(ctx, 2, s);
+    if ((e = launch_scan(counts, g, ctx->ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "scan");
+    if ((e = launch_scatter(d_field, g, codes, counts, ctx->ws, out + L.off[4],
+                            (out_capacity - L.off[4]) / tsize, s)) != hipSuccess)
+        return hip_fail(ctx, e, "scatter");
+    if (opt.use_net) {
+        if ((e = hipMemcpyAsync(out + L.off[0], model, sizeof(pwrel_mlp), hipMemcpyHostToDevice,
+                                s)) != hipSuccess)
+            return hip_fail(ctx, e, "model copy");
+    }
+    if ((e = launch_header(g, flags, L.off, ctx->ws, out, out_capacity, s)) != hipSuccess)
+        return hip_fail(ctx, e, "header");
+    mark(ctx, 3, s);
+    pwrel_header h;
+    if ((e = hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "synchronize");
+    static const int spans[3][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}};
+    collect(ctx, spans, 3);
+    if (h.status != PWREL_OK)
+        return finish_status(ctx, h.status);
+    *out_size = h.total_size;
+    return PWREL_OK;
+}
+
+int pwrel_read_header(const void *buf, uint64_t size, pwrel_header *out)
+{
+    if (!buf || !out || size < sizeof(pwrel_header))
+        return PWREL_ECORRUPT;
+    pwrel_header h;
+    std::memcpy(&h, buf, sizeof h);
+    if (h.magic != PWREL_MAGIC || h.version != PWREL_VERSION)
+        return PWREL_ECORRUPT;
+    if (h.dtype != PWREL_F32 && h.dtype != PWREL_F64)
+        return PWREL_ECORRUPT;
+    Geom g;
+    if (!make_geom(h.dims, h.ndim, h.dtype, h.block, g))
+        return PWREL_ECORRUPT;
+    if ((uint64_t)g.N != h.n || (uint64_t)g.nblocks != h.nblocks || h.status != PWREL_OK)
+        return PWREL_ECORRUPT;
+    if (h.flags & ~(PWREL_HF_NET | PWREL_HF_JUDGE | PWREL_HF_INDEPENDENT))
+        return PWREL_ECORRUPT;
+    const Layout L = layout_for(g, h.flags);
+    if (h.off_model != L.off[0] || h.off_bflags != L.off[1] || h.off_counts != L.off[2] ||
+        h.off_codes != L.off[3] || h.off_raw != L.off[4])
+        return PWREL_ECORRUPT;
+    const uint64_t tsize = h.dtype == PWREL_F32 ? 4u : 8u;
+    if (h.n_raw > h.n || h.total_size != h.off_raw + h.n_raw * tsize || h.total_size > size)
+        return PWREL_ECORRUPT;
+    if (!(h.w > 0.0) || !std::isfinite(h.w) || !std::isfinite(h.Lp) || !std::isfinite(h.Ln) ||
+        !(h.eps > 0.0 && h.eps < 1.0) || !(h.p_zero <= h.b_sign) || h.delta < 0)
+        return PWREL_ECORRUPT;
+    *out = h;
+    return PWREL_OK;
+}
+
+int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d_field,
+                     const uint64_t *dims, int ndim, int dtype, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!d_in || !d_field || !dims)
+        return fail(ctx, PWREL_EINVAL, "NULL stream, field or dims");
+    if (in_size < PWREL_HEADER_BYTES)
+        return fail(ctx, PWREL_ECORRUPT, "stream shorter than its header");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    struct {
+        pwrel_header h;
+        unsigned char pad[PWREL_HEADER_BYTES - sizeof(pwrel_header)];
+        pwrel_mlp m;
+    } head;
+    static_assert(sizeof(pwrel_header) <= PWREL_HEADER_BYTES, "header too large");
+    const uint64_t want = std::min<uint64_t>(in_size, sizeof head);
+    std::memset(&head, 0, sizeof head);
+    hipError_t e = hipMemcpyAsync(&head, d_in, want, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    pwrel_header h;
+    if (pwrel_read_header(&head.h, in_size, &h) != PWREL_OK)
+        return fail(ctx, PWREL_ECORRUPT, "stream header is corrupt or truncated");
+    if (h.ndim != ndim || h.dtype != dtype)
+        return fail(ctx, PWREL_EINVAL, "dims/dtype do not match the stream");
+    for (int d = 0; d < ndim; ++d)
+        if (h.dims[d] != dims[d])
+            return fail(ctx, PWREL_EINVAL, "dims do not match the stream");
+    if ((h.flags & PWREL_HF_JUDGE))
+        return fail(ctx, PWREL_EINVAL, "per-block judge streams need the matrix-core path");
+    const pwrel_mlp *model = nullptr;
+    if (h.flags & PWREL_HF_NET) {
+        if (want < PWREL_HEADER_BYTES + sizeof(pwrel_mlp))
+            return fail(ctx, PWREL_ECORRUPT, "stream too short for its model");
+        model = &head.m;
+        if (check_model(ctx, model, ndim) != PWREL_OK)
+            return fail(ctx, PWREL_ECORRUPT, "stream model is invalid");
+    }
+    Geom g;
+    make_geom(h.dims, h.ndim, h.dtype, h.block, g);
+    int st = ensure_scan(ctx, g);
+    if (st)
+        return st;
+    if (!(h.flags & PWREL_HF_INDEPENDENT)) {
+        if ((e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
+            return fail(ctx, PWREL_ENOMEM, "grid scratch allocation failed");
+    }
+    DevConsts c{};
+    c.eps = h.eps;
+    c.eps0 = h.eps0;
+    c.b_a = h.b_a;
+    c.w = h.w;
+    c.r = h.r;
+    c.Lp = h.Lp;
+    c.Ln = h.Ln;
+    c.d0 = h.d0;
+    c.p_zero = h.p_zero;
+    c.b_sign = h.b_sign;
+    c.n_lo = h.n_lo;
+    c.delta = h.delta;
+    const unsigned char *in = static_cast<const unsigned char *>(d_in);
+    const uint32_t *counts = reinterpret_cast<const uint32_t *>(in + h.off_counts);
+    const uint16_t *codes = reinterpret_cast<const uint16_t *>(in + h.off_codes);
+    const uint8_t *bflags = (h.flags & PWREL_HF_JUDGE) ? in + h.off_bflags : nullptr;
+    if ((e = launch_reset(ctx->ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "reset");
+    mark(ctx, 4, s);
+    if ((e = launch_scan(counts, g, ctx->ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "scan");
+    mark(ctx, 5, s);
+    if ((e = launch_decode(g, c, model, h.flags, bflags, codes, counts, in + h.off_raw, h.n_raw,
+                           ctx->ws, d_field, s)) != hipSuccess)
+        return hip_fail(ctx, e, "decode");
+    mark(ctx, 6, s);
+    int dst = 0;
+    unsigned long long nr = 0;
+    if ((e = hipMemcpyAsync(&dst, ctx->ws.status, sizeof dst, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&nr, ctx->ws.n_raw, sizeof nr, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "status copy");
+    if (dst == PWREL_OK && nr != h.n_raw)
+        dst = PWREL_ECORRUPT;
+    static const int spans[2][3] = {{3, 4, 5}, {4, 5, 6}};
+    collect(ctx, spans, 2);
+    return finish_status(ctx, dst);
+}
+
+int pwrel_transform(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                    int dtype, double eps, int32_t *d_p, pwrel_header *hdr_out, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (pwrel_check_args(dims, ndim, dtype, eps, 2) != PWREL_OK || !d_field || !d_p)
+        return fail(ctx, PWREL_EINVAL, "bad arguments");
+    Geom g;
+    make_geom(dims, ndim, dtype, 2, g);
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = launch_reset(ctx->ws, s)) != hipSuccess ||
+        (e = launch_stats(d_field, g, ctx->ws, s)) != hipSuccess ||
+        (e = launch_consts(g, eps, ctx->ws, s)) != hipSuccess ||
+        (e = launch_transform(d_field, g, ctx->ws, d_p, s)) != hipSuccess)
+        return hip_fail(ctx, e, "transform");
+    DevConsts c;
+    int dst = 0;
+    if ((e = hipMemcpyAsync(&c, ctx->ws.consts, sizeof c, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&dst, ctx->ws.status, sizeof dst, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "constants copy");
+    if (dst != PWREL_OK)
+        return finish_status(ctx, dst);
+    if (hdr_out) {
+        pwrel_header h{};
+        h.magic = PWREL_MAGIC;
+        h.version = PWREL_VERSION;
+        h.dtype = dtype;
+        h.ndim = ndim;
+        for (int d = 0; d < ndim; ++d)
+            h.dims[d] = dims[d];
+        h.eps = c.eps;
+        h.eps0 = c.eps0;
+        h.b_a = c.b_a;
+        h.w = c.w;
+        h.r = c.r;
+        h.Lp = c.Lp;
+        h.Ln = c.Ln;
+        h.d0 = c.d0;
+        h.p_zero = c.p_zero;
+        h.b_sign = c.b_sign;
+        h.n_lo = c.n_lo;
+        h.delta = c.delta;
+        h.n = (uint64_t)g.N;
+        h.abs_min = c.abs_min;
+        h.abs_max = c.abs_max;
+        h.n_zero = c.n_zero;
+        h.n_neg = c.n_neg;
+        *hdr_out = h;
+    }
+    return PWREL_OK;
+}
+
+int pwrel_encode_grid(pwrel_ctx *ctx, const int32_t *d_p, const uint64_t *dims, int ndim,
+                      int block_size, const pwrel_mlp *model, const pwrel_options *opt_in,
+                      uint16_t *d_codes, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    pwrel_options opt{1, 0, 0, 0};
+    if (opt_in)
+        opt = *opt_in;
+    Geom g;
+    if (!make_geom(dims, ndim, PWREL_F32, block_size, g) || !d_p || !d_codes)
+        return fail(ctx, PWREL_EINVAL, "bad arguments");
+    if (opt.judge)
+        return fail(ctx, PWREL_EINVAL, "judge is not available on grid input");
+    if (opt.use_net) {
+        const int st = check_model(ctx, model, ndim);
+        if (st)
+            return st;
+    }
+    Tile tile;
+    if (!tile_for(g, tile))
+        return fail(ctx, PWREL_EINVAL, "block too large for the LDS tile");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = grow(ctx->counts_scratch, ctx->counts_scratch_cap, (size_t)g.nblocks);
+    if (e != hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, "count scratch allocation failed");
+    if ((e = launch_reset(ctx->ws, s)) != hipSuccess ||
+        (e = launch_compress(nullptr, d_p, g, tile, model, opt, ctx->ws, d_codes,
+                             ctx->counts_scratch, nullptr, ctx->num_cus, s)) != hipSuccess)
+        return hip_fail(ctx, e, "encode_grid");
+    int dst = 0;
+    if ((e = hipMemcpyAsync(&dst, ctx->ws.status, sizeof dst, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "status copy");
+    return finish_status(ctx, dst);
+}
+
+int pwrel_detmath(pwrel_ctx *ctx, const double *d_x, double *d_log2, double *d_exp2, uint64_t n,
+                  void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!d_x && n)
+        return fail(ctx, PWREL_EINVAL, "NULL input");
+    DeviceGuard guard(ctx->device);
+    const hipError_t e =
+        launch_detmath(d_x, d_log2, d_exp2, n, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PWREL_OK : hip_fail(ctx, e, "detmath");
+}
+
+int pwrel_set_profiling(pwrel_ctx *ctx, int enable)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (enable && !ctx->ev_ok) {
+        bool ok = true;
+        for (hipEvent_t &e : ctx->ev)
+            ok = ok && hipEventCreate(&e) == hipSuccess;
+        if (!ok)
+            return fail(ctx, PWREL_EHIP, "event creation failed");
+        ctx->ev_ok = true;
+    }
+    ctx->profiling = enable ? 1 : 0;
+    return PWREL_OK;
+}
+
+int pwrel_phase_times(pwrel_ctx *ctx, double *ms, int n)
+{
+    if (!ctx || !ms || n < 0)
+        return PWREL_EINVAL;
+    const int k = std::min(n, PWREL_NUM_PHASES);
+    for (int i = 0; i < k; ++i)
+        ms[i] = ctx->phase_ms[i];
+    return k;
+}
+
+int pwrel_histogram(pwrel_ctx *ctx, const uint16_t *d_codes, uint64_t n, uint64_t *hist,
+                    void *stream)
+{
+    if (!ctx || !hist || (!d_codes && n))
+        return PWREL_EINVAL;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = launch_hist(d_codes, (long long)n, ctx->ws.hist, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hist, ctx->ws.hist, 65536 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                           s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    return e == hipSuccess ? PWREL_OK : hip_fail(ctx, e, "histogram");
+}
+
+uint64_t pwrel_huffman_bits(const uint64_t *hist, uint32_t *max_len_out)
+{
+    // Huffman code lengths by repeated merging of the two lightest subtrees;
+    // the coded size is sum(count * length).  A single used symbol costs one
+    // bit per occurrence.
+    if (!hist)
+        return 0;
+    struct Node {
+        uint64_t w;
+        int id;
+    };
+    auto cmp = [](const Node &a, const Node &b) { return a.w > b.w || (a.w == b.w && a.id > b.id); };
+    std::priority_queue<Node, std::vector<Node>, decltype(cmp)> q(cmp);
+    std::vector<int> parent;
+    std::vector<int> leaf_of;
+    for (int s = 0; s < 65536; ++s)
+        if (hist[s]) {
+            leaf_of.push_back(s);
+            q.push({hist[s], (int)parent.size()});
+            parent.push_back(-1);
+        }
+    if (parent.empty()) {
+        if (max_len_out)
+            *max_len_out = 0;
+        return 0;
+    }
+    if (parent.size() == 1) {
+        if (max_len_out)
+            *max_len_out = 1;
+        return hist[leaf_of[0]];
+    }
+    while (q.size() > 1) {
+        const Node a = q.top();
+        q.pop();
+        const Node b = q.top();
+        q.pop();
+        const int id = (int)parent.size();
+        parent.push_back(-1);
+        parent[a.id] = id;
+        parent[b.id] = id;
+        q.push({a.w + b.w, id});
+    }
+    uint64_t bits = 0;
+    uint32_t maxl = 0;
+    std::vector<uint32_t> depth(parent.size(), 0);
+    for (int i = (int)parent.size() - 2; i >= 0; --i)
+        depth[i] = depth[parent[i]] + 1;
+    for (size_t i = 0; i < leaf_of.size(); ++i) {
+        bits += hist[leaf_of[i]] * depth[i];
+        maxl = std::max(maxl, depth[i]);
+    }
+    if (max_len_out)
+        *max_len_out = maxl;
+    return bits;
+}
+
+int pwrel_mlp_init(pwrel_mlp *m, int ndim, int hidden, float alpha, uint64_t seed)
+{
+    // hidden unit 0 carries the Lorenzo combination of the neighbour
+    // differences, unit 1 its negation; output weights +-1/(1+alpha) turn the
+    // two leaky-ReLU halves back into the identity; the remaining units get
+    // small hashed input weights and zero output weight.
+    if (!m || ndim < 1 || ndim > 3 || hidden < 2 || hidden > PWREL_MAX_HIDDEN)
+        return PWREL_EINVAL;
+    std::memset(m, 0, sizeof *m);
+    m->hidden = hidden;
+    m->inputs = (1 << ndim) - 2;
+    m->alpha = alpha;
+    for (int k = 0; k < m->inputs; ++k) {
+        const float c = (float)lorenzo_sign(k + 2);
+        m->w1[0][k] = c;
+        m->w1[1][k] = -c;
+    }
+    m->v[0] = (float)(1.0 / (1.0 + (double)alpha));
+    m->v[1] = -m->v[0];
+    for (int j = 2; j < hidden; ++j)
+        for (int k = 0; k < m->inputs; ++k) {
+            const uint64_t h = splitmix64(seed ^ (uint64_t)(j * m->inputs + k));
+            const double u = (double)(h >> 11) * 0x1p-53;
+            m->w1[j][k] = (float)(0.1 * (2.0 * u - 1.0));
+        }
+    return PWREL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,616 @@
+// Field statistics, constants, scan / raw scatter, stream header, histogram
+// and inspection kernels of the PW_REL perceptron codec (gfx950).
+//
+// Compression:   reset -> stats -> consts -> compress -> scan -> scatter -> header
+// Decompression: reset -> scan -> decode (per block level, or all blocks at once)
+#include "pwrel_kernels.h"
+
+namespace pwrel {
+
+// ---------------------------------------------------------------------------
+// reset: status and balance-point total (graph-safe: a kernel, not a memset)
+// ---------------------------------------------------------------------------
+__global__ void k_reset(int *status, unsigned long long *n_raw)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *status = kOk;
+        *n_raw = 0ULL;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a1: statistics in two stages.  Each workgroup reduces its part of the field
+// (per-lane min / max of |x| bit patterns -- order-preserving for finite
+// non-negative floats -- and counts; wave shuffles, then LDS) to one record;
+// the constants kernel reduces the records.  No same-address atomics.
+// ---------------------------------------------------------------------------
+struct Acc {
+    unsigned long long mn, mx, nz, nn, nf;
+};
+
+__device__ __forceinline__ void classify(float v, Acc &a)
+{
+    const unsigned b = __float_as_uint(v);
+    const unsigned m = b & 0x7fffffffu;
+    if ((m >> 23) == 0xffu) {
+        a.nf++;
+    } else if (m == 0u) {
+        a.nz++;
+    } else {
+        a.nn += (b >> 31);
+        a.mn = (unsigned long long)m < a.mn ? (unsigned long long)m : a.mn;
+        a.mx = (unsigned long long)m > a.mx ? (unsigned long long)m : a.mx;
+    }
+}
+
+__device__ __forceinline__ void classify(double v, Acc &a)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long m = b & 0x7fffffffffffffffULL;
+    if ((m >> 52) == 0x7ffULL) {
+        a.nf++;
+    } else if (m == 0ULL) {
+        a.nz++;
+    } else {
+        a.nn += (b >> 63);
+        a.mn = m < a.mn ? m : a.mn;
+        a.mx = m > a.mx ? m : a.mx;
+    }
+}
+
+__device__ __forceinline__ void wave_reduce(Acc &a)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long mn = __shfl_xor(a.mn, off, 64);
+        const unsigned long long mx = __shfl_xor(a.mx, off, 64);
+        a.mn = mn < a.mn ? mn : a.mn;
+        a.mx = mx > a.mx ? mx : a.mx;
+        a.nz += __shfl_xor(a.nz, off, 64);
+        a.nn += __shfl_xor(a.nn, off, 64);
+        a.nf += __shfl_xor(a.nf, off, 64);
+    }
+}
+
+// combine the per-wave records of the workgroup into thread 0
+__device__ __forceinline__ void block_reduce(Acc &a)
+{
+    __shared__ Acc part[4];
+    wave_reduce(a);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        part[w] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+            a.mn = part[q].mn < a.mn ? part[q].mn : a.mn;
+            a.mx = part[q].mx > a.mx ? part[q].mx : a.mx;
+            a.nz += part[q].nz;
+            a.nn += part[q].nn;
+            a.nf += part[q].nf;
+        }
+    }
+}
+
+template <typename T, typename V, int VW>
+__global__ void __launch_bounds__(256) k_stats(const T *__restrict__ x, long long n,
+                                               DevStats *parts)
+{
+    Acc a{~0ULL, 0ULL, 0ULL, 0ULL, 0ULL};
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nthr = (long long)gridDim.x * blockDim.x;
+    const long long nv = n / VW;
+    const V *xv = reinterpret_cast<const V *>(x);
+    for (long long i = tid; i < nv; i += nthr) {
+        const V v = xv[i];
+        const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+        for (int q = 0; q < VW; ++q)
+            classify(e[q], a);
+    }
+    for (long long i = nv * VW + tid; i < n; i += nthr)
+        classify(x[i], a);
+    block_reduce(a);
+    if (threadIdx.x == 0) {
+        DevStats r{};
+        r.min_bits = a.mn;
+        r.max_bits = a.mx;
+        r.n_zero = a.nz;
+        r.n_neg = a.nn;
+        r.n_nonfinite = a.nf;
+        parts[blockIdx.x] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a2: reduce the statistics records, then the constants (Eq. 8-12) on one
+// thread; everything stays on the device.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double from_abs_bits(unsigned long long b);
+template <>
+__device__ __forceinline__ double from_abs_bits<float>(unsigned long long b)
+{
+    return (double)__uint_as_float((unsigned)b);
+}
+template <>
+__device__ __forceinline__ double from_abs_bits<double>(unsigned long long b)
+{
+    return __longlong_as_double((long long)b);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_consts(const DevStats *parts, int nparts, double eps,
+                                                DevConsts *c, int *status)
+{
+    Acc a{~0ULL, 0ULL, 0ULL, 0ULL, 0ULL};
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        const DevStats r = parts[i];
+        a.mn = r.min_bits < a.mn ? r.min_bits : a.mn;
+        a.mx = r.max_bits > a.mx ? r.max_bits : a.mx;
+        a.nz += r.n_zero;
+        a.nn += r.n_neg;
+        a.nf += r.n_nonfinite;
+    }
+    block_reduce(a);
+    if (threadIdx.x != 0)
+        return;
+    double amin = 1.0, amax = 1.0;
+    if (a.mn != ~0ULL) {
+        amin = from_abs_bits<T>(a.mn);
+        amax = from_abs_bits<T>(a.mx);
+    }
+    DevConsts k{};
+    k.abs_min = amin;
+    k.abs_max = amax;
+    k.n_zero = a.nz;
+    k.n_neg = a.nn;
+    k.n_nonfinite = a.nf;
+    int err = kOk;
+    if (a.nf)
+        err = kENonFinite;
+    const double tau = sizeof(T) == 4 ? 0x1p-126 : 0x1p-1022;
+    double eps0 = amin * 0.5;
+    if (tau < eps0)
+        eps0 = tau;
+    if (err == kOk && !(eps0 > 0.0))
+        err = kERange;
+    const double one_eps = 1.0 + eps;
+    if (err == kOk) {
+        k.eps = eps;
+        k.eps0 = eps0;
+        k.b_a = det_log2(one_eps);
+        k.w = k.b_a + k.b_a;
+        k.r = 1.0 / k.w;
+        k.Lp = det_log2(amin);
+        k.Ln = ((det_log2(amax + eps0) + k.Lp) + k.w) - det_log2(amin - eps0);
+        k.d0 = det_log2(eps0) + k.Lp;
+        const double tz = k.d0 * k.r;
+        const double tb = (det_log2(amax) + k.Lp) * k.r;
+        const double tn = (det_log2(amin) + k.Ln) * k.r;
+        if (!(__builtin_fabs(tz) < kGridLimit) || !(__builtin_fabs(tb) < kGridLimit) ||
+            !(__builtin_fabs(tn) < kGridLimit)) {
+            err = kERange;
+        } else {
+            k.p_zero = (long long)__builtin_rint(tz);
+            k.b_sign = (long long)__builtin_rint(tb);
+            k.n_lo = (long long)__builtin_rint(tn);
+            k.delta = k.b_sign + 1 - k.n_lo;
+            if (k.delta < 0)
+                k.delta = 0;
+        }
+    }
+    k.status = err;
+    *c = k;
+    set_status(status, err);
+}
+
+// ---------------------------------------------------------------------------
+// a3 alone: grid value of every point (inspection entry point).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_transform(const T *__restrict__ x, long long n,
+                                                   const DevConsts *cp, int *status,
+                                                   int *__restrict__ p)
+{
+    if (*status != kOk)
+        return;  // no barrier below: a per-thread exit is safe
+    const DevConsts c = *cp;
+    int err = kOk;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = grid_value((double)x[i], c, err);
+    set_status(status, err);
+}
+
+// ---------------------------------------------------------------------------
+// a7: exclusive scan of per-block balance-point counts (two levels).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned o = __shfl_up(v, d, 64);
+        if (lane >= d)
+            v += o;
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_scan_local(const uint32_t *__restrict__ counts,
+                                                    long long nb,
+                                                    unsigned long long *__restrict__ offs,
+                                                    unsigned long long *__restrict__ partials)
+{
+    __shared__ unsigned wsum[4];
+    constexpr int PER = kScanChunk / 256;
+    const long long base = (long long)blockIdx.x * kScanChunk + threadIdx.x * PER;
+    unsigned v[PER];
+    unsigned s = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        v[q] = (base + q < nb) ? counts[base + q] : 0u;
+        s += v[q];
+    }
+    const unsigned incl = wave_incl_scan(s);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63)
+        wsum[w] = incl;
+    __syncthreads();
+    unsigned wbase = 0;
+    for (int q = 0; q < w; ++q)
+        wbase += wsum[q];
+    unsigned run = wbase + incl - s;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        if (base + q < nb)
+            offs[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == 255)
+        partials[blockIdx.x] = (unsigned long long)(wbase + incl);
+}
+
+__global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long *partials,
+                                                        long long np,
+                                                        unsigned long long *total)
+{
+    __shared__ unsigned long long sh[1024];
+    unsigned long long carry = 0;
+    for (long long b0 = 0; b0 < np; b0 += 1024) {
+        const long long i = b0 + threadIdx.x;
+        const unsigned long long v = i < np ? partials[i] : 0ULL;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const unsigned long long o = threadIdx.x >= d ? sh[threadIdx.x - d] : 0ULL;
+            __syncthreads();
+            sh[threadIdx.x] += o;
+            __syncthreads();
+        }
+        if (i < np)
+            partials[i] = carry + sh[threadIdx.x] - v;
+        const unsigned long long tot = sh[1023];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0)
+        *total = carry;
+}
+
+// ---------------------------------------------------------------------------
+// a7: raw values of balance points in stream order (one wave per block, wave
+// ballot + popcount for the in-block rank).
+// ---------------------------------------------------------------------------
+struct GeoArgs {
+    long long n[3];
+    int bd[3];
+    long long nb[3];
+    long long nblocks;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter(const T *__restrict__ x, GeoArgs g,
+                                                 const uint16_t *__restrict__ codes,
+                                                 const uint32_t *__restrict__ counts,
+                                                 const unsigned long long *offs,
+                                                 const unsigned long long *partials,
+                                                 T *__restrict__ raw, unsigned long long raw_cap,
+                                                 int *status)
+{
+    if (*status != kOk)
+        return;  // wave-level work only: a per-thread exit is safe
+    const int lane = threadIdx.x & 63;
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    for (long long b = wave; b < g.nblocks; b += nwaves) {
+        const unsigned cnt = counts[b];
+        if (cnt == 0)
+            continue;
+        const long long bx = b % g.nb[2], by = (b / g.nb[2]) % g.nb[1],
+                        bz = b / (g.nb[1] * g.nb[2]);
+        const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
+        const long long bsize = (long long)q.ez * q.ey * q.ex;
+        const unsigned long long base = offs[b] + partials[b / kScanChunk];
+        unsigned run = 0;
+        for (long long c0 = 0; c0 < bsize && run < cnt; c0 += 64) {
+            const long long li = c0 + lane;
+            const bool z = li < bsize && codes[q.start + li] == 0;
+            const unsigned long long mask = __ballot(z);
+            if (z) {
+                const unsigned rank = run + (unsigned)__popcll(mask & below);
+                const long long lx = li % q.ex, ly = (li / q.ex) % q.ey, lz = li / (q.ex * q.ey);
+                const long long gi = ((bz * g.bd[0] + lz) * g.n[1] + by * g.bd[1] + ly) *
+                                         g.n[2] + bx * g.bd[2] + lx;
+                if (base + rank < raw_cap)
+                    raw[base + rank] = x[gi];
+                else
+                    set_status(status, kENoSpc);
+            }
+            run += (unsigned)__popcll(mask);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stream header (one thread)
+// ---------------------------------------------------------------------------
+struct HeaderArgs {
+    int dtype, ndim, block, flags;
+    unsigned long long dims[3];
+    unsigned long long n, nblocks;
+    unsigned long long off_model, off_bflags, off_counts, off_codes, off_raw;
+    unsigned long long capacity;
+    int raw_size;
+};
+
+__global__ void k_header(HeaderArgs h, const DevConsts *cp, const unsigned long long *n_raw,
+                         int *status, pwrel_header *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    pwrel_header o{};
+    const DevConsts c = *cp;
+    o.magic = PWREL_MAGIC;
+    o.version = PWREL_VERSION;
+    o.dtype = h.dtype;
+    o.ndim = h.ndim;
+    for (int d = 0; d < 3; ++d)
+        o.dims[d] = h.dims[d];
+    o.block = h.block;
+    o.flags = h.flags;
+    o.eps = c.eps;
+    o.eps0 = c.eps0;
+    o.b_a = c.b_a;
+    o.w = c.w;
+    o.r = c.r;
+    o.Lp = c.Lp;
+    o.Ln = c.Ln;
+    o.d0 = c.d0;
+    o.p_zero = c.p_zero;
+    o.b_sign = c.b_sign;
+    o.n_lo = c.n_lo;
+    o.delta = c.delta;
+    o.n = h.n;
+    o.nblocks = h.nblocks;
+    o.n_raw = *n_raw;
+    o.off_model = h.off_model;
+    o.off_bflags = h.off_bflags;
+    o.off_counts = h.off_counts;
+    o.off_codes = h.off_codes;
+    o.off_raw = h.off_raw;
+    o.total_size = h.off_raw + o.n_raw * (unsigned long long)h.raw_size;
+    o.abs_min = c.abs_min;
+    o.abs_max = c.abs_max;
+    o.n_zero = c.n_zero;
+    o.n_neg = c.n_neg;
+    int st = *status;
+    if (st == kOk && o.total_size > h.capacity)
+        st = kENoSpc;
+    o.status = st;
+    *out = o;
+}
+
+// ---------------------------------------------------------------------------
+// code histogram (on demand, not on the codec path): LDS window around the
+// zero-error code, global atomics outside it, one flush per workgroup.
+// ---------------------------------------------------------------------------
+constexpr int kHistWin = 8192;
+
+__global__ void __launch_bounds__(256) k_hist(const uint16_t *__restrict__ codes, long long n,
+                                              unsigned long long *hist)
+{
+    __shared__ unsigned win[kHistWin];
+    for (int i = threadIdx.x; i < kHistWin; i += blockDim.x)
+        win[i] = 0u;
+    __syncthreads();
+    const int lo = kR - kHistWin / 2;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int cd = codes[i];
+        const int k = cd - lo;
+        if (k >= 0 && k < kHistWin)
+            atomicAdd(&win[k], 1u);
+        else
+            atomicAdd(&hist[cd], 1ULL);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistWin; i += blockDim.x)
+        if (win[i])
+            atomicAdd(&hist[lo + i], (unsigned long long)win[i]);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0ULL;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic math on the device (inspection entry point)
+// ---------------------------------------------------------------------------
+__global__ void k_detmath(const double *x, double *l2, double *e2, unsigned long long n)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const double v = x[i];
+    if (l2)
+        l2[i] = v > 0.0 ? det_log2(v) : 0.0;
+    if (e2)
+        e2[i] = det_exp2(v);
+}
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+static unsigned grid_for(long long work, int per, unsigned cap)
+{
+    long long g = (work + per - 1) / per;
+    if (g < 1)
+        g = 1;
+    if (g > cap)
+        g = cap;
+    return (unsigned)g;
+}
+
+hipError_t launch_reset(Workspace &ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ws.status, ws.n_raw);
+    return hipGetLastError();
+}
+
+static unsigned stats_grid(const Geom &g) { return grid_for(g.N, 256 * 16, kStatParts); }
+
+hipError_t launch_stats(const void *x, const Geom &g, Workspace &ws, hipStream_t s)
+{
+    const unsigned grid = stats_grid(g);
+    const bool al16 = (reinterpret_cast<uintptr_t>(x) & 15u) == 0;
+    if (g.dtype == PWREL_F32) {
+        if (al16)
+            hipLaunchKernelGGL((k_stats<float, float4, 4>), dim3(grid), dim3(256), 0, s,
+                               (const float *)x, g.N, ws.stats);
+        else
+            hipLaunchKernelGGL((k_stats<float, float, 1>), dim3(grid), dim3(256), 0, s,
+                               (const float *)x, g.N, ws.stats);
+    } else {
+        if (al16)
+            hipLaunchKernelGGL((k_stats<double, double2, 2>), dim3(grid), dim3(256), 0, s,
+                               (const double *)x, g.N, ws.stats);
+        else
+            hipLaunchKernelGGL((k_stats<double, double, 1>), dim3(grid), dim3(256), 0, s,
+                               (const double *)x, g.N, ws.stats);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_consts(const Geom &g, double eps, Workspace &ws, hipStream_t s)
+{
+    const int nparts = (int)stats_grid(g);
+    if (g.dtype == PWREL_F32)
+        hipLaunchKernelGGL(k_consts<float>, dim3(1), dim3(256), 0, s, ws.stats, nparts, eps,
+                           ws.consts, ws.status);
+    else
+        hipLaunchKernelGGL(k_consts<double>, dim3(1), dim3(256), 0, s, ws.stats, nparts, eps,
+                           ws.consts, ws.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_transform(const void *x, const Geom &g, Workspace &ws, int *d_p, hipStream_t s)
+{
+    const unsigned grid = grid_for(g.N, 256 * 8, 8192);
+    if (g.dtype == PWREL_F32)
+        hipLaunchKernelGGL(k_transform<float>, dim3(grid), dim3(256), 0, s, (const float *)x,
+                           g.N, ws.consts, ws.status, d_p);
+    else
+        hipLaunchKernelGGL(k_transform<double>, dim3(grid), dim3(256), 0, s, (const double *)x,
+                           g.N, ws.consts, ws.status, d_p);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t *counts, const Geom &g, Workspace &ws, hipStream_t s)
+{
+    const long long nparts = (g.nblocks + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nparts), dim3(256), 0, s, counts, g.nblocks,
+                       ws.offsets, ws.partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, ws.partials, nparts,
+                       ws.n_raw);
+    return hipGetLastError();
+}
+
+static GeoArgs geo_args(const Geom &g)
+{
+    GeoArgs a{};
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = g.n[d];
+        a.bd[d] = g.bd[d];
+        a.nb[d] = g.nb[d];
+    }
+    a.nblocks = g.nblocks;
+    return a;
+}
+
+hipError_t launch_scatter(const void *x, const Geom &g, const uint16_t *codes,
+                          const uint32_t *counts, Workspace &ws, void *raw,
+                          unsigned long long raw_cap, hipStream_t s)
+{
+    const unsigned grid = grid_for(g.nblocks, 4, 8192);
+    const GeoArgs ga = geo_args(g);
+    if (g.dtype == PWREL_F32)
+        hipLaunchKernelGGL(k_scatter<float>, dim3(grid), dim3(256), 0, s, (const float *)x, ga,
+                           codes, counts, ws.offsets, ws.partials, (float *)raw, raw_cap,
+                           ws.status);
+    else
+        hipLaunchKernelGGL(k_scatter<double>, dim3(grid), dim3(256), 0, s, (const double *)x, ga,
+                           codes, counts, ws.offsets, ws.partials, (double *)raw, raw_cap,
+                           ws.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspace &ws,
+                         void *d_header, uint64_t capacity, hipStream_t s)
+{
+    HeaderArgs h{};
+    h.dtype = g.dtype;
+    h.ndim = g.D;
+    h.block = g.B;
+    h.flags = flags;
+    for (int d = 0; d < 3; ++d)
+        h.dims[d] = d < g.D ? (unsigned long long)g.n[3 - g.D + d] : 0ULL;
+    h.n = g.N;
+    h.nblocks = g.nblocks;
+    h.off_model = offs[0];
+    h.off_bflags = offs[1];
+    h.off_counts = offs[2];
+    h.off_codes = offs[3];
+    h.off_raw = offs[4];
+    h.capacity = capacity;
+    h.raw_size = g.dtype == PWREL_F32 ? 4 : 8;
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, h, ws.consts, ws.n_raw, ws.status,
+                       (pwrel_header *)d_header);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist(const uint16_t *codes, long long n, unsigned long long *hist,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, hist, 65536LL);
+    if (n > 0)
+        hipLaunchKernelGGL(k_hist, dim3(grid_for(n, 256 * 64, 1024)), dim3(256), 0, s, codes, n,
+                           hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_detmath(const double *x, double *l2, double *e2, uint64_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_detmath, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, l2, e2,
+                       (unsigned long long)n);
+    return hipGetLastError();
+}
+
+}  // namespace pwrel

@@ -1,0 +1,177 @@
+// Device-side arithmetic of the PW_REL perceptron compressor (gfx950).
+//
+// Everything here is plain IEEE-754 arithmetic (+, -, *, /, explicit fma,
+// rint, ldexp, bit extraction) so that every device result is a fixed
+// function of its inputs.  Compile with -ffp-contract=off: an a*b+c that is
+// not written as __builtin_fma must round twice.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pwrel {
+
+constexpr int kR = 32768;                 // 2^(m-1), m = 16 code bits
+constexpr double kGridLimit = 1073741824.0; // grid values stay inside +-2^30
+
+// Status codes shared with the C ABI (pwrel.h).
+constexpr int kOk = 0, kEInval = -1, kERange = -2, kENonFinite = -3, kENoSpc = -4,
+              kECorrupt = -5;
+
+// Constants of a field (Sec. 3.2, Eq. 8-12), produced on the device.
+struct DevConsts {
+    double eps, eps0, b_a, w, r, Lp, Ln, d0;
+    long long p_zero, b_sign, n_lo, delta;
+    double abs_min, abs_max;
+    unsigned long long n_zero, n_neg, n_nonfinite;
+    int status;
+    int pad;
+};
+
+// Running statistics of a field (reduced with integer atomics).
+struct DevStats {
+    unsigned long long min_bits;  // smallest |x| bit pattern among finite non-zero x
+    unsigned long long max_bits;  // largest |x| bit pattern among finite x
+    unsigned long long n_zero, n_neg, n_nonfinite;
+    unsigned long long pad[3];
+};
+
+// ---------------------------------------------------------------------------
+// log2 by the atanh series: with x = m 2^e, m in (sqrt(1/2), sqrt(2)],
+// ln m = 2 sum_{k>=0} s^(2k+1) / (2k+1), s = (m - 1) / (m + 1), |s| < 0.1716;
+// eleven terms leave a truncation error below 1e-18.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double det_log2(double x)
+{
+    int scale_e = 0;
+    if (x < 0x1p-1022) {        // subnormal: bring into the normal range exactly
+        x = x * 0x1p54;
+        scale_e = -54;
+    }
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7ffULL) - 1023;
+    double m = __longlong_as_double((long long)((bits & 0x000fffffffffffffULL) |
+                                                0x3ff0000000000000ULL));
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e += 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double acc = 1.0 / 21.0;
+    acc = __builtin_fma(acc, s2, 1.0 / 19.0);
+    acc = __builtin_fma(acc, s2, 1.0 / 17.0);
+    acc = __builtin_fma(acc, s2, 1.0 / 15.0);
+    acc = __builtin_fma(acc, s2, 1.0 / 13.0);
+    acc = __builtin_fma(acc, s2, 1.0 / 11.0);
+    acc = __builtin_fma(acc, s2, 1.0 / 9.0);
+    acc = __builtin_fma(acc, s2, 1.0 / 7.0);
+    acc = __builtin_fma(acc, s2, 1.0 / 5.0);
+    acc = __builtin_fma(acc, s2, 1.0 / 3.0);
+    acc = __builtin_fma(acc, s2, 1.0);
+    return (double)(e + scale_e) + ((s + s) * acc) * 1.4426950408889634;
+}
+
+// ---------------------------------------------------------------------------
+// 2^t = 2^k e^a with k = rint(t), a = (t - k) ln 2, |a| <= 0.347, and e^a by
+// its Taylor polynomial of degree 13 (truncation below 5e-18).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double det_exp2(double t)
+{
+    const double k = __builtin_rint(t);
+    const double a = (t - k) * 0.6931471805599453;
+    double acc = 1.0 / 6227020800.0;
+    acc = __builtin_fma(acc, a, 1.0 / 479001600.0);
+    acc = __builtin_fma(acc, a, 1.0 / 39916800.0);
+    acc = __builtin_fma(acc, a, 1.0 / 3628800.0);
+    acc = __builtin_fma(acc, a, 1.0 / 362880.0);
+    acc = __builtin_fma(acc, a, 1.0 / 40320.0);
+    acc = __builtin_fma(acc, a, 1.0 / 5040.0);
+    acc = __builtin_fma(acc, a, 1.0 / 720.0);
+    acc = __builtin_fma(acc, a, 1.0 / 120.0);
+    acc = __builtin_fma(acc, a, 1.0 / 24.0);
+    acc = __builtin_fma(acc, a, 1.0 / 6.0);
+    acc = __builtin_fma(acc, a, 1.0 / 2.0);
+    acc = __builtin_fma(acc, a, 1.0);
+    acc = __builtin_fma(acc, a, 1.0);
+    return __builtin_ldexp(acc, (int)k);
+}
+
+template <typename T> __device__ __forceinline__ double to_dtype(double v);
+template <> __device__ __forceinline__ double to_dtype<float>(double v) { return (double)(float)v; }
+template <> __device__ __forceinline__ double to_dtype<double>(double v) { return v; }
+
+// Grid value of an input value: Eq. 6 (positive), Eq. 7 (negative, plus the
+// integer offset delta), Eq. 12 (zero), clamped so that the zero image, the
+// positive range and the negative range stay disjoint.
+__device__ __forceinline__ int grid_value(double x, const DevConsts &c, int &err)
+{
+    if (x == 0.0)
+        return (int)c.p_zero;
+    if (x > 0.0) {
+        const double t = (det_log2(x) + c.Lp) * c.r;
+        if (!(__builtin_fabs(t) < kGridLimit)) {
+            err = kERange;
+            return 0;
+        }
+        long long q = (long long)__builtin_rint(t);
+        q = q < c.p_zero + 1 ? c.p_zero + 1 : q;
+        q = q > c.b_sign ? c.b_sign : q;
+        return (int)q;
+    }
+    const double t = (det_log2(-x) + c.Ln) * c.r;
+    if (!(__builtin_fabs(t) < kGridLimit)) {
+        err = kERange;
+        return 0;
+    }
+    long long q = (long long)__builtin_rint(t) + c.delta;
+    q = q < c.b_sign + 1 ? c.b_sign + 1 : q;
+    if (!(__builtin_fabs((double)q) < kGridLimit)) {
+        err = kERange;
+        return 0;
+    }
+    return (int)q;
+}
+
+// Inverse of the grid map (zero / positive / negative by threshold), rounded
+// to the field's dtype.
+template <typename T>
+__device__ __forceinline__ double grid_inverse(int p, const DevConsts &c)
+{
+    const long long q = p;
+    double v;
+    if (q <= c.p_zero)
+        v = 0.0;
+    else if (q <= c.b_sign)
+        v = det_exp2((double)q * c.w - c.Lp);
+    else
+        v = -det_exp2((double)(q - c.delta) * c.w - c.Ln);
+    return to_dtype<T>(v);
+}
+
+// |x - x^| <= eps |x| with sign and zero preserved, in FP64.
+__device__ __forceinline__ bool within_bound(double x, double xh, double eps)
+{
+    if (x == 0.0)
+        return xh == 0.0;
+    if (xh == 0.0)
+        return false;
+    if (__builtin_signbit(x) != __builtin_signbit(xh))
+        return false;
+    return __builtin_fabs(x - xh) <= eps * __builtin_fabs(x);
+}
+
+// Quantization code of a prediction (Algorithm 1: error = prediction - actual).
+__device__ __forceinline__ unsigned short make_code(long long pred, int p, bool ok)
+{
+    const long long e = pred - (long long)p;
+    return (ok && e > -kR && e < kR) ? (unsigned short)(e + kR) : (unsigned short)0;
+}
+
+// Lorenzo coefficient (-1)^(|o|+1) of the one-layer Lorenzo predictor.
+__host__ __device__ constexpr int lorenzo_sign(int o)
+{
+    return (__builtin_popcount((unsigned)o) & 1) ? 1 : -1;
+}
+
+}  // namespace pwrel

@@ -1,0 +1,153 @@
+// Device helpers shared by the compression and decompression kernels.
+#pragma once
+
+#include <algorithm>
+
+#include "pwrel_internal.h"
+
+namespace pwrel {
+
+// Network weights as a kernel argument (scalar-loaded, uniform across lanes).
+// Hidden units beyond `hidden` are zero: they add fma(0, 0, y) to the output,
+// which leaves every rounded prediction unchanged.
+struct MlpW {
+    float w1[PWREL_MAX_HIDDEN][PWREL_MAX_INPUTS];
+    float b1[PWREL_MAX_HIDDEN];
+    float v[PWREL_MAX_HIDDEN];
+    float b2;
+    float alpha;
+};
+
+inline MlpW pack_mlp(const pwrel_mlp *m)
+{
+    MlpW w{};
+    if (!m)
+        return w;
+    for (int j = 0; j < m->hidden; ++j) {
+        for (int k = 0; k < m->inputs; ++k)
+            w.w1[j][k] = m->w1[j][k];
+        w.b1[j] = m->b1[j];
+        w.v[j] = m->v[j];
+    }
+    w.b2 = m->b2;
+    w.alpha = m->alpha;
+    return w;
+}
+
+inline int hidden_pad(const pwrel_mlp *m)
+{
+    if (!m || m->hidden <= 8)
+        return 8;
+    return m->hidden <= 16 ? 16 : 32;
+}
+
+__device__ __forceinline__ void set_status(int *status, int code)
+{
+    if (code != kOk)
+        atomicCAS(status, kOk, code);
+}
+
+// Prediction of one point (Sec. 4.1 / 4.2 with the data selection rule of
+// Sec. 4.4.1: the inputs are grid values of the neighbours).
+//   nv[o], o = 1 .. 2^D-1 : neighbour grid values; bit i of o = one step back
+//                           along axis 2-i (axis 2 is the fastest).
+//   amask                 : bit i set iff axis 2-i has a neighbour.
+// The network applies when every neighbour exists; otherwise the one-layer
+// Lorenzo predictor with missing neighbours counted as zero.
+template <int D, int HP>
+__device__ __forceinline__ long long predict(const int (&nv)[8], int amask, bool net,
+                                             const MlpW &m)
+{
+    constexpr int NO = (1 << D) - 1;
+    constexpr int K = (1 << D) - 2;
+    if (net && amask == NO) {
+        float u[K > 0 ? K : 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            u[k] = (float)(nv[k + 2] - nv[1]);
+        float y = m.b2;
+#pragma unroll
+        for (int j = 0; j < HP; ++j) {
+            float z = m.b1[j];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                z = __builtin_fmaf(m.w1[j][k], u[k], z);
+            const float h = (z < 0.0f) ? z * m.alpha : z;
+            y = __builtin_fmaf(m.v[j], h, y);
+        }
+        if (y > 0x1p30f)
+            y = 0x1p30f;
+        if (!(y >= -0x1p30f))
+            y = -0x1p30f;
+        return (long long)nv[1] + (long long)__builtin_rintf(y);
+    }
+    long long s = 0;
+#pragma unroll
+    for (int o = 1; o <= NO; ++o)
+        if ((o & ~amask) == 0)
+            s += (long long)lorenzo_sign(o) * (long long)nv[o];
+    return s;
+}
+
+// Compile-time tile shapes (points per axis, multiples of the block edge) of
+// the common block sizes; ShapeOf<D, 0> means "runtime shape".
+template <int D, int BB> struct ShapeOf {
+    static constexpr bool known = false;
+    static constexpr int T0 = 0, T1 = 0, T2 = 0;
+};
+#define PWREL_SHAPE(DD, BB_, A, Bv, Cv)                                                       \
+    template <> struct ShapeOf<DD, BB_> {                                                     \
+        static constexpr bool known = true;                                                   \
+        static constexpr int T0 = A, T1 = Bv, T2 = Cv;                                        \
+    };
+PWREL_SHAPE(3, 4, 8, 8, 64)
+PWREL_SHAPE(3, 8, 8, 8, 64)
+PWREL_SHAPE(3, 16, 16, 16, 32)
+PWREL_SHAPE(2, 16, 1, 16, 128)
+PWREL_SHAPE(2, 32, 1, 32, 128)
+PWREL_SHAPE(2, 64, 1, 64, 64)
+PWREL_SHAPE(1, 256, 1, 1, 4096)
+#undef PWREL_SHAPE
+
+// Host-side copy of the same table.
+inline bool known_shape(int D, int B, int *t)
+{
+    struct E {
+        int D, B, t0, t1, t2;
+    };
+    static const E tab[] = {{3, 4, 8, 8, 64},    {3, 8, 8, 8, 64},     {3, 16, 16, 16, 32},
+                            {2, 16, 1, 16, 128}, {2, 32, 1, 32, 128},  {2, 64, 1, 64, 64},
+                            {1, 256, 1, 1, 4096}};
+    for (const E &e : tab)
+        if (e.D == D && e.B == B) {
+            t[0] = e.t0;
+            t[1] = e.t1;
+            t[2] = e.t2;
+            return true;
+        }
+    return false;
+}
+
+// Start of block (bz, by, bx) in the block-major stream and its extents.
+struct BlockGeo {
+    long long bz, by, bx;
+    int ez, ey, ex;
+    long long start;
+};
+
+__device__ __forceinline__ BlockGeo block_geo3(long long bz, long long by, long long bx,
+                                               const long long *n, int bd0, int bd1, int bd2)
+{
+    BlockGeo q;
+    q.bz = bz;
+    q.by = by;
+    q.bx = bx;
+    q.ez = (int)std::min((long long)bd0, n[0] - bz * bd0);
+    q.ey = (int)std::min((long long)bd1, n[1] - by * bd1);
+    q.ex = (int)std::min((long long)bd2, n[2] - bx * bd2);
+    q.start = bz * bd0 * n[1] * n[2] + (long long)q.ez * (by * bd1 * n[2]) +
+              (long long)q.ez * q.ey * (bx * bd2);
+    return q;
+}
+
+}  // namespace pwrel

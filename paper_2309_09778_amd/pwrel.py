@@ -1,0 +1,354 @@
+"""Thin ctypes binding of libpwrel.so (C ABI in include/pwrel.h).
+
+Argument marshalling only: every step of compression and decompression runs
+in the library's HIP kernels.  PyTorch provides device memory (tensors) and
+streams (torch.cuda.current_stream()).  Importing this module does not touch
+the GPU; loading the library fails loudly if it has not been built.
+
+A network ("model") is a plain dict:
+    {"alpha": float, "w1": float32[H, K], "b1": float32[H], "v": float32[H],
+     "b2": float, "precision": 0 (FP32 vector ALU) | 1 (BF16 matrix cores)}
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpwrel.so")
+
+F32, F64 = 0, 1
+OK, EINVAL, ERANGE, ENONFINITE, ENOSPC, ECORRUPT, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+HF_NET, HF_JUDGE, HF_INDEPENDENT = 1, 2, 4
+HEADER_BYTES = 512
+MAXH, MAXK = 32, 6
+R = 32768
+
+
+class PwrelError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pwrel status {status}: {msg}")
+        self.status = status
+
+
+class Mlp(C.Structure):
+    _fields_ = [("hidden", C.c_int32), ("inputs", C.c_int32), ("alpha", C.c_float),
+                ("w1", (C.c_float * MAXK) * MAXH), ("b1", C.c_float * MAXH),
+                ("v", C.c_float * MAXH), ("b2", C.c_float), ("precision", C.c_int32)]
+
+
+class Options(C.Structure):
+    _fields_ = [("use_net", C.c_int32), ("judge", C.c_int32),
+                ("independent_blocks", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Header(C.Structure):
+    _fields_ = [("magic", C.c_uint32), ("version", C.c_uint32), ("dtype", C.c_int32),
+                ("ndim", C.c_int32), ("dims", C.c_uint64 * 3), ("block", C.c_int32),
+                ("flags", C.c_int32), ("eps", C.c_double), ("eps0", C.c_double),
+                ("b_a", C.c_double), ("w", C.c_double), ("r", C.c_double), ("Lp", C.c_double),
+                ("Ln", C.c_double), ("d0", C.c_double), ("p_zero", C.c_int64),
+                ("b_sign", C.c_int64), ("n_lo", C.c_int64), ("delta", C.c_int64),
+                ("n", C.c_uint64), ("nblocks", C.c_uint64), ("n_raw", C.c_uint64),
+                ("off_model", C.c_uint64), ("off_bflags", C.c_uint64),
+                ("off_counts", C.c_uint64), ("off_codes", C.c_uint64), ("off_raw", C.c_uint64),
+                ("total_size", C.c_uint64), ("abs_min", C.c_double), ("abs_max", C.c_double),
+                ("n_zero", C.c_uint64), ("n_neg", C.c_uint64), ("status", C.c_int32),
+                ("pad0", C.c_int32)]
+
+
+# every symbol the header declares, with its signature
+_P = C.c_void_p
+_SIGS = {
+    "pwrel_create": (C.c_int, [C.POINTER(_P), C.c_int]),
+    "pwrel_destroy": (None, [_P]),
+    "pwrel_last_error": (C.c_char_p, [_P]),
+    "pwrel_status_string": (C.c_char_p, [C.c_int]),
+    "pwrel_check_args": (C.c_int, [_P, C.c_int, C.c_int, C.c_double, C.c_int]),
+    "pwrel_compress_bound": (C.c_uint64, [_P, C.c_int, C.c_int, C.c_int]),
+    "pwrel_compress": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
+                                 C.POINTER(Mlp), C.POINTER(Options), _P, C.c_uint64,
+                                 C.POINTER(C.c_uint64), _P]),
+    "pwrel_decompress": (C.c_int, [_P, _P, C.c_uint64, _P, _P, C.c_int, C.c_int, _P]),
+    "pwrel_read_header": (C.c_int, [_P, C.c_uint64, C.POINTER(Header)]),
+    "pwrel_transform": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, _P,
+                                  C.POINTER(Header), _P]),
+    "pwrel_encode_grid": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.POINTER(Mlp),
+                                    C.POINTER(Options), _P, _P]),
+    "pwrel_detmath": (C.c_int, [_P, _P, _P, _P, C.c_uint64, _P]),
+    "pwrel_histogram": (C.c_int, [_P, _P, C.c_uint64, _P, _P]),
+    "pwrel_huffman_bits": (C.c_uint64, [_P, C.POINTER(C.c_uint32)]),
+    "pwrel_mlp_init": (C.c_int, [C.POINTER(Mlp), C.c_int, C.c_int, C.c_float, C.c_uint64]),
+    "pwrel_set_profiling": (C.c_int, [_P, C.c_int]),
+    "pwrel_phase_times": (C.c_int, [_P, _P, C.c_int]),
+}
+PHASES = ("stats+consts", "compress", "scan+scatter+header", "decode_scan", "decode_levels")
+
+_lib = None
+
+
+def lib():
+    """Load libpwrel.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        assert C.sizeof(Header) <= HEADER_BYTES
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+# --- helpers --------------------------------------------------------------------
+
+def _dims(shape):
+    return (C.c_uint64 * len(shape))(*[int(s) for s in shape])
+
+
+def _dtype_code(tdtype):
+    import torch
+    if tdtype == torch.float32:
+        return F32
+    if tdtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {tdtype}")
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def model_struct(model):
+    if model is None:
+        return None
+    m = Mlp()
+    w1 = np.asarray(model["w1"], dtype=np.float32)
+    H = len(model["b1"])
+    K = w1.shape[1] if w1.ndim == 2 else 0
+    m.hidden, m.inputs = H, K
+    m.alpha = float(model["alpha"])
+    for j in range(H):
+        for k in range(K):
+            m.w1[j][k] = float(w1[j, k])
+        m.b1[j] = float(model["b1"][j])
+        m.v[j] = float(model["v"][j])
+    m.b2 = float(model["b2"])
+    m.precision = int(model.get("precision", 0))
+    return m
+
+
+def model_dict(m):
+    H, K = m.hidden, m.inputs
+    w1 = np.array([[m.w1[j][k] for k in range(K)] for j in range(H)],
+                  dtype=np.float32).reshape(H, K)
+    return {"alpha": float(np.float32(m.alpha)), "w1": w1,
+            "b1": np.array([m.b1[j] for j in range(H)], dtype=np.float32),
+            "v": np.array([m.v[j] for j in range(H)], dtype=np.float32),
+            "b2": float(np.float32(m.b2)), "precision": int(m.precision)}
+
+
+def mlp_init(ndim, hidden, alpha=0.01, seed=0):
+    m = Mlp()
+    st = lib().pwrel_mlp_init(C.byref(m), ndim, hidden, alpha, seed)
+    if st:
+        raise PwrelError(st, "mlp_init")
+    return model_dict(m)
+
+
+def header_dict(h):
+    out = {}
+    for name, _ in Header._fields_:
+        v = getattr(h, name)
+        out[name] = list(v) if name == "dims" else v
+    return out
+
+
+def check_args(shape, dtype_code, eps, block):
+    return lib().pwrel_check_args(_dims(shape), len(shape), dtype_code, float(eps), int(block))
+
+
+def compress_bound(shape, dtype_code, block):
+    return int(lib().pwrel_compress_bound(_dims(shape), len(shape), dtype_code, int(block)))
+
+
+def read_header_bytes(buf, size=None):
+    """Validate a header held in host memory; `size` is the whole stream's
+    length (default: len(buf)).  Returns a dict."""
+    raw = bytes(buf)
+    h = Header()
+    b = C.create_string_buffer(raw, max(len(raw), HEADER_BYTES))
+    st = lib().pwrel_read_header(C.cast(b, _P), len(raw) if size is None else int(size),
+                                 C.byref(h))
+    if st:
+        raise PwrelError(st, "read_header")
+    return header_dict(h)
+
+
+def huffman_bits(hist):
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    assert hist.size == 65536
+    ml = C.c_uint32(0)
+    bits = lib().pwrel_huffman_bits(hist.ctypes.data_as(_P), C.byref(ml))
+    return int(bits), int(ml.value)
+
+
+# --- context ----------------------------------------------------------------------
+
+class Context:
+    """A pwrel context on one GPU (owns the device workspace)."""
+
+    def __init__(self, device=0):
+        self._L = lib()
+        self.device = device
+        h = _P()
+        st = self._L.pwrel_create(C.byref(h), device)
+        if st:
+            raise PwrelError(st, "pwrel_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.pwrel_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st:
+            msg = self._L.pwrel_last_error(self.h)
+            raise PwrelError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    # codec -------------------------------------------------------------------
+    def compress(self, x, eps, block=8, model=None, use_net=True, judge=False,
+                 independent=False, out=None, stream=None):
+        """Compress a contiguous CUDA tensor; returns a uint8 CUDA tensor view."""
+        import torch
+        assert x.is_cuda and x.is_contiguous()
+        dt = _dtype_code(x.dtype)
+        cap = compress_bound(x.shape, dt, block)
+        if cap == 0:
+            raise PwrelError(EINVAL, "bad shape/block")
+        if out is None:
+            out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+        m = model_struct(model) if use_net else None
+        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
+        size = C.c_uint64(0)
+        st = self._L.pwrel_compress(self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(),
+                                    dt, float(eps), int(block),
+                                    C.byref(m) if m is not None else None, C.byref(opt),
+                                    C.c_void_p(out.data_ptr()), out.numel(), C.byref(size),
+                                    _stream(stream))
+        self._check(st, "compress")
+        return out[:size.value]
+
+    def decompress(self, stream_t, shape=None, dtype=None, out=None, stream=None):
+        import torch
+        assert stream_t.is_cuda and stream_t.dtype == torch.uint8
+        if shape is None or dtype is None:
+            h = header(stream_t)
+            shape = tuple(h["dims"][:h["ndim"]])
+            dtype = torch.float32 if h["dtype"] == F32 else torch.float64
+        if out is None:
+            out = torch.empty(shape, dtype=dtype, device=stream_t.device)
+        st = self._L.pwrel_decompress(self.h, C.c_void_p(stream_t.data_ptr()), stream_t.numel(),
+                                      C.c_void_p(out.data_ptr()), _dims(shape), len(shape),
+                                      _dtype_code(dtype), _stream(stream))
+        self._check(st, "decompress")
+        return out
+
+    # inspection ----------------------------------------------------------------
+    def transform(self, x, eps, stream=None):
+        import torch
+        p = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+        h = Header()
+        st = self._L.pwrel_transform(self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(),
+                                     _dtype_code(x.dtype), float(eps), C.c_void_p(p.data_ptr()),
+                                     C.byref(h), _stream(stream))
+        self._check(st, "transform")
+        return p, header_dict(h)
+
+    def encode_grid(self, p, block, model=None, use_net=True, independent=False, stream=None):
+        import torch
+        assert p.dtype == torch.int32 and p.is_cuda and p.is_contiguous()
+        codes = torch.empty(p.numel(), dtype=torch.int16, device=p.device)
+        m = model_struct(model) if use_net else None
+        opt = Options(int(bool(use_net)), 0, int(bool(independent)), 0)
+        st = self._L.pwrel_encode_grid(self.h, C.c_void_p(p.data_ptr()), _dims(p.shape), p.dim(),
+                                       int(block), C.byref(m) if m is not None else None,
+                                       C.byref(opt), C.c_void_p(codes.data_ptr()),
+                                       _stream(stream))
+        self._check(st, "encode_grid")
+        return codes
+
+    def detmath(self, x, stream=None):
+        import torch
+        assert x.dtype == torch.float64 and x.is_cuda
+        l2 = torch.empty_like(x)
+        e2 = torch.empty_like(x)
+        st = self._L.pwrel_detmath(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(l2.data_ptr()),
+                                   C.c_void_p(e2.data_ptr()), x.numel(), _stream(stream))
+        self._check(st, "detmath")
+        return l2, e2
+
+    def set_profiling(self, enable=True):
+        self._check(self._L.pwrel_set_profiling(self.h, int(bool(enable))), "set_profiling")
+
+    def phase_times(self):
+        ms = (C.c_double * len(PHASES))()
+        n = self._L.pwrel_phase_times(self.h, C.cast(ms, _P), len(PHASES))
+        return {PHASES[i]: ms[i] for i in range(n)}
+
+    def histogram(self, codes, stream=None):
+        """65536-bin histogram of a device tensor of codes (int16 / uint16 view)."""
+        hist = np.zeros(65536, dtype=np.uint64)
+        st = self._L.pwrel_histogram(self.h, C.c_void_p(codes.data_ptr()), codes.numel(),
+                                     hist.ctypes.data_as(_P), _stream(stream))
+        self._check(st, "histogram")
+        return hist
+
+
+# --- stream inspection (host copies of the sections) ------------------------------
+
+def header(stream_t):
+    """Parse and validate the header of a device stream tensor."""
+    head = stream_t[:HEADER_BYTES].cpu().numpy().tobytes()
+    return read_header_bytes(head, size=stream_t.numel())
+
+
+def sections(stream_t):
+    """Header dict plus the sections of a device stream, as device tensor views."""
+    import torch
+    raw = stream_t.cpu().numpy().tobytes()
+    h = read_header_bytes(raw)
+    n, nb, nr = h["n"], h["nblocks"], h["n_raw"]
+    tdt = torch.float32 if h["dtype"] == F32 else torch.float64
+    tsz = 4 if h["dtype"] == F32 else 8
+
+    def view(off, count, dt, size):
+        return stream_t[off:off + count * size].view(dt)
+
+    out = {"header": h,
+           "counts": view(h["off_counts"], nb, torch.int32, 4),
+           "codes": view(h["off_codes"], n, torch.int16, 2),
+           "raw": view(h["off_raw"], nr, tdt, tsz)}
+    if h["flags"] & HF_JUDGE:
+        out["bflags"] = stream_t[h["off_bflags"]:h["off_bflags"] + nb]
+    if h["flags"] & HF_NET:
+        m = Mlp.from_buffer_copy(raw[h["off_model"]:h["off_model"] + C.sizeof(Mlp)])
+        out["model"] = model_dict(m)
+    return out

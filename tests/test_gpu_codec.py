@@ -1,0 +1,301 @@
+"""GPU parity of the HIP codec against the CPU oracle (run on an MI355X).
+
+Bar: bit-exact for every integer/byte output (grid values, codes, per-block
+counts, raw-value lists, header constants) and for the reconstruction
+(x^ is a function of the grid value only), on fields that span several tiles
+with ragged edges, in 1-D/2-D/3-D, FP32/FP64, halo and independent blocks,
+and at the full 512^3 size on sampled points plus whole-field invariants.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2309_09778_amd import pwrel, synth
+
+pytestmark = pytest.mark.gpu
+
+CONST_KEYS = ("eps0", "b_a", "w", "r", "Lp", "Ln", "d0", "p_zero", "b_sign", "n_lo", "delta")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pwrel.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host_sections(stream):
+    sec = pwrel.sections(stream)
+    return {"h": sec["header"],
+            "codes": sec["codes"].cpu().numpy().view(np.uint16),
+            "counts": sec["counts"].cpu().numpy().view(np.uint32),
+            "raw": sec["raw"].cpu().numpy(),
+            "model": sec.get("model")}
+
+
+def random_model(ndim, H, seed, scale=0.2):
+    rng = np.random.default_rng(seed)
+    K = (1 << ndim) - 2
+    m = O.mlp_init(ndim, H, seed=seed)
+    m["w1"] = (m["w1"] + rng.normal(0, scale, size=(H, K))).astype(np.float32)
+    m["b1"] = rng.normal(0, 0.5, H).astype(np.float32)
+    m["v"] = (m["v"] + rng.normal(0, scale, H)).astype(np.float32)
+    m["b2"] = float(np.float32(rng.normal(0, 0.3)))
+    return m
+
+
+def assert_bound(x, xh, eps):
+    xd, hd = x.astype(np.float64), xh.astype(np.float64)
+    z = xd == 0
+    assert np.all(hd[z] == 0)
+    assert np.all(np.signbit(hd[~z]) == np.signbit(xd[~z]))
+    assert np.all(np.abs(xd[~z] - hd[~z]) <= eps * np.abs(xd[~z]))
+
+
+# --- deterministic math ----------------------------------------------------------
+
+def test_detmath_bit_identical_to_oracle(ctx):
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([
+        np.ldexp(1.0 + rng.random(20000), rng.integers(-1074, 1023, 20000)),
+        np.ldexp(1.0, np.arange(-1074, 1024)).astype(np.float64),
+        rng.random(2000) * 2.0 ** -1022,                      # subnormals
+        1.0 + (rng.random(2000) - 0.5) * 1e-12,
+        np.array([1.4142135623730951, np.nextafter(1.4142135623730951, 2), 5e-324]),
+    ])
+    xs = xs[np.isfinite(xs) & (xs > 0)]
+    l2, _ = ctx.detmath(dev(xs))
+    ts = np.concatenate([rng.uniform(-1100, 1030, 20000), rng.uniform(-1075, -1020, 5000),
+                         np.arange(-1080, 1030).astype(np.float64) + 0.5,
+                         rng.uniform(-3, 3, 5000)])
+    _, e2 = ctx.detmath(dev(ts))
+    ref_l = O.det_log2(xs)
+    ref_e = O.det_exp2(ts)
+    assert np.array_equal(l2.cpu().numpy().view(np.uint64), ref_l.view(np.uint64))
+    assert np.array_equal(e2.cpu().numpy().view(np.uint64), ref_e.view(np.uint64))
+
+
+# --- transform (a1-a3) -------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["bumps_f32", "grf_f64_subnormal", "grf_f32_1e-3"])
+def test_transform_and_constants_match_oracle(ctx, case):
+    if case == "bumps_f32":
+        x, eps = synth.gaussian_bumps((64, 64, 64), seed=1000, zero_frac=0.01), 1e-2
+    elif case == "grf_f64_subnormal":
+        x = synth.lognormal_grf((24, 40, 50), seed=5, decades=12, neg_frac=0.1,
+                                zero_frac=0.01, dtype=np.float64)
+        x.reshape(-1)[::997] = 3e-320
+        eps = 1e-4
+    else:
+        x, eps = synth.lognormal_grf((33, 65, 130), seed=6), 1e-3
+    p, h = ctx.transform(dev(x), eps)
+    c = O.consts(x, eps)
+    for k in CONST_KEYS:
+        assert h[k] == c[k], k
+    assert np.array_equal(p.cpu().numpy(), O.transform_field(x, c))
+
+
+# --- prediction on a given grid field (a4-a5) ------------------------------------------
+
+@pytest.mark.parametrize("shape,B", [((37, 29, 41), 8), ((16, 16, 16), 4), ((20, 33, 17), 16),
+                                     ((70, 131), 16), ((5000,), 64), ((19, 23, 29), 5)])
+@pytest.mark.parametrize("net", ["lorenzo", "random"])
+@pytest.mark.parametrize("indep", [False, True])
+def test_encode_grid_matches_oracle(ctx, shape, B, net, indep):
+    rng = np.random.default_rng(abs(hash((shape, B))) % 1000)
+    p = np.cumsum(rng.integers(-40, 41, size=shape), axis=-1).astype(np.int32)
+    model = None if net == "lorenzo" else random_model(len(shape), 16, 3)
+    got = ctx.encode_grid(dev(p), B, model, use_net=model is not None, independent=indep)
+    ref = O.encode_p(p, B, model, use_net=model is not None, independent=indep)
+    assert np.array_equal(got.cpu().numpy().view(np.uint16), ref)
+
+
+def test_encode_grid_annihilation(ctx):
+    rng = np.random.default_rng(11)
+    nz, ny, nx = 33, 40, 70
+    g = rng.integers(-5000, 5000, size=(ny, nx))
+    h = rng.integers(-5000, 5000, size=(nz, nx))
+    k = rng.integers(-5000, 5000, size=(nz, ny))
+    p = (g[None] + h[:, None] + k[:, :, None]).astype(np.int32)
+    codes = ctx.encode_grid(dev(p), 8, None, use_net=False).cpu().numpy().view(np.uint16)
+    pos = O.codes_at(np.ones(p.shape, np.float32), O.consts(np.ones(4, np.float32), 0.01), 8,
+                     np.arange(p.size), None, O.MODE_LORENZO)["pos"].astype(np.int64)
+    zz, yy, xx = np.unravel_index(np.arange(p.size), p.shape)
+    interior = (zz > 0) & (yy > 0) & (xx > 0)
+    assert np.all(codes[pos[interior]] == 32768)
+
+
+# --- full codec (a1-a8) -------------------------------------------------------------------
+
+def _case(name):
+    if name == "config0_bumps64":
+        x = synth.gaussian_bumps((64, 64, 64), seed=1000, zero_frac=0.01)
+        c = O.consts(x, 1e-2)
+        model, *_ = O.train_rule(O.transform_field(x, c), c, 8, O.mlp_init(3, 16, seed=1000),
+                                 rho=0.10, seed=1000)
+        return x, 1e-2, 8, model, False
+    if name == "grf_ragged_1e-3":
+        return synth.lognormal_grf((37, 45, 51), seed=2), 1e-3, 8, random_model(3, 16, 1), False
+    if name == "grf_ragged_indep":
+        return synth.lognormal_grf((37, 45, 51), seed=2), 1e-3, 8, random_model(3, 16, 1), True
+    if name == "grf_B4_H32":
+        return synth.lognormal_grf((24, 28, 90), seed=3), 1e-2, 4, random_model(3, 32, 2), False
+    if name == "grf_B16_H8":
+        return synth.lognormal_grf((40, 50, 70), seed=4), 1e-2, 16, random_model(3, 8, 4), False
+    if name == "grf_B5":
+        return synth.lognormal_grf((21, 22, 23), seed=5), 1e-2, 5, random_model(3, 16, 5), False
+    if name == "zonal_2d":
+        x = synth.zonal_bands_2d((150, 301), seed=6)
+        return x, 1e-2, 16, random_model(2, 16, 6), False
+    if name == "grf_2d_B64":
+        return synth.lognormal_grf((130, 200), seed=7), 1e-2, 64, random_model(2, 16, 7), False
+    if name == "grf_1d_halo":
+        return synth.lognormal_grf((10007,), seed=8), 1e-2, 256, random_model(1, 8, 8), False
+    if name == "grf_1d_indep":
+        return synth.lognormal_grf((10007,), seed=8), 1e-2, 256, random_model(1, 8, 8), True
+    if name == "f64_1e-4":
+        x = synth.lognormal_grf((24, 40, 50), seed=9, decades=12, neg_frac=0.1, zero_frac=0.01,
+                                dtype=np.float64)
+        x.reshape(-1)[::991] = 7e-321
+        return x, 1e-4, 8, random_model(3, 16, 9), False
+    if name == "lorenzo_only":
+        return synth.lognormal_grf((30, 31, 66), seed=10), 1e-2, 8, None, False
+    if name == "single_point":
+        return np.array([[[-2.5]]], dtype=np.float32), 1e-2, 8, random_model(3, 16, 1), False
+    if name == "all_zero":
+        return np.zeros((9, 10, 11), dtype=np.float32), 1e-2, 8, random_model(3, 16, 1), False
+    if name == "tiny_1d":
+        return np.array([3.0], dtype=np.float64), 0.5, 2, random_model(1, 4, 1), False
+    raise KeyError(name)
+
+
+CASES = ["config0_bumps64", "grf_ragged_1e-3", "grf_ragged_indep", "grf_B4_H32", "grf_B16_H8",
+         "grf_B5", "zonal_2d", "grf_2d_B64", "grf_1d_halo", "grf_1d_indep", "f64_1e-4",
+         "lorenzo_only", "single_point", "all_zero", "tiny_1d"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_codec_bit_exact_vs_oracle(ctx, name):
+    x, eps, B, model, indep = _case(name)
+    use_net = model is not None
+    mode = O.MODE_PLAIN if use_net else O.MODE_LORENZO
+    stream = ctx.compress(dev(x), eps, B, model, use_net=use_net, independent=indep)
+    g = host_sections(stream)
+    ref = O.compress(x, eps, B, model, mode, independent=indep)
+    for k in CONST_KEYS:
+        assert g["h"][k] == ref["consts"][k], k
+    assert np.array_equal(g["codes"], ref["codes"])
+    assert np.array_equal(g["counts"], ref["counts"])
+    assert np.array_equal(g["raw"].view(np.uint8), ref["raw"].view(np.uint8))
+    xh = ctx.decompress(stream).cpu().numpy()
+    ref_xh, _ = O.decompress(ref["codes"], ref["raw"], ref["consts"], x.shape, x.dtype, B, model,
+                             mode, independent=indep)
+    assert np.array_equal(xh.view(np.uint8), ref_xh.view(np.uint8))
+    assert_bound(x, xh, eps)
+
+
+def test_determinism_and_histogram(ctx):
+    x, eps, B, model, _ = _case("grf_ragged_1e-3")
+    a = ctx.compress(dev(x), eps, B, model).clone()
+    b = ctx.compress(dev(x), eps, B, model)
+    assert torch.equal(a, b)
+    hist = ctx.histogram(pwrel.sections(a)["codes"])
+    codes = host_sections(a)["codes"]
+    assert np.array_equal(hist, np.bincount(codes, minlength=65536).astype(np.uint64))
+
+
+# --- error paths ----------------------------------------------------------------------------
+
+def test_error_paths(ctx):
+    x = synth.lognormal_grf((20, 20, 20), seed=1)
+    bad = x.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.compress(dev(bad), 1e-2, 8, None, use_net=False)
+    assert e.value.status == pwrel.ENONFINITE
+    out = torch.empty(600, dtype=torch.uint8, device="cuda")
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.compress(dev(x), 1e-2, 8, None, use_net=False, out=out)
+    assert e.value.status == pwrel.ENOSPC
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.compress(dev(np.array([1e-300, 1e300])), 1e-9, 2, None, use_net=False)
+    assert e.value.status == pwrel.ERANGE
+    s = ctx.compress(dev(x), 1e-2, 8, None, use_net=False).clone()
+    s[0] ^= 0xFF
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.decompress(s, x.shape, torch.float32)
+    assert e.value.status == pwrel.ECORRUPT
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.decompress(ctx.compress(dev(x), 1e-2, 8, None, use_net=False)[:-4], x.shape,
+                       torch.float32)
+    assert e.value.status == pwrel.ECORRUPT
+
+
+# --- full size (512^3 FP32), sampled parity and whole-field invariants ------------------------
+
+def stream_to_field_index(shape, B, pos):
+    """C-order index of stream positions (block-major order), numpy."""
+    n = np.array(shape, dtype=np.int64)
+    nb = -(-n // B)
+    ext = [np.minimum(B, n[d] - np.arange(nb[d]) * B) for d in range(3)]
+    sizes = (ext[0][:, None, None] * ext[1][None, :, None] * ext[2][None, None, :]).ravel()
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    b = np.searchsorted(starts, pos, side="right") - 1
+    loc = pos - starts[b]
+    bz, by, bx = np.unravel_index(b, tuple(nb))
+    ey, ex = ext[1][by], ext[2][bx]
+    lx = loc % ex
+    ly = (loc // ex) % ey
+    lz = loc // (ex * ey)
+    return ((bz * B + lz) * n[1] + by * B + ly) * n[2] + bx * B + lx
+
+
+@pytest.fixture(scope="module")
+def big_field():
+    return synth.lognormal_grf((512, 512, 512), seed=1001)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_full_size_512cubed(ctx, big_field, eps):
+    x = big_field
+    model = random_model(3, 16, 1001, scale=0.05)
+    xd = dev(x)
+    stream = ctx.compress(xd, eps, 8, model)
+    h = pwrel.header(stream)
+    c = O.consts(x, eps)
+    for k in CONST_KEYS:
+        assert h[k] == c[k], k
+    sec = pwrel.sections(stream)
+    codes = sec["codes"].cpu().numpy().view(np.uint16)
+    counts = sec["counts"].cpu().numpy().view(np.uint32)
+    raw = sec["raw"].cpu().numpy()
+    # sampled codes against the oracle, point by point
+    rng = np.random.default_rng(int(eps * 1e6))
+    idx = np.concatenate([rng.choice(x.size, 200000, replace=False),
+                          np.arange(0, 512 * 512 * 2),                # first planes (faces)
+                          np.arange(x.size - 4096, x.size)])
+    ref = O.codes_at(x, c, 8, idx, model, O.MODE_PLAIN)
+    assert np.array_equal(codes[ref["pos"].astype(np.int64)], ref["codes"])
+    # every balance point: count per block and raw value, in stream order
+    zpos = np.flatnonzero(codes == 0)
+    assert counts.sum() == zpos.size == h["n_raw"]
+    fi = stream_to_field_index(x.shape, 8, zpos)
+    assert np.array_equal(raw.view(np.uint32), x.reshape(-1)[fi].view(np.uint32))
+    # reconstruction: bound on every point, sampled values bit-exact vs the oracle
+    xh = ctx.decompress(stream)
+    hd, xt = xh.double(), xd.double()
+    z = xt == 0
+    assert bool(torch.all(hd[z] == 0))
+    assert bool(torch.all(torch.signbit(hd[~z]) == torch.signbit(xt[~z])))
+    assert bool(torch.all((xt - hd).abs() <= eps * xt.abs()))
+    xh_s = xh.reshape(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ref_xh = O.inverse_field(ref["p"], c, np.float32)
+    is_raw = ref["codes"] == 0
+    ref_xh[is_raw] = x.reshape(-1)[idx[is_raw]]
+    assert np.array_equal(xh_s.view(np.uint32), ref_xh.view(np.uint32))

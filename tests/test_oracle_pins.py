@@ -259,3 +259,23 @@ def test_error_paths():
     with pytest.raises(O.OracleError) as e:
         O.compress(z, 1e-9, 2, None, O.MODE_LORENZO)
     assert e.value.status == O.ERANGE
+
+
+def test_grid_clamps_keep_ranges_disjoint():
+    # The clamps of the transform hold even when rounding would cross a
+    # threshold: with the positive ceiling moved below the largest positive's
+    # grid value, positives saturate at it; with the floor of negatives moved
+    # above the smallest negative's grid value, negatives saturate there.
+    x = np.array([0.5, 3.0, -0.25, -7.0, 0.0], dtype=np.float64)
+    c = O.consts(x, 1e-2)
+    p = O.transform_field(x, c)
+    low = dict(c, b_sign=int(p[1]) - 5)
+    q = O.transform_field(x, low)
+    assert q[1] == low["b_sign"] and q[0] <= low["b_sign"]
+    assert np.all(q[2:4] >= low["b_sign"] + 1) and q[4] == c["p_zero"]
+    high = dict(c, b_sign=int(p[3]) + 3)
+    q = O.transform_field(x, high)
+    assert q[2] == q[3] == high["b_sign"] + 1
+    zlow = dict(c, p_zero=int(p[0]) + 2)
+    q = O.transform_field(x, zlow)
+    assert q[0] == zlow["p_zero"] + 1 and q[4] == zlow["p_zero"]
