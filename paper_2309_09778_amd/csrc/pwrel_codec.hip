@@ -364,11 +364,19 @@ struct HeaderArgs {
     unsigned long long off_model, off_bflags, off_counts, off_codes, off_raw;
     unsigned long long capacity;
     int raw_size;
+    unsigned long long pad_lo[5], pad_hi[5];  // alignment gaps between sections
 };
 
-__global__ void k_header(HeaderArgs h, const DevConsts *cp, const unsigned long long *n_raw,
-                         int *status, pwrel_header *out)
+// Writes the header and zeroes every alignment gap, so that equal inputs give
+// byte-identical streams.
+__global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *cp,
+                                                const unsigned long long *n_raw, int *status,
+                                                pwrel_header *out)
 {
+    unsigned char *bytes = reinterpret_cast<unsigned char *>(out);
+    for (int r = 0; r < 5; ++r)
+        for (unsigned long long i = h.pad_lo[r] + threadIdx.x; i < h.pad_hi[r]; i += blockDim.x)
+            bytes[i] = 0;
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
     pwrel_header o{};
@@ -589,7 +597,18 @@ hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspa
     h.off_raw = offs[4];
     h.capacity = capacity;
     h.raw_size = g.dtype == PWREL_F32 ? 4 : 8;
-    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, h, ws.consts, ws.n_raw, ws.status,
+    const unsigned long long ends[5] = {
+        sizeof(pwrel_header),
+        (flags & PWREL_HF_NET) ? offs[0] + sizeof(pwrel_mlp) : offs[0],
+        (flags & PWREL_HF_JUDGE) ? offs[1] + (unsigned long long)g.nblocks : offs[1],
+        offs[2] + 4ull * (unsigned long long)g.nblocks,
+        offs[3] + 2ull * (unsigned long long)g.N};
+    const unsigned long long nexts[5] = {offs[0], offs[1], offs[2], offs[3], offs[4]};
+    for (int r = 0; r < 5; ++r) {
+        h.pad_lo[r] = ends[r];
+        h.pad_hi[r] = nexts[r] > ends[r] ? nexts[r] : ends[r];
+    }
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(256), 0, s, h, ws.consts, ws.n_raw, ws.status,
                        (pwrel_header *)d_header);
     return hipGetLastError();
 }

@@ -57,6 +57,9 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
     unsigned char *okb = reinterpret_cast<unsigned char *>(cnt + nbt);
 
     __shared__ int s_status;
+    __shared__ float4 wl[kWlds];
+    stage_weights<HP>(wl, a.mlp);
+    const float b2 = a.mlp.b2, alpha = a.mlp.alpha;
     for (int i = tid; i < nbt; i += NT)
         cnt[i] = 0u;
     if (tid == 0)
@@ -162,7 +165,7 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
             else
                 amask = (gx != 0 ? 1 : 0) | (D >= 2 && gy != 0 ? 2 : 0) |
                         (D >= 3 && gz != 0 ? 4 : 0);
-            const long long pred = predict<D, HP>(nv, amask, a.use_net != 0, a.mlp);
+            const long long pred = predict<D, HP>(nv, amask, a.use_net != 0, wl, b2, alpha);
             const bool ok = okb[(cz * T1 + cy) * T2 + cx] != 0;
             const unsigned short code = make_code(pred, nv[0], ok);
             const BlockGeo bg = block_geo3(bz0 + btz, by0 + bty, bx0 + btx, a.n, bd0, bd1, bd2);

@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
     int *ptile = reinterpret_cast<int *>(smem);
     unsigned short *cl = reinterpret_cast<unsigned short *>(ptile + ne);
     unsigned short *rk = cl + BV;
+    __shared__ float4 wl[kWlds];
 
     long long bz, by, bx;
     if (a.independent) {
@@ -77,6 +78,8 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
     const T *raw = reinterpret_cast<const T *>(a.raw);
     T *xh = reinterpret_cast<T *>(a.xh);
 
+    stage_weights<HP>(wl, a.mlp);
+    const float b2 = a.mlp.b2, alpha = a.mlp.alpha;
     // codes in full-block layout (lz * bd1 + ly) * bd2 + lx
     for (int li = tid; li < bsize; li += NT) {
         int ci = li;
@@ -168,7 +171,7 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
                         nv[o] = ptile[ei - noff[o]];
                     const int ax = a.independent ? (lx != 0) : (g0x + lx != 0);
                     const long long pv =
-                        predict<D, HP>(nv, amask_zy | ax, net, a.mlp) - ((long long)code - kR);
+                        predict<D, HP>(nv, amask_zy | ax, net, wl, b2, alpha) - ((long long)code - kR);
                     if (!(pv > -(long long)kGridLimit && pv < (long long)kGridLimit)) {
                         err = kECorrupt;
                         p = 0;

@@ -47,6 +47,21 @@ __device__ __forceinline__ void set_status(int *status, int code)
         atomicCAS(status, kOk, code);
 }
 
+// Network weights staged in LDS, two float4 per hidden unit:
+//   [w1[j][0..3]] [w1[j][4], w1[j][5], b1[j], v[j]]
+// Every lane reads the same address (a broadcast), so the 130-258 uniform
+// weights neither occupy nor spill scalar registers.
+constexpr int kWlds = 2 * PWREL_MAX_HIDDEN;
+
+template <int HP>
+__device__ __forceinline__ void stage_weights(float4 *wl, const MlpW &m)
+{
+    for (int j = threadIdx.x; j < HP; j += blockDim.x) {
+        wl[2 * j] = make_float4(m.w1[j][0], m.w1[j][1], m.w1[j][2], m.w1[j][3]);
+        wl[2 * j + 1] = make_float4(m.w1[j][4], m.w1[j][5], m.b1[j], m.v[j]);
+    }
+}
+
 // Prediction of one point (Sec. 4.1 / 4.2 with the data selection rule of
 // Sec. 4.4.1: the inputs are grid values of the neighbours).
 //   nv[o], o = 1 .. 2^D-1 : neighbour grid values; bit i of o = one step back
@@ -56,24 +71,26 @@ __device__ __forceinline__ void set_status(int *status, int code)
 // Lorenzo predictor with missing neighbours counted as zero.
 template <int D, int HP>
 __device__ __forceinline__ long long predict(const int (&nv)[8], int amask, bool net,
-                                             const MlpW &m)
+                                             const float4 *wl, float b2, float alpha)
 {
     constexpr int NO = (1 << D) - 1;
     constexpr int K = (1 << D) - 2;
     if (net && amask == NO) {
-        float u[K > 0 ? K : 1];
+        float u[6];
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            u[k] = (float)(nv[k + 2] - nv[1]);
-        float y = m.b2;
+        for (int k = 0; k < 6; ++k)
+            u[k] = k < K ? (float)(nv[k + 2] - nv[1]) : 0.0f;
+        float y = b2;
 #pragma unroll
         for (int j = 0; j < HP; ++j) {
-            float z = m.b1[j];
+            const float4 wa = wl[2 * j], wb = wl[2 * j + 1];
+            const float w[6] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y};
+            float z = wb.z;
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                z = __builtin_fmaf(m.w1[j][k], u[k], z);
-            const float h = (z < 0.0f) ? z * m.alpha : z;
-            y = __builtin_fmaf(m.v[j], h, y);
+                z = __builtin_fmaf(w[k], u[k], z);
+            const float h = (z < 0.0f) ? z * alpha : z;
+            y = __builtin_fmaf(wb.w, h, y);
         }
         if (y > 0x1p30f)
             y = 0x1p30f;

@@ -276,6 +276,36 @@ def test_grid_clamps_keep_ranges_disjoint():
     high = dict(c, b_sign=int(p[3]) + 3)
     q = O.transform_field(x, high)
     assert q[2] == q[3] == high["b_sign"] + 1
-    zlow = dict(c, p_zero=int(p[0]) + 2)
-    q = O.transform_field(x, zlow)
-    assert q[0] == zlow["p_zero"] + 1 and q[4] == zlow["p_zero"]
+    for lift in (0, 2):  # a positive rounding onto or below the zero image moves above it
+        zlow = dict(c, p_zero=int(p[0]) + lift)
+        q = O.transform_field(x, zlow)
+        assert q[0] == zlow["p_zero"] + 1 and q[4] == zlow["p_zero"]
+
+
+def test_negative_offset_when_rounding_closes_the_sign_gap():
+    # In exact arithmetic the smallest-magnitude negative lands one grid step
+    # above the largest positive (Eq. 10).  For this field FP64 rounding puts
+    # both on the same step (n_lo == b_sign), so the integer offset delta = 1
+    # lifts every negative by one step (constant-factor lemma, Eq. 4-5); the
+    # round trip stays exact on the grid and no point needs a raw value.
+    amax = 1.1609689553699987
+    x = np.array([1.0, amax, -1.0, -amax, 1.05, -1.1], dtype=np.float64)
+    c = O.consts(x, 1e-2)
+    assert c["n_lo"] == c["b_sign"] and c["delta"] == 1
+    p = O.transform_field(x, c)
+    assert p[2] == c["b_sign"] + 1 == c["n_lo"] + c["delta"]
+    out = O.compress(x, 1e-2, 8, None, O.MODE_LORENZO)
+    assert out["raw"].size == 0
+    xh, _ = O.decompress(out["codes"], out["raw"], out["consts"], x.shape, x.dtype, 8)
+    assert np.all(np.abs(x - xh) <= 1e-2 * np.abs(x)) and np.all(np.sign(x) == np.sign(xh))
+
+
+def test_quantizer_code_range():
+    # m = 16 code bits (Sec. 4.3: codes 0 .. 2^m - 1): prediction errors
+    # -2^15 < e < 2^15 map to e + 2^15 in 1 .. 65535, anything else to the
+    # balance-point flag 0 (Algorithm 1).  1-D Lorenzo predicts the previous
+    # value, the first point 0.
+    p = np.array([0, 32767, 0, -32767, 0, 32768, 0, -32768, 5], dtype=np.int32)
+    codes = O.encode_p(p, 16, None, use_net=False)
+    assert codes.tolist() == [32768, 1, 65535, 65535, 1, 0, 0, 0, 0]
+    # e = pred - p for the last point: -32768 - 5 -> out of range
