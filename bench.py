@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--side", type=int, default=512)
     ap.add_argument("--block", type=int, default=8)
     ap.add_argument("--hidden", type=int, default=16)
+    ap.add_argument("--independent", action="store_true",
+                    help="blocks predicted without neighbours outside the block (every block "
+                         "decodes on its own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -99,8 +102,9 @@ def main():
     xd.clone()
     torch.cuda.synchronize()
 
+    ind = args.independent
     for _ in range(args.warmup):
-        s = ctx.compress(xd, eps, B, model, out=out)
+        s = ctx.compress(xd, eps, B, model, out=out, independent=ind)
         ctx.decompress(s, out=xh)
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
@@ -112,7 +116,7 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         a = time.perf_counter()
-        s = ctx.compress(xd, eps, B, model, out=out)
+        s = ctx.compress(xd, eps, B, model, out=out, independent=ind)
         b = time.perf_counter()
         ctx.decompress(s, out=xh)
         torch.cuda.synchronize()
@@ -158,7 +162,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"{S}^3 FP32 log-normal k^-3 GRF (8 decades, 10% negative, "
                                f"0.5% zeros), block {B}^3, eps {eps:g}, plain FP32 perceptron "
-                               f"H={Hp} (Lorenzo-initialised)",
+                               f"H={Hp} (Lorenzo-initialised)" + (", independent blocks" if ind else
+                                                                   ", halo prediction"),
                    "path": "plain", "field_bytes": x.nbytes},
         "compress_GBps": round(gb / (tc / K), 3),
         "decompress_GBps": round(gb / (td / K), 3),

@@ -172,12 +172,16 @@ def _case(name):
         return np.zeros((9, 10, 11), dtype=np.float32), 1e-2, 8, random_model(3, 16, 1), False
     if name == "tiny_1d":
         return np.array([3.0], dtype=np.float64), 0.5, 2, random_model(1, 4, 1), False
+    if name == "sign_gap_delta":  # FP64 rounding closes the sign gap: delta = 1
+        x = np.array([1.0, 1.1609689553699987, -1.0, -1.1609689553699987, 1.05, -1.1] * 7,
+                     dtype=np.float64).reshape(6, 7)
+        return x, 1e-2, 4, random_model(2, 8, 3), False
     raise KeyError(name)
 
 
 CASES = ["config0_bumps64", "grf_ragged_1e-3", "grf_ragged_indep", "grf_B4_H32", "grf_B16_H8",
          "grf_B5", "zonal_2d", "grf_2d_B64", "grf_1d_halo", "grf_1d_indep", "f64_1e-4",
-         "lorenzo_only", "single_point", "all_zero", "tiny_1d"]
+         "lorenzo_only", "single_point", "all_zero", "tiny_1d", "sign_gap_delta"]
 
 
 @pytest.mark.parametrize("name", CASES)
