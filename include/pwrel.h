@@ -66,7 +66,7 @@ typedef enum {
 typedef struct {
     int32_t hidden;    /* H, 2..32 */
     int32_t inputs;    /* K = 2^ndim - 2 */
-    float alpha;       /* leaky-ReLU slope */
+    float alpha;       /* leaky-ReLU slope, 0 <= alpha <= 1 */
     float w1[PWREL_MAX_HIDDEN][PWREL_MAX_INPUTS];
     float b1[PWREL_MAX_HIDDEN];
     float v[PWREL_MAX_HIDDEN];

@@ -117,8 +117,10 @@ int check_model(pwrel_ctx *ctx, const pwrel_mlp *m, int ndim)
         return fail(ctx, PWREL_EINVAL, "model inputs must equal 2^ndim - 2");
     if (m->precision != 0)
         return fail(ctx, PWREL_EINVAL, "this build evaluates FP32 networks (precision 0) only");
+    if (!(m->alpha >= 0.0f && m->alpha <= 1.0f))
+        return fail(ctx, PWREL_EINVAL, "leaky-ReLU slope must lie in [0, 1]");
     auto bad = [](float v) { return !std::isfinite(v) || std::fabs(v) > 65536.0f; };
-    if (bad(m->alpha) || bad(m->b2))
+    if (bad(m->b2))
         return fail(ctx, PWREL_EINVAL, "model weights must be finite and below 2^16");
     for (int j = 0; j < m->hidden; ++j) {
         if (bad(m->b1[j]) || bad(m->v[j]))

@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
             else
                 amask = (gx != 0 ? 1 : 0) | (D >= 2 && gy != 0 ? 2 : 0) |
                         (D >= 3 && gz != 0 ? 4 : 0);
-            const long long pred = predict<D, HP>(nv, amask, a.use_net != 0, wl, b2, alpha);
+            const long long pred = predict<D, HP>(nv, amask, a.use_net != 0, WeightsLds{wl}, b2, alpha);
             const bool ok = okb[(cz * T1 + cy) * T2 + cx] != 0;
             const unsigned short code = make_code(pred, nv[0], ok);
             const BlockGeo bg = block_geo3(bz0 + btz, by0 + bty, bx0 + btx, a.n, bd0, bd1, bd2);

@@ -7,6 +7,8 @@
 // encoder.  Then x^ = inverse(grid value) for coded points and the raw value
 // for balance points.  Only the block's high faces go back to the scratch
 // field (later blocks read nothing else).
+#include <type_traits>
+
 #include "pwrel_kernels.h"
 
 namespace pwrel {
@@ -141,7 +143,14 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
         noff[o] = (o & 1) + ((o >> 1) & 1) * E2 + ((o >> 2) & 1) * E1 * E2;
     __syncthreads();
 
-    // hyperplane sweep: lane `line` owns (lz, ly); its point at step s is lx = s - lz - ly
+    // hyperplane sweep: lane `line` owns (lz, ly); its point at step s is lx = s - lz - ly.
+    // Up to 16 hidden units the weights live in registers for the whole sweep.
+    using Wt = typename std::conditional<(HP <= 16), WeightsReg<HP>, WeightsLds>::type;
+    Wt wt;
+    if constexpr (HP <= 16)
+        wt.load(wl);
+    else
+        wt.wl = wl;
     int err = kOk;
     const int nlines = bd0 * bd1;
     const int nsteps = (ez - 1) + (ey - 1) + (ex - 1) + 1;
@@ -171,7 +180,7 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
                         nv[o] = ptile[ei - noff[o]];
                     const int ax = a.independent ? (lx != 0) : (g0x + lx != 0);
                     const long long pv =
-                        predict<D, HP>(nv, amask_zy | ax, net, wl, b2, alpha) - ((long long)code - kR);
+                        predict<D, HP>(nv, amask_zy | ax, net, wt, b2, alpha) - ((long long)code - kR);
                     if (!(pv > -(long long)kGridLimit && pv < (long long)kGridLimit)) {
                         err = kECorrupt;
                         p = 0;

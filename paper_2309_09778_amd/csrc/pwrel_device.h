@@ -103,49 +103,35 @@ template <> __device__ __forceinline__ double to_dtype<double>(double v) { retur
 
 // Grid value of an input value: Eq. 6 (positive), Eq. 7 (negative, plus the
 // integer offset delta), Eq. 12 (zero), clamped so that the zero image, the
-// positive range and the negative range stay disjoint.
+// positive range and the negative range stay disjoint.  Written without
+// branches on the sign so that a wave holding both signs evaluates one log2.
 __device__ __forceinline__ int grid_value(double x, const DevConsts &c, int &err)
 {
-    if (x == 0.0)
-        return (int)c.p_zero;
-    if (x > 0.0) {
-        const double t = (det_log2(x) + c.Lp) * c.r;
-        if (!(__builtin_fabs(t) < kGridLimit)) {
-            err = kERange;
-            return 0;
-        }
-        long long q = (long long)__builtin_rint(t);
-        q = q < c.p_zero + 1 ? c.p_zero + 1 : q;
-        q = q > c.b_sign ? c.b_sign : q;
-        return (int)q;
-    }
-    const double t = (det_log2(-x) + c.Ln) * c.r;
-    if (!(__builtin_fabs(t) < kGridLimit)) {
+    const double a = __builtin_fabs(x);
+    const bool neg = x < 0.0;
+    const double t = (det_log2(a > 0.0 ? a : 1.0) + (neg ? c.Ln : c.Lp)) * c.r;
+    if (x != 0.0 && !(__builtin_fabs(t) < kGridLimit))
         err = kERange;
-        return 0;
-    }
-    long long q = (long long)__builtin_rint(t) + c.delta;
-    q = q < c.b_sign + 1 ? c.b_sign + 1 : q;
-    if (!(__builtin_fabs((double)q) < kGridLimit)) {
+    long long q = (long long)__builtin_rint(t);
+    const long long qp = q < c.p_zero + 1 ? c.p_zero + 1 : (q > c.b_sign ? c.b_sign : q);
+    long long qn = q + c.delta;
+    qn = qn < c.b_sign + 1 ? c.b_sign + 1 : qn;
+    if (neg && !(__builtin_fabs((double)qn) < kGridLimit))
         err = kERange;
-        return 0;
-    }
-    return (int)q;
+    q = neg ? qn : qp;
+    return x == 0.0 ? (int)c.p_zero : (int)q;
 }
 
 // Inverse of the grid map (zero / positive / negative by threshold), rounded
-// to the field's dtype.
+// to the field's dtype; one exp2 per point whatever the range.
 template <typename T>
 __device__ __forceinline__ double grid_inverse(int p, const DevConsts &c)
 {
     const long long q = p;
-    double v;
-    if (q <= c.p_zero)
-        v = 0.0;
-    else if (q <= c.b_sign)
-        v = det_exp2((double)q * c.w - c.Lp);
-    else
-        v = -det_exp2((double)(q - c.delta) * c.w - c.Ln);
+    const bool neg = q > c.b_sign;
+    const double t = neg ? (double)(q - c.delta) * c.w - c.Ln : (double)q * c.w - c.Lp;
+    const double e = det_exp2(t);
+    const double v = q <= c.p_zero ? 0.0 : (neg ? -e : e);
     return to_dtype<T>(v);
 }
 

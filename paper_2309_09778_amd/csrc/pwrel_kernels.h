@@ -62,16 +62,39 @@ __device__ __forceinline__ void stage_weights(float4 *wl, const MlpW &m)
     }
 }
 
+// Weight access for the prediction: from LDS (broadcast loads) or from a
+// register copy made once per kernel.
+struct WeightsLds {
+    const float4 *wl;
+    __device__ __forceinline__ float4 a(int j) const { return wl[2 * j]; }
+    __device__ __forceinline__ float4 b(int j) const { return wl[2 * j + 1]; }
+};
+
+template <int HP> struct WeightsReg {
+    float4 wa[HP], wb[HP];
+    __device__ __forceinline__ void load(const float4 *wl)
+    {
+#pragma unroll
+        for (int j = 0; j < HP; ++j) {
+            wa[j] = wl[2 * j];
+            wb[j] = wl[2 * j + 1];
+        }
+    }
+    __device__ __forceinline__ float4 a(int j) const { return wa[j]; }
+    __device__ __forceinline__ float4 b(int j) const { return wb[j]; }
+};
+
 // Prediction of one point (Sec. 4.1 / 4.2 with the data selection rule of
 // Sec. 4.4.1: the inputs are grid values of the neighbours).
 //   nv[o], o = 1 .. 2^D-1 : neighbour grid values; bit i of o = one step back
 //                           along axis 2-i (axis 2 is the fastest).
 //   amask                 : bit i set iff axis 2-i has a neighbour.
 // The network applies when every neighbour exists; otherwise the one-layer
-// Lorenzo predictor with missing neighbours counted as zero.
-template <int D, int HP>
+// Lorenzo predictor with missing neighbours counted as zero.  The leaky ReLU
+// is max(z, alpha z), equal to (z < 0 ? alpha z : z) for 0 <= alpha <= 1.
+template <int D, int HP, class W>
 __device__ __forceinline__ long long predict(const int (&nv)[8], int amask, bool net,
-                                             const float4 *wl, float b2, float alpha)
+                                             const W &wt, float b2, float alpha)
 {
     constexpr int NO = (1 << D) - 1;
     constexpr int K = (1 << D) - 2;
@@ -83,13 +106,13 @@ __device__ __forceinline__ long long predict(const int (&nv)[8], int amask, bool
         float y = b2;
 #pragma unroll
         for (int j = 0; j < HP; ++j) {
-            const float4 wa = wl[2 * j], wb = wl[2 * j + 1];
+            const float4 wa = wt.a(j), wb = wt.b(j);
             const float w[6] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y};
             float z = wb.z;
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 z = __builtin_fmaf(w[k], u[k], z);
-            const float h = (z < 0.0f) ? z * alpha : z;
+            const float h = __builtin_fmaxf(z, z * alpha);
             y = __builtin_fmaf(wb.w, h, y);
         }
         if (y > 0x1p30f)
