@@ -36,6 +36,38 @@ def compress_flops_per_point(H, K):
     return transform + verify + net
 
 
+COMPRESS_SOURCES = ["paper_2309_09778_amd/csrc/pwrel_compress.hip",
+                    "paper_2309_09778_amd/csrc/pwrel_kernels.h",
+                    "paper_2309_09778_amd/csrc/pwrel_device.h"]
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(summary, files):
+    """HBM bytes per launch from a committed rocprofv3 summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated on a copy kernel), or None if the kernel's sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        for key in ("traffic_bytes_per_launch:", "source_hash:"):
+            if line.startswith(key):
+                vals[key] = line.split(":", 1)[1].strip()
+    if vals.get("source_hash:") != source_hash(files):
+        return None
+    return int(vals["traffic_bytes_per_launch:"]) if "traffic_bytes_per_launch:" in vals else None
+
+
 def huffman_stream_bytes(h, hist, huffman_bits):
     """Compressed size with the codes Huffman-coded: header + model + per-block
     counts + coded bits + codebook (2-byte symbol + 1-byte length per used
@@ -152,7 +184,10 @@ def main():
     roofline = {"kernel": "k_compress<float,3,16> (fused a3-a7)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_ms": round(kern_ms, 4),
+                "traffic": profiled_traffic(
+                    f"k_compress_plain_{S}cubed_f32_eps{eps:.0e}".replace("e-0", "e-") + ".txt",
+                    COMPRESS_SOURCES) if not ind else None,
+                "avg_ms": round(kern_ms, 4),
                 "flops_per_point": compress_flops_per_point(Hp, 6)}
 
     res = {
