@@ -103,6 +103,8 @@ def lib():
         L.or_bf16_rne.argtypes = [C.c_float]
         L.or_entropy_j.restype = C.c_int64
         L.or_entropy_j.argtypes = [P, C.c_int64]
+        L.or_judge_j.restype = C.c_int64
+        L.or_judge_j.argtypes = [P, C.c_int64]
         L.or_qlog.restype = C.c_int64
         L.or_qlog.argtypes = [C.c_int64]
         for fn in ("or_sizeof_mlp", "or_sizeof_consts", "or_sizeof_stats"):
@@ -360,6 +362,12 @@ def block_start(shape, B, bc):
 def entropy_j(codes):
     codes = np.ascontiguousarray(codes, dtype=np.uint16)
     return int(lib().or_entropy_j(_ptr(codes), codes.size))
+
+
+def judge_j(codes):
+    """Per-block judge score of a code list (balance point and clamped errors)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    return int(lib().or_judge_j(_ptr(codes), codes.size))
 
 
 def qlog(c):

@@ -375,13 +375,22 @@ static float bf16_rne(float f)
     return g;
 }
 
-/* Reference value of the BF16-operand network, evaluated in FP64: inputs,
- * weights and hidden activations rounded to bf16, biases kept in FP32,
- * products and sums exact-ish in FP64.  Used only as a tolerance reference
- * for the matrix-core path, whose accumulation order is the hardware's. */
+/* Reference value of the BF16-operand network, in FP64, with the leaky ReLU
+ * written as lrelu(z) = (1 - alpha) relu(z) + alpha z:
+ *   z_j  = b1_j + sum_k bf16(w1_jk) bf16(u_k)
+ *   y    = b2 + sum_j bf16((1 - alpha) v_j) relu(bf16(z_j)) + bf16(alpha v_j) bf16(z_j)
+ * ((1 - alpha) and the products with v_j in FP32 before the bf16 rounding).
+ * The matrix-core path accumulates in FP32 in the hardware's order: its z_j
+ * lies within d_j = Z_j 2^-19 of the exact one (Z_j = |b1_j| + sum |products|,
+ * a generous bound for at most 8 FP32 roundings), so its bf16(z_j) lies
+ * between bf16(z_j - d_j) and bf16(z_j + d_j) (rounding is monotone).
+ * *slack bounds |y_device - y|: (|a_j| + |c_j|) times the largest such move
+ * of bf16(z_j), summed over hidden units, plus 2^-18 times the sum of the
+ * magnitudes of layer 2 (its FP32 accumulation). */
 static double mlp_eval_bf16_ref(const or_mlp *m, const float *u, double *slack)
 {
-    double y = (double)m->b2, sl = 0.0;
+    const float ar = 1.0f - m->alpha, al = m->alpha;
+    double y = (double)m->b2, sl = 0.0, mag = fabs((double)m->b2);
     for (int j = 0; j < m->hidden; ++j) {
         double z = (double)m->b1[j], za = fabs(z);
         for (int k = 0; k < m->inputs; ++k) {
@@ -389,17 +398,18 @@ static double mlp_eval_bf16_ref(const or_mlp *m, const float *u, double *slack)
             z += t;
             za += fabs(t);
         }
-        double hz = (z < 0.0) ? z * (double)m->alpha : z;
-        float hf = lrelu_f((float)z, m->alpha);
-        double hb = (double)bf16_rne(hf);
-        double vb = (double)bf16_rne(m->v[j]);
-        y += vb * hb;
-        /* slack: bf16 rounding of h may land one bf16 ulp either way, plus
-         * FP32 accumulation error of the hidden pre-activation */
-        double hul = fabs(hz) * 0x1p-7 + za * 0x1p-20 + 1e-30;
-        sl += fabs(vb) * hul;
+        double zb = (double)bf16_rne((float)z);
+        double a = (double)bf16_rne(ar * m->v[j]);
+        double c = (double)bf16_rne(al * m->v[j]);
+        double t1 = a * (zb > 0.0 ? zb : 0.0), t2 = c * zb;
+        y += t1 + t2;
+        mag += fabs(t1) + fabs(t2);
+        double d = za * 0x1p-19;
+        double zlo = (double)bf16_rne((float)(z - d)), zhi = (double)bf16_rne((float)(z + d));
+        double dz = fabs(zlo - zb) > fabs(zhi - zb) ? fabs(zlo - zb) : fabs(zhi - zb);
+        sl += (fabs(a) + fabs(c)) * dz;
     }
-    *slack = sl + fabs(y) * 0x1p-20;
+    *slack = sl + mag * 0x1p-18;
     return y;
 }
 
@@ -635,6 +645,33 @@ static int64_t entropy_j(uint16_t *tmp, int64_t n)
     return J;
 }
 
+/* Per-block judge score: J over bins, bin 0 = the balance point (code 0),
+ * else 1 + (error clamped to [-127, 127]) + 127. */
+static int64_t judge_j(const uint16_t *codes, int64_t n)
+{
+    int64_t cnt[256];
+    memset(cnt, 0, sizeof cnt);
+    for (int64_t i = 0; i < n; ++i) {
+        int bin = 0;
+        if (codes[i] != 0) {
+            int64_t e = (int64_t)codes[i] - OR_R;
+            if (e < -127)
+                e = -127;
+            if (e > 127)
+                e = 127;
+            bin = (int)(e + 128);
+        }
+        cnt[bin]++;
+    }
+    int64_t J = 0;
+    for (int b = 0; b < 256; ++b)
+        if (cnt[b])
+            J += cnt[b] * qlog(cnt[b]);
+    return J;
+}
+
+int64_t or_judge_j(const uint16_t *codes, int64_t n) { return judge_j(codes, n); }
+
 int64_t or_entropy_j(const uint16_t *codes, int64_t n)
 {
     uint16_t *tmp = (uint16_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint16_t));
@@ -739,21 +776,8 @@ int or_compress(const void *x, const uint64_t *dims, int ndim, int dtype, double
             k++;
         } while (!it_next(&it));
         int use_net = (mode == 1);
-        if (mode == 2) {
-            uint16_t *tmp = (uint16_t *)malloc((size_t)k * sizeof(uint16_t));
-            if (!tmp) {
-                free(cn); free(cl); free(okb); free(idxb);
-                if (!p_out)
-                    free(P);
-                return OR_ENOMEM;
-            }
-            memcpy(tmp, cn, (size_t)k * sizeof(uint16_t));
-            int64_t jn = entropy_j(tmp, k);
-            memcpy(tmp, cl, (size_t)k * sizeof(uint16_t));
-            int64_t jl = entropy_j(tmp, k);
-            free(tmp);
-            use_net = jn > jl; /* network's entropy strictly lower */
-        }
+        if (mode == 2)
+            use_net = judge_j(cn, k) > judge_j(cl, k); /* network's entropy strictly lower */
         if (flags)
             flags[b] = (uint8_t)(mode == 2 ? use_net : (mode == 1));
         uint32_t cnt = 0;
