@@ -58,10 +58,13 @@ typedef enum {
  *   explicit fused multiply-adds: z_j = fma(w1[j][K-1], u_{K-1}, ... fma(w1[j][0],
  *   u_0, b1[j])), h_j = z_j < 0 ? z_j * alpha : z_j, y = fma(v[H-1], h_{H-1},
  *   ... fma(v[0], h_0, b2)).  Bit-identical to the CPU oracle.
- * precision 1: inputs, w1, hidden activations and v rounded to bfloat16 and
- *   multiplied on the matrix cores with FP32 accumulation (b1, b2 in FP32).
- *   Encoder and decoder run the same instruction sequence, so streams are
- *   self-consistent; the bound is enforced by the quantizer either way.
+ * precision 1: the same network on the matrix cores, 64 points per wave:
+ *   z = b1 + bf16(w1) bf16(u) (BF16 products, FP32 accumulation), then, using
+ *   lrelu(z) = (1 - alpha) relu(z) + alpha z,
+ *   y = b2 + sum_j bf16((1 - alpha) v_j) relu(bf16(z_j)) + bf16(alpha v_j) bf16(z_j)
+ *   (BF16 products, FP32 accumulation).  Encoder and decoder issue the same
+ *   instructions on the same operands, so streams are self-consistent; the
+ *   PW_REL bound is enforced by the quantizer and verification either way.
  */
 typedef struct {
     int32_t hidden;    /* H, 2..32 */
@@ -78,8 +81,13 @@ typedef struct {
 typedef struct {
     int32_t use_net;            /* 0: one-layer Lorenzo everywhere; 1: network where all
                                    neighbours exist (needs a model) */
-    int32_t judge;              /* 1: per block keep the network only if its code entropy is
-                                   strictly below Lorenzo's (flag per block in the stream) */
+    int32_t judge;              /* 1 (needs use_net): per block keep the network only if the
+                                   entropy of its codes is strictly below that of Lorenzo's
+                                   codes (flag per block in the stream).  Entropy of a block's
+                                   codes with every code mapped to a bin: 0 for the balance
+                                   point, else the error clamped to [-127, 127]; compared as
+                                   J = sum over bins of c rint(2^32 log2 c), higher J = lower
+                                   entropy (Sec. 4.3) */
     int32_t independent_blocks; /* 0: the prediction surface crosses block faces (halo mode);
                                    1: neighbours outside the block count as missing, so every
                                    block decodes on its own (Sec. 4.4.2) */
@@ -203,6 +211,92 @@ uint64_t pwrel_huffman_bits(const uint64_t *hist65536, uint32_t *max_len_out);
 #define PWREL_NUM_PHASES 5
 int pwrel_set_profiling(pwrel_ctx *ctx, int enable);
 int pwrel_phase_times(pwrel_ctx *ctx, double *ms, int n);
+
+/*
+ * Learned part (Sec. 4.3; Fig. 4): draw training pairs from the field itself,
+ * train several (learning rate, L2) candidates at once on the device (one
+ * workgroup each: forward, backward and Adam in FP32), keep the candidate
+ * whose validation codes have the lowest empirical entropy (the untrained
+ * network, i.e. Lorenzo, is candidate 0, so the result is never worse on the
+ * validation set), and return it with the scale folded in.
+ *
+ * Sampling: point i is drawn iff U(i) < rho, U(i) = (splitmix64(seed ^ i) >> 11)
+ * 2^-53; it is a validation pair iff U(i) < 0.2 rho (8:2 split).  Only points
+ * whose neighbours all exist (inside the block when independent_blocks is set)
+ * and whose 2^ndim grid values (point and neighbours) lie in one sign range
+ * are kept, and only if every input u_k = n_{k+2} - n_1 and the target
+ * t = p - n_1 satisfy |.| < 2^15.
+ * Loss per candidate: mean over each minibatch of 0.5 (y(u / s) - t / s)^2 plus
+ * (lambda / 2)(|w1|^2 + |v|^2), s = max(1, RMS of the training targets);
+ * minibatches in pair order, Adam (beta 0.9 / 0.999, epsilon 1e-8) from the
+ * initial network's weights taken as scaled-domain parameters.
+ * Selection: validation codes of each candidate's FP32 network (raw domain:
+ * w1 / s, b1, v s, b2 s), score J = sum over code values of c rint(2^32 log2 c)
+ * (higher J = lower entropy); the highest J wins, ties to the lower index.
+ */
+#define PWREL_MAX_CANDIDATES 17 /* the untrained network + up to 4 x 4 trained */
+typedef struct {
+    double rho;            /* sampling rate, 0 < rho <= 1 */
+    uint64_t seed;
+    int32_t hidden;        /* H of the trained network, 2..32 (init == NULL only) */
+    int32_t epochs;        /* passes over the training pairs, 1..64 (the paper: one) */
+    int32_t batch;         /* minibatch size, 1..256 */
+    int32_t n_lr, n_lambda; /* 1..4 each; candidate 1 + a n_lambda + b = (lr[a], lambda[b]) */
+    int32_t independent_blocks;
+    double lr[4], lambda[4];
+    float alpha;           /* leaky-ReLU slope in [0, 1] (init == NULL only) */
+    int32_t precision;     /* precision stored in the returned network (0 or 1) */
+} pwrel_train_options;
+
+typedef struct {
+    uint64_t n_train, n_val;
+    double sigma;
+    int32_t chosen;                           /* 0 = untrained network */
+    int32_t n_candidates;                     /* 1 + n_lr n_lambda */
+    int64_t val_score[PWREL_MAX_CANDIDATES];  /* J of each candidate's validation codes */
+    double ms_sample, ms_train, ms_select;    /* device time per phase */
+} pwrel_train_report;
+
+/*
+ * pwrel_train: d_field as for pwrel_compress (device, C order); init = the
+ * starting network (host; NULL = pwrel_mlp_init(ndim, opt->hidden, opt->alpha,
+ * opt->seed)); *out (host) receives the chosen network, *report (host,
+ * optional) the counts, scale, scores and phase times.  Synchronizes the
+ * stream.  Errors: PWREL_EINVAL for bad arguments (no pairs drawn is not an
+ * error: the untrained network is returned), the field's own errors as for
+ * pwrel_compress, PWREL_ENOMEM when the pair buffers cannot be allocated.
+ */
+int pwrel_train(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim, int dtype,
+                double rel_error_bound, int block_size, const pwrel_train_options *opt,
+                const pwrel_mlp *init, pwrel_mlp *out, pwrel_train_report *report, void *stream);
+
+/*
+ * Training pieces on their own (same kernels as pwrel_train), for checking.
+ * Device pointers carry the d_ prefix; all calls synchronize the stream.
+ *  pwrel_sample     - the pairs of a field in ascending point order: d_idx (point
+ *                     index), d_u (int32 [n][K], K = 2^ndim - 2), d_t (int32),
+ *                     d_isval (u8, 1 = validation); writes at most cap pairs
+ *                     (any of the four may be NULL only when cap is 0) and
+ *                     returns the total in *n_out.
+ *  pwrel_loss_grad  - loss (host *loss_out) and gradient (d_grad, P floats) of
+ *                     the scaled-domain parameters d_theta ([w1 (H x K) | b1 (H)
+ *                     | v (H) | b2], FP32, P = H K + 2 H + 1) on n pairs (d_u
+ *                     FP32 [n][K], d_t FP32 [n]), mean over all n pairs.
+ *  pwrel_train_pairs- Adam training of n_cand (1..16) candidates from d_theta0
+ *                     (P floats) on given pairs; candidate c uses lr[c] and
+ *                     lambda[c] (host arrays); d_theta_out [n_cand][P].
+ */
+int pwrel_sample(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim, int dtype,
+                 double rel_error_bound, int block_size, int independent_blocks, double rho,
+                 uint64_t seed, uint64_t *d_idx, int32_t *d_u, int32_t *d_t, uint8_t *d_isval,
+                 uint64_t cap, uint64_t *n_out, void *stream);
+int pwrel_loss_grad(pwrel_ctx *ctx, const float *d_theta, int hidden, int inputs, float alpha,
+                    const float *d_u, const float *d_t, uint64_t n, double sigma, double lambda,
+                    float *d_grad, float *loss_out, void *stream);
+int pwrel_train_pairs(pwrel_ctx *ctx, const float *d_u, const float *d_t, uint64_t n, int hidden,
+                      int inputs, float alpha, double sigma, const float *d_theta0, int n_cand,
+                      const double *lr, const double *lambda, int batch, int epochs,
+                      float *d_theta_out, void *stream);
 
 /* Network that reproduces Lorenzo exactly (end of Sec. 4.2). */
 int pwrel_mlp_init(pwrel_mlp *out, int ndim, int hidden, float alpha, uint64_t seed);

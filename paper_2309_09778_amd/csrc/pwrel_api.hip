@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "pwrel_internal.h"
+#include "pwrel_train.h"
 
 using namespace pwrel;
 
@@ -22,6 +23,19 @@ struct pwrel_ctx {
     hipEvent_t ev[8] = {};
     bool ev_ok = false;
     double phase_ms[PWREL_NUM_PHASES] = {};
+    // learned part: chunk counts and offsets, pairs, parameters, scores
+    uint32_t *chunk_cnt = nullptr;
+    size_t chunk_cnt_cap = 0;
+    unsigned long long *chunk_off = nullptr;
+    size_t chunk_off_cap = 0;
+    float *pairs = nullptr;
+    size_t pairs_cap = 0;
+    float *theta = nullptr;  // [1 + candidates][kMaxParams]
+    MlpW *nets = nullptr;    // [1 + candidates]
+    unsigned long long *vhist = nullptr;  // [1 + candidates][65536]
+    size_t vhist_cap = 0;
+    double *scal = nullptr;  // sigma, partial sums (256), loss
+    long long *scores = nullptr;
 };
 
 namespace {
@@ -115,8 +129,8 @@ int check_model(pwrel_ctx *ctx, const pwrel_mlp *m, int ndim)
         return fail(ctx, PWREL_EINVAL, "model hidden width must be 2..32");
     if (m->inputs != (1 << ndim) - 2)
         return fail(ctx, PWREL_EINVAL, "model inputs must equal 2^ndim - 2");
-    if (m->precision != 0)
-        return fail(ctx, PWREL_EINVAL, "this build evaluates FP32 networks (precision 0) only");
+    if (m->precision != 0 && m->precision != 1)
+        return fail(ctx, PWREL_EINVAL, "model precision must be 0 (FP32) or 1 (BF16 matrix cores)");
     if (!(m->alpha >= 0.0f && m->alpha <= 1.0f))
         return fail(ctx, PWREL_EINVAL, "leaky-ReLU slope must lie in [0, 1]");
     auto bad = [](float v) { return !std::isfinite(v) || std::fabs(v) > 65536.0f; };
@@ -203,6 +217,64 @@ uint64_t splitmix64(uint64_t s)
     return z ^ (z >> 31);
 }
 
+// Statistics, constants and the per-chunk pair counts of a field, then the
+// exclusive offsets of the chunks (host scan, copied back to the device).
+int sample_counts(pwrel_ctx *ctx, const void *d_field, const Geom &g, double eps,
+                  int independent, double rho, uint64_t seed, hipStream_t s, SampleArgs &a,
+                  unsigned long long &ntr, unsigned long long &nva, long long &nch)
+{
+    a = SampleArgs{};
+    a.x = d_field;
+    for (int d = 0; d < 3; ++d)
+        a.n[d] = g.n[d];
+    a.N = g.N;
+    a.B = g.B;
+    a.independent = independent ? 1 : 0;
+    a.rho = rho;
+    a.seed = seed;
+    a.c = ctx->ws.consts;
+    nch = (g.N + kSampleChunk - 1) / kSampleChunk;
+    hipError_t e = grow(ctx->chunk_cnt, ctx->chunk_cnt_cap, (size_t)(2 * nch));
+    if (e == hipSuccess)
+        e = grow(ctx->chunk_off, ctx->chunk_off_cap, (size_t)(2 * nch));
+    if (e != hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, "sampling workspace allocation failed");
+    if ((e = launch_reset(ctx->ws, s)) != hipSuccess ||
+        (e = launch_stats(d_field, g, ctx->ws, s)) != hipSuccess ||
+        (e = launch_consts(g, eps, ctx->ws, s)) != hipSuccess ||
+        (e = launch_sample(true, a, g.D, g.dtype, ctx->chunk_cnt, ctx->chunk_cnt + nch, nullptr,
+                           s)) != hipSuccess)
+        return hip_fail(ctx, e, "sample count");
+    std::vector<uint32_t> cnt((size_t)(2 * nch));
+    int dst = 0;
+    if ((e = hipMemcpyAsync(cnt.data(), ctx->chunk_cnt, cnt.size() * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&dst, ctx->ws.status, sizeof dst, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "sample count copy");
+    if (dst != PWREL_OK)
+        return finish_status(ctx, dst);
+    std::vector<unsigned long long> off((size_t)(2 * nch));
+    ntr = nva = 0;
+    for (long long i = 0; i < nch; ++i) {
+        off[(size_t)i] = ntr;
+        off[(size_t)(nch + i)] = nva;
+        ntr += cnt[(size_t)i];
+        nva += cnt[(size_t)(nch + i)];
+    }
+    if ((e = hipMemcpyAsync(ctx->chunk_off, off.data(), off.size() * sizeof(unsigned long long),
+                            hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "sample offsets copy");
+    return PWREL_OK;
+}
+
+bool train_shape_ok(int hidden, int inputs)
+{
+    return hidden >= 1 && hidden <= PWREL_MAX_HIDDEN && (inputs == 0 || inputs == 2 || inputs == 6);
+}
+
 }  // namespace
 
 extern "C" {
@@ -267,6 +339,22 @@ int pwrel_create(pwrel_ctx **out, int device)
         e = hipMalloc(reinterpret_cast<void **>(&ws.hist), 65536 * sizeof(unsigned long long));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&ws.n_raw), 256);
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.qtab), kQtab * sizeof(long long));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ctx->theta),
+                      (PWREL_MAX_CANDIDATES + 1) * kMaxParams * sizeof(float));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ctx->nets), PWREL_MAX_CANDIDATES * sizeof(MlpW));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ctx->scal), 512 * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ctx->scores),
+                      PWREL_MAX_CANDIDATES * sizeof(long long));
+    if (e == hipSuccess)
+        e = launch_qtable(ws.qtab, kQtab, nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         pwrel_destroy(ctx);
         return PWREL_ENOMEM;
@@ -281,8 +369,10 @@ void pwrel_destroy(pwrel_ctx *ctx)
         return;
     DeviceGuard guard(ctx->device);
     Workspace &ws = ctx->ws;
-    void *ptrs[] = {ws.stats, ws.consts, ws.status, ws.hist, ws.n_raw, ws.offsets, ws.partials,
-                    ws.pgrid, ctx->counts_scratch};
+    void *ptrs[] = {ws.stats,       ws.consts,      ws.status,     ws.hist,        ws.n_raw,
+                    ws.offsets,     ws.partials,    ws.pgrid,      ws.qtab,        ctx->counts_scratch,
+                    ctx->chunk_cnt, ctx->chunk_off, ctx->pairs,    ctx->theta,     ctx->nets,
+                    ctx->vhist,     ctx->scal,      ctx->scores};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -311,8 +401,8 @@ int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, in
         return fail(ctx, PWREL_EINVAL, "bad dims/ndim/dtype/bound/block size");
     if (!d_field || !d_out || !out_size)
         return fail(ctx, PWREL_EINVAL, "NULL field, output or size pointer");
-    if (opt.judge)
-        return fail(ctx, PWREL_EINVAL, "per-block judge needs the matrix-core network path");
+    if (opt.judge && !opt.use_net)
+        return fail(ctx, PWREL_EINVAL, "the per-block judge needs a network (use_net)");
     if (opt.use_net) {
         const int st = check_model(ctx, model, ndim);
         if (st)
@@ -440,8 +530,8 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
     for (int d = 0; d < ndim; ++d)
         if (h.dims[d] != dims[d])
             return fail(ctx, PWREL_EINVAL, "dims do not match the stream");
-    if ((h.flags & PWREL_HF_JUDGE))
-        return fail(ctx, PWREL_EINVAL, "per-block judge streams need the matrix-core path");
+    if ((h.flags & PWREL_HF_JUDGE) && !(h.flags & PWREL_HF_NET))
+        return fail(ctx, PWREL_ECORRUPT, "judge flag without a network");
     const pwrel_mlp *model = nullptr;
     if (h.flags & PWREL_HF_NET) {
         if (want < PWREL_HEADER_BYTES + sizeof(pwrel_mlp))
@@ -707,6 +797,302 @@ uint64_t pwrel_huffman_bits(const uint64_t *hist, uint32_t *max_len_out)
     if (max_len_out)
         *max_len_out = maxl;
     return bits;
+}
+
+int pwrel_sample(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim, int dtype,
+                 double eps, int block_size, int independent_blocks, double rho, uint64_t seed,
+                 uint64_t *d_idx, int32_t *d_u, int32_t *d_t, uint8_t *d_isval, uint64_t cap,
+                 uint64_t *n_out, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (pwrel_check_args(dims, ndim, dtype, eps, block_size) != PWREL_OK || !d_field || !n_out)
+        return fail(ctx, PWREL_EINVAL, "bad dims/ndim/dtype/bound/block size or NULL pointer");
+    if (!(rho > 0.0 && rho <= 1.0))
+        return fail(ctx, PWREL_EINVAL, "sampling rate must lie in (0, 1]");
+    if (cap > 0 && (!d_idx || !d_t || !d_isval || (ndim > 1 && !d_u)))
+        return fail(ctx, PWREL_EINVAL, "NULL output with a nonzero capacity");
+    Geom g;
+    make_geom(dims, ndim, dtype, block_size, g);
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    SampleArgs a;
+    unsigned long long ntr = 0, nva = 0;
+    long long nch = 0;
+    int st = sample_counts(ctx, d_field, g, eps, independent_blocks, rho, seed, s, a, ntr, nva, nch);
+    if (st)
+        return st;
+    SampleOut o{};
+    o.off_tr = ctx->chunk_off;
+    o.off_va = ctx->chunk_off + nch;
+    if (cap > 0) {
+        o.u_all = d_u;
+        o.t_all = d_t;
+        o.isval = d_isval;
+        o.idx_all = reinterpret_cast<unsigned long long *>(d_idx);
+        o.cap_all = cap;
+        hipError_t e;
+        if ((e = launch_sample(false, a, g.D, g.dtype, nullptr, nullptr, &o, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(ctx, e, "sample write");
+    }
+    *n_out = ntr + nva;
+    return PWREL_OK;
+}
+
+int pwrel_loss_grad(pwrel_ctx *ctx, const float *d_theta, int hidden, int inputs, float alpha,
+                    const float *d_u, const float *d_t, uint64_t n, double sigma, double lambda,
+                    float *d_grad, float *loss_out, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!train_shape_ok(hidden, inputs) || n == 0 || !d_theta || !d_t || (inputs && !d_u) ||
+        !d_grad || !loss_out || !(sigma > 0.0) || !(lambda >= 0.0) ||
+        !(alpha >= 0.0f && alpha <= 1.0f))
+        return fail(ctx, PWREL_EINVAL, "bad arguments");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    GradArgs a{};
+    a.H = hidden;
+    a.theta = d_theta;
+    a.u = d_u;
+    a.t = d_t;
+    a.n = (long long)n;
+    a.sigma = sigma;
+    a.lambda = lambda;
+    a.alpha = alpha;
+    a.grad = d_grad;
+    a.loss = reinterpret_cast<float *>(ctx->scal + 300);
+    hipError_t e;
+    if ((e = launch_loss_grad(hidden, inputs, a, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(loss_out, a.loss, sizeof(float), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "loss_grad");
+    return PWREL_OK;
+}
+
+int pwrel_train_pairs(pwrel_ctx *ctx, const float *d_u, const float *d_t, uint64_t n, int hidden,
+                      int inputs, float alpha, double sigma, const float *d_theta0, int n_cand,
+                      const double *lr, const double *lambda, int batch, int epochs,
+                      float *d_theta_out, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!train_shape_ok(hidden, inputs) || !d_t || (inputs && !d_u) || !d_theta0 ||
+        !d_theta_out || !lr || !lambda || n_cand < 1 || n_cand > kMaxTrained || batch < 1 ||
+        batch > 256 || epochs < 1 || epochs > 64 || !(sigma > 0.0) ||
+        !(alpha >= 0.0f && alpha <= 1.0f))
+        return fail(ctx, PWREL_EINVAL, "bad arguments");
+    TrainArgs a{};
+    for (int c = 0; c < n_cand; ++c) {
+        if (!(lr[c] > 0.0 && std::isfinite(lr[c])) || !(lambda[c] >= 0.0 && std::isfinite(lambda[c])))
+            return fail(ctx, PWREL_EINVAL, "learning rates must be positive, L2 weights >= 0");
+        a.lr[c] = lr[c];
+        a.lambda[c] = lambda[c];
+    }
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    double *d_sigma = ctx->scal + 400;
+    const double sg = sigma;
+    a.H = hidden;
+    a.u = d_u;
+    a.t = d_t;
+    a.n = (long long)n;
+    a.sigma = d_sigma;
+    a.alpha = alpha;
+    a.batch = batch;
+    a.epochs = epochs;
+    a.theta0 = d_theta0;
+    a.theta_out = d_theta_out;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d_sigma, &sg, sizeof sg, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_train(hidden, inputs, a, n_cand, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "train_pairs");
+    return PWREL_OK;
+}
+
+int pwrel_train(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim, int dtype,
+                double eps, int block_size, const pwrel_train_options *opt,
+                const pwrel_mlp *init, pwrel_mlp *out, pwrel_train_report *report, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (pwrel_check_args(dims, ndim, dtype, eps, block_size) != PWREL_OK || !d_field || !opt ||
+        !out)
+        return fail(ctx, PWREL_EINVAL, "bad dims/ndim/dtype/bound/block size or NULL pointer");
+    const pwrel_train_options &o = *opt;
+    if (!(o.rho > 0.0 && o.rho <= 1.0) || o.batch < 1 || o.batch > 256 || o.epochs < 1 ||
+        o.epochs > 64 || o.n_lr < 1 || o.n_lr > 4 || o.n_lambda < 1 || o.n_lambda > 4 ||
+        (o.precision != 0 && o.precision != 1))
+        return fail(ctx, PWREL_EINVAL, "bad training options");
+    TrainArgs ta{};
+    const int ncand = o.n_lr * o.n_lambda;
+    for (int c = 0; c < ncand; ++c) {
+        const double l = o.lr[c / o.n_lambda], m = o.lambda[c % o.n_lambda];
+        if (!(l > 0.0 && std::isfinite(l)) || !(m >= 0.0 && std::isfinite(m)))
+            return fail(ctx, PWREL_EINVAL, "learning rates must be positive, L2 weights >= 0");
+        ta.lr[c] = l;
+        ta.lambda[c] = m;
+    }
+    pwrel_mlp m0;
+    if (init) {
+        m0 = *init;
+    } else if (pwrel_mlp_init(&m0, ndim, o.hidden, o.alpha, o.seed) != PWREL_OK) {
+        return fail(ctx, PWREL_EINVAL, "bad hidden width for the initial network");
+    }
+    int st = check_model(ctx, &m0, ndim);
+    if (st)
+        return st;
+    const int H = m0.hidden, K = m0.inputs, P = H * K + 2 * H + 1;
+    Geom g;
+    make_geom(dims, ndim, dtype, block_size, g);
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t ev[4] = {};
+    for (hipEvent_t &e : ev)
+        if (hipEventCreate(&e) != hipSuccess)
+            e = nullptr;
+    auto cleanup = [&]() {
+        for (hipEvent_t &e : ev)
+            if (e)
+                (void)hipEventDestroy(e);
+    };
+    auto rec = [&](int i) {
+        if (ev[i])
+            (void)hipEventRecord(ev[i], s);
+    };
+    rec(0);
+    SampleArgs sa;
+    unsigned long long ntr = 0, nva = 0;
+    long long nch = 0;
+    st = sample_counts(ctx, d_field, g, eps, o.independent_blocks, o.rho, o.seed, s, sa, ntr, nva,
+                       nch);
+    if (st) {
+        cleanup();
+        return st;
+    }
+    hipError_t e = grow(ctx->pairs, ctx->pairs_cap,
+                        std::max<size_t>(1, (size_t)((ntr + nva) * (unsigned long long)(K + 1))));
+    if (e == hipSuccess)
+        e = grow(ctx->vhist, ctx->vhist_cap, (size_t)(ncand + 1) * 65536);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, PWREL_ENOMEM, "training pair buffers");
+    }
+    SampleOut so{};
+    so.off_tr = ctx->chunk_off;
+    so.off_va = ctx->chunk_off + nch;
+    so.u_tr = ctx->pairs;
+    so.t_tr = so.u_tr + ntr * K;
+    so.u_va = so.t_tr + ntr;
+    so.t_va = so.u_va + nva * K;
+    so.cap_tr = ntr;
+    so.cap_va = nva;
+    std::vector<float> th0((size_t)P);
+    for (int j = 0; j < H; ++j) {
+        for (int k = 0; k < K; ++k)
+            th0[(size_t)(j * K + k)] = m0.w1[j][k];
+        th0[(size_t)(H * K + j)] = m0.b1[j];
+        th0[(size_t)(H * K + H + j)] = m0.v[j];
+    }
+    th0[(size_t)(H * K + 2 * H)] = m0.b2;
+    ta.H = H;
+    ta.u = so.u_tr;
+    ta.t = so.t_tr;
+    ta.n = (long long)ntr;
+    ta.sigma = ctx->scal;
+    ta.alpha = m0.alpha;
+    ta.batch = o.batch;
+    ta.epochs = o.epochs;
+    ta.theta0 = ctx->theta;
+    ta.theta_out = ctx->theta + P;
+    FoldArgs fa{};
+    fa.theta = ctx->theta + P;
+    fa.sigma = ctx->scal;
+    fa.H = H;
+    fa.K = K;
+    fa.ncand = ncand;
+    fa.init = pack_mlp(&m0);
+    fa.nets = ctx->nets;
+    ValArgs va{};
+    va.u = so.u_va;
+    va.t = so.t_va;
+    va.n = (long long)nva;
+    va.nets = ctx->nets;
+    va.hist = ctx->vhist;
+    if ((e = launch_sample(false, sa, g.D, g.dtype, nullptr, nullptr, &so, s)) != hipSuccess) {
+        cleanup();
+        return hip_fail(ctx, e, "sample write");
+    }
+    rec(1);
+    if ((e = launch_sigma(so.t_tr, (long long)ntr, ctx->scal + 1, ctx->scal, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(ctx->theta, th0.data(), th0.size() * sizeof(float),
+                            hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_train(H, K, ta, ncand, s)) != hipSuccess) {
+        cleanup();
+        return hip_fail(ctx, e, "train");
+    }
+    rec(2);
+    if ((e = launch_fold(fa, s)) != hipSuccess ||
+        (e = launch_validate(g.D, hidden_pad(&m0), va, ncand + 1, ctx->scores, s)) !=
+            hipSuccess) {
+        cleanup();
+        return hip_fail(ctx, e, "validate");
+    }
+    rec(3);
+    std::vector<long long> sc((size_t)(ncand + 1));
+    std::vector<float> th((size_t)ncand * P);
+    double sigma = 1.0;
+    if ((e = hipMemcpyAsync(sc.data(), ctx->scores, sc.size() * sizeof(long long),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(th.data(), ctx->theta + P, th.size() * sizeof(float),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&sigma, ctx->scal, sizeof sigma, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        cleanup();
+        return hip_fail(ctx, e, "training results copy");
+    }
+    int best = 0;
+    for (int c = 1; c <= ncand; ++c)
+        if (sc[(size_t)c] > sc[(size_t)best])
+            best = c;
+    pwrel_mlp res = m0;
+    if (best > 0) {
+        // the same fold as the validation networks (FP64 then FP32)
+        const float *t = th.data() + (size_t)(best - 1) * P;
+        for (int j = 0; j < H; ++j) {
+            for (int k = 0; k < K; ++k)
+                res.w1[j][k] = (float)((double)t[j * K + k] / sigma);
+            res.b1[j] = t[H * K + j];
+            res.v[j] = (float)((double)t[H * K + H + j] * sigma);
+        }
+        res.b2 = (float)((double)t[H * K + 2 * H] * sigma);
+    }
+    res.precision = o.precision;
+    if (report) {
+        pwrel_train_report r{};
+        r.n_train = ntr;
+        r.n_val = nva;
+        r.sigma = sigma;
+        r.chosen = best;
+        r.n_candidates = ncand + 1;
+        for (int c = 0; c <= ncand; ++c)
+            r.val_score[c] = sc[(size_t)c];
+        float ms = 0.0f;
+        if (ev[0] && ev[1] && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess)
+            r.ms_sample = ms;
+        if (ev[1] && ev[2] && hipEventElapsedTime(&ms, ev[1], ev[2]) == hipSuccess)
+            r.ms_train = ms;
+        if (ev[2] && ev[3] && hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess)
+            r.ms_select = ms;
+        *report = r;
+    }
+    cleanup();
+    *out = res;
+    return PWREL_OK;
 }
 
 int pwrel_mlp_init(pwrel_mlp *m, int ndim, int hidden, float alpha, uint64_t seed)

@@ -11,7 +11,7 @@
 // balance points of each block in LDS.  Workgroups are persistent; the
 // workgroups of XCD x (= workgroup id mod 8) walk a contiguous eighth of the
 // tiles so that tiles sharing halo rows meet in the same L2.
-#include "pwrel_kernels.h"
+#include "pwrel_bf16.h"
 
 namespace pwrel {
 
@@ -30,10 +30,33 @@ struct CompressArgs {
     uint8_t *bflags;
     const DevConsts *consts;
     int *status;
+    const long long *qtab;  // q(c) = rint(2^32 log2 c), c = 0 .. points per block (judge)
     MlpW mlp;
 };
 
-template <typename T, int D, int BB, int HP, bool FROM_P>
+// Judge bins: code 0 (balance point) and the prediction error clamped to
+// [-127, 127] (Sec. 4.3 judge reading: entropy of the clamped code).
+__device__ __forceinline__ int judge_bin(unsigned code)
+{
+    if (code == 0)
+        return 0;
+    int e = (int)code - kR;
+    e = e < -127 ? -127 : (e > 127 ? 127 : e);
+    return e + 128;
+}
+
+template <int D>
+__device__ __forceinline__ long long lorenzo_pred(const int (&nv)[8], int amask)
+{
+    long long s = 0;
+#pragma unroll
+    for (int o = 1; o < (1 << D); ++o)
+        if ((o & ~amask) == 0)
+            s += (long long)lorenzo_sign(o) * (long long)nv[o];
+    return s;
+}
+
+template <typename T, int D, int BB, int HP, bool FROM_P, int PREC>
 __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
 {
     using S = ShapeOf<D, BB>;
@@ -52,16 +75,30 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
     const int nbt = nbt0 * nbt1 * nbt2;
     const int BV = bd0 * bd1 * bd2;
 
-    int *ptile = reinterpret_cast<int *>(smem);
+    // judge only (first, so that the 64-bit scores are 8-byte aligned):
+    // per-block scores and code histograms (network count in the low 16 bits,
+    // Lorenzo count in the high 16 bits; bin 0 = balance points)
+    unsigned long long *jsum = reinterpret_cast<unsigned long long *>(smem);
+    int *ptile = reinterpret_cast<int *>(jsum + (a.judge ? 2 * nbt : 0));
     unsigned int *cnt = reinterpret_cast<unsigned int *>(ptile + ne);
-    unsigned char *okb = reinterpret_cast<unsigned char *>(cnt + nbt);
+    unsigned int *jh = cnt + nbt;
+    unsigned char *okb = reinterpret_cast<unsigned char *>(jh + (a.judge ? nbt * 256 : 0));
 
     __shared__ int s_status;
     __shared__ float4 wl[kWlds];
     stage_weights<HP>(wl, a.mlp);
     const float b2 = a.mlp.b2, alpha = a.mlp.alpha;
+    NetBf16 net16;
+    if constexpr (PREC == 1)
+        net16 = make_net_bf16(a.mlp, (1 << D) - 2);
     for (int i = tid; i < nbt; i += NT)
         cnt[i] = 0u;
+    if (a.judge) {
+        for (int i = tid; i < nbt * 256; i += NT)
+            jh[i] = 0u;
+        for (int i = tid; i < 2 * nbt; i += NT)
+            jsum[i] = 0ULL;
+    }
     if (tid == 0)
         s_status = *a.status;
     __syncthreads();
@@ -143,37 +180,111 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
         __syncthreads();
 
         // --- predict, quantize, count (stream order) -------------------------
+        // Rounds of NT points; every lane of a wave takes part in each round
+        // (the matrix-core network works on whole waves).
         const long long bz0 = g0z / bd0, by0 = g0y / bd1, bx0 = g0x / bd2;
-        for (int q = tid; q < nbt * BV; q += NT) {
-            const int bt = q / BV, li = q - bt * BV;
+        const int nq = nbt * BV;
+        for (int q0 = 0; q0 < nq; q0 += NT) {
+            const int q = q0 + tid;
+            const int qq = q < nq ? q : 0;
+            const int bt = qq / BV, li = qq - bt * BV;
             const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
             const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
             const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
             const long long gz = g0z + cz, gy = g0y + cy, gx = g0x + cx;
-            if (gz >= n0 || gy >= n1 || gx >= n2)
-                continue;
-            const int ei = ((cz + h0) * E1 + (cy + h1)) * E2 + (cx + h2);
-            int nv[8];
-            nv[0] = ptile[ei];
+            const bool inside = q < nq && gz < n0 && gy < n1 && gx < n2;
+            int nv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int amask = 0;
+            if (inside) {
+                const int ei = ((cz + h0) * E1 + (cy + h1)) * E2 + (cx + h2);
+                nv[0] = ptile[ei];
 #pragma unroll
-            for (int o = 1; o < (1 << D); ++o)
-                nv[o] = ptile[ei - noff[o]];
-            int amask;
-            if (a.independent)
-                amask = (lx != 0 ? 1 : 0) | (D >= 2 && ly != 0 ? 2 : 0) |
-                        (D >= 3 && lz != 0 ? 4 : 0);
+                for (int o = 1; o < (1 << D); ++o)
+                    nv[o] = ptile[ei - noff[o]];
+                if (a.independent)
+                    amask = (lx != 0 ? 1 : 0) | (D >= 2 && ly != 0 ? 2 : 0) |
+                            (D >= 3 && lz != 0 ? 4 : 0);
+                else
+                    amask = (gx != 0 ? 1 : 0) | (D >= 2 && gy != 0 ? 2 : 0) |
+                            (D >= 3 && gz != 0 ? 4 : 0);
+            }
+            long long pred;
+            if constexpr (PREC == 1)
+                pred = predict_bf16<D>(nv, amask, a.use_net != 0 && inside, net16);
             else
-                amask = (gx != 0 ? 1 : 0) | (D >= 2 && gy != 0 ? 2 : 0) |
-                        (D >= 3 && gz != 0 ? 4 : 0);
-            const long long pred = predict<D, HP>(nv, amask, a.use_net != 0, WeightsLds{wl}, b2, alpha);
+                pred = inside ? predict<D, HP>(nv, amask, a.use_net != 0, WeightsLds{wl}, b2, alpha)
+                              : 0;
+            if (!inside)
+                continue;
             const bool ok = okb[(cz * T1 + cy) * T2 + cx] != 0;
             const unsigned short code = make_code(pred, nv[0], ok);
             const BlockGeo bg = block_geo3(bz0 + btz, by0 + bty, bx0 + btx, a.n, bd0, bd1, bd2);
             a.codes[bg.start + ((long long)lz * bg.ey + ly) * bg.ex + lx] = code;
-            if (code == 0)
+            if (a.judge) {
+                const unsigned short lcode = make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
+                atomicAdd(&jh[bt * 256 + judge_bin(code)], 1u);
+                atomicAdd(&jh[bt * 256 + judge_bin(lcode)], 1u << 16);
+            } else if (code == 0) {
                 atomicAdd(&cnt[bt], 1u);
+            }
         }
         __syncthreads();
+
+        if (a.judge) {
+            // --- per-block judge: keep the network iff the entropy of its
+            //     clamped codes is strictly below Lorenzo's (fixed-point scores) ---
+            for (int i = tid; i < nbt * 256; i += NT) {
+                const unsigned w = jh[i];
+                const unsigned c_n = w & 0xffffu, c_l = w >> 16;
+                const int bt = i >> 8;
+                if ((i & 255) == 0)  // bin 0 holds the balance points of both
+                    cnt[bt] = w;
+                if (c_n)
+                    atomicAdd(&jsum[2 * bt],
+                              (unsigned long long)c_n * (unsigned long long)a.qtab[c_n]);
+                if (c_l)
+                    atomicAdd(&jsum[2 * bt + 1],
+                              (unsigned long long)c_l * (unsigned long long)a.qtab[c_l]);
+                jh[i] = 0u;
+            }
+            __syncthreads();
+            // blocks where Lorenzo wins: overwrite the network codes written above
+            for (int q = tid; q < nq; q += NT) {
+                const int bt = q / BV;
+                if (jsum[2 * bt] > jsum[2 * bt + 1])
+                    continue;
+                const int li = q - bt * BV;
+                const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
+                const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
+                const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
+                const long long gz = g0z + cz, gy = g0y + cy, gx = g0x + cx;
+                if (gz >= n0 || gy >= n1 || gx >= n2)
+                    continue;
+                const int ei = ((cz + h0) * E1 + (cy + h1)) * E2 + (cx + h2);
+                int nv[8];
+                nv[0] = ptile[ei];
+#pragma unroll
+                for (int o = 1; o < (1 << D); ++o)
+                    nv[o] = ptile[ei - noff[o]];
+                int amask;
+                if (a.independent)
+                    amask = (lx != 0 ? 1 : 0) | (D >= 2 && ly != 0 ? 2 : 0) |
+                            (D >= 3 && lz != 0 ? 4 : 0);
+                else
+                    amask = (gx != 0 ? 1 : 0) | (D >= 2 && gy != 0 ? 2 : 0) |
+                            (D >= 3 && gz != 0 ? 4 : 0);
+                const bool ok = okb[(cz * T1 + cy) * T2 + cx] != 0;
+                const BlockGeo bg =
+                    block_geo3(bz0 + btz, by0 + bty, bx0 + btx, a.n, bd0, bd1, bd2);
+                a.codes[bg.start + ((long long)lz * bg.ey + ly) * bg.ex + lx] =
+                    make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
+            }
+            for (int bt = tid; bt < nbt; bt += NT) {
+                const bool use_n = jsum[2 * bt] > jsum[2 * bt + 1];
+                cnt[bt] = use_n ? (cnt[bt] & 0xffffu) : (cnt[bt] >> 16);
+            }
+            __syncthreads();
+        }
 
         // --- per-block balance-point counts ------------------------------------
         for (int bt = tid; bt < nbt; bt += NT) {
@@ -183,9 +294,12 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
                 const long long b = (bz * a.nb[1] + by) * a.nb[2] + bx;
                 a.counts[b] = cnt[bt];
                 if (a.bflags)
-                    a.bflags[b] = a.use_net ? 1 : 0;
+                    a.bflags[b] = a.judge ? (jsum[2 * bt] > jsum[2 * bt + 1] ? 1 : 0)
+                                          : (a.use_net ? 1 : 0);
             }
             cnt[bt] = 0u;
+            if (a.judge)
+                jsum[2 * bt] = jsum[2 * bt + 1] = 0ULL;
         }
         // the next tile's staging overwrites ptile/okb only after this barrier
         __syncthreads();
@@ -194,13 +308,16 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
 }
 
 // ---------------------------------------------------------------------------
-static size_t compress_lds(const Geom &g, const int *t)
+static size_t compress_lds(const Geom &g, const int *t, bool judge = true)
 {
     const int h0 = g.D >= 3 ? 1 : 0, h1 = g.D >= 2 ? 1 : 0;
     const size_t ne = (size_t)(t[0] + h0) * (t[1] + h1) * (t[2] + 1);
     const size_t nbt = (size_t)(t[0] / g.bd[0]) * (t[1] / g.bd[1]) * (t[2] / g.bd[2]);
     const size_t ntp = (size_t)t[0] * t[1] * t[2];
-    return ne * 4 + nbt * 4 + ntp;
+    size_t n = ne * 4 + nbt * 4;
+    if (judge)
+        n += nbt * 256 * 4 + 2 * nbt * 8;
+    return n + ntp;
 }
 
 bool tile_for(const Geom &g, Tile &tile)
@@ -240,21 +357,23 @@ bool tile_for(const Geom &g, Tile &tile)
     return true;
 }
 
-template <typename T, int D, int BB, int HP, bool FP>
+template <typename T, int D, int BB, int HP, bool FP, int PREC>
 static void go(const CompressArgs &a, unsigned grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC>), dim3(grid), dim3(256), lds, s, a);
 }
 
 template <typename T, int D, int BB, bool FP>
 static void by_hidden(int HP, const CompressArgs &a, unsigned grid, size_t lds, hipStream_t s)
 {
-    if (HP == 8)
-        go<T, D, BB, 8, FP>(a, grid, lds, s);
+    if (HP == 0)
+        go<T, D, BB, 8, FP, 1>(a, grid, lds, s);  // matrix-core network
+    else if (HP == 8)
+        go<T, D, BB, 8, FP, 0>(a, grid, lds, s);
     else if (HP == 16)
-        go<T, D, BB, 16, FP>(a, grid, lds, s);
+        go<T, D, BB, 16, FP, 0>(a, grid, lds, s);
     else
-        go<T, D, BB, 32, FP>(a, grid, lds, s);
+        go<T, D, BB, 32, FP, 0>(a, grid, lds, s);
 }
 
 template <typename T, bool FP>
@@ -307,13 +426,15 @@ hipError_t launch_compress(const void *x, const int *pfield, const Geom &g, cons
     a.bflags = bflags;
     a.consts = ws.consts;
     a.status = ws.status;
+    a.qtab = ws.qtab;
     a.mlp = pack_mlp(opt.use_net ? model : nullptr);
-    const int HP = hidden_pad(opt.use_net ? model : nullptr);
+    const bool mfma = opt.use_net && model && model->precision == 1;
+    const int HP = mfma ? 0 : hidden_pad(opt.use_net ? model : nullptr);
     const long long gmax = (long long)std::max(num_cus, 8) * 4;
     long long grid = std::min(gmax, (tile.ntiles + 7) / 8 * 8);
     if (grid < 8)
         grid = 8;
-    const size_t lds = compress_lds(g, tile.t);
+    const size_t lds = compress_lds(g, tile.t, opt.judge != 0);
     if (pfield)
         by_shape<float, true>(g.D, g.B, HP, a, (unsigned)grid, lds, s);
     else if (g.dtype == PWREL_F32)

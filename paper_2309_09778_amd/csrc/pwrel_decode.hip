@@ -9,7 +9,7 @@
 // field (later blocks read nothing else).
 #include <type_traits>
 
-#include "pwrel_kernels.h"
+#include "pwrel_bf16.h"
 
 namespace pwrel {
 
@@ -40,7 +40,7 @@ __device__ __forceinline__ unsigned long long raw_offset(const unsigned long lon
     return offs[b] + partials[b / kScanChunk];
 }
 
-template <typename T, int D, int BB, int HP>
+template <typename T, int D, int BB, int HP, int PREC>
 __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
 {
     constexpr bool CT = BB > 0;
@@ -151,6 +151,9 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
         wt.load(wl);
     else
         wt.wl = wl;
+    NetBf16 net16;
+    if constexpr (PREC == 1)
+        net16 = make_net_bf16(a.mlp, (1 << D) - 2);
     int err = kOk;
     const int nlines = bd0 * bd1;
     const int nsteps = (ez - 1) + (ey - 1) + (ex - 1) + 1;
@@ -168,19 +171,33 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
             amask_zy = (D >= 2 && gy != 0 ? 2 : 0) | (D >= 3 && gz != 0 ? 4 : 0);
         for (int s = 0; s < nsteps; ++s) {
             const int lx = s - lz - ly;
-            if (lane_on && lx >= 0 && lx < ex) {
-                const int ei = ebase + lx;
-                const unsigned code = cl[cbase + lx];
+            const bool on = lane_on && lx >= 0 && lx < ex;
+            const int ei = ebase + lx;
+            const unsigned code = on ? cl[cbase + lx] : 0u;
+            int nv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int amask = 0;
+            if (on && code != 0) {
+#pragma unroll
+                for (int o = 1; o < (1 << D); ++o)
+                    nv[o] = ptile[ei - noff[o]];
+                amask = amask_zy | (a.independent ? (lx != 0) : (g0x + lx != 0));
+            }
+            long long pred = 0;
+            if constexpr (PREC == 1) {
+                // block-uniform branch; inside it every lane of the wave runs
+                // the matrix-core network (lanes without a coded point feed zeros)
+                if (net)
+                    pred = predict_bf16<D>(nv, amask, on && code != 0, net16);
+                else if (on && code != 0)
+                    pred = predict<D, HP>(nv, amask, false, wt, b2, alpha);
+            } else {
+                if (on && code != 0)
+                    pred = predict<D, HP>(nv, amask, net, wt, b2, alpha);
+            }
+            if (on) {
                 int p;
                 if (code != 0) {
-                    int nv[8];
-                    nv[0] = 0;
-#pragma unroll
-                    for (int o = 1; o < (1 << D); ++o)
-                        nv[o] = ptile[ei - noff[o]];
-                    const int ax = a.independent ? (lx != 0) : (g0x + lx != 0);
-                    const long long pv =
-                        predict<D, HP>(nv, amask_zy | ax, net, wt, b2, alpha) - ((long long)code - kR);
+                    const long long pv = pred - ((long long)code - kR);
                     if (!(pv > -(long long)kGridLimit && pv < (long long)kGridLimit)) {
                         err = kECorrupt;
                         p = 0;
@@ -225,22 +242,24 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int D, int BB, int HP>
+template <typename T, int D, int BB, int HP, int PREC>
 static void go(const DecodeArgs &a, unsigned grid, unsigned nt, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_decode<T, D, BB, HP>), dim3(grid), dim3(nt), lds, s, a);
+    hipLaunchKernelGGL((k_decode<T, D, BB, HP, PREC>), dim3(grid), dim3(nt), lds, s, a);
 }
 
 template <typename T, int D, int BB>
 static void by_hidden(int HP, const DecodeArgs &a, unsigned grid, unsigned nt, size_t lds,
                       hipStream_t s)
 {
-    if (HP == 8)
-        go<T, D, BB, 8>(a, grid, nt, lds, s);
+    if (HP == 0)
+        go<T, D, BB, 8, 1>(a, grid, nt, lds, s);  // matrix-core network (Lorenzo blocks: HP 8)
+    else if (HP == 8)
+        go<T, D, BB, 8, 0>(a, grid, nt, lds, s);
     else if (HP == 16)
-        go<T, D, BB, 16>(a, grid, nt, lds, s);
+        go<T, D, BB, 16, 0>(a, grid, nt, lds, s);
     else
-        go<T, D, BB, 32>(a, grid, nt, lds, s);
+        go<T, D, BB, 32, 0>(a, grid, nt, lds, s);
 }
 
 template <typename T>
@@ -295,7 +314,8 @@ hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *mod
     a.status = ws.status;
     a.c = c;
     a.mlp = pack_mlp(a.use_net ? model : nullptr);
-    const int HP = hidden_pad(a.use_net ? model : nullptr);
+    const bool mfma = a.use_net && model && model->precision == 1;
+    const int HP = mfma ? 0 : hidden_pad(a.use_net ? model : nullptr);
     const int h0 = g.D >= 3 ? 1 : 0, h1 = g.D >= 2 ? 1 : 0;
     const size_t ne = (size_t)(g.bd[0] + h0) * (g.bd[1] + h1) * (g.bd[2] + 1);
     const size_t bv = (size_t)g.bd[0] * g.bd[1] * g.bd[2];

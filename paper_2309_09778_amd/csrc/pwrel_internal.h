@@ -44,7 +44,10 @@ struct Workspace {
     size_t offsets_cap = 0, partials_cap = 0;
     int *pgrid = nullptr;  // decoder grid-value scratch (N int32)
     size_t pgrid_cap = 0;
+    long long *qtab = nullptr;  // rint(2^32 log2 c), c = 0 .. kQtab - 1 (judge scores)
 };
+
+constexpr int kQtab = 4097;
 
 constexpr int kScanChunk = 4096;
 

@@ -140,7 +140,7 @@ template <int D, int BB> struct ShapeOf {
         static constexpr bool known = true;                                                   \
         static constexpr int T0 = A, T1 = Bv, T2 = Cv;                                        \
     };
-PWREL_SHAPE(3, 4, 8, 8, 64)
+PWREL_SHAPE(3, 4, 8, 8, 32)
 PWREL_SHAPE(3, 8, 8, 8, 64)
 PWREL_SHAPE(3, 16, 16, 16, 32)
 PWREL_SHAPE(2, 16, 1, 16, 128)
@@ -155,7 +155,7 @@ inline bool known_shape(int D, int B, int *t)
     struct E {
         int D, B, t0, t1, t2;
     };
-    static const E tab[] = {{3, 4, 8, 8, 64},    {3, 8, 8, 8, 64},     {3, 16, 16, 16, 32},
+    static const E tab[] = {{3, 4, 8, 8, 32},    {3, 8, 8, 8, 64},     {3, 16, 16, 16, 32},
                             {2, 16, 1, 16, 128}, {2, 32, 1, 32, 128},  {2, 64, 1, 64, 64},
                             {1, 256, 1, 1, 4096}};
     for (const E &e : tab)

@@ -57,6 +57,27 @@ class Header(C.Structure):
                 ("pad0", C.c_int32)]
 
 
+MAX_CANDIDATES = 17
+
+
+class TrainOptions(C.Structure):
+    _fields_ = [("rho", C.c_double), ("seed", C.c_uint64), ("hidden", C.c_int32),
+                ("epochs", C.c_int32), ("batch", C.c_int32), ("n_lr", C.c_int32),
+                ("n_lambda", C.c_int32), ("independent_blocks", C.c_int32),
+                ("lr", C.c_double * 4), ("lambda_", C.c_double * 4), ("alpha", C.c_float),
+                ("precision", C.c_int32)]
+
+
+class TrainReport(C.Structure):
+    _fields_ = [("n_train", C.c_uint64), ("n_val", C.c_uint64), ("sigma", C.c_double),
+                ("chosen", C.c_int32), ("n_candidates", C.c_int32),
+                ("val_score", C.c_int64 * MAX_CANDIDATES), ("ms_sample", C.c_double),
+                ("ms_train", C.c_double), ("ms_select", C.c_double)]
+
+
+DEFAULT_LRS = (3e-2, 1e-2, 3e-3)
+DEFAULT_LAMBDAS = (0.0, 1e-5, 1e-4)
+
 # every symbol the header declares, with its signature
 _P = C.c_void_p
 _SIGS = {
@@ -81,6 +102,17 @@ _SIGS = {
     "pwrel_mlp_init": (C.c_int, [C.POINTER(Mlp), C.c_int, C.c_int, C.c_float, C.c_uint64]),
     "pwrel_set_profiling": (C.c_int, [_P, C.c_int]),
     "pwrel_phase_times": (C.c_int, [_P, _P, C.c_int]),
+    "pwrel_train": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
+                              C.POINTER(TrainOptions), C.POINTER(Mlp), C.POINTER(Mlp),
+                              C.POINTER(TrainReport), _P]),
+    "pwrel_sample": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                               C.c_double, C.c_uint64, _P, _P, _P, _P, C.c_uint64,
+                               C.POINTER(C.c_uint64), _P]),
+    "pwrel_loss_grad": (C.c_int, [_P, _P, C.c_int, C.c_int, C.c_float, _P, _P, C.c_uint64,
+                                  C.c_double, C.c_double, _P, C.POINTER(C.c_float), _P]),
+    "pwrel_train_pairs": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_float,
+                                    C.c_double, _P, C.c_int, _P, _P, C.c_int, C.c_int, _P,
+                                    _P]),
 }
 PHASES = ("stats+consts", "compress", "scan+scatter+header", "decode_scan", "decode_levels")
 
@@ -269,6 +301,91 @@ class Context:
                                       C.c_void_p(out.data_ptr()), _dims(shape), len(shape),
                                       _dtype_code(dtype), _stream(stream))
         self._check(st, "decompress")
+        return out
+
+    # learned part ------------------------------------------------------------
+    def train(self, x, eps, block=8, init=None, rho=0.01, seed=0, hidden=32, alpha=0.01,
+              epochs=1, batch=256, lrs=DEFAULT_LRS, lambdas=DEFAULT_LAMBDAS,
+              independent=False, precision=1, stream=None):
+        """Train a network on the field x (Sec. 4.3); returns (model, report dict)."""
+        assert x.is_cuda and x.is_contiguous()
+        o = TrainOptions()
+        o.rho, o.seed, o.hidden, o.epochs, o.batch = float(rho), int(seed), int(hidden), \
+            int(epochs), int(batch)
+        o.n_lr, o.n_lambda = len(lrs), len(lambdas)
+        for i, v in enumerate(lrs):
+            o.lr[i] = float(v)
+        for i, v in enumerate(lambdas):
+            o.lambda_[i] = float(v)
+        o.independent_blocks, o.alpha, o.precision = int(bool(independent)), float(alpha), \
+            int(precision)
+        m0 = model_struct(init) if init is not None else None
+        out = Mlp()
+        rep = TrainReport()
+        st = self._L.pwrel_train(self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(),
+                                 _dtype_code(x.dtype), float(eps), int(block), C.byref(o),
+                                 C.byref(m0) if m0 is not None else None, C.byref(out),
+                                 C.byref(rep), _stream(stream))
+        self._check(st, "train")
+        r = {"n_train": rep.n_train, "n_val": rep.n_val, "sigma": rep.sigma,
+             "chosen": rep.chosen, "n_candidates": rep.n_candidates,
+             "val_score": [rep.val_score[i] for i in range(rep.n_candidates)],
+             "ms_sample": rep.ms_sample, "ms_train": rep.ms_train,
+             "ms_select": rep.ms_select}
+        return model_dict(out), r
+
+    def sample(self, x, eps, block=8, independent=False, rho=0.01, seed=0, stream=None):
+        """Training/validation pairs of x in ascending point order:
+        (idx uint64, u int32 [n, K], t int32, isval uint8) as CUDA tensors."""
+        import torch
+        K = (1 << x.dim()) - 2
+        n = C.c_uint64(0)
+        args = (self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(), _dtype_code(x.dtype),
+                float(eps), int(block), int(bool(independent)), float(rho), int(seed))
+        st = self._L.pwrel_sample(*args, None, None, None, None, 0, C.byref(n),
+                                  _stream(stream))
+        self._check(st, "sample")
+        cnt = n.value
+        dev = x.device
+        idx = torch.empty(max(cnt, 1), dtype=torch.int64, device=dev)
+        u = torch.empty((max(cnt, 1), max(K, 1)), dtype=torch.int32, device=dev)
+        t = torch.empty(max(cnt, 1), dtype=torch.int32, device=dev)
+        iv = torch.empty(max(cnt, 1), dtype=torch.uint8, device=dev)
+        st = self._L.pwrel_sample(*args, C.c_void_p(idx.data_ptr()), C.c_void_p(u.data_ptr()),
+                                  C.c_void_p(t.data_ptr()), C.c_void_p(iv.data_ptr()), cnt,
+                                  C.byref(n), _stream(stream))
+        self._check(st, "sample")
+        return idx[:cnt], u[:cnt, :K], t[:cnt], iv[:cnt]
+
+    def loss_grad(self, theta, hidden, inputs, alpha, u, t, sigma, lam, stream=None):
+        """Loss and gradient (FP32) of scaled-domain parameters on pairs (u, t)."""
+        import torch
+        theta = theta.contiguous()
+        g = torch.empty_like(theta)
+        loss = C.c_float(0.0)
+        st = self._L.pwrel_loss_grad(self.h, C.c_void_p(theta.data_ptr()), int(hidden),
+                                     int(inputs), float(alpha), C.c_void_p(u.data_ptr()),
+                                     C.c_void_p(t.data_ptr()), t.numel(), float(sigma),
+                                     float(lam), C.c_void_p(g.data_ptr()), C.byref(loss),
+                                     _stream(stream))
+        self._check(st, "loss_grad")
+        return float(loss.value), g
+
+    def train_pairs(self, u, t, hidden, inputs, alpha, sigma, theta0, lrs, lambdas, batch=256,
+                    epochs=1, stream=None):
+        """Adam-train len(lrs) candidates from theta0 on pairs; returns [n_cand, P]."""
+        import torch
+        nc = len(lrs)
+        P = hidden * inputs + 2 * hidden + 1
+        out = torch.empty((nc, P), dtype=torch.float32, device=t.device)
+        lr = (C.c_double * nc)(*[float(v) for v in lrs])
+        lm = (C.c_double * nc)(*[float(v) for v in lambdas])
+        st = self._L.pwrel_train_pairs(self.h, C.c_void_p(u.data_ptr()), C.c_void_p(t.data_ptr()),
+                                       t.numel(), int(hidden), int(inputs), float(alpha),
+                                       float(sigma), C.c_void_p(theta0.data_ptr()), nc,
+                                       C.cast(lr, _P), C.cast(lm, _P), int(batch), int(epochs),
+                                       C.c_void_p(out.data_ptr()), _stream(stream))
+        self._check(st, "train_pairs")
         return out
 
     # inspection ----------------------------------------------------------------
