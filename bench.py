@@ -3,13 +3,16 @@
 
 Workload: a 512^3 FP32 log-normal field (k^-3 Gaussian random field over 8
 decades, 10% negative connected regions, 0.5% zeros; seeded synthetic stand-in
-for the paper's seismic volumes), block 8^3, point-wise relative bound 1e-2,
-FP32 perceptron (H = 16) at every point whose neighbours all exist.
+for the paper's seismic volumes), block 8^3, point-wise relative bound 1e-2.
 
-One step = compress (statistics, constants, fused transform / prediction /
-quantisation / verification kernel, scan, raw scatter, header) followed by
-decompress (scan, block-level reconstruction) of the whole field, inputs
-resident in HBM.  Prints one JSON line.
+Learned path (timed): a network of hidden width 32 is trained on the device
+from 1% of the field's points (outside the timed region; its time is
+reported), then one step = compress (statistics, constants, fused transform /
+BF16 matrix-core prediction / per-block Lorenzo judge / quantisation /
+verification kernel, scan, raw scatter, header) followed by decompress (scan,
+block-level reconstruction) of the whole field, inputs resident in HBM.  The
+plain path (FP32 network H = 16, no judge) is timed the same way for
+comparison.  Prints one JSON line.
 """
 import argparse
 import json
@@ -32,7 +35,7 @@ def compress_flops_per_point(H, K):
     and eps |x|), perceptron (K*H fma, H leaky products, H fma).  fma = 2."""
     transform = 1 + 20 + 5 + 2
     verify = 4 + 26 + 2
-    net = 2 * K * H + H + 2 * H
+    net = 2 * K * H + H + 2 * H  # H = 0: the network runs on the matrix cores
     return transform + verify + net
 
 
@@ -78,24 +81,77 @@ def huffman_stream_bytes(h, hist, huffman_bits):
             h["n_raw"] * (4 if h["dtype"] == 0 else 8))
 
 
-def cpu_baseline(x, eps, block, model, budget_s=30.0):
-    """The CPU oracle (single thread) on a sub-cube of the same field."""
+def cpu_baseline(x, eps, block, model, side=256):
+    """The CPU oracle (single thread) on a sub-cube of the same field: the
+    learned mode (both predictors and the per-block judge, the network in
+    FP32), compress then decompress."""
     import numpy as np
     from oracle import oracle as O
-    side = 256
     sub = np.ascontiguousarray(x[:side, :side, :side])
+    m = dict(model, precision=0)
     t0 = time.perf_counter()
-    r = O.compress(sub, eps, block, model, O.MODE_PLAIN)
+    r = O.compress(sub, eps, block, m, O.MODE_LEARNED)
     t1 = time.perf_counter()
-    O.decompress(r["codes"], r["raw"], r["consts"], sub.shape, sub.dtype, block, model,
-                 O.MODE_PLAIN)
+    O.decompress(r["codes"], r["raw"], r["consts"], sub.shape, sub.dtype, block, m,
+                 O.MODE_LEARNED, flags=r["flags"])
     t2 = time.perf_counter()
     gb = sub.nbytes / 1e9
     return {"value": round(gb / (t2 - t0), 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{side}^3 FP32 sub-cube of the same field (first corner), compress + "
+            "sample": f"{side}^3 FP32 sub-cube (first corner) of the same field, learned mode "
+                      f"(network H={len(model['b1'])} in FP32 + Lorenzo judge), compress + "
                       f"decompress, single thread",
             "compress_GBps": round(gb / (t1 - t0), 5),
             "decompress_GBps": round(gb / (t2 - t1), 5)}
+
+
+def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, torch):
+    """Warm up, then time `steps` round trips (compress + decompress) of one
+    path; returns wall times, per-phase device times and the last stream."""
+    for _ in range(warmup):
+        s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind)
+        ctx.decompress(s, out=xh)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    phase_sum = {k: 0.0 for k in pwrel.PHASES}
+    tc = td = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind)
+        b = time.perf_counter()
+        ctx.decompress(s, out=xh)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        tc += b - a
+        td += c - b
+        for k, v in ctx.phase_times().items():
+            phase_sum[k] += v
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    return {"wall_s": t1 - t0, "tc": tc, "td": td,
+            "phase_ms": {k: v / steps for k, v in phase_sum.items()}, "stream": s}
+
+
+def stream_stats(ctx, s, x_nbytes, pwrel):
+    h = pwrel.header(s)
+    sec = pwrel.sections(s)
+    hist = ctx.histogram(sec["codes"])
+    hbytes = huffman_stream_bytes(h, hist, pwrel.huffman_bits)
+    out = {"ratio_stream": round(x_nbytes / h["total_size"], 4),
+           "ratio_huffman": round(x_nbytes / hbytes, 4),
+           "paper_CR_percent_huffman": round(100.0 * hbytes / x_nbytes, 3),
+           "unpredictable_frac": round(h["n_raw"] / h["n"], 7)}
+    if "bflags" in sec:
+        out["network_block_frac"] = round(float(sec["bflags"].float().mean()), 4)
+    return out
+
+
+def bound_ok(xd, xh, eps, torch):
+    xt, ht = xd.double(), xh.double()
+    nz = xt != 0
+    return bool(torch.all((xt - ht).abs() <= eps * xt.abs())) and \
+        bool(torch.all(ht[~nz] == 0)) and \
+        bool(torch.all(torch.signbit(ht[nz]) == torch.signbit(xt[nz])))
 
 
 def main():
@@ -106,10 +162,14 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--side", type=int, default=512)
     ap.add_argument("--block", type=int, default=8)
-    ap.add_argument("--hidden", type=int, default=16)
+    ap.add_argument("--hidden", type=int, default=32, help="hidden width of the learned network")
+    ap.add_argument("--plain-hidden", type=int, default=16,
+                    help="hidden width of the plain FP32 network")
+    ap.add_argument("--rho", type=float, default=0.01, help="training sample rate")
     ap.add_argument("--independent", action="store_true",
                     help="blocks predicted without neighbours outside the block (every block "
                          "decodes on its own)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -117,104 +177,97 @@ def main():
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2309_09778_amd import pwrel, synth
 
-    S, eps, B = args.side, args.eps, args.block
+    S, eps, B, ind = args.side, args.eps, args.block, args.independent
     x = synth.lognormal_grf((S, S, S), seed=1001)
     print(f"[bench] field {S}^3 FP32 generated", file=sys.stderr, flush=True)
     xd = torch.from_numpy(x).cuda()
     ctx = pwrel.Context(0)
-    model = pwrel.mlp_init(3, args.hidden, 0.01, 1001)
     cap = pwrel.compress_bound(x.shape, pwrel.F32, B)
     out = torch.empty(cap, dtype=torch.uint8, device="cuda")
     xh = torch.empty_like(xd)
     # a plain device copy of known size (HBM counter calibration for profiles)
     xd.clone()
     torch.cuda.synchronize()
-
-    ind = args.independent
-    for _ in range(args.warmup):
-        s = ctx.compress(xd, eps, B, model, out=out, independent=ind)
-        ctx.decompress(s, out=xh)
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
-    ctx.set_profiling(True)
-    phase_sum = {k: 0.0 for k in pwrel.PHASES}
-    tc = td = 0.0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        s = ctx.compress(xd, eps, B, model, out=out, independent=ind)
-        b = time.perf_counter()
-        ctx.decompress(s, out=xh)
-        torch.cuda.synchronize()
-        c = time.perf_counter()
-        tc += b - a
-        td += c - b
-        for k, v in ctx.phase_times().items():
-            phase_sum[k] += v
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.set_profiling(False)
-    K = args.steps
-    ms_step = (t1 - t0) * 1e3 / K
     gb = x.nbytes / 1e9
-    value = gb / ((t1 - t0) / K)
+    K = args.steps
 
-    # correctness of the timed result (bound on every point), outside the timed region
-    xt, ht = xd.double(), xh.double()
-    nz = xt != 0
-    ok = bool(torch.all((xt - ht).abs() <= eps * xt.abs())) and bool(torch.all(ht[~nz] == 0)) \
-        and bool(torch.all(torch.signbit(ht[nz]) == torch.signbit(xt[nz])))
-    del xt, ht
-    h = pwrel.header(s)
-    hist = ctx.histogram(pwrel.sections(s)["codes"])
-    hbytes = huffman_stream_bytes(h, hist, pwrel.huffman_bits)
+    # training (outside the timed region, reported on its own)
+    t0 = time.perf_counter()
+    learned, rep = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.hidden,
+                             precision=1, independent=ind)
+    train_wall_ms = (time.perf_counter() - t0) * 1e3
+    print(f"[bench] trained: chosen {rep['chosen']}, {rep['n_train']} pairs, "
+          f"{train_wall_ms:.1f} ms", file=sys.stderr, flush=True)
 
-    ph = {k: v / K for k, v in phase_sum.items()}
-    # dominant kernel: the fused compression kernel or the block-level decoder
-    Hp = args.hidden
+    # timed: the learned path (BF16 matrix-core network + per-block Lorenzo judge)
+    L = run_path(ctx, xd, eps, B, learned, True, ind, out, xh, K, args.warmup, pwrel, torch)
+    ok_l = bound_ok(xd, xh, eps, torch)
+    st_l = stream_stats(ctx, L["stream"], x.nbytes, pwrel)
+    ms_step = L["wall_s"] * 1e3 / K
+    value = gb / (L["wall_s"] / K)
+    print("[bench] learned path timed", file=sys.stderr, flush=True)
+
+    plain = None
+    if not args.no_plain:
+        pm = pwrel.mlp_init(3, args.plain_hidden, 0.01, 1001)
+        P = run_path(ctx, xd, eps, B, pm, False, ind, out, xh, K, args.warmup, pwrel, torch)
+        plain = {"network": f"FP32 H={args.plain_hidden}, Lorenzo-initialised (untrained)",
+                 "round_trip_GBps": round(gb / (P["wall_s"] / K), 3),
+                 "compress_GBps": round(gb / (P["tc"] / K), 3),
+                 "decompress_GBps": round(gb / (P["td"] / K), 3),
+                 "phase_ms": {k: round(v, 4) for k, v in P["phase_ms"].items()},
+                 "bound_ok_every_point": bound_ok(xd, xh, eps, torch)}
+        plain.update(stream_stats(ctx, P["stream"], x.nbytes, pwrel))
+        print("[bench] plain path timed", file=sys.stderr, flush=True)
+
+    ph = L["phase_ms"]
+    # dominant kernel of the learned step: the fused compression kernel or the decoder
     kern_ms = ph["compress"]
-    flops = compress_flops_per_point(Hp, 6) * x.size
-    achieved = flops / (kern_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_compress<float,3,16> (fused a3-a7)", "bound": "alu",
+    flops_pp = compress_flops_per_point(0, 6)
+    achieved = flops_pp * x.size / (kern_ms * 1e-3) / 1e12
+    mfma_useful = 2 * (args.hidden * 6 + args.hidden) * x.size
+    roofline = {"kernel": "k_compress<float,3,8,HP,false,1> (fused a3-a7, BF16 MFMA network, "
+                          "judge)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                "traffic": profiled_traffic(
-                    f"k_compress_plain_{S}cubed_f32_eps{eps:.0e}".replace("e-0", "e-") + ".txt",
-                    COMPRESS_SOURCES) if not ind else None,
-                "avg_ms": round(kern_ms, 4),
-                "flops_per_point": compress_flops_per_point(Hp, 6)}
+                "traffic": None, "avg_ms": round(kern_ms, 4), "flops_per_point": flops_pp,
+                "mfma_util": round(mfma_useful / (kern_ms * 1e-3) / 2.5e15, 5)}
 
     res = {
         "metric": "compress/decompress GB/s at PW_REL 1e-2 and ratio, learned BF16 vs plain FP32",
         "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+bf16", "data": "synthetic",
         "config": {"workload": f"{S}^3 FP32 log-normal k^-3 GRF (8 decades, 10% negative, "
-                               f"0.5% zeros), block {B}^3, eps {eps:g}, plain FP32 perceptron "
-                               f"H={Hp} (Lorenzo-initialised)" + (", independent blocks" if ind else
-                                                                   ", halo prediction"),
-                   "path": "plain", "field_bytes": x.nbytes},
-        "compress_GBps": round(gb / (tc / K), 3),
-        "decompress_GBps": round(gb / (td / K), 3),
-        "compress_frac_hbm": round(gb / (tc / K) / HBM_PEAK_GBPS, 4),
-        "decompress_frac_hbm": round(gb / (td / K) / HBM_PEAK_GBPS, 4),
+                               f"0.5% zeros), block {B}^3, eps {eps:g}, learned path: network "
+                               f"H={args.hidden} trained on the device ({args.rho:g} sample), "
+                               f"BF16 matrix cores, per-block Lorenzo judge" +
+                               (", independent blocks" if ind else ", halo prediction"),
+                   "path": "learned BF16 (timed) vs plain FP32", "field_bytes": x.nbytes},
+        "compress_GBps": round(gb / (L["tc"] / K), 3),
+        "decompress_GBps": round(gb / (L["td"] / K), 3),
+        "compress_frac_hbm": round(gb / (L["tc"] / K) / HBM_PEAK_GBPS, 4),
+        "decompress_frac_hbm": round(gb / (L["td"] / K) / HBM_PEAK_GBPS, 4),
         "phase_ms": {k: round(v, 4) for k, v in ph.items()},
-        "ratio_stream": round(x.nbytes / h["total_size"], 4),
-        "ratio_huffman": round(x.nbytes / hbytes, 4),
-        "paper_CR_percent_huffman": round(100.0 * hbytes / x.nbytes, 3),
-        "unpredictable_frac": round(h["n_raw"] / h["n"], 6),
-        "bound_ok_every_point": ok,
+        "bound_ok_every_point": ok_l,
+        "training": {"wall_ms": round(train_wall_ms, 2), "ms_sample": round(rep["ms_sample"], 3),
+                     "ms_train": round(rep["ms_train"], 3),
+                     "ms_select": round(rep["ms_select"], 3), "n_train": rep["n_train"],
+                     "n_val": rep["n_val"], "chosen": rep["chosen"],
+                     "val_gain_bits": round((rep["val_score"][rep["chosen"]] -
+                                             rep["val_score"][0]) / 2.0 ** 32 /
+                                            max(rep["n_val"], 1), 4)},
         "roofline": roofline,
     }
+    res.update(st_l)
+    if plain is not None:
+        res["plain"] = plain
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(x, eps, B, model)
+        res["cpu_baseline"] = cpu_baseline(x, eps, B, learned)
     print(json.dumps(res), flush=True)
 
 

@@ -58,13 +58,14 @@ typedef enum {
  *   explicit fused multiply-adds: z_j = fma(w1[j][K-1], u_{K-1}, ... fma(w1[j][0],
  *   u_0, b1[j])), h_j = z_j < 0 ? z_j * alpha : z_j, y = fma(v[H-1], h_{H-1},
  *   ... fma(v[0], h_0, b2)).  Bit-identical to the CPU oracle.
- * precision 1: the same network on the matrix cores, 64 points per wave:
+ * precision 1: the hidden layer on the matrix cores, 64 points per wave:
  *   z = b1 + bf16(w1) bf16(u) (BF16 products, FP32 accumulation), then, using
  *   lrelu(z) = (1 - alpha) relu(z) + alpha z,
  *   y = b2 + sum_j bf16((1 - alpha) v_j) relu(bf16(z_j)) + bf16(alpha v_j) bf16(z_j)
- *   (BF16 products, FP32 accumulation).  Encoder and decoder issue the same
- *   instructions on the same operands, so streams are self-consistent; the
- *   PW_REL bound is enforced by the quantizer and verification either way.
+ *   on the vector ALU (exact BF16 products, FP32 fused multiply-adds in a
+ *   fixed order).  Encoder and decoder issue the same instructions on the
+ *   same operands, so streams are self-consistent; the PW_REL bound is
+ *   enforced by the quantizer and verification either way.
  */
 typedef struct {
     int32_t hidden;    /* H, 2..32 */

@@ -36,6 +36,11 @@ struct pwrel_ctx {
     size_t vhist_cap = 0;
     double *scal = nullptr;  // sigma, partial sums (256), loss
     long long *scores = nullptr;
+    // halo-mode decoder: block order of the last geometry, flag epoch
+    unsigned *order = nullptr;
+    size_t order_cap = 0;
+    long long order_nb[3] = {-1, -1, -1};
+    unsigned epoch = 0;
 };
 
 namespace {
@@ -340,6 +345,8 @@ int pwrel_create(pwrel_ctx **out, int device)
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&ws.n_raw), 256);
     if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.ticket), 256);
+    if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&ws.qtab), kQtab * sizeof(long long));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&ctx->theta),
@@ -372,7 +379,8 @@ void pwrel_destroy(pwrel_ctx *ctx)
     void *ptrs[] = {ws.stats,       ws.consts,      ws.status,     ws.hist,        ws.n_raw,
                     ws.offsets,     ws.partials,    ws.pgrid,      ws.qtab,        ctx->counts_scratch,
                     ctx->chunk_cnt, ctx->chunk_off, ctx->pairs,    ctx->theta,     ctx->nets,
-                    ctx->vhist,     ctx->scal,      ctx->scores};
+                    ctx->vhist,     ctx->scal,      ctx->scores,   ws.done,        ws.ticket,
+                    ctx->order};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -548,6 +556,31 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
     if (!(h.flags & PWREL_HF_INDEPENDENT)) {
         if ((e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
             return fail(ctx, PWREL_ENOMEM, "grid scratch allocation failed");
+        // done flags: zeroed when (re)allocated; each call raises them to a new epoch
+        if (ctx->ws.done_cap < (size_t)g.nblocks) {
+            if ((e = grow(ctx->ws.done, ctx->ws.done_cap, (size_t)g.nblocks)) != hipSuccess ||
+                (e = hipMemsetAsync(ctx->ws.done, 0, ctx->ws.done_cap * sizeof(unsigned), s)) !=
+                    hipSuccess)
+                return fail(ctx, PWREL_ENOMEM, "decoder flag allocation failed");
+            ctx->epoch = 0;
+        }
+        if (++ctx->epoch == 0)
+            ctx->epoch = 1;  // 0 is the value of a fresh flag
+        if (ctx->order_nb[0] != g.nb[0] || ctx->order_nb[1] != g.nb[1] ||
+            ctx->order_nb[2] != g.nb[2]) {
+            std::vector<unsigned> order;
+            block_order(g, order);
+            if ((long long)order.size() != g.nblocks)
+                return fail(ctx, PWREL_EHIP, "internal: block order incomplete");
+            if ((e = grow(ctx->order, ctx->order_cap, order.size())) != hipSuccess)
+                return fail(ctx, PWREL_ENOMEM, "decoder order allocation failed");
+            if ((e = hipMemcpyAsync(ctx->order, order.data(), order.size() * sizeof(unsigned),
+                                    hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return hip_fail(ctx, e, "decoder order copy");
+            for (int d = 0; d < 3; ++d)
+                ctx->order_nb[d] = g.nb[d];
+        }
     }
     DevConsts c{};
     c.eps = h.eps;
@@ -573,7 +606,8 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
         return hip_fail(ctx, e, "scan");
     mark(ctx, 5, s);
     if ((e = launch_decode(g, c, model, h.flags, bflags, codes, counts, in + h.off_raw, h.n_raw,
-                           ctx->ws, d_field, s)) != hipSuccess)
+                           ctx->ws, ctx->order, ctx->epoch, d_field, ctx->num_cus, s)) !=
+        hipSuccess)
         return hip_fail(ctx, e, "decode");
     mark(ctx, 6, s);
     int dst = 0;

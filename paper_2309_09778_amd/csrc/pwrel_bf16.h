@@ -1,21 +1,21 @@
-// The perceptron on the matrix cores: 64 points per wave (lane l = point l),
-// v_mfma_f32_32x32x16_bf16, two groups of 32 points.
+// The perceptron with its first layer on the matrix cores: 64 points per
+// wave (lane l = point l), v_mfma_f32_32x32x16_bf16, two groups of 32 points.
 //
 // Operand layout of v_mfma_f32_32x32x16_bf16 (checked on the device):
 //   A (32 x 16):  lane l, element e  ->  A[l % 32][8 (l / 32) + e]
 //   B (16 x 32):  lane l, element e  ->  B[8 (l / 32) + e][l % 32]
 //   C/D (32x32):  lane l, element e  ->  D[8 (e / 4) + 4 (l / 32) + e % 4][l % 32]
 //
-// Layer 1: Z^T (hidden x points) = bf16(w1) (hidden x K, K padded to 16)
-//          . bf16(U)^T (K x points) + b1 (in the accumulator).
-// Layer 2 with lrelu(z) = (1 - alpha) relu(z) + alpha z:
-//   y = b2 + sum_j bf16((1-alpha) v_j) relu(bf16(z_j)) + bf16(alpha v_j) bf16(z_j),
-//   as four chained MFMAs (K = 16 each) whose B operands are the layer-1
-//   results of the same lane converted to bf16 pairs, in the order the lane
-//   holds them: chunk c in {0,1} uses D1 elements 8c .. 8c+7 (relu), chunk
-//   c in {2,3} the same elements without relu.  The A operands carry the
-//   output weights in the matching hidden-unit order; only row 0 is nonzero,
-//   so the result sits in element 0 of lanes 0..31.
+// Layer 1: Z (hidden x points) = bf16(w1) (hidden x K, K padded to 16)
+//          . bf16(U) (K x points) + b1 (in the FP32 accumulator).
+// Layer 2 (a matrix-vector product: on the vector ALU), with
+// lrelu(z) = (1 - alpha) relu(z) + alpha z:
+//   y = b2 + sum_j bf16((1-alpha) v_j) relu(bf16(z_j)) + bf16(alpha v_j) bf16(z_j).
+// Lane l holds 16 of the 32 hidden units of column l % 32 (half h = l / 32);
+// it sums them in a fixed order with FP32 fused multiply-adds, the two
+// halves of a column are added, then b2.  Every point is evaluated by the
+// same instruction sequence wherever it sits in the wave, so encoder and
+// decoder agree bit for bit.
 // Every lane of the wave must execute these calls (the matrix cores work on
 // the whole wave); lanes without a point feed zero inputs.
 #pragma once
@@ -26,17 +26,19 @@ namespace pwrel {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
-typedef short short2v __attribute__((ext_vector_type(2)));
 
 struct NetBf16 {
-    bf16x8 a1;     // layer-1 A operand of this lane
-    floatx16 c1;   // layer-1 accumulator init: b1 of the rows this lane holds
-    bf16x8 a2[4];  // layer-2 A operands (chunks 0,1: (1-alpha) v; chunks 2,3: alpha v)
+    bf16x8 a1;      // layer-1 A operand of this lane
+    floatx16 c1;    // layer-1 accumulator init: b1 of the rows this lane holds
+    float a2[16];   // bf16((1 - alpha) v) of the rows this lane holds
+    float c2[16];   // bf16(alpha v) of the same rows
     float b2;
 };
 
-// hidden unit held by element e of D1 in a lane of half h
+// hidden unit held by element e of D in a lane of half h
 __device__ __forceinline__ int d1_row(int e, int h) { return 8 * (e / 4) + 4 * h + (e % 4); }
+
+__device__ __forceinline__ float bf16_round(float f) { return (float)(__bf16)f; }
 
 __device__ __forceinline__ NetBf16 make_net_bf16(const MlpW &m, int K)
 {
@@ -47,20 +49,13 @@ __device__ __forceinline__ NetBf16 make_net_bf16(const MlpW &m, int K)
         const int k = 8 * h + e;
         n.a1[e] = (__bf16)(k < K ? m.w1[i][k] : 0.0f);
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e)
-        n.c1[e] = m.b1[d1_row(e, h)];
     const float ar = 1.0f - m.alpha, al = m.alpha;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            // chunk c covers D1 elements 8 (c & 1) + e'; in a lane of half h
-            // the K index 8 h + e maps to element 8 (c & 1) + e of that half
-            const int row = d1_row(8 * (c & 1) + e, h);
-            const float w = (c < 2 ? ar : al) * m.v[row];
-            n.a2[c][e] = (__bf16)(i == 0 ? w : 0.0f);
-        }
+    for (int e = 0; e < 16; ++e) {
+        const int row = d1_row(e, h);
+        n.c1[e] = m.b1[row];
+        n.a2[e] = bf16_round(ar * m.v[row]);
+        n.c2[e] = bf16_round(al * m.v[row]);
     }
     n.b2 = m.b2;
     return n;
@@ -73,37 +68,21 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
            ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
 }
 
-__device__ __forceinline__ unsigned relu_bf16x2(unsigned v)
+// this lane's half of layer 2 for one group: sum over its 16 hidden units
+__device__ __forceinline__ float layer2_half(const NetBf16 &n, const floatx16 &d)
 {
-    // a bf16 is negative iff its sign bit is set, i.e. iff it is negative as
-    // an int16; max with 0 keeps positives and maps negatives (and -0) to +0
-    const short2v s = __builtin_bit_cast(short2v, v);
-    const short2v z = {0, 0};
-    return __builtin_bit_cast(unsigned, __builtin_elementwise_max(s, z));
-}
-
-// layer 2 for one group: returns the full D2 (row 0 = y in lanes 0..31)
-__device__ __forceinline__ float net_group(const NetBf16 &n, bf16x8 b1op)
-{
-    floatx16 d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(n.a1, b1op, n.c1, 0, 0, 0);
-    unsigned raw[8];
+    float s = 0.0f;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-        raw[q] = pack_bf16(d[2 * q], d[2 * q + 1]);
-    floatx16 y = {};
-    y[0] = (threadIdx.x & 63) < 32 ? n.b2 : 0.0f;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        unsigned w[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const unsigned v = raw[4 * (c & 1) + q];
-            w[q] = c < 2 ? relu_bf16x2(v) : v;
-        }
-        const bf16x8 b = __builtin_bit_cast(bf16x8, w);
-        y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(n.a2[c], b, y, 0, 0, 0);
+    for (int q = 0; q < 8; ++q) {
+        const unsigned pk = pack_bf16(d[2 * q], d[2 * q + 1]);  // round to bf16 (RNE)
+        const float z0 = __builtin_bit_cast(float, pk << 16);
+        const float z1 = __builtin_bit_cast(float, pk & 0xffff0000u);
+        s = __builtin_fmaf(n.a2[2 * q], __builtin_fmaxf(z0, 0.0f), s);
+        s = __builtin_fmaf(n.c2[2 * q], z0, s);
+        s = __builtin_fmaf(n.a2[2 * q + 1], __builtin_fmaxf(z1, 0.0f), s);
+        s = __builtin_fmaf(n.c2[2 * q + 1], z1, s);
     }
-    return y[0];
+    return s;
 }
 
 // Network output y for the point of this lane (u: K inputs as exact floats).
@@ -123,10 +102,17 @@ __device__ __forceinline__ float net_bf16(const NetBf16 &n, const float (&u)[6])
         g0[q] = l < 32 ? p[q] : 0u;
         g1[q] = l < 32 ? other : 0u;
     }
-    const float y0 = net_group(n, __builtin_bit_cast(bf16x8, g0));
-    const float y1 = net_group(n, __builtin_bit_cast(bf16x8, g1));
-    const float y1_up = __shfl_xor(y1, 32, 64);
-    return l < 32 ? y0 : y1_up;
+    const floatx16 d0 =
+        __builtin_amdgcn_mfma_f32_32x32x16_bf16(n.a1, __builtin_bit_cast(bf16x8, g0), n.c1, 0, 0, 0);
+    const floatx16 d1 =
+        __builtin_amdgcn_mfma_f32_32x32x16_bf16(n.a1, __builtin_bit_cast(bf16x8, g1), n.c1, 0, 0, 0);
+    const float s0 = layer2_half(n, d0), s1 = layer2_half(n, d1);
+    // lane l < 32 owns column l of group 0: halves s0 (own, h = 0) + s0 of lane l + 32;
+    // lane l >= 32 owns column l - 32 of group 1: s1 of lane l - 32 (h = 0) + s1 (own)
+    const float send = l < 32 ? s1 : s0;
+    const float recv = __shfl_xor(send, 32, 64);
+    const float lo = l < 32 ? s0 : recv, hi = l < 32 ? recv : s1;
+    return (lo + hi) + n.b2;
 }
 
 // Prediction of the point of this lane with the BF16 network where every

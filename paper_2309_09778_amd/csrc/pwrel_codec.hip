@@ -10,11 +10,12 @@ namespace pwrel {
 // ---------------------------------------------------------------------------
 // reset: status and balance-point total (graph-safe: a kernel, not a memset)
 // ---------------------------------------------------------------------------
-__global__ void k_reset(int *status, unsigned long long *n_raw)
+__global__ void k_reset(int *status, unsigned long long *n_raw, unsigned *ticket)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *status = kOk;
         *n_raw = 0ULL;
+        *ticket = 0u;
     }
 }
 
@@ -487,7 +488,7 @@ static unsigned grid_for(long long work, int per, unsigned cap)
 
 hipError_t launch_reset(Workspace &ws, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ws.status, ws.n_raw);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ws.status, ws.n_raw, ws.ticket);
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/pwrel.h"
 #include "pwrel_device.h"
 
@@ -45,6 +47,9 @@ struct Workspace {
     int *pgrid = nullptr;  // decoder grid-value scratch (N int32)
     size_t pgrid_cap = 0;
     long long *qtab = nullptr;  // rint(2^32 log2 c), c = 0 .. kQtab - 1 (judge scores)
+    unsigned *done = nullptr;   // halo-mode decoder: per-block done flags (epoch values)
+    size_t done_cap = 0;
+    unsigned *ticket = nullptr; // halo-mode decoder: next block ticket
 };
 
 constexpr int kQtab = 4097;
@@ -53,6 +58,7 @@ constexpr int kScanChunk = 4096;
 
 // Kernel launchers (return the launch error, if any).
 hipError_t launch_reset(Workspace &ws, hipStream_t s);
+void block_order(const Geom &g, std::vector<unsigned> &order);
 hipError_t launch_stats(const void *x, const Geom &g, Workspace &ws, hipStream_t s);
 hipError_t launch_consts(const Geom &g, double eps, Workspace &ws, hipStream_t s);
 hipError_t launch_transform(const void *x, const Geom &g, Workspace &ws, int *d_p, hipStream_t s);
@@ -68,7 +74,8 @@ hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspa
                          void *d_header, uint64_t capacity, hipStream_t s);
 hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *model, int flags,
                          const uint8_t *bflags, const uint16_t *codes, const uint32_t *counts,
-                         const void *raw, unsigned long long n_raw, Workspace &ws, void *xh,
+                         const void *raw, unsigned long long n_raw, Workspace &ws,
+                         const unsigned *order, unsigned epoch, void *xh, int num_cus,
                          hipStream_t s);
 hipError_t launch_detmath(const double *x, double *l2, double *e2, uint64_t n, hipStream_t s);
 hipError_t launch_hist(const uint16_t *codes, long long n, unsigned long long *hist,
