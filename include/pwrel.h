@@ -299,6 +299,22 @@ int pwrel_train_pairs(pwrel_ctx *ctx, const float *d_u, const float *d_t, uint64
                       const double *lr, const double *lambda, int batch, int epochs,
                       float *d_theta_out, void *stream);
 
+/*
+ * FP32 fields take fast paths for the transform and the bound check: the
+ * hardware log2 (v_log_f32 on the significand in [sqrt(1/2), sqrt(2)), plus
+ * the exponent) and exp2 (v_exp_f32 on the fraction of the exponent).  A fast
+ * result is used only where these bounds prove it equal to the FP64 result:
+ *   |fast_log2(a) - det_log2(a)| <= PWREL_FAST_LOG2_ERR  (every normal float a > 0)
+ *   |v_exp_f32(f) - 2^f| <= PWREL_FAST_EXP2_ERR * 2^f    (every float |f| <= 1/2)
+ * so the output is identical to the FP64 path's.  pwrel_fastmath_check
+ * measures both maxima on the device over every such input (a few ms) and
+ * writes them to the two host doubles; the bounds hold iff each is <= its
+ * constant.  Synchronizes the stream.
+ */
+#define PWREL_FAST_LOG2_ERR 0x1p-20
+#define PWREL_FAST_EXP2_ERR 0x1p-20
+int pwrel_fastmath_check(pwrel_ctx *ctx, double *log2_err, double *exp2_rel_err, void *stream);
+
 /* Network that reproduces Lorenzo exactly (end of Sec. 4.2). */
 int pwrel_mlp_init(pwrel_mlp *out, int ndim, int hidden, float alpha, uint64_t seed);
 

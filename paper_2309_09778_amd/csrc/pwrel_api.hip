@@ -734,6 +734,26 @@ int pwrel_detmath(pwrel_ctx *ctx, const double *d_x, double *d_log2, double *d_e
     return e == hipSuccess ? PWREL_OK : hip_fail(ctx, e, "detmath");
 }
 
+int pwrel_fastmath_check(pwrel_ctx *ctx, double *log2_err, double *exp2_rel_err, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!log2_err || !exp2_rel_err)
+        return fail(ctx, PWREL_EINVAL, "NULL output");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long bits[2] = {0, 0};
+    hipError_t e;
+    if ((e = launch_fastmath_check(ctx->ws.hist, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(bits, ctx->ws.hist, sizeof bits, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "fastmath_check");
+    std::memcpy(log2_err, &bits[0], sizeof(double));
+    std::memcpy(exp2_rel_err, &bits[1], sizeof(double));
+    return PWREL_OK;
+}
+
 int pwrel_set_profiling(pwrel_ctx *ctx, int enable)
 {
     if (!ctx)

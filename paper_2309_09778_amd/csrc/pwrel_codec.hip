@@ -200,6 +200,23 @@ __global__ void __launch_bounds__(256) k_consts(const DevStats *parts, int npart
             if (k.delta < 0)
                 k.delta = 0;
         }
+        // largest grid value any point can take: positive values end at
+        // b_sign, negative ones grow with |x| up to |x| = abs_max
+        if (err == kOk) {
+            long long qmax = k.b_sign;
+            if (a.nn) {
+                long long qn = (long long)__builtin_rint((det_log2(amax) + k.Ln) * k.r) + k.delta;
+                qn = qn < k.b_sign + 1 ? k.b_sign + 1 : qn;
+                qmax = qn > qmax ? qn : qmax;
+            }
+            k.w32 = (qmax - k.p_zero) < (1LL << 27) ? 1 : 0;
+        }
+        // fast-path margins: |t_fast - t| <= (err(log2) + 2^-52 (|log2 x| + |L| + 1))
+        // r + 2^-52 |t| with |log2 x| < 129 and |t| < 2^30, enlarged by 1/64
+        k.fm_p = ((kFastLog2Err + 0x1p-52 * (130.0 + __builtin_fabs(k.Lp))) * k.r + 0x1p-22) *
+                 (1.0 + 0x1p-6);
+        k.fm_n = ((kFastLog2Err + 0x1p-52 * (130.0 + __builtin_fabs(k.Ln))) * k.r + 0x1p-22) *
+                 (1.0 + 0x1p-6);
     }
     k.status = err;
     *c = k;
@@ -473,6 +490,53 @@ __global__ void k_detmath(const double *x, double *l2, double *e2, unsigned long
         e2[i] = det_exp2(v);
 }
 
+// ---------------------------------------------------------------------------
+// Exhaustive checks of the fast-path bounds: the largest |fast_log2(a) -
+// det_log2(a)| over every normal float a > 0, and the largest relative error
+// of v_exp_f32 over every float |f| <= 1/2 (reduced as ordered bit patterns
+// of non-negative doubles).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void max_bits(unsigned long long *dst, double v, unsigned long long *sh)
+{
+    // wave maximum, then one atomic per wave
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long ob = __shfl_xor(b, o, 64);
+        b = ob > b ? ob : b;
+    }
+    (void)sh;
+    if ((threadIdx.x & 63) == 0)
+        atomicMax(dst, b);
+}
+
+__global__ void __launch_bounds__(256) k_fm_log(unsigned long long *out)
+{
+    const unsigned lo = 0x00800000u, hi = 0x7f7fffffu;  // normal positive floats
+    double worst = 0.0;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+         i <= hi - lo; i += (unsigned long long)gridDim.x * blockDim.x) {
+        const float a = __uint_as_float(lo + (unsigned)i);
+        const double e = __builtin_fabs(fast_log2(a) - det_log2((double)a));
+        worst = e > worst ? e : worst;
+    }
+    max_bits(out, worst, nullptr);
+}
+
+__global__ void __launch_bounds__(256) k_fm_exp(unsigned long long *out)
+{
+    const unsigned hi = 0x3f000000u;  // |f| <= 0.5, both signs, subnormals included
+    double worst = 0.0;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+         i < 2ULL * (hi + 1ULL); i += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned mag = (unsigned)(i >> 1);
+        const float f = __uint_as_float(mag | ((unsigned)(i & 1) << 31));
+        const double ref = det_exp2((double)f);
+        const double e = __builtin_fabs((double)__builtin_amdgcn_exp2f(f) - ref) / ref;
+        worst = e > worst ? e : worst;
+    }
+    max_bits(out, worst, nullptr);
+}
+
 // ===========================================================================
 // launchers
 // ===========================================================================
@@ -621,6 +685,14 @@ hipError_t launch_hist(const uint16_t *codes, long long n, unsigned long long *h
     if (n > 0)
         hipLaunchKernelGGL(k_hist, dim3(grid_for(n, 256 * 64, 1024)), dim3(256), 0, s, codes, n,
                            hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_fastmath_check(unsigned long long *out2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out2, 2LL);
+    hipLaunchKernelGGL(k_fm_log, dim3(4096), dim3(256), 0, s, out2);
+    hipLaunchKernelGGL(k_fm_exp, dim3(4096), dim3(256), 0, s, out2 + 1);
     return hipGetLastError();
 }
 

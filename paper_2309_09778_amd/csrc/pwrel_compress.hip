@@ -1,16 +1,20 @@
 // Fused compression kernel (steps: transform, prediction, quantisation,
-// verification, per-block balance-point counts) for gfx950.
+// verification, per-block balance-point counts, per-block judge) for gfx950.
 //
-// A workgroup stages the grid values of a tile of whole blocks plus the
-// one-point halo on the low side of every active axis in LDS: first the tile
-// points (coalesced row loads of x, FP64 transform, FP64 verification of the
-// reconstruction), then the halo points (transform only).  It then walks the
-// tile in stream order (block-major, so a wave writes 64 consecutive codes),
-// predicting every point independently from its neighbours' grid values (the
-// data selection rule that removes the serial dependency), and counts the
-// balance points of each block in LDS.  Workgroups are persistent; the
-// workgroups of XCD x (= workgroup id mod 8) walk a contiguous eighth of the
-// tiles so that tiles sharing halo rows meet in the same L2.
+// A workgroup works on a tile of whole blocks plus the one-point halo on the
+// low side of every active axis (the "extended tile").  Its input values are
+// loaded into registers one tile ahead (coalesced rows), so the loads of the
+// next tile are in flight while the current one is predicted.  Grid values go
+// to LDS (FP32 fields: the hardware log2 / exp2 fast paths with certified
+// fallback to FP64); the tile points are bound-checked.  The tile is then
+// walked in stream order (block-major, so a wave writes 64 consecutive
+// codes), every point predicted independently from its neighbours' grid
+// values (the data selection rule that removes the serial dependency), and
+// the balance points of each block counted in LDS.  Workgroups are
+// persistent; those of XCD x (= workgroup id mod 8) walk a contiguous eighth
+// of the tiles so that tiles sharing halo rows meet in the same L2.
+#include <type_traits>
+
 #include "pwrel_bf16.h"
 
 namespace pwrel {
@@ -45,6 +49,29 @@ __device__ __forceinline__ int judge_bin(unsigned code)
     return e + 128;
 }
 
+__device__ __forceinline__ unsigned short code32(int e, bool ok)
+{
+    return (ok && e > -kR && e < kR) ? (unsigned short)(e + kR) : (unsigned short)0;
+}
+
+// Prediction errors e = prediction - p in 32-bit arithmetic, for fields whose
+// grid values span less than 2^27 (DevConsts::w32): then every neighbour
+// difference and every error below fits.  Same values as the 64-bit path.
+//   Lorenzo: with at least one axis available the coefficients of the
+//   available neighbours sum to 1, so e = sum c_o (n_o - p); with none, e = -p.
+template <int D>
+__device__ __forceinline__ int lorenzo_err32(const int (&nv)[8], int amask)
+{
+    if (amask == 0)
+        return -nv[0];
+    int s = 0;
+#pragma unroll
+    for (int o = 1; o < (1 << D); ++o)
+        if ((o & ~amask) == 0)
+            s += lorenzo_sign(o) * (nv[o] - nv[0]);
+    return s;
+}
+
 template <int D>
 __device__ __forceinline__ long long lorenzo_pred(const int (&nv)[8], int amask)
 {
@@ -54,6 +81,51 @@ __device__ __forceinline__ long long lorenzo_pred(const int (&nv)[8], int amask)
         if ((o & ~amask) == 0)
             s += (long long)lorenzo_sign(o) * (long long)nv[o];
     return s;
+}
+
+// network error in 32 bits: e = (n_1 - p) + rint(y), |rint(y)| <= 2^30
+__device__ __forceinline__ int net_err32(float y, const int (&nv)[8])
+{
+    if (y > 0x1p30f)
+        y = 0x1p30f;
+    if (!(y >= -0x1p30f))
+        y = -0x1p30f;
+    return (nv[1] - nv[0]) + (int)__builtin_rintf(y);
+}
+
+// FP32 network output (the evaluation order of predict<>)
+template <int D, int HP, class W>
+__device__ __forceinline__ float net_f32(const int (&nv)[8], const W &wt, float b2, float alpha)
+{
+    constexpr int K = (1 << D) - 2;
+    float u[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        u[k] = k < K ? (float)(nv[k + 2] - nv[1]) : 0.0f;
+    float y = b2;
+#pragma unroll 1
+    for (int j0 = 0; j0 < HP; j0 += 4) {
+#pragma unroll
+        for (int j = j0; j < j0 + 4; ++j) {
+            const float4 wa = wt.a(j), wb = wt.b(j);
+            const float w[6] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y};
+            float z = wb.z;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                z = __builtin_fmaf(w[k], u[k], z);
+            const float h = __builtin_fmaxf(z, z * alpha);
+            y = __builtin_fmaf(wb.w, h, y);
+        }
+    }
+    return y;
+}
+
+// s_waitcnt vmcnt(0): this wave's outstanding global loads and stores are done
+__device__ __forceinline__ void wait_vmem()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt = 0, expcnt and lgkmcnt not waited on
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 template <typename T, int D, int BB, int HP, bool FROM_P, int PREC>
@@ -75,14 +147,19 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
     const int nbt = nbt0 * nbt1 * nbt2;
     const int BV = bd0 * bd1 * bd2;
 
-    // judge only (first, so that the 64-bit scores are 8-byte aligned):
-    // per-block scores and code histograms (network count in the low 16 bits,
-    // Lorenzo count in the high 16 bits; bin 0 = balance points)
+    // LDS: [judge: per-block scores] [block stream starts] [block extents]
+    // [grid tile] [balance counts] [judge: per-block histograms] [bound bits]
+    // (the 64-bit arrays first for alignment)
     unsigned long long *jsum = reinterpret_cast<unsigned long long *>(smem);
-    int *ptile = reinterpret_cast<int *>(jsum + (a.judge ? 2 * nbt : 0));
+    long long *bst = reinterpret_cast<long long *>(jsum + (a.judge ? 2 * nbt : 0));
+    unsigned *bext = reinterpret_cast<unsigned *>(bst + nbt);
+    int *ptile = reinterpret_cast<int *>(bext + nbt);
     unsigned int *cnt = reinterpret_cast<unsigned int *>(ptile + ne);
+    using V = typename std::conditional<FROM_P, int, T>::type;
     unsigned int *jh = cnt + nbt;
-    unsigned char *okb = reinterpret_cast<unsigned char *>(jh + (a.judge ? nbt * 256 : 0));
+    // judge only: both bins of every tile point (bit 16 marks a point)
+    unsigned *jb = jh + (a.judge ? nbt * 256 : 0);
+    unsigned char *okb = reinterpret_cast<unsigned char *>(jb + (a.judge ? ntp : 0));
 
     __shared__ int s_status;
     __shared__ float4 wl[kWlds];
@@ -105,8 +182,8 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
     if (s_status != kOk)  // uniform: every thread reads the same shared value
         return;
     const DevConsts c = *a.consts;
-    const T *x = reinterpret_cast<const T *>(a.x);
     const long long n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const bool w32 = c.w32 != 0;
 
     // LDS offsets of the neighbours, o = 1 .. 2^D-1
     int noff[8];
@@ -120,119 +197,285 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
     const long long chunk = (a.ntiles + 7) / 8;
     const long long tend = std::min(a.ntiles, (long long)(xcd + 1) * chunk);
 
-    for (long long t = (long long)xcd * chunk + slot; t < tend; t += nslot) {
-        const long long tz = t / (a.nt[1] * a.nt[2]);
-        const long long ty = (t / a.nt[2]) % a.nt[1];
-        const long long tx = t % a.nt[2];
-        const long long g0z = tz * T0, g0y = ty * T1, g0x = tx * T2;
-
-        // --- tile points: grid value and verification ----------------------
-        for (int q = tid; q < ntp; q += NT) {
-            const int c2 = q % T2, c1 = (q / T2) % T1, c0 = q / (T1 * T2);
-            const long long gz = g0z + c0, gy = g0y + c1, gx = g0x + c2;
-            int p = 0;
-            unsigned char ok = 0;
-            if (gz < n0 && gy < n1 && gx < n2) {
-                const long long li = (gz * n1 + gy) * n2 + gx;
-                if (FROM_P) {
-                    p = a.pfield[li];
-                    ok = 1;
-                } else {
-                    const double xv = (double)x[li];
-                    p = grid_value(xv, c, err);
-                    ok = within_bound(xv, grid_inverse<T>(p, c), c.eps) ? 1 : 0;
-                }
+    // grid value (and bound check) of one point from its value
+    const V *src = FROM_P ? reinterpret_cast<const V *>(a.pfield) : reinterpret_cast<const V *>(a.x);
+    auto point = [&](V v, bool verify, int &p, unsigned char &ok) {
+        if constexpr (FROM_P) {
+            p = (int)v;
+            ok = 1;
+        } else if constexpr (std::is_same<T, float>::value) {
+            const float xf = (float)v;
+            if (!grid_value_fast(xf, c, p))
+                p = grid_value((double)xf, c, err);
+            if (verify) {
+                bool okv;
+                if (!within_bound_fast(xf, p, c, okv))
+                    okv = within_bound((double)xf, grid_inverse<T>(p, c), c.eps);
+                ok = okv ? 1 : 0;
             }
-            ptile[((c0 + h0) * E1 + (c1 + h1)) * E2 + (c2 + h2)] = p;
-            okb[q] = ok;
+        } else {
+            const double xv = (double)v;
+            p = grid_value(xv, c, err);
+            if (verify)
+                ok = within_bound(xv, grid_inverse<T>(p, c), c.eps) ? 1 : 0;
         }
-        // --- halo points (low faces): grid value only --------------------------
-        // enumeration: plane e0 = 0 (if the axis is active), then e1 = 0 rows,
-        // then e2 = 0 columns
-        const int nh0 = h0 ? E1 * E2 : 0;
-        const int nh1 = h1 ? T0 * E2 : 0;
-        const int nh2 = T0 * T1;
-        for (int hq = tid; hq < nh0 + nh1 + nh2; hq += NT) {
-            int e0, e1, e2;
-            if (hq < nh0) {
-                e0 = 0;
-                e1 = hq / E2;
-                e2 = hq - e1 * E2;
-            } else if (hq < nh0 + nh1) {
-                const int r = hq - nh0;
-                e0 = h0 + r / E2;
-                e1 = 0;
-                e2 = r - (r / E2) * E2;
-            } else {
-                const int r = hq - nh0 - nh1;
-                e0 = h0 + r / T1;
-                e1 = h1 + r % T1;
-                e2 = 0;
+    };
+
+    // The extended tile is E0 x E1 rows of E2 entries; entry (e0, e1, e2) is
+    // the point (z0 + e0 - h0, y0 + e1 - h1, x0 + e2 - h2).  Per tile: its
+    // origin, the linear index of entry (0, 0, 0), and the entry ranges that
+    // lie inside the field.
+    struct TileRef {
+        long long z0, y0, x0, base;
+        int lo0, hi0, lo1, hi1, lo2, hi2;
+    };
+    auto tile_ref = [&](long long t) {
+        TileRef r;
+        r.z0 = t / (a.nt[1] * a.nt[2]) * T0;
+        r.y0 = (t / a.nt[2]) % a.nt[1] * T1;
+        r.x0 = t % a.nt[2] * T2;
+        r.lo0 = (h0 && r.z0 == 0) ? 1 : 0;
+        r.lo1 = (h1 && r.y0 == 0) ? 1 : 0;
+        r.lo2 = r.x0 == 0 ? 1 : 0;
+        r.hi0 = (int)std::min((long long)E0, n0 - r.z0 + h0);
+        r.hi1 = (int)std::min((long long)E1, n1 - r.y0 + h1);
+        r.hi2 = (int)std::min((long long)E2, n2 - r.x0 + h2);
+        r.base = ((r.z0 - h0) * n1 + (r.y0 - h1)) * n2 + (r.x0 - h2);
+        return r;
+    };
+    auto row_base = [&](const TileRef &r, int row) {
+        const int e0 = row / E1, e1 = row - (row / E1) * E1;
+        return r.base + ((long long)e0 * n1 + e1) * n2;
+    };
+    auto row_in = [&](const TileRef &r, int row) {
+        const int e0 = row / E1, e1 = row - (row / E1) * E1;
+        return e0 >= r.lo0 && e0 < r.hi0 && e1 >= r.lo1 && e1 < r.hi1;
+    };
+    const int nrows = E0 * E1;
+
+    // Compile-time tiles of FP32 fields or grid input: the next tile's values
+    // are copied global -> LDS (no registers held) while the current tile is
+    // predicted, one row of the extended tile per wave instruction.  xs is an
+    // LDS object of its own, so no other LDS access can alias the copies.
+    constexpr bool PIPE = CT && (FROM_P || std::is_same<T, float>::value);
+    constexpr int NEX = CT ? (S::T0 + h0) * (S::T1 + h1) * (S::T2 + h2) : 1;
+    __shared__ unsigned xs[PIPE ? NEX : 1];
+    const unsigned *src32 = reinterpret_cast<const unsigned *>(src);
+    const int lane = tid & 63, wave = tid >> 6;
+    auto stage = [&](long long t) {
+        const TileRef r = tile_ref(t);
+        for (int row = wave; row < nrows; row += NT / 64) {
+            if (!row_in(r, row))
+                continue;  // uniform across the wave
+            const long long rb = row_base(r, row);
+            for (int c0 = 0; c0 < E2; c0 += 64) {
+                const int e2 = c0 + lane;
+                if (e2 >= r.lo2 && e2 < r.hi2)
+                    __builtin_amdgcn_global_load_lds(src32 + rb + e2, xs + row * E2 + c0, 4, 0,
+                                                     0);
             }
-            const long long gz = g0z + e0 - h0, gy = g0y + e1 - h1, gx = g0x + e2 - h2;
-            int p = 0;
-            if (gz >= 0 && gy >= 0 && gx >= 0 && gz < n0 && gy < n1 && gx < n2) {
-                const long long li = (gz * n1 + gy) * n2 + gx;
-                p = FROM_P ? a.pfield[li] : grid_value((double)x[li], c, err);
+        }
+    };
+
+    // prediction units: a segment of SEG consecutive points of one block row
+    const int SEG = CT ? (BB < 8 ? BB : 8) : (bd2 % 8 == 0 ? 8 : (bd2 % 4 == 0 ? 4 : 1));
+    const int nseg = bd2 / SEG;
+    const int nunits = nbt * bd0 * bd1 * nseg;
+    // transform items: a chunk of CL entries of one extended-tile row
+    constexpr int CL = 11;
+    const int nch = (E2 + CL - 1) / CL;
+
+    long long t = (long long)xcd * chunk + slot;
+    if constexpr (PIPE) {
+        if (t < tend)
+            stage(t);
+    }
+
+    for (; t < tend; t += nslot) {
+        const TileRef r = tile_ref(t);
+        const long long g0z = r.z0, g0y = r.y0, g0x = r.x0;
+        if constexpr (PIPE)
+            wait_vmem();  // this wave's copies have landed
+        __syncthreads();  // ... and every other wave's
+
+        // --- grid values of the extended tile; bound check of the tile points --
+        for (int it = tid; it < nrows * nch; it += NT) {
+            const int row = it / nch, ch = it - (it / nch) * nch;
+            const int e0 = row / E1, e1 = row - (row / E1) * E1;
+            const bool rin = row_in(r, row);
+            const bool rhalo = e0 < h0 || e1 < h1;
+            const long long rb = row_base(r, row);
+            const int okrow = ((e0 - h0) * T1 + (e1 - h1)) * T2 - h2;
+            const int cend = std::min(E2, ch * CL + CL);
+            for (int e2 = ch * CL; e2 < cend; ++e2) {
+                const bool in = rin && e2 >= r.lo2 && e2 < r.hi2;
+                const bool halo = rhalo || e2 < h2;
+                int p = 0;
+                unsigned char ok = 0;
+                if (in) {
+                    V v;
+                    if constexpr (PIPE)
+                        __builtin_memcpy(&v, &xs[row * E2 + e2], 4);
+                    else
+                        v = src[rb + e2];
+                    point(v, !halo, p, ok);
+                }
+                ptile[row * E2 + e2] = p;
+                if (!halo)
+                    okb[okrow + e2] = ok;
             }
-            ptile[(e0 * E1 + e1) * E2 + e2] = p;
+        }
+        // block stream starts and extents of the tile's blocks
+        const long long bz0 = g0z / bd0, by0 = g0y / bd1, bx0 = g0x / bd2;
+        for (int bt = tid; bt < nbt; bt += NT) {
+            const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
+            const long long bz = bz0 + btz, by = by0 + bty, bx = bx0 + btx;
+            if (bz < a.nb[0] && by < a.nb[1] && bx < a.nb[2]) {
+                const BlockGeo bg = block_geo3(bz, by, bx, a.n, bd0, bd1, bd2);
+                bst[bt] = bg.start;
+                bext[bt] = (unsigned)bg.ex | ((unsigned)bg.ey << 16);
+            }
         }
         __syncthreads();
 
-        // --- predict, quantize, count (stream order) -------------------------
-        // Rounds of NT points; every lane of a wave takes part in each round
-        // (the matrix-core network works on whole waves).
-        const long long bz0 = g0z / bd0, by0 = g0y / bd1, bx0 = g0x / bd2;
-        const int nq = nbt * BV;
-        for (int q0 = 0; q0 < nq; q0 += NT) {
-            const int q = q0 + tid;
-            const int qq = q < nq ? q : 0;
-            const int bt = qq / BV, li = qq - bt * BV;
+        // the next tile's copies are in flight during this tile's prediction
+        // (issued after the barrier: a barrier waits for outstanding copies)
+        if constexpr (PIPE) {
+            if (t + nslot < tend)
+                stage(t + nslot);
+        }
+
+        // --- predict, quantize, count --------------------------------------
+        // Unit u = ((bt * bd0 + lz) * bd1 + ly) * nseg + seg walks its segment
+        // along x; units in stream order, so a wave writes consecutive codes.
+        // The x - 1 neighbours come from the previous step of the same unit.
+        // Every lane of a wave runs the same number of steps (the matrix-core
+        // network works on whole waves).
+        const int limz = (int)std::min((long long)T0, n0 - g0z);
+        const int limy = (int)std::min((long long)T1, n1 - g0y);
+        const int limx = (int)std::min((long long)T2, n2 - g0x);
+        const int first = (g0x == 0 ? 1 : 0) | (D >= 2 && g0y == 0 ? 2 : 0) |
+                          (D >= 3 && g0z == 0 ? 4 : 0);  // axes that start at the field edge
+        const int edge = a.independent ? 7 : first;
+        constexpr int NO = (1 << D) - 1;
+        const int DZ = E1 * E2, DY = E2;
+#pragma unroll 1
+        for (int u0 = 0; u0 < nunits; u0 += NT) {
+            const int u = u0 + tid;
+            const int uu = u < nunits ? u : 0;
+            const int seg = uu % nseg, row = uu / nseg;
+            const int ly = row % bd1, lz = (row / bd1) % bd0, bt = row / (bd1 * bd0);
             const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
-            const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
-            const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
-            const long long gz = g0z + cz, gy = g0y + cy, gx = g0x + cx;
-            const bool inside = q < nq && gz < n0 && gy < n1 && gx < n2;
-            int nv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            int amask = 0;
-            if (inside) {
-                const int ei = ((cz + h0) * E1 + (cy + h1)) * E2 + (cx + h2);
-                nv[0] = ptile[ei];
-#pragma unroll
-                for (int o = 1; o < (1 << D); ++o)
-                    nv[o] = ptile[ei - noff[o]];
-                if (a.independent)
-                    amask = (lx != 0 ? 1 : 0) | (D >= 2 && ly != 0 ? 2 : 0) |
-                            (D >= 3 && lz != 0 ? 4 : 0);
-                else
-                    amask = (gx != 0 ? 1 : 0) | (D >= 2 && gy != 0 ? 2 : 0) |
-                            (D >= 3 && gz != 0 ? 4 : 0);
+            const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx0 = btx * bd2 + seg * SEG;
+            const bool urow = u < nunits && cz < limz && cy < limy;
+            // axes y, z available for this row (the x axis is decided per point)
+            const int pz = a.independent ? lz : cz, py = a.independent ? ly : cy;
+            const int amask_zy = (D >= 2 && (py != 0 || !(edge & 2)) ? 2 : 0) |
+                                 (D >= 3 && (pz != 0 || !(edge & 4)) ? 4 : 0);
+            const int eb = ((cz + h0) * E1 + (cy + h1)) * E2 + (cx0 + h2);  // entry of point 0
+            const int ex = (int)(bext[bt] & 0xffffu), ey = (int)(bext[bt] >> 16);
+            const long long pos0 = bst[bt] + (long long)((lz * ey + ly) * ex + seg * SEG);
+            const int okr = (cz * T1 + cy) * T2 + cx0;
+            // previous column (x - 1): own row, row y - 1, plane z - 1, both
+            int q0 = 0, q2 = 0, q4 = 0, q6 = 0;
+            if (urow) {
+                q0 = ptile[eb - 1];
+                if (D >= 2)
+                    q2 = ptile[eb - 1 - DY];
+                if (D >= 3) {
+                    q4 = ptile[eb - 1 - DZ];
+                    q6 = ptile[eb - 1 - DZ - DY];
+                }
             }
-            long long pred;
-            if constexpr (PREC == 1)
-                pred = predict_bf16<D>(nv, amask, a.use_net != 0 && inside, net16);
-            else
-                pred = inside ? predict<D, HP>(nv, amask, a.use_net != 0, WeightsLds{wl}, b2, alpha)
-                              : 0;
-            if (!inside)
-                continue;
-            const bool ok = okb[(cz * T1 + cy) * T2 + cx] != 0;
-            const unsigned short code = make_code(pred, nv[0], ok);
-            const BlockGeo bg = block_geo3(bz0 + btz, by0 + bty, bx0 + btx, a.n, bd0, bd1, bd2);
-            a.codes[bg.start + ((long long)lz * bg.ey + ly) * bg.ex + lx] = code;
+            unsigned nzero = 0;
+            for (int i = 0; i < SEG; ++i) {
+                const int cx = cx0 + i;
+                const bool inside = urow && cx < limx;
+                int nv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                int amask = 0;
+                int c0 = q0, c2 = q2, c4 = q4, c6 = q6;
+                if (inside) {
+                    const int ei = eb + i;
+                    c0 = ptile[ei];
+                    if (D >= 2)
+                        c2 = ptile[ei - DY];
+                    if (D >= 3) {
+                        c4 = ptile[ei - DZ];
+                        c6 = ptile[ei - DZ - DY];
+                    }
+                    nv[0] = c0;
+                    nv[1] = q0;
+                    nv[2] = c2;
+                    nv[3] = q2;
+                    nv[4] = c4;
+                    nv[5] = q4;
+                    nv[6] = c6;
+                    nv[7] = q6;
+                    const int px = a.independent ? seg * SEG + i : cx;
+                    amask = amask_zy | ((px != 0 || !(edge & 1)) ? 1 : 0);
+                }
+                q0 = c0;
+                q2 = c2;
+                q4 = c4;
+                q6 = c6;
+                const bool full = amask == NO;
+                const bool ok = inside && okb[okr + i] != 0;
+                unsigned short code;
+                if constexpr (PREC == 1) {
+                    const long long pred =
+                        predict_bf16<D>(nv, amask, a.use_net != 0 && inside, net16);
+                    code = make_code(pred, nv[0], ok);
+                } else {
+                    if (w32) {
+                        const int e =
+                            (a.use_net && full)
+                                ? net_err32(net_f32<D, HP>(nv, WeightsLds{wl}, b2, alpha), nv)
+                                : lorenzo_err32<D>(nv, amask);
+                        code = code32(e, ok);
+                    } else {
+                        code = make_code(inside ? predict<D, HP>(nv, amask, a.use_net != 0,
+                                                                 WeightsLds{wl}, b2, alpha)
+                                                : 0,
+                                         nv[0], ok);
+                    }
+                }
+                if (!inside)
+                    continue;
+                a.codes[pos0 + i] = code;
+                nzero += code == 0 ? 1u : 0u;
+                if (a.judge) {
+                    const unsigned short lcode =
+                        w32 ? code32(lorenzo_err32<D>(nv, amask), ok)
+                            : make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
+                    jb[okr + i] =
+                        0x10000u | (unsigned)judge_bin(code) | ((unsigned)judge_bin(lcode) << 8);
+                }
+            }
             if (a.judge) {
-                const unsigned short lcode = make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
-                atomicAdd(&jh[bt * 256 + judge_bin(code)], 1u);
-                atomicAdd(&jh[bt * 256 + judge_bin(lcode)], 1u << 16);
-            } else if (code == 0) {
-                atomicAdd(&cnt[bt], 1u);
+                for (int i = 0; i < SEG; ++i)
+                    if (!(urow && cx0 + i < limx) && u < nunits)
+                        jb[okr + i] = 0u;  // no point
+            } else if (nzero) {
+                atomicAdd(&cnt[bt], nzero);
             }
         }
         __syncthreads();
 
         if (a.judge) {
             // --- per-block judge: keep the network iff the entropy of its
-            //     clamped codes is strictly below Lorenzo's (fixed-point scores) ---
+            //     clamped codes is strictly below Lorenzo's (fixed-point scores).
+            // Histograms from the bins noted above (LDS atomics outside the
+            // prediction loop, where no memory operation is outstanding) ---
+            for (int q = tid; q < ntp; q += NT) {
+                const unsigned v = jb[q];
+                if (v == 0u)
+                    continue;
+                const int cx = q % T2, cy = (q / T2) % T1, cz = q / (T1 * T2);
+                const int bt = ((cz / bd0) * nbt1 + cy / bd1) * nbt2 + cx / bd2;
+                atomicAdd(&jh[bt * 256 + (v & 255u)], 1u);
+                atomicAdd(&jh[bt * 256 + ((v >> 8) & 255u)], 1u << 16);
+            }
+            __syncthreads();
             for (int i = tid; i < nbt * 256; i += NT) {
                 const unsigned w = jh[i];
                 const unsigned c_n = w & 0xffffu, c_l = w >> 16;
@@ -249,7 +492,7 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
             }
             __syncthreads();
             // blocks where Lorenzo wins: overwrite the network codes written above
-            for (int q = tid; q < nq; q += NT) {
+            for (int q = tid; q < nbt * BV; q += NT) {
                 const int bt = q / BV;
                 if (jsum[2 * bt] > jsum[2 * bt + 1])
                     continue;
@@ -257,8 +500,7 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
                 const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
                 const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
                 const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
-                const long long gz = g0z + cz, gy = g0y + cy, gx = g0x + cx;
-                if (gz >= n0 || gy >= n1 || gx >= n2)
+                if (!(cz < limz && cy < limy && cx < limx))
                     continue;
                 const int ei = ((cz + h0) * E1 + (cy + h1)) * E2 + (cx + h2);
                 int nv[8];
@@ -266,18 +508,17 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
 #pragma unroll
                 for (int o = 1; o < (1 << D); ++o)
                     nv[o] = ptile[ei - noff[o]];
-                int amask;
-                if (a.independent)
-                    amask = (lx != 0 ? 1 : 0) | (D >= 2 && ly != 0 ? 2 : 0) |
-                            (D >= 3 && lz != 0 ? 4 : 0);
-                else
-                    amask = (gx != 0 ? 1 : 0) | (D >= 2 && gy != 0 ? 2 : 0) |
-                            (D >= 3 && gz != 0 ? 4 : 0);
+                const int pz = a.independent ? lz : cz, py = a.independent ? ly : cy,
+                          px = a.independent ? lx : cx;
+                const int amask = ((px != 0 || !(edge & 1)) ? 1 : 0) |
+                                  (D >= 2 && (py != 0 || !(edge & 2)) ? 2 : 0) |
+                                  (D >= 3 && (pz != 0 || !(edge & 4)) ? 4 : 0);
                 const bool ok = okb[(cz * T1 + cy) * T2 + cx] != 0;
-                const BlockGeo bg =
-                    block_geo3(bz0 + btz, by0 + bty, bx0 + btx, a.n, bd0, bd1, bd2);
-                a.codes[bg.start + ((long long)lz * bg.ey + ly) * bg.ex + lx] =
-                    make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
+                const long long pos = bst[bt] + (long long)((lz * (int)(bext[bt] >> 16) + ly) *
+                                                                (int)(bext[bt] & 0xffffu) +
+                                                            lx);
+                a.codes[pos] = w32 ? code32(lorenzo_err32<D>(nv, amask), ok)
+                                   : make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
             }
             for (int bt = tid; bt < nbt; bt += NT) {
                 const bool use_n = jsum[2 * bt] > jsum[2 * bt + 1];
@@ -301,7 +542,7 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
             if (a.judge)
                 jsum[2 * bt] = jsum[2 * bt + 1] = 0ULL;
         }
-        // the next tile's staging overwrites ptile/okb only after this barrier
+        // the next tile overwrites the LDS arrays only after this barrier
         __syncthreads();
     }
     set_status(a.status, err);
@@ -314,10 +555,10 @@ static size_t compress_lds(const Geom &g, const int *t, bool judge = true)
     const size_t ne = (size_t)(t[0] + h0) * (t[1] + h1) * (t[2] + 1);
     const size_t nbt = (size_t)(t[0] / g.bd[0]) * (t[1] / g.bd[1]) * (t[2] / g.bd[2]);
     const size_t ntp = (size_t)t[0] * t[1] * t[2];
-    size_t n = ne * 4 + nbt * 4;
+    size_t n = nbt * 8 + nbt * 4 + ne * 4 + nbt * 4;  // starts, extents, tile, counts
     if (judge)
-        n += nbt * 256 * 4 + 2 * nbt * 8;
-    return n + ntp;
+        n += nbt * 256 * 4 + 2 * nbt * 8 + ntp * 4;  // histograms, scores, bins
+    return n + ntp;  // bound bits
 }
 
 bool tile_for(const Geom &g, Tile &tile)
@@ -358,9 +599,19 @@ bool tile_for(const Geom &g, Tile &tile)
 }
 
 template <typename T, int D, int BB, int HP, bool FP, int PREC>
-static void go(const CompressArgs &a, unsigned grid, size_t lds, hipStream_t s)
+static void go(const CompressArgs &a, unsigned num_cus, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC>), dim3(grid), dim3(256), lds, s, a);
+    // persistent grid: every workgroup that can be resident at once (a
+    // multiple of 8 so that each XCD gets the same number), at most one per tile
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&k_compress<T, D, BB, HP, FP, PREC>), 256,
+            lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    long long grid = std::min((long long)per_cu * num_cus, (a.ntiles + 7) / 8 * 8);
+    grid = std::max(8LL, grid / 8 * 8);
+    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC>), dim3((unsigned)grid), dim3(256), lds,
+                       s, a);
 }
 
 template <typename T, int D, int BB, bool FP>
@@ -430,10 +681,7 @@ hipError_t launch_compress(const void *x, const int *pfield, const Geom &g, cons
     a.mlp = pack_mlp(opt.use_net ? model : nullptr);
     const bool mfma = opt.use_net && model && model->precision == 1;
     const int HP = mfma ? 0 : hidden_pad(opt.use_net ? model : nullptr);
-    const long long gmax = (long long)std::max(num_cus, 8) * 4;
-    long long grid = std::min(gmax, (tile.ntiles + 7) / 8 * 8);
-    if (grid < 8)
-        grid = 8;
+    const unsigned grid = (unsigned)std::max(num_cus, 8);  // CUs; go() sizes the grid
     const size_t lds = compress_lds(g, tile.t, opt.judge != 0);
     if (pfield)
         by_shape<float, true>(g.D, g.B, HP, a, (unsigned)grid, lds, s);

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/pwrel.h"
+
 namespace pwrel {
 
 constexpr int kR = 32768;                 // 2^(m-1), m = 16 code bits
@@ -26,6 +28,9 @@ struct DevConsts {
     unsigned long long n_zero, n_neg, n_nonfinite;
     int status;
     int pad;
+    double fm_p, fm_n;  // fast-path margins of t = (log2|x| + L) r, per sign range
+    int w32;            // grid values span < 2^27: prediction errors fit 32-bit arithmetic
+    int pad2;
 };
 
 // Running statistics of a field (reduced with integer atomics).
@@ -97,6 +102,32 @@ __device__ __forceinline__ double det_exp2(double t)
     return __builtin_ldexp(acc, (int)k);
 }
 
+// ---------------------------------------------------------------------------
+// FP32 fast paths (FP32 fields only).  They use the hardware log2 / exp2
+// (v_log_f32, v_exp_f32) and decide a result only where an error bound proves
+// it equal to the FP64 path's; elsewhere the caller takes the FP64 path.  The
+// bounds are properties of the hardware instructions, checked over every
+// input they can receive (pwrel_fastmath_check):
+//   |fast_log2(a) - det_log2(a)| <= kFastLog2Err   for every normal float a > 0
+//   |v_exp_f32(f) - 2^f| <= kFastExp2Err 2^f       for every float |f| <= 1/2
+// ---------------------------------------------------------------------------
+constexpr double kFastLog2Err = PWREL_FAST_LOG2_ERR;
+constexpr double kFastExp2Err = PWREL_FAST_EXP2_ERR;
+
+// log2 of a normal float a > 0: exponent plus v_log_f32 of the significand
+// taken into [sqrt(1/2), sqrt(2)), summed in FP64
+__device__ __forceinline__ double fast_log2(float a)
+{
+    const unsigned bits = __float_as_uint(a);
+    int e = (int)((bits >> 23) & 0xffu) - 127;
+    float m = __uint_as_float((bits & 0x7fffffu) | 0x3f800000u);
+    if (m >= 1.41421356f) {
+        m = m * 0.5f;
+        e += 1;
+    }
+    return (double)e + (double)__builtin_amdgcn_logf(m);
+}
+
 template <typename T> __device__ __forceinline__ double to_dtype(double v);
 template <> __device__ __forceinline__ double to_dtype<float>(double v) { return (double)(float)v; }
 template <> __device__ __forceinline__ double to_dtype<double>(double v) { return v; }
@@ -120,6 +151,64 @@ __device__ __forceinline__ int grid_value(double x, const DevConsts &c, int &err
         err = kERange;
     q = neg ? qn : qp;
     return x == 0.0 ? (int)c.p_zero : (int)q;
+}
+
+// Grid value of an FP32 input by the fast path: returns false when the bound
+// cannot decide the rounding, or the input is subnormal, non-finite, or so
+// large in the grid that the range checks matter (the FP64 path decides then).
+// x = 0 is exact (p_zero).  Written without branches: both sign ranges and
+// all checks are evaluated and combined with selects.
+__device__ __forceinline__ bool grid_value_fast(float x, const DevConsts &c, int &q)
+{
+    const float a = __builtin_fabsf(x);
+    const bool neg = x < 0.0f;
+    const double t = (fast_log2(a) + (neg ? c.Ln : c.Lp)) * c.r;
+    const double margin = neg ? c.fm_n : c.fm_p;
+    const double fr = t - __builtin_floor(t);
+    const bool in_range = __builtin_fabs(t) < 0x1p29;
+    const bool ok = a >= 0x1p-126f && a <= 0x1.fffffep127f && in_range &&
+                    __builtin_fabs(fr - 0.5) > margin;
+    const int qi = (int)__builtin_rint(in_range ? t : 0.0);
+    const int pz = (int)c.p_zero, bs = (int)c.b_sign, dl = (int)c.delta;
+    int v;
+    bool fits = true;
+    if (neg) {
+        // q + delta can reach 2^30 only for fields the FP64 path rejects
+        const long long w = (long long)qi + dl;
+        fits = w < (long long)kGridLimit;
+        v = (int)(w < bs + 1 ? bs + 1 : w);
+    } else {
+        v = qi < pz + 1 ? pz + 1 : (qi > bs ? bs : qi);
+    }
+    q = x == 0.0f ? pz : v;
+    return x == 0.0f || (ok && fits);
+}
+
+// Bound check of an FP32 input against the grid value p by the fast path:
+// returns false when the bound cannot decide; else sets ok to the FP64
+// path's verdict on x^ = (float) inverse(p).
+__device__ __forceinline__ bool within_bound_fast(float x, int p, const DevConsts &c, bool &ok)
+{
+    const int pz = (int)c.p_zero, bs = (int)c.b_sign, dl = (int)c.delta;
+    const bool zero_hat = p <= pz;  // x^ = 0
+    const bool neg = p > bs;
+    // the operations of grid_inverse: t = q w - L
+    const double tq = neg ? (double)(p - dl) * c.w - c.Ln : (double)p * c.w - c.Lp;
+    const double k = __builtin_rint(tq);
+    const bool k_ok = k >= -125.0 && k <= 127.0;
+    const double f = tq - k;  // exact, |f| <= 1/2
+    const int ki = (int)(k_ok ? k : 0.0);
+    const double y = __builtin_ldexp((double)__builtin_amdgcn_exp2f((float)f), ki);
+    // |y - x^| <= y (kFastExp2Err + 2^-26 (rounding of f) + 2^-24 (rounding of x^)
+    // + 2^-50), enlarged slightly
+    const double slack = y * (kFastExp2Err + 0x1p-23);
+    const double ax = __builtin_fabs((double)x);
+    const double d = __builtin_fabs(ax - y);
+    const double bnd = c.eps * ax;
+    const bool yes = d + slack <= bnd, no = d - slack > bnd;
+    const bool exact_no = x == 0.0f || __builtin_signbit(x) != neg;  // x^ != 0 here
+    ok = zero_hat ? x == 0.0f : (!exact_no && yes);
+    return zero_hat || exact_no || (k_ok && (yes || no));
 }
 
 // Inverse of the grid map (zero / positive / negative by threshold), rounded

@@ -78,6 +78,7 @@ hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *mod
                          const unsigned *order, unsigned epoch, void *xh, int num_cus,
                          hipStream_t s);
 hipError_t launch_detmath(const double *x, double *l2, double *e2, uint64_t n, hipStream_t s);
+hipError_t launch_fastmath_check(unsigned long long *out2, hipStream_t s);
 hipError_t launch_hist(const uint16_t *codes, long long n, unsigned long long *hist,
                        hipStream_t s);
 

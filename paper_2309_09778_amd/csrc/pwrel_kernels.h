@@ -1,6 +1,8 @@
 // Device helpers shared by the compression and decompression kernels.
 #pragma once
 
+#include <type_traits>
+
 #include <algorithm>
 
 #include "pwrel_internal.h"
@@ -104,8 +106,7 @@ __device__ __forceinline__ long long predict(const int (&nv)[8], int amask, bool
         for (int k = 0; k < 6; ++k)
             u[k] = k < K ? (float)(nv[k + 2] - nv[1]) : 0.0f;
         float y = b2;
-#pragma unroll
-        for (int j = 0; j < HP; ++j) {
+        auto unit = [&](int j) {
             const float4 wa = wt.a(j), wb = wt.b(j);
             const float w[6] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y};
             float z = wb.z;
@@ -114,6 +115,19 @@ __device__ __forceinline__ long long predict(const int (&nv)[8], int amask, bool
                 z = __builtin_fmaf(w[k], u[k], z);
             const float h = __builtin_fmaxf(z, z * alpha);
             y = __builtin_fmaf(wb.w, h, y);
+        };
+        if constexpr (std::is_same<W, WeightsLds>::value) {
+            // weights read from LDS four units at a time (bounded register use)
+#pragma unroll 1
+            for (int j0 = 0; j0 < HP; j0 += 4) {
+#pragma unroll
+                for (int j = j0; j < j0 + 4; ++j)
+                    unit(j);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < HP; ++j)
+                unit(j);
         }
         if (y > 0x1p30f)
             y = 0x1p30f;
@@ -141,7 +155,7 @@ template <int D, int BB> struct ShapeOf {
         static constexpr int T0 = A, T1 = Bv, T2 = Cv;                                        \
     };
 PWREL_SHAPE(3, 4, 8, 8, 32)
-PWREL_SHAPE(3, 8, 8, 8, 64)
+PWREL_SHAPE(3, 8, 8, 8, 32)
 PWREL_SHAPE(3, 16, 16, 16, 32)
 PWREL_SHAPE(2, 16, 1, 16, 128)
 PWREL_SHAPE(2, 32, 1, 32, 128)
@@ -155,7 +169,7 @@ inline bool known_shape(int D, int B, int *t)
     struct E {
         int D, B, t0, t1, t2;
     };
-    static const E tab[] = {{3, 4, 8, 8, 32},    {3, 8, 8, 8, 64},     {3, 16, 16, 16, 32},
+    static const E tab[] = {{3, 4, 8, 8, 32},    {3, 8, 8, 8, 32},     {3, 16, 16, 16, 32},
                             {2, 16, 1, 16, 128}, {2, 32, 1, 32, 128},  {2, 64, 1, 64, 64},
                             {1, 256, 1, 1, 4096}};
     for (const E &e : tab)

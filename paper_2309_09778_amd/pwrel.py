@@ -58,6 +58,8 @@ class Header(C.Structure):
 
 
 MAX_CANDIDATES = 17
+FAST_LOG2_ERR = 2.0 ** -20  # PWREL_FAST_LOG2_ERR
+FAST_EXP2_ERR = 2.0 ** -20  # PWREL_FAST_EXP2_ERR
 
 
 class TrainOptions(C.Structure):
@@ -102,6 +104,7 @@ _SIGS = {
     "pwrel_mlp_init": (C.c_int, [C.POINTER(Mlp), C.c_int, C.c_int, C.c_float, C.c_uint64]),
     "pwrel_set_profiling": (C.c_int, [_P, C.c_int]),
     "pwrel_phase_times": (C.c_int, [_P, _P, C.c_int]),
+    "pwrel_fastmath_check": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]),
     "pwrel_train": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
                               C.POINTER(TrainOptions), C.POINTER(Mlp), C.POINTER(Mlp),
                               C.POINTER(TrainReport), _P]),
@@ -421,6 +424,14 @@ class Context:
                                    C.c_void_p(e2.data_ptr()), x.numel(), _stream(stream))
         self._check(st, "detmath")
         return l2, e2
+
+    def fastmath_check(self, stream=None):
+        """Largest errors of the FP32 fast-path log2 / exp2 over every input
+        they can receive: (log2 absolute error, exp2 relative error)."""
+        a, b = C.c_double(0.0), C.c_double(0.0)
+        self._check(self._L.pwrel_fastmath_check(self.h, C.byref(a), C.byref(b),
+                                                 _stream(stream)), "fastmath_check")
+        return a.value, b.value
 
     def set_profiling(self, enable=True):
         self._check(self._L.pwrel_set_profiling(self.h, int(bool(enable))), "set_profiling")

@@ -303,3 +303,49 @@ def test_full_size_512cubed(ctx, big_field, eps):
     is_raw = ref["codes"] == 0
     ref_xh[is_raw] = x.reshape(-1)[idx[is_raw]]
     assert np.array_equal(xh_s.view(np.uint32), ref_xh.view(np.uint32))
+
+
+# --- FP32 fast paths ------------------------------------------------------------------------
+
+def test_fastmath_bounds_hold(ctx):
+    """The hardware log2 / exp2 errors, over every input the fast paths can
+    receive, stay within the bounds the kernels assume."""
+    lerr, eerr = ctx.fastmath_check()
+    assert 0.0 < lerr <= pwrel.FAST_LOG2_ERR, lerr
+    assert 0.0 < eerr <= pwrel.FAST_EXP2_ERR, eerr
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_fast_path_boundaries(ctx, eps):
+    """Values swept densely across grid cells (both rounding boundaries of the
+    transform and both ends of the bound check, both signs): codes, counts and
+    raw values bit-exact to the oracle's FP64 path."""
+    anchors = np.array([1e-3, 1e3, -1e-3, -1e3, 0.0], dtype=np.float32)
+    c = O.consts(anchors, eps)
+    rng = np.random.default_rng(11)
+    lo, hi = int(c["p_zero"]) + 2, int(c["b_sign"]) - 2
+    cells = rng.integers(lo, hi, 120)
+    ncell = int(c["n_lo"]) + 2 + rng.integers(0, hi - lo, 120)
+    p = np.concatenate([cells, ncell]).astype(np.int32)
+    centre = O.inverse_field(p, c, np.float32).astype(np.float64)
+    s = np.linspace(-1.25, 1.25, 1001) * c["b_a"]
+    x = (centre[:, None] * np.exp2(s)[None, :]).astype(np.float32).ravel()
+    x = x[(np.abs(x) > 1e-3) & (np.abs(x) < 1e3)]
+    # neighbours in the float grid of a few sweep points: every ulp near the edges
+    edge = x[::97]
+    ulps = np.concatenate([np.nextafter(edge, np.float32(np.inf)),
+                           np.nextafter(edge, np.float32(-np.inf))]).astype(np.float32)
+    x = np.concatenate([anchors, x, ulps]).astype(np.float32)
+    n = (x.size // 64) * 64
+    x = np.ascontiguousarray(np.concatenate([anchors, x[5:n]]).reshape(-1, 64))
+    assert O.consts(x, eps)["Lp"] == c["Lp"]
+    stream = ctx.compress(dev(x), eps, 8, None, use_net=False)
+    g = host_sections(stream)
+    ref = O.compress(x, eps, 8, None, O.MODE_LORENZO)
+    assert np.array_equal(g["codes"], ref["codes"])
+    assert np.array_equal(g["counts"], ref["counts"])
+    assert np.array_equal(g["raw"].view(np.uint8), ref["raw"].view(np.uint8))
+    xh = ctx.decompress(stream).cpu().numpy()
+    assert_bound(x, xh, eps)
+    # the sweep reaches both verdicts of the bound check
+    assert 0 < g["h"]["n_raw"] < x.size
