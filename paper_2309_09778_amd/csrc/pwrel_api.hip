@@ -40,6 +40,7 @@ struct pwrel_ctx {
     unsigned *order = nullptr;
     size_t order_cap = 0;
     long long order_nb[3] = {-1, -1, -1};
+    int order_pen = -1;  // the cached order is of pencils (1) or of blocks (0)
     unsigned epoch = 0;
 };
 
@@ -380,7 +381,7 @@ void pwrel_destroy(pwrel_ctx *ctx)
                     ws.offsets,     ws.partials,    ws.pgrid,      ws.qtab,        ctx->counts_scratch,
                     ctx->chunk_cnt, ctx->chunk_off, ctx->pairs,    ctx->theta,     ctx->nets,
                     ctx->vhist,     ctx->scal,      ctx->scores,   ws.done,        ws.ticket,
-                    ctx->order};
+                    ctx->order,     ws.praw,        ws.zf,         ws.yf};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -553,24 +554,47 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
     int st = ensure_scan(ctx, g);
     if (st)
         return st;
+    if ((e = grow(ctx->ws.praw, ctx->ws.praw_cap, (size_t)std::max<uint64_t>(h.n_raw, 1))) !=
+        hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, "raw grid value allocation failed");
     if (!(h.flags & PWREL_HF_INDEPENDENT)) {
         if ((e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
             return fail(ctx, PWREL_ENOMEM, "grid scratch allocation failed");
-        // done flags: zeroed when (re)allocated; each call raises them to a new epoch
+        // Done flags and tagged faces: zeroed when (re)allocated; each call
+        // uses a new epoch (0 is the value of a fresh word), so words of
+        // earlier calls never match.  When the epoch wraps, all are cleared.
+        const bool pen = pencil_mode(g);
+        const size_t nzf = pen ? (size_t)(g.nb[0] * g.n[1] * g.n[2]) : 0;
+        const size_t nyf = pen ? (size_t)(g.nb[1] * g.n[0] * g.n[2]) : 0;
         if (ctx->ws.done_cap < (size_t)g.nblocks) {
             if ((e = grow(ctx->ws.done, ctx->ws.done_cap, (size_t)g.nblocks)) != hipSuccess ||
                 (e = hipMemsetAsync(ctx->ws.done, 0, ctx->ws.done_cap * sizeof(unsigned), s)) !=
                     hipSuccess)
                 return fail(ctx, PWREL_ENOMEM, "decoder flag allocation failed");
-            ctx->epoch = 0;
         }
-        if (++ctx->epoch == 0)
-            ctx->epoch = 1;  // 0 is the value of a fresh flag
+        if (pen && (ctx->ws.zf_cap < nzf || ctx->ws.yf_cap < nyf)) {
+            if ((e = grow(ctx->ws.zf, ctx->ws.zf_cap, nzf)) != hipSuccess ||
+                (e = hipMemsetAsync(ctx->ws.zf, 0, ctx->ws.zf_cap * 8, s)) != hipSuccess ||
+                (e = grow(ctx->ws.yf, ctx->ws.yf_cap, nyf)) != hipSuccess ||
+                (e = hipMemsetAsync(ctx->ws.yf, 0, ctx->ws.yf_cap * 8, s)) != hipSuccess)
+                return fail(ctx, PWREL_ENOMEM, "decoder face allocation failed");
+        }
+        if (++ctx->epoch == 0) {
+            ctx->epoch = 1;
+            if ((ctx->ws.done &&
+                 (e = hipMemsetAsync(ctx->ws.done, 0, ctx->ws.done_cap * sizeof(unsigned), s)) !=
+                     hipSuccess) ||
+                (ctx->ws.zf && (e = hipMemsetAsync(ctx->ws.zf, 0, ctx->ws.zf_cap * 8, s)) !=
+                                   hipSuccess) ||
+                (ctx->ws.yf && (e = hipMemsetAsync(ctx->ws.yf, 0, ctx->ws.yf_cap * 8, s)) !=
+                                   hipSuccess))
+                return hip_fail(ctx, e, "decoder flag reset");
+        }
         if (ctx->order_nb[0] != g.nb[0] || ctx->order_nb[1] != g.nb[1] ||
-            ctx->order_nb[2] != g.nb[2]) {
+            ctx->order_nb[2] != g.nb[2] || ctx->order_pen != (int)pen) {
             std::vector<unsigned> order;
             block_order(g, order);
-            if ((long long)order.size() != g.nblocks)
+            if ((long long)order.size() != (pen ? g.nb[0] * g.nb[1] : g.nblocks))
                 return fail(ctx, PWREL_EHIP, "internal: block order incomplete");
             if ((e = grow(ctx->order, ctx->order_cap, order.size())) != hipSuccess)
                 return fail(ctx, PWREL_ENOMEM, "decoder order allocation failed");
@@ -580,6 +604,7 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
                 return hip_fail(ctx, e, "decoder order copy");
             for (int d = 0; d < 3; ++d)
                 ctx->order_nb[d] = g.nb[d];
+            ctx->order_pen = (int)pen;
         }
     }
     DevConsts c{};

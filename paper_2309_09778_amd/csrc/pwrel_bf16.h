@@ -69,7 +69,8 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
 }
 
 // this lane's half of layer 2 for one group: sum over its 16 hidden units
-__device__ __forceinline__ float layer2_half(const NetBf16 &n, const floatx16 &d)
+__device__ __forceinline__ float layer2_half(const float (&a2)[16], const float (&c2)[16],
+                                             const floatx16 &d)
 {
     float s = 0.0f;
 #pragma unroll
@@ -77,16 +78,19 @@ __device__ __forceinline__ float layer2_half(const NetBf16 &n, const floatx16 &d
         const unsigned pk = pack_bf16(d[2 * q], d[2 * q + 1]);  // round to bf16 (RNE)
         const float z0 = __builtin_bit_cast(float, pk << 16);
         const float z1 = __builtin_bit_cast(float, pk & 0xffff0000u);
-        s = __builtin_fmaf(n.a2[2 * q], __builtin_fmaxf(z0, 0.0f), s);
-        s = __builtin_fmaf(n.c2[2 * q], z0, s);
-        s = __builtin_fmaf(n.a2[2 * q + 1], __builtin_fmaxf(z1, 0.0f), s);
-        s = __builtin_fmaf(n.c2[2 * q + 1], z1, s);
+        s = __builtin_fmaf(a2[2 * q], __builtin_fmaxf(z0, 0.0f), s);
+        s = __builtin_fmaf(c2[2 * q], z0, s);
+        s = __builtin_fmaf(a2[2 * q + 1], __builtin_fmaxf(z1, 0.0f), s);
+        s = __builtin_fmaf(c2[2 * q + 1], z1, s);
     }
     return s;
 }
 
-// Network output y for the point of this lane (u: K inputs as exact floats).
-__device__ __forceinline__ float net_bf16(const NetBf16 &n, const float (&u)[6])
+// Both groups of layer 1 (lanes 0..31 and lanes 32..63 as the 32 columns),
+// then layer 2; c1, a2, c2 as in NetBf16 for this lane's half.
+__device__ __forceinline__ float net_bf16_core(const bf16x8 &a1, const floatx16 &c1,
+                                               const float (&a2)[16], const float (&c2)[16],
+                                               float b2, const float (&u)[6])
 {
     const int l = threadIdx.x & 63;
     unsigned p[4];
@@ -103,23 +107,77 @@ __device__ __forceinline__ float net_bf16(const NetBf16 &n, const float (&u)[6])
         g1[q] = l < 32 ? other : 0u;
     }
     const floatx16 d0 =
-        __builtin_amdgcn_mfma_f32_32x32x16_bf16(n.a1, __builtin_bit_cast(bf16x8, g0), n.c1, 0, 0, 0);
+        __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, __builtin_bit_cast(bf16x8, g0), c1, 0, 0, 0);
     const floatx16 d1 =
-        __builtin_amdgcn_mfma_f32_32x32x16_bf16(n.a1, __builtin_bit_cast(bf16x8, g1), n.c1, 0, 0, 0);
-    const float s0 = layer2_half(n, d0), s1 = layer2_half(n, d1);
+        __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, __builtin_bit_cast(bf16x8, g1), c1, 0, 0, 0);
+    const float s0 = layer2_half(a2, c2, d0), s1 = layer2_half(a2, c2, d1);
     // lane l < 32 owns column l of group 0: halves s0 (own, h = 0) + s0 of lane l + 32;
     // lane l >= 32 owns column l - 32 of group 1: s1 of lane l - 32 (h = 0) + s1 (own)
     const float send = l < 32 ? s1 : s0;
     const float recv = __shfl_xor(send, 32, 64);
     const float lo = l < 32 ? s0 : recv, hi = l < 32 ? recv : s1;
-    return (lo + hi) + n.b2;
+    return (lo + hi) + b2;
+}
+
+// Network output y for the point of this lane (u: K inputs as exact floats).
+__device__ __forceinline__ float net_bf16(const NetBf16 &n, const float (&u)[6])
+{
+    return net_bf16_core(n.a1, n.c1, n.a2, n.c2, n.b2, u);
+}
+
+// The same network with c1, a2 and c2 kept in LDS (read at each evaluation)
+// instead of registers: per half h, 48 floats at t + 48 h (c1, a2, c2).
+struct NetBf16Lds {
+    bf16x8 a1;
+    const float *t;
+    float b2;
+};
+
+__device__ __forceinline__ void stage_net_bf16(float *t, const MlpW &m)
+{
+    const float ar = 1.0f - m.alpha, al = m.alpha;
+    for (int i = threadIdx.x; i < 32; i += blockDim.x) {
+        const int h = i >> 4, e = i & 15, row = d1_row(e, h);
+        t[48 * h + e] = m.b1[row];
+        t[48 * h + 16 + e] = bf16_round(ar * m.v[row]);
+        t[48 * h + 32 + e] = bf16_round(al * m.v[row]);
+    }
+}
+
+__device__ __forceinline__ NetBf16Lds make_net_bf16_lds(const MlpW &m, int K, const float *t)
+{
+    NetBf16Lds n;
+    const int l = threadIdx.x & 63, h = l >> 5, i = l & 31;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = 8 * h + e;
+        n.a1[e] = (__bf16)(k < K ? m.w1[i][k] : 0.0f);
+    }
+    n.t = t + 48 * h;
+    n.b2 = m.b2;
+    return n;
+}
+
+__device__ __forceinline__ float net_bf16(const NetBf16Lds &n, const float (&u)[6])
+{
+    const float4 *t4 = reinterpret_cast<const float4 *>(n.t);
+    floatx16 c1;
+    float a2[16], c2[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 c = t4[q], a = t4[4 + q], v = t4[8 + q];
+        c1[4 * q] = c.x; c1[4 * q + 1] = c.y; c1[4 * q + 2] = c.z; c1[4 * q + 3] = c.w;
+        a2[4 * q] = a.x; a2[4 * q + 1] = a.y; a2[4 * q + 2] = a.z; a2[4 * q + 3] = a.w;
+        c2[4 * q] = v.x; c2[4 * q + 1] = v.y; c2[4 * q + 2] = v.z; c2[4 * q + 3] = v.w;
+    }
+    return net_bf16_core(n.a1, c1, a2, c2, n.b2, u);
 }
 
 // Prediction of the point of this lane with the BF16 network where every
 // neighbour exists, else one-layer Lorenzo (as predict<>).  Wave-uniform call.
-template <int D>
+template <int D, class N>
 __device__ __forceinline__ long long predict_bf16(const int (&nv)[8], int amask, bool net,
-                                                  const NetBf16 &n)
+                                                  const N &n)
 {
     constexpr int NO = (1 << D) - 1;
     constexpr int K = (1 << D) - 2;

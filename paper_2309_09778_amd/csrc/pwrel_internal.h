@@ -46,10 +46,15 @@ struct Workspace {
     size_t offsets_cap = 0, partials_cap = 0;
     int *pgrid = nullptr;  // decoder grid-value scratch (N int32)
     size_t pgrid_cap = 0;
+    int *praw = nullptr;   // decoder: grid values of the raw values (n_raw int32)
+    size_t praw_cap = 0;
     long long *qtab = nullptr;  // rint(2^32 log2 c), c = 0 .. kQtab - 1 (judge scores)
     unsigned *done = nullptr;   // halo-mode decoder: per-block done flags (epoch values)
     size_t done_cap = 0;
     unsigned *ticket = nullptr; // halo-mode decoder: next block ticket
+    // pencil decoder: tagged z faces (nb0 x n1 x n2) and y faces (nb1 x n0 x n2)
+    unsigned long long *zf = nullptr, *yf = nullptr;
+    size_t zf_cap = 0, yf_cap = 0;
 };
 
 constexpr int kQtab = 4097;
@@ -59,6 +64,7 @@ constexpr int kScanChunk = 4096;
 // Kernel launchers (return the launch error, if any).
 hipError_t launch_reset(Workspace &ws, hipStream_t s);
 void block_order(const Geom &g, std::vector<unsigned> &order);
+bool pencil_mode(const Geom &g);
 hipError_t launch_stats(const void *x, const Geom &g, Workspace &ws, hipStream_t s);
 hipError_t launch_consts(const Geom &g, double eps, Workspace &ws, hipStream_t s);
 hipError_t launch_transform(const void *x, const Geom &g, Workspace &ws, int *d_p, hipStream_t s);
