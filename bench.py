@@ -41,7 +41,14 @@ def compress_flops_per_point(H, K):
 
 COMPRESS_SOURCES = ["paper_2309_09778_amd/csrc/pwrel_compress.hip",
                     "paper_2309_09778_amd/csrc/pwrel_kernels.h",
+                    "paper_2309_09778_amd/csrc/pwrel_bf16.h",
                     "paper_2309_09778_amd/csrc/pwrel_device.h"]
+DECODE_SOURCES = ["paper_2309_09778_amd/csrc/pwrel_decode.hip",
+                  "paper_2309_09778_amd/csrc/pwrel_kernels.h",
+                  "paper_2309_09778_amd/csrc/pwrel_bf16.h",
+                  "paper_2309_09778_amd/csrc/pwrel_device.h"]
+COMPRESS_PROFILE = "k_compress_learned_bf16_judge_512cubed_f32_eps1e-2.txt"
+DECODE_PROFILE = "k_decode_pencil_learned_bf16_judge_512cubed_f32_eps1e-2.txt"
 
 
 def source_hash(files):
@@ -140,7 +147,7 @@ def stream_stats(ctx, s, x_nbytes, pwrel):
     out = {"ratio_stream": round(x_nbytes / h["total_size"], 4),
            "ratio_huffman": round(x_nbytes / hbytes, 4),
            "paper_CR_percent_huffman": round(100.0 * hbytes / x_nbytes, 3),
-           "unpredictable_frac": round(h["n_raw"] / h["n"], 7)}
+           "unpredictable_frac": round(h["n_raw"] / h["n"], 7), "n_raw": int(h["n_raw"])}
     if "bflags" in sec:
         out["network_block_frac"] = round(float(sec["bflags"].float().mean()), 4)
     return out
@@ -224,17 +231,41 @@ def main():
         print("[bench] plain path timed", file=sys.stderr, flush=True)
 
     ph = L["phase_ms"]
-    # dominant kernel of the learned step: the fused compression kernel or the decoder
-    kern_ms = ph["compress"]
+    N = x.size
+    n_raw = st_l["n_raw"]
+    nblocks = (S // B) ** 3
+    # fused compression kernel: ALU-bound (FP64 transform and verification per
+    # point; the network runs on the matrix cores)
     flops_pp = compress_flops_per_point(0, 6)
-    achieved = flops_pp * x.size / (kern_ms * 1e-3) / 1e12
-    mfma_useful = 2 * (args.hidden * 6 + args.hidden) * x.size
-    roofline = {"kernel": "k_compress<float,3,8,HP,false,1> (fused a3-a7, BF16 MFMA network, "
-                          "judge)", "bound": "alu",
-                "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_ms": round(kern_ms, 4), "flops_per_point": flops_pp,
-                "mfma_util": round(mfma_useful / (kern_ms * 1e-3) / 2.5e15, 5)}
+    c_ms = ph["compress"]
+    c_ach = flops_pp * N / (c_ms * 1e-3) / 1e12
+    c_bytes = N * 4 + N * 2 + nblocks * 5 + n_raw * 4  # field in; codes, counts, flags, raw out
+    mfma_useful = 2 * (args.hidden * 6 + args.hidden) * N
+    roof_c = {"kernel": "k_compress<float,3,8,8,false,1> (fused a3-a7, BF16 MFMA network, "
+                        "judge)", "bound": "alu", "achieved": round(c_ach, 3),
+              "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
+              "frac": round(c_ach / ALU_PEAK_TFLOPS, 4),
+              "traffic": profiled_traffic(COMPRESS_PROFILE, COMPRESS_SOURCES),
+              "avg_ms": round(c_ms, 4), "flops_per_point": flops_pp,
+              "algorithmic_bytes": c_bytes,
+              "hbm_frac": round(c_bytes / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+              "mfma_util": round(mfma_useful / (c_ms * 1e-3) / 2.5e15, 5)}
+    # halo-mode decoder (pencils): bound by its chain of dependent pencils;
+    # priced against HBM with its algorithmic bytes (codes in, grid values out)
+    d_ms = ph["decode_levels"]
+    d_bytes = N * 2 + N * 4 + n_raw * 4
+    d_ach = d_bytes / (d_ms * 1e-3) / 1e9
+    roof_d = {"kernel": "k_decode_pencil<float,8,1> (a8 halo mode, BF16 network, judge)",
+              "bound": "hbm", "achieved": round(d_ach, 2), "peak": HBM_PEAK_GBPS,
+              "unit": "GB/s", "frac": round(d_ach / HBM_PEAK_GBPS, 5),
+              "traffic": profiled_traffic(DECODE_PROFILE, DECODE_SOURCES),
+              "avg_ms": round(d_ms, 4), "algorithmic_bytes": d_bytes,
+              "limiter": "dependency chain of pencils (levels bz + by)"}
+    # the roofline line is the dominant kernel's; the other is reported beside it
+    if d_ms >= c_ms:
+        roofline, other = roof_d, ("roofline_compress", roof_c)
+    else:
+        roofline, other = roof_c, ("roofline_decode", roof_d)
 
     res = {
         "metric": "compress/decompress GB/s at PW_REL 1e-2 and ratio, learned BF16 vs plain FP32",
@@ -261,6 +292,7 @@ def main():
                                              rep["val_score"][0]) / 2.0 ** 32 /
                                             max(rep["n_val"], 1), 4)},
         "roofline": roofline,
+        other[0]: other[1],
     }
     res.update(st_l)
     if plain is not None:

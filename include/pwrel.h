@@ -206,10 +206,12 @@ uint64_t pwrel_huffman_bits(const uint64_t *hist65536, uint32_t *max_len_out);
  * context, in milliseconds, from HIP events recorded on the caller's stream
  * while profiling is enabled (off by default; enabling adds no host sync).
  * Phases: 0 statistics + constants, 1 fused compression kernel,
- * 2 scan + raw scatter + header, 3 decoder scan, 4 decoder block levels.
- * Returns the number of phases written (<= n).
+ * 2 scan + raw scatter + header, 3 decoder scan, 4 decoder main kernel
+ * (block levels, pencils or independent blocks), 5 decoder grid values of
+ * the raw values, 6 decoder inverse map of the scratch grid field (halo
+ * mode; 0 otherwise).  Returns the number of phases written (<= n).
  */
-#define PWREL_NUM_PHASES 5
+#define PWREL_NUM_PHASES 7
 int pwrel_set_profiling(pwrel_ctx *ctx, int enable);
 int pwrel_phase_times(pwrel_ctx *ctx, double *ms, int n);
 

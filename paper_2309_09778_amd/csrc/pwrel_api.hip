@@ -20,7 +20,7 @@ struct pwrel_ctx {
     size_t counts_scratch_cap = 0;
     std::string err;
     int profiling = 0;
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[10] = {};
     bool ev_ok = false;
     double phase_ms[PWREL_NUM_PHASES] = {};
     // learned part: chunk counts and offsets, pairs, parameters, scores
@@ -630,11 +630,18 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
     if ((e = launch_scan(counts, g, ctx->ws, s)) != hipSuccess)
         return hip_fail(ctx, e, "scan");
     mark(ctx, 5, s);
+    if ((e = launch_raw_grid(g, c, in + h.off_raw, h.n_raw, ctx->ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "raw grid values");
+    mark(ctx, 6, s);
     if ((e = launch_decode(g, c, model, h.flags, bflags, codes, counts, in + h.off_raw, h.n_raw,
                            ctx->ws, ctx->order, ctx->epoch, d_field, ctx->num_cus, s)) !=
         hipSuccess)
         return hip_fail(ctx, e, "decode");
-    mark(ctx, 6, s);
+    mark(ctx, 7, s);
+    if (!(h.flags & PWREL_HF_INDEPENDENT) &&
+        (e = launch_inverse(g, c, ctx->ws, d_field, s)) != hipSuccess)
+        return hip_fail(ctx, e, "inverse");
+    mark(ctx, 8, s);
     int dst = 0;
     unsigned long long nr = 0;
     if ((e = hipMemcpyAsync(&dst, ctx->ws.status, sizeof dst, hipMemcpyDeviceToHost, s)) !=
@@ -645,8 +652,8 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
         return hip_fail(ctx, e, "status copy");
     if (dst == PWREL_OK && nr != h.n_raw)
         dst = PWREL_ECORRUPT;
-    static const int spans[2][3] = {{3, 4, 5}, {4, 5, 6}};
-    collect(ctx, spans, 2);
+    static const int spans[4][3] = {{3, 4, 5}, {5, 5, 6}, {4, 6, 7}, {6, 7, 8}};
+    collect(ctx, spans, 4);
     return finish_status(ctx, dst);
 }
 

@@ -12,8 +12,8 @@
 // lrelu(z) = (1 - alpha) relu(z) + alpha z:
 //   y = b2 + sum_j bf16((1-alpha) v_j) relu(bf16(z_j)) + bf16(alpha v_j) bf16(z_j).
 // Lane l holds 16 of the 32 hidden units of column l % 32 (half h = l / 32);
-// it sums them in a fixed order with FP32 fused multiply-adds, the two
-// halves of a column are added, then b2.  Every point is evaluated by the
+// it sums them in a fixed order with FP32 fused multiply-adds (four partial
+// sums, then their sum), the two halves of a column are added, then b2.  Every point is evaluated by the
 // same instruction sequence wherever it sits in the wave, so encoder and
 // decoder agree bit for bit.
 // Every lane of the wave must execute these calls (the matrix cores work on
@@ -61,6 +61,14 @@ __device__ __forceinline__ NetBf16 make_net_bf16(const MlpW &m, int K)
     return n;
 }
 
+// the value of lane l ^ 32 (v_permlane32_swap: lanes 32..63 of the first
+// operand trade places with lanes 0..31 of the second)
+__device__ __forceinline__ unsigned xor32_lanes(unsigned x)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
+}
+
 __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
 {
     const __bf16 a = (__bf16)lo, b = (__bf16)hi;
@@ -68,22 +76,24 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
            ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
 }
 
-// this lane's half of layer 2 for one group: sum over its 16 hidden units
+// this lane's half of layer 2 for one group: sum over its 16 hidden units,
+// in four partial sums (relu and linear terms of even and odd units) added
+// as (s0 + s1) + (s2 + s3)
 __device__ __forceinline__ float layer2_half(const float (&a2)[16], const float (&c2)[16],
                                              const floatx16 &d)
 {
-    float s = 0.0f;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const unsigned pk = pack_bf16(d[2 * q], d[2 * q + 1]);  // round to bf16 (RNE)
         const float z0 = __builtin_bit_cast(float, pk << 16);
         const float z1 = __builtin_bit_cast(float, pk & 0xffff0000u);
-        s = __builtin_fmaf(a2[2 * q], __builtin_fmaxf(z0, 0.0f), s);
-        s = __builtin_fmaf(c2[2 * q], z0, s);
-        s = __builtin_fmaf(a2[2 * q + 1], __builtin_fmaxf(z1, 0.0f), s);
-        s = __builtin_fmaf(c2[2 * q + 1], z1, s);
+        s0 = __builtin_fmaf(a2[2 * q], __builtin_fmaxf(z0, 0.0f), s0);
+        s1 = __builtin_fmaf(c2[2 * q], z0, s1);
+        s2 = __builtin_fmaf(a2[2 * q + 1], __builtin_fmaxf(z1, 0.0f), s2);
+        s3 = __builtin_fmaf(c2[2 * q + 1], z1, s3);
     }
-    return s;
+    return (s0 + s1) + (s2 + s3);
 }
 
 // Both groups of layer 1 (lanes 0..31 and lanes 32..63 as the 32 columns),
@@ -102,7 +112,7 @@ __device__ __forceinline__ float net_bf16_core(const bf16x8 &a1, const floatx16 
     unsigned g0[4], g1[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const unsigned other = (unsigned)__shfl_xor((int)p[q], 32, 64);
+        const unsigned other = xor32_lanes(p[q]);
         g0[q] = l < 32 ? p[q] : 0u;
         g1[q] = l < 32 ? other : 0u;
     }
@@ -114,7 +124,7 @@ __device__ __forceinline__ float net_bf16_core(const bf16x8 &a1, const floatx16 
     // lane l < 32 owns column l of group 0: halves s0 (own, h = 0) + s0 of lane l + 32;
     // lane l >= 32 owns column l - 32 of group 1: s1 of lane l - 32 (h = 0) + s1 (own)
     const float send = l < 32 ? s1 : s0;
-    const float recv = __shfl_xor(send, 32, 64);
+    const float recv = __builtin_bit_cast(float, xor32_lanes(__builtin_bit_cast(unsigned, send)));
     const float lo = l < 32 ? s0 : recv, hi = l < 32 ? recv : s1;
     return (lo + hi) + b2;
 }

@@ -517,8 +517,11 @@ k_decode_flow(DecodeArgs a)
 // as tagged words (epoch << 32 | grid value): the lanes of the last z line
 // store each grid value they decode to the z-face buffer, the lanes of the
 // last y line to the y-face buffer; 17 lanes of the memory wave load the 17
-// halo lines kPenLook steps ahead and take a word once its tag is this
-// call's epoch (else they poll it, bounded).  Nothing else orders pencils: a
+// halo lines in batches of kPenGroup steps, two batches ahead, and take a
+// word once its tag is this call's epoch (else they poll it, bounded).  The
+// loads are issued by every lane, without branches (lanes with nothing to
+// fetch read a valid dummy word), so that waiting for the older batch never
+// waits for the newer one.  Nothing else orders pencils: a
 // pencil only polls pencils with a lower ticket, which running workgroups
 // hold.
 //
@@ -528,7 +531,7 @@ k_decode_flow(DecodeArgs a)
 // counter; the LDS executes one wave's operations in order.
 constexpr int kPenRing = 32;  // tile columns (a power of two)
 constexpr int kPenRS = 34;    // tile row stride: at most two-way LDS bank conflicts
-constexpr int kPenLook = 8;   // halo words in flight per halo lane (steps ahead)
+constexpr int kPenGroup = 4;  // halo words per load batch; two batches are in flight
 constexpr int kPenAhead = 8;  // halo delivered at most this many steps ahead
 constexpr int kPenRows = 81;  // (tz, ty) in [0, 9)^2
 constexpr unsigned kPenPollLimit = 1u << 26;  // LDS polls of one wave before giving up
@@ -632,15 +635,15 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                 const int lx = (int)(x & 7);
                 const unsigned code = act ? cring[bs * 512 + (lz * 8 + ly) * 8 + lx] : 0u;
                 const bool coded = code != 0;
-                int nv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                const int amask = amask_zy | (x > 0 ? 1 : 0);
-                if (coded) {
+                // read with the code (one LDS round trip); used when coded
+                int nv[8];
+                nv[0] = 0;
 #pragma unroll
-                    for (int o = 1; o < 8; ++o) {
-                        const int dz = (o >> 2) & 1, dy = (o >> 1) & 1, dx = o & 1;
-                        nv[o] = tile[r0 - (dz * 9 + dy) * kPenRS + (dx ? xs1 : xs)];
-                    }
+                for (int o = 1; o < 8; ++o) {
+                    const int dz = (o >> 2) & 1, dy = (o >> 1) & 1, dx = o & 1;
+                    nv[o] = tile[r0 - (dz * 9 + dy) * kPenRS + (dx ? xs1 : xs)];
                 }
+                const int amask = amask_zy | (x > 0 ? 1 : 0);
                 const bool net = use_net && coded && fring[bs] != 0;
                 long long pred = 0;
                 if constexpr (PREC == 1) {
@@ -693,12 +696,7 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                 if (by >= 1 && tz <= ez)
                     hsrc = a.yf + ((by - 1) * n0 + z) * n2;
             }
-            unsigned long long fifo[kPenLook];
-#pragma unroll
-            for (int k = 0; k < kPenLook; ++k) {
-                const long long c = k - hoff;
-                fifo[k] = (hsrc && c >= 0 && c < n2) ? load_tagged(hsrc + c) : 0ULL;
-            }
+            const unsigned long long *hbase = hsrc ? hsrc : a.zf;
             long long cd = -1;  // compute wave progress, as last read
             unsigned polls = 0;
             auto wait_compute = [&](long long need) {
@@ -767,6 +765,17 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                 const bool raw_ok = d_nz <= (unsigned)bsize && d_roff + d_nz <= a.n_raw;
                 if (!raw_ok)
                     err = kECorrupt;
+                if (full && d_nz == 0) {
+                    // no balance point (the common case): only check that no code is 0
+                    const unsigned w[4] = {d_codes.x, d_codes.y, d_codes.z, d_codes.w};
+                    bool z = false;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        z = z || (w[i] & 0xffffu) == 0u || (w[i] >> 16) == 0u;
+                    if (__ballot(z) != 0ULL)
+                        err = kECorrupt;
+                    return;
+                }
                 unsigned run = 0;
                 const unsigned long long below = (1ULL << lane) - 1ULL;
                 for (int c0 = 0; c0 < bsize; c0 += 64) {
@@ -869,43 +878,55 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                 load_meta(2);
             publish();
 
-            for (long long t0 = 0; t0 <= s_last; t0 += kPenLook) {
+            auto issue = [&](unsigned long long (&h)[kPenGroup], long long tau0) {
 #pragma unroll
-                for (int k = 0; k < kPenLook; ++k) {
-                    const long long tau = t0 + k;
+                for (int k = 0; k < kPenGroup; ++k) {
+                    long long c = tau0 + k - hoff;
+                    c = c < 0 ? 0 : (c >= n2 ? n2 - 1 : c);
+                    h[k] = load_tagged(hbase + (hsrc ? c : 0));
+                }
+            };
+            auto deliver = [&](unsigned long long (&h)[kPenGroup], long long tau0) {
+#pragma unroll
+                for (int k = 0; k < kPenGroup; ++k) {
+                    const long long tau = tau0 + k;
                     if (tau > s_last)
                         break;  // uniform
-                    // every four steps: stage the next block when the compute wave
-                    // is done with the block it replaces; wait for that if the
-                    // block is needed within four steps
-                    if ((k & 3) == 0)
-                        try_stage(8 * (staged + 1) <= tau + 4);
                     if (cd < tau - kPenAhead)
                         wait_compute(tau - kPenAhead);
-                    if (hsrc) {
-                        const long long c = tau - hoff;
-                        if (c >= 0 && c < n2) {
-                            unsigned long long v = fifo[k];
-                            unsigned spins = 0;
-                            while ((unsigned)(v >> 32) != epoch) {
-                                if (++spins == kSpinLimit ||
-                                    load_flag(reinterpret_cast<unsigned *>(a.status))) {
-                                    err = kECorrupt;
-                                    atomicCAS(a.status, kOk, kECorrupt);
-                                    break;
-                                }
-                                __builtin_amdgcn_s_sleep(1);
-                                v = load_tagged(hsrc + c);
+                    const long long c = tau - hoff;
+                    const bool need = hsrc && c >= 0 && c < n2;
+                    unsigned long long v = h[k];
+                    if (__ballot(need && (unsigned)(v >> 32) != epoch) != 0ULL) {
+                        // not yet written by the upstream pencil: poll it
+                        unsigned spins = 0;
+                        while (need && (unsigned)(v >> 32) != epoch) {
+                            if (++spins == kSpinLimit ||
+                                load_flag(reinterpret_cast<unsigned *>(a.status))) {
+                                err = kECorrupt;
+                                atomicCAS(a.status, kOk, kECorrupt);
+                                break;
                             }
-                            tile[hrow + (int)(c & (kPenRing - 1))] = (int)(unsigned)v;
+                            __builtin_amdgcn_s_sleep(1);
+                            v = load_tagged(hsrc + c);
                         }
-                        const long long cn = tau + kPenLook - hoff;
-                        if (cn >= 0 && cn < n2)
-                            fifo[k] = load_tagged(hsrc + cn);
                     }
+                    if (need)
+                        tile[hrow + (int)(c & (kPenRing - 1))] = (int)(unsigned)v;
                     hready = tau;
                     publish();
                 }
+            };
+            unsigned long long hA[kPenGroup], hB[kPenGroup];
+            issue(hA, 0);
+            issue(hB, kPenGroup);
+            for (long long t0 = 0; t0 <= s_last; t0 += 2 * kPenGroup) {
+                deliver(hA, t0);
+                try_stage(8 * (staged + 1) <= t0 + 2 * kPenGroup);
+                issue(hA, t0 + 2 * kPenGroup);
+                deliver(hB, t0 + kPenGroup);
+                try_stage(8 * (staged + 1) <= t0 + 3 * kPenGroup);
+                issue(hB, t0 + 3 * kPenGroup);
             }
             hready = s_last + 1;
             publish();
@@ -1084,32 +1105,48 @@ hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *mod
     const unsigned nt = (unsigned)std::min(256LL, std::max(64LL, (nlines + 63) / 64 * 64));
     const bool flow = !a.independent;
     const unsigned grid = flow ? (unsigned)std::max(num_cus, 1) : (unsigned)g.nblocks;
-    const unsigned rgrid = (unsigned)std::min<unsigned long long>((n_raw + 255) / 256, 4096);
-    const unsigned igrid = (unsigned)std::min<long long>((g.N + 255) / 256, 8192);
     const bool pencils = flow && pencil_mode(g);
     if (g.dtype == PWREL_F32) {
-        if (n_raw)
-            hipLaunchKernelGGL(k_raw_grid<float>, dim3(rgrid), dim3(256), 0, s,
-                               static_cast<const float *>(raw), n_raw, c, ws.praw, ws.status);
         if (pencils)
             pencil_by_hidden<float>(HP, a, grid, s);
         else
             by_shape<float>(flow, g.D, g.B, HP, a, grid, nt, lds, s);
-        if (flow)
-            hipLaunchKernelGGL(k_inverse<float>, dim3(igrid), dim3(256), 0, s, ws.pgrid, g.N, c,
-                               static_cast<float *>(xh));
     } else {
-        if (n_raw)
-            hipLaunchKernelGGL(k_raw_grid<double>, dim3(rgrid), dim3(256), 0, s,
-                               static_cast<const double *>(raw), n_raw, c, ws.praw, ws.status);
         if (pencils)
             pencil_by_hidden<double>(HP, a, grid, s);
         else
             by_shape<double>(flow, g.D, g.B, HP, a, grid, nt, lds, s);
-        if (flow)
-            hipLaunchKernelGGL(k_inverse<double>, dim3(igrid), dim3(256), 0, s, ws.pgrid, g.N,
-                               c, static_cast<double *>(xh));
     }
+    return hipGetLastError();
+}
+
+// Grid values of the raw values, before the decoder.
+hipError_t launch_raw_grid(const Geom &g, const DevConsts &c, const void *raw,
+                           unsigned long long n_raw, Workspace &ws, hipStream_t s)
+{
+    if (!n_raw)
+        return hipSuccess;
+    const unsigned grid = (unsigned)std::min<unsigned long long>((n_raw + 255) / 256, 4096);
+    if (g.dtype == PWREL_F32)
+        hipLaunchKernelGGL(k_raw_grid<float>, dim3(grid), dim3(256), 0, s,
+                           static_cast<const float *>(raw), n_raw, c, ws.praw, ws.status);
+    else
+        hipLaunchKernelGGL(k_raw_grid<double>, dim3(grid), dim3(256), 0, s,
+                           static_cast<const double *>(raw), n_raw, c, ws.praw, ws.status);
+    return hipGetLastError();
+}
+
+// x^ of the coded points from the scratch grid field (halo mode), after the decoder.
+hipError_t launch_inverse(const Geom &g, const DevConsts &c, Workspace &ws, void *xh,
+                          hipStream_t s)
+{
+    const unsigned grid = (unsigned)std::min<long long>((g.N + 255) / 256, 8192);
+    if (g.dtype == PWREL_F32)
+        hipLaunchKernelGGL(k_inverse<float>, dim3(grid), dim3(256), 0, s, ws.pgrid, g.N, c,
+                           static_cast<float *>(xh));
+    else
+        hipLaunchKernelGGL(k_inverse<double>, dim3(grid), dim3(256), 0, s, ws.pgrid, g.N, c,
+                           static_cast<double *>(xh));
     return hipGetLastError();
 }
 

@@ -83,6 +83,10 @@ hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *mod
                          const void *raw, unsigned long long n_raw, Workspace &ws,
                          const unsigned *order, unsigned epoch, void *xh, int num_cus,
                          hipStream_t s);
+hipError_t launch_raw_grid(const Geom &g, const DevConsts &c, const void *raw,
+                           unsigned long long n_raw, Workspace &ws, hipStream_t s);
+hipError_t launch_inverse(const Geom &g, const DevConsts &c, Workspace &ws, void *xh,
+                          hipStream_t s);
 hipError_t launch_detmath(const double *x, double *l2, double *e2, uint64_t n, hipStream_t s);
 hipError_t launch_fastmath_check(unsigned long long *out2, hipStream_t s);
 hipError_t launch_hist(const uint16_t *codes, long long n, unsigned long long *hist,

@@ -117,7 +117,8 @@ _SIGS = {
                                     C.c_double, _P, C.c_int, _P, _P, C.c_int, C.c_int, _P,
                                     _P]),
 }
-PHASES = ("stats+consts", "compress", "scan+scatter+header", "decode_scan", "decode_levels")
+PHASES = ("stats+consts", "compress", "scan+scatter+header", "decode_scan", "decode_levels",
+          "decode_raw_grid", "decode_inverse")
 
 _lib = None
 
