@@ -93,33 +93,6 @@ __device__ __forceinline__ int net_err32(float y, const int (&nv)[8])
     return (nv[1] - nv[0]) + (int)__builtin_rintf(y);
 }
 
-// FP32 network output (the evaluation order of predict<>)
-template <int D, int HP, class W>
-__device__ __forceinline__ float net_f32(const int (&nv)[8], const W &wt, float b2, float alpha)
-{
-    constexpr int K = (1 << D) - 2;
-    float u[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        u[k] = k < K ? (float)(nv[k + 2] - nv[1]) : 0.0f;
-    float y = b2;
-#pragma unroll 1
-    for (int j0 = 0; j0 < HP; j0 += 4) {
-#pragma unroll
-        for (int j = j0; j < j0 + 4; ++j) {
-            const float4 wa = wt.a(j), wb = wt.b(j);
-            const float w[6] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y};
-            float z = wb.z;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                z = __builtin_fmaf(w[k], u[k], z);
-            const float h = __builtin_fmaxf(z, z * alpha);
-            y = __builtin_fmaf(wb.w, h, y);
-        }
-    }
-    return y;
-}
-
 // s_waitcnt vmcnt(0): this wave's outstanding global loads and stores are done
 __device__ __forceinline__ void wait_vmem()
 {
@@ -420,11 +393,35 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
                 q6 = c6;
                 const bool full = amask == NO;
                 const bool ok = inside && okb[okr + i] != 0;
-                unsigned short code;
+                unsigned short code, lcode = 0;
                 if constexpr (PREC == 1) {
-                    const long long pred =
-                        predict_bf16<D>(nv, amask, a.use_net != 0 && inside, net16);
-                    code = make_code(pred, nv[0], ok);
+                    // the network on the matrix cores (every lane takes part), Lorenzo
+                    // where it does not apply; the same predictions as predict_bf16
+                    constexpr int K = (1 << D) - 2;
+                    const bool use = a.use_net != 0 && inside && full;
+                    float u[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        u[k] = (k < K && use)
+                                   ? (float)(int)((unsigned)nv[k + 2] - (unsigned)nv[1])
+                                   : 0.0f;
+                    const float y = net_bf16(net16, u);
+                    if (w32) {
+                        const int el = lorenzo_err32<D>(nv, amask);
+                        code = code32(use ? net_err32(y, nv) : el, ok);
+                        lcode = code32(el, ok);
+                    } else {
+                        float yc = y;
+                        if (yc > 0x1p30f)
+                            yc = 0x1p30f;
+                        if (!(yc >= -0x1p30f))
+                            yc = -0x1p30f;
+                        const long long pl = lorenzo_pred<D>(nv, amask);
+                        code = make_code(use ? (long long)nv[1] + (long long)__builtin_rintf(yc)
+                                             : pl,
+                                         nv[0], ok);
+                        lcode = make_code(pl, nv[0], ok);
+                    }
                 } else {
                     if (w32) {
                         const int e =
@@ -444,9 +441,9 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
                 a.codes[pos0 + i] = code;
                 nzero += code == 0 ? 1u : 0u;
                 if (a.judge) {
-                    const unsigned short lcode =
-                        w32 ? code32(lorenzo_err32<D>(nv, amask), ok)
-                            : make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
+                    if constexpr (PREC != 1)
+                        lcode = w32 ? code32(lorenzo_err32<D>(nv, amask), ok)
+                                    : make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
                     jb[okr + i] =
                         0x10000u | (unsigned)judge_bin(code) | ((unsigned)judge_bin(lcode) << 8);
                 }
@@ -476,19 +473,38 @@ __global__ void __launch_bounds__(256) k_compress(CompressArgs a)
                 atomicAdd(&jh[bt * 256 + ((v >> 8) & 255u)], 1u << 16);
             }
             __syncthreads();
-            for (int i = tid; i < nbt * 256; i += NT) {
-                const unsigned w = jh[i];
-                const unsigned c_n = w & 0xffffu, c_l = w >> 16;
-                const int bt = i >> 8;
-                if ((i & 255) == 0)  // bin 0 holds the balance points of both
-                    cnt[bt] = w;
-                if (c_n)
-                    atomicAdd(&jsum[2 * bt],
-                              (unsigned long long)c_n * (unsigned long long)a.qtab[c_n]);
-                if (c_l)
-                    atomicAdd(&jsum[2 * bt + 1],
-                              (unsigned long long)c_l * (unsigned long long)a.qtab[c_l]);
-                jh[i] = 0u;
+            // scores: one wave per block, four bins per lane, then a wave sum
+            for (int bt = tid >> 6; bt < nbt; bt += NT / 64) {
+                const int ln = tid & 63;
+                unsigned *h = jh + bt * 256 + 4 * ln;
+                unsigned w[4];
+                long long qn[4], ql[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    w[k] = h[k];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    qn[k] = a.qtab[w[k] & 0xffffu];  // q(0) = 0
+                    ql[k] = a.qtab[w[k] >> 16];
+                }
+                unsigned long long sn = 0, sl = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    sn += (unsigned long long)(w[k] & 0xffffu) * (unsigned long long)qn[k];
+                    sl += (unsigned long long)(w[k] >> 16) * (unsigned long long)ql[k];
+                    h[k] = 0u;
+                }
+                if (ln == 0)
+                    cnt[bt] = w[0];  // bin 0 holds the balance points of both
+#pragma unroll
+                for (int d = 32; d > 0; d >>= 1) {
+                    sn += (unsigned long long)__shfl_xor((long long)sn, d, 64);
+                    sl += (unsigned long long)__shfl_xor((long long)sl, d, 64);
+                }
+                if (ln == 0) {
+                    jsum[2 * bt] = sn;
+                    jsum[2 * bt + 1] = sl;
+                }
             }
             __syncthreads();
             // blocks where Lorenzo wins: overwrite the network codes written above

@@ -634,8 +634,8 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                 const int bs = (int)((x >> 3) & 7);
                 const int lx = (int)(x & 7);
                 const unsigned code = act ? cring[bs * 512 + (lz * 8 + ly) * 8 + lx] : 0u;
-                const bool coded = code != 0;
-                // read with the code (one LDS round trip); used when coded
+                const bool flag = fring[bs] != 0;
+                // neighbours read with the code (one LDS round trip); used when coded
                 int nv[8];
                 nv[0] = 0;
 #pragma unroll
@@ -643,25 +643,50 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                     const int dz = (o >> 2) & 1, dy = (o >> 1) & 1, dx = o & 1;
                     nv[o] = tile[r0 - (dz * 9 + dy) * kPenRS + (dx ? xs1 : xs)];
                 }
+                const bool coded = code != 0;
                 const int amask = amask_zy | (x > 0 ? 1 : 0);
-                const bool net = use_net && coded && fring[bs] != 0;
-                long long pred = 0;
+                const bool net = use_net && coded && flag;
+                const bool full_nb = amask == 7;
+                // Predictions in 32-bit wrap-around arithmetic: exact wherever the
+                // point is coded (then |prediction - p| < 2^15 and |p| < 2^30).
+                unsigned lor = 0u;
+#pragma unroll
+                for (int o = 1; o < 8; ++o)
+                    if ((o & ~amask) == 0)
+                        lor = lorenzo_sign(o) > 0 ? lor + (unsigned)nv[o] : lor - (unsigned)nv[o];
+                unsigned pred = lor;
                 if constexpr (PREC == 1) {
-                    if (__ballot(net) != 0ULL)  // wave-uniform
-                        pred = predict_bf16<3>(nv, amask, net, net16);
-                    else if (coded)
-                        pred = predict<3, HP>(nv, amask, false, wt, b2, alpha);
+                    if (__ballot(net) != 0ULL) {  // wave-uniform: the matrix cores take every lane
+                        const bool use = net && full_nb;
+                        float u[6];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            u[k] = use ? (float)(int)((unsigned)nv[k + 2] - (unsigned)nv[1]) : 0.0f;
+                        float y = net_bf16(net16, u);
+                        if (y > 0x1p30f)
+                            y = 0x1p30f;
+                        if (!(y >= -0x1p30f))
+                            y = -0x1p30f;
+                        if (use)
+                            pred = (unsigned)nv[1] + (unsigned)(int)__builtin_rintf(y);
+                    }
                 } else {
-                    if (coded)
-                        pred = predict<3, HP>(nv, amask, net, wt, b2, alpha);
+                    if (net && full_nb) {
+                        float y = net_f32<3, HP>(nv, wt, b2, alpha);
+                        if (y > 0x1p30f)
+                            y = 0x1p30f;
+                        if (!(y >= -0x1p30f))
+                            y = -0x1p30f;
+                        pred = (unsigned)nv[1] + (unsigned)(int)__builtin_rintf(y);
+                    }
                 }
                 int p = 0;
                 if (coded) {
-                    const long long pv = pred - ((long long)code - kR);
-                    if (!(pv > -(long long)kGridLimit && pv < (long long)kGridLimit))
+                    const int pv = (int)(pred - (code - (unsigned)kR));
+                    if (!(pv > -(1 << 30) && pv < (1 << 30)))
                         err = kECorrupt;
                     else
-                        p = (int)pv;
+                        p = pv;
                     tile[r0 + xs] = p;
                 } else if (act) {
                     p = tile[r0 + xs];  // a balance point, staged

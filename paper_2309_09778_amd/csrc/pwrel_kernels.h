@@ -143,6 +143,33 @@ __device__ __forceinline__ long long predict(const int (&nv)[8], int amask, bool
     return s;
 }
 
+// FP32 network output (the evaluation order of predict<>)
+template <int D, int HP, class W>
+__device__ __forceinline__ float net_f32(const int (&nv)[8], const W &wt, float b2, float alpha)
+{
+    constexpr int K = (1 << D) - 2;
+    float u[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        u[k] = k < K ? (float)(nv[k + 2] - nv[1]) : 0.0f;
+    float y = b2;
+#pragma unroll 1
+    for (int j0 = 0; j0 < HP; j0 += 4) {
+#pragma unroll
+        for (int j = j0; j < j0 + 4; ++j) {
+            const float4 wa = wt.a(j), wb = wt.b(j);
+            const float w[6] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y};
+            float z = wb.z;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                z = __builtin_fmaf(w[k], u[k], z);
+            const float h = __builtin_fmaxf(z, z * alpha);
+            y = __builtin_fmaf(wb.w, h, y);
+        }
+    }
+    return y;
+}
+
 // Compile-time tile shapes (points per axis, multiples of the block edge) of
 // the common block sizes; ShapeOf<D, 0> means "runtime shape".
 template <int D, int BB> struct ShapeOf {
