@@ -101,8 +101,12 @@ __device__ __forceinline__ void wait_vmem()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Occupancy bound (measured at 512^3): six waves per SIMD for the FP32 and
+// Lorenzo variants, four for the BF16 one; the registers the bound takes away
+// cost a few spills, far less than the latency the extra waves hide.
 template <typename T, int D, int BB, int HP, bool FROM_P, int PREC>
-__global__ void __launch_bounds__(256) k_compress(CompressArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 4 : 6)))
+k_compress(CompressArgs a)
 {
     using S = ShapeOf<D, BB>;
     constexpr bool CT = S::known;

@@ -531,7 +531,7 @@ k_decode_flow(DecodeArgs a)
 // counter; the LDS executes one wave's operations in order.
 constexpr int kPenRing = 32;  // tile columns (a power of two)
 constexpr int kPenRS = 34;    // tile row stride: at most two-way LDS bank conflicts
-constexpr int kPenGroup = 4;  // halo words per load batch; two batches are in flight
+constexpr int kPenGroup = 2;  // halo words per load batch; two batches are in flight
 constexpr int kPenAhead = 8;  // halo delivered at most this many steps ahead
 constexpr int kPenRows = 81;  // (tz, ty) in [0, 9)^2
 constexpr unsigned kPenPollLimit = 1u << 26;  // LDS polls of one wave before giving up
