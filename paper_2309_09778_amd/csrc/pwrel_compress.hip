@@ -484,8 +484,10 @@ k_compress(CompressArgs a)
                 unsigned w[4];
                 long long qn[4], ql[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
+                for (int k = 0; k < 4; ++k) {
                     w[k] = h[k];
+                    h[k] = 0u;
+                }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     qn[k] = a.qtab[w[k] & 0xffffu];  // q(0) = 0
@@ -496,7 +498,6 @@ k_compress(CompressArgs a)
                 for (int k = 0; k < 4; ++k) {
                     sn += (unsigned long long)(w[k] & 0xffffu) * (unsigned long long)qn[k];
                     sl += (unsigned long long)(w[k] >> 16) * (unsigned long long)ql[k];
-                    h[k] = 0u;
                 }
                 if (ln == 0)
                     cnt[bt] = w[0];  // bin 0 holds the balance points of both
@@ -703,6 +704,15 @@ hipError_t launch_compress(const void *x, const int *pfield, const Geom &g, cons
     const int HP = mfma ? 0 : hidden_pad(opt.use_net ? model : nullptr);
     const unsigned grid = (unsigned)std::max(num_cus, 8);  // CUs; go() sizes the grid
     const size_t lds = compress_lds(g, tile.t, opt.judge != 0);
+    // dynamic LDS plus the kernel's static arrays (weights, status) must fit
+    // in one workgroup's share
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess)
+        return hipErrorInvalidDevice;
+    if (lds + sizeof(float4) * kWlds + 64 > (size_t)lds_max)
+        return hipErrorInvalidConfiguration;
     if (pfield)
         by_shape<float, true>(g.D, g.B, HP, a, (unsigned)grid, lds, s);
     else if (g.dtype == PWREL_F32)
