@@ -161,6 +161,22 @@ def bound_ok(xd, xh, eps, torch):
         bool(torch.all(torch.signbit(ht[nz]) == torch.signbit(xt[nz])))
 
 
+def error_stats(ctx, xd, xh, stream, torch, pwrel):
+    """Max relative error of x^ (FP64, over non-zero x) and the RMS prediction
+    error in grid units (from the code histogram: e = code - 2^15, balance
+    points excluded)."""
+    import numpy as np
+    xt, ht = xd.double(), xh.double()
+    nz = xt != 0
+    rel = float(((xt[nz] - ht[nz]).abs() / xt[nz].abs()).max())
+    hist = ctx.histogram(pwrel.sections(stream)["codes"]).astype(np.float64)
+    e = np.arange(65536, dtype=np.float64) - 32768.0
+    h = hist.copy()
+    h[0] = 0.0
+    rms = float(np.sqrt((h * e * e).sum() / max(h.sum(), 1.0)))
+    return {"max_rel_error": rel, "pred_error_rms": round(rms, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +193,8 @@ def main():
                     help="blocks predicted without neighbours outside the block (every block "
                          "decodes on its own)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison")
+    ap.add_argument("--no-alt", action="store_true",
+                    help="skip the learned path with independent blocks (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -213,6 +231,7 @@ def main():
     L = run_path(ctx, xd, eps, B, learned, True, ind, out, xh, K, args.warmup, pwrel, torch)
     ok_l = bound_ok(xd, xh, eps, torch)
     st_l = stream_stats(ctx, L["stream"], x.nbytes, pwrel)
+    st_l.update(error_stats(ctx, xd, xh, L["stream"], torch, pwrel))
     ms_step = L["wall_s"] * 1e3 / K
     value = gb / (L["wall_s"] / K)
     print("[bench] learned path timed", file=sys.stderr, flush=True)
@@ -228,7 +247,26 @@ def main():
                  "phase_ms": {k: round(v, 4) for k, v in P["phase_ms"].items()},
                  "bound_ok_every_point": bound_ok(xd, xh, eps, torch)}
         plain.update(stream_stats(ctx, P["stream"], x.nbytes, pwrel))
+        plain.update(error_stats(ctx, xd, xh, P["stream"], torch, pwrel))
         print("[bench] plain path timed", file=sys.stderr, flush=True)
+
+    # context: the learned path with independent blocks (each block predicted
+    # from its own points only; every block decodes on its own)
+    alt = None
+    if not args.no_alt and not ind:
+        alt_model, alt_rep = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.hidden,
+                                       precision=1, independent=True)
+        A = run_path(ctx, xd, eps, B, alt_model, True, True, out, xh, K, args.warmup, pwrel,
+                     torch)
+        alt = {"network": f"BF16 H={args.hidden} trained with independent blocks, judge",
+               "round_trip_GBps": round(gb / (A["wall_s"] / K), 3),
+               "compress_GBps": round(gb / (A["tc"] / K), 3),
+               "decompress_GBps": round(gb / (A["td"] / K), 3),
+               "phase_ms": {k: round(v, 4) for k, v in A["phase_ms"].items()},
+               "bound_ok_every_point": bound_ok(xd, xh, eps, torch)}
+        alt.update(stream_stats(ctx, A["stream"], x.nbytes, pwrel))
+        alt.update(error_stats(ctx, xd, xh, A["stream"], torch, pwrel))
+        print("[bench] learned path with independent blocks timed", file=sys.stderr, flush=True)
 
     ph = L["phase_ms"]
     N = x.size
@@ -297,6 +335,8 @@ def main():
     res.update(st_l)
     if plain is not None:
         res["plain"] = plain
+    if alt is not None:
+        res["learned_independent_blocks"] = alt
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(x, eps, B, learned)

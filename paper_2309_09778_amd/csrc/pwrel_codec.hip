@@ -217,6 +217,8 @@ __global__ void __launch_bounds__(256) k_consts(const DevStats *parts, int npart
                  (1.0 + 0x1p-6);
         k.fm_n = ((kFastLog2Err + 0x1p-52 * (130.0 + __builtin_fabs(k.Ln))) * k.r + 0x1p-22) *
                  (1.0 + 0x1p-6);
+        // certified-bound margin: 2^-21 / ln(1 + eps), ln(1 + eps) = b_a ln 2
+        k.vm = 0x1p-21 / (k.b_a * 0.6931471805599453);
     }
     k.status = err;
     *c = k;

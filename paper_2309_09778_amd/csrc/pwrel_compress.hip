@@ -182,11 +182,14 @@ k_compress(CompressArgs a)
             ok = 1;
         } else if constexpr (std::is_same<T, float>::value) {
             const float xf = (float)v;
-            if (!grid_value_fast(xf, c, p))
+            bool sure;
+            if (!grid_value_fast(xf, c, p, sure)) {
                 p = grid_value((double)xf, c, err);
+                sure = false;
+            }
             if (verify) {
-                bool okv;
-                if (!within_bound_fast(xf, p, c, okv))
+                bool okv = true;  // certified by the grid value's position in its cell
+                if (!sure && !within_bound_fast(xf, p, c, okv))
                     okv = within_bound((double)xf, grid_inverse<T>(p, c), c.eps);
                 ok = okv ? 1 : 0;
             }

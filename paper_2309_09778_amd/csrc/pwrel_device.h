@@ -31,6 +31,7 @@ struct DevConsts {
     double fm_p, fm_n;  // fast-path margins of t = (log2|x| + L) r, per sign range
     int w32;            // grid values span < 2^27: prediction errors fit 32-bit arithmetic
     int pad2;
+    double vm;          // bound certified when t is this far inside its grid cell (below)
 };
 
 // Running statistics of a field (reduced with integer atomics).
@@ -158,29 +159,43 @@ __device__ __forceinline__ int grid_value(double x, const DevConsts &c, int &err
 // large in the grid that the range checks matter (the FP64 path decides then).
 // x = 0 is exact (p_zero).  Written without branches: both sign ranges and
 // all checks are evaluated and combined with selects.
-__device__ __forceinline__ bool grid_value_fast(float x, const DevConsts &c, int &q)
+//
+// sure: the PW_REL bound certainly holds for x^ = (float) inverse(q), so the
+// verification can be skipped.  With t the exact (log2|x| + L) r, an
+// unclamped q = rint(t) has |q - t| <= 1/2 - d', d' = (distance of the fast t
+// to the rounding boundary) - fm; then x^ / |x| lies within
+// (1 + eps)^(+-(1 - 2 d')) up to the FP32 rounding of x^ (2^-24 relative for
+// 2^-124 <= |x| < 2^126, where x^ stays normal and finite), and
+// d' > vm = 2^-21 / ln(1 + eps) leaves more than eight times the room those
+// roundings and the FP64 comparison need on either side of the bound.  Same
+// sign range as x, never zero.
+__device__ __forceinline__ bool grid_value_fast(float x, const DevConsts &c, int &q, bool &sure)
 {
     const float a = __builtin_fabsf(x);
     const bool neg = x < 0.0f;
     const double t = (fast_log2(a) + (neg ? c.Ln : c.Lp)) * c.r;
     const double margin = neg ? c.fm_n : c.fm_p;
     const double fr = t - __builtin_floor(t);
+    const double dist = __builtin_fabs(fr - 0.5);
     const bool in_range = __builtin_fabs(t) < 0x1p29;
-    const bool ok = a >= 0x1p-126f && a <= 0x1.fffffep127f && in_range &&
-                    __builtin_fabs(fr - 0.5) > margin;
+    const bool ok = a >= 0x1p-126f && a <= 0x1.fffffep127f && in_range && dist > margin;
     const int qi = (int)__builtin_rint(in_range ? t : 0.0);
     const int pz = (int)c.p_zero, bs = (int)c.b_sign, dl = (int)c.delta;
     int v;
-    bool fits = true;
+    bool fits = true, clamped;
     if (neg) {
         // q + delta can reach 2^30 only for fields the FP64 path rejects
         const long long w = (long long)qi + dl;
         fits = w < (long long)kGridLimit;
-        v = (int)(w < bs + 1 ? bs + 1 : w);
+        clamped = w < bs + 1;
+        v = (int)(clamped ? bs + 1 : w);
     } else {
+        clamped = qi < pz + 1 || qi > bs;
         v = qi < pz + 1 ? pz + 1 : (qi > bs ? bs : qi);
     }
     q = x == 0.0f ? pz : v;
+    sure = x == 0.0f || (ok && fits && !clamped && dist > margin + c.vm && a >= 0x1p-124f &&
+                         a < 0x1p126f);
     return x == 0.0f || (ok && fits);
 }
 

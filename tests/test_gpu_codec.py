@@ -164,6 +164,28 @@ def _case(name):
                                 dtype=np.float64)
         x.reshape(-1)[::991] = 7e-321
         return x, 1e-4, 8, random_model(3, 16, 9), False
+    if name.startswith("f32_range_ends"):
+        # magnitudes across the whole FP32 range, with extra mass at the edges
+        # of the fast paths' certified range (2^-124, 2^126), a few subnormals,
+        # zeros and both signs
+        rng = np.random.default_rng(11)
+        n = 20 * 24 * 30
+        e = rng.uniform(-126.0, 127.9, n)
+        pick = rng.random(n)
+        e[pick < 0.15] = rng.uniform(-126.0, -122.0, int((pick < 0.15).sum()))
+        m = (pick >= 0.15) & (pick < 0.30)
+        e[m] = rng.uniform(124.0, 127.9, int(m.sum()))
+        m = (pick >= 0.30) & (pick < 0.32)
+        e[m] = rng.uniform(-140.0, -126.5, int(m.sum()))
+        x = (np.exp2(e) * np.where(rng.random(n) < 0.3, -1.0, 1.0)).astype(np.float32)
+        x[rng.random(n) < 0.01] = 0.0
+        return x.reshape(20, 24, 30), 1e-2, 8, random_model(3, 16, 11), False
+    if name.startswith("f32_smooth_range"):
+        # a smooth field over 75 decades (every point coded at 1e-2), shifted
+        # across the upper or the lower edge of the certified range
+        x = synth.lognormal_grf((20, 24, 30), seed=12, decades=75, neg_frac=0.3, zero_frac=0.01)
+        x = (x * (8.0 if name.endswith("hi") else 2.0 ** -6)).astype(np.float32)
+        return x, 1e-2, 8, random_model(3, 16, 12), False
     if name == "lorenzo_only":
         return synth.lognormal_grf((30, 31, 66), seed=10), 1e-2, 8, None, False
     if name == "single_point":
@@ -181,7 +203,8 @@ def _case(name):
 
 CASES = ["config0_bumps64", "grf_ragged_1e-3", "grf_ragged_indep", "grf_B4_H32", "grf_B16_H8",
          "grf_B5", "zonal_2d", "grf_2d_B64", "grf_1d_halo", "grf_1d_indep", "f64_1e-4",
-         "lorenzo_only", "single_point", "all_zero", "tiny_1d", "sign_gap_delta"]
+         "lorenzo_only", "single_point", "all_zero", "tiny_1d", "sign_gap_delta",
+         "f32_range_ends_1e-2", "f32_smooth_range_hi", "f32_smooth_range_lo"]
 
 
 @pytest.mark.parametrize("name", CASES)
