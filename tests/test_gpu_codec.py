@@ -186,6 +186,12 @@ def _case(name):
         x = synth.lognormal_grf((20, 24, 30), seed=12, decades=75, neg_frac=0.3, zero_frac=0.01)
         x = (x * (8.0 if name.endswith("hi") else 2.0 ** -6)).astype(np.float32)
         return x, 1e-2, 8, random_model(3, 16, 12), False
+    if name.startswith("pencil_"):
+        # halo-mode pencil decoder edges: one pencil row (n0 < 8), short y,
+        # long pencils with a ragged last block, one block column
+        shape = {"pencil_thin_z": (3, 17, 40), "pencil_thin_y": (17, 3, 40),
+                 "pencil_long": (9, 10, 203), "pencil_single_x": (20, 19, 7)}[name]
+        return synth.lognormal_grf(shape, seed=13), 1e-2, 8, random_model(3, 16, 13), False
     if name == "lorenzo_only":
         return synth.lognormal_grf((30, 31, 66), seed=10), 1e-2, 8, None, False
     if name == "single_point":
@@ -204,7 +210,8 @@ def _case(name):
 CASES = ["config0_bumps64", "grf_ragged_1e-3", "grf_ragged_indep", "grf_B4_H32", "grf_B16_H8",
          "grf_B5", "zonal_2d", "grf_2d_B64", "grf_1d_halo", "grf_1d_indep", "f64_1e-4",
          "lorenzo_only", "single_point", "all_zero", "tiny_1d", "sign_gap_delta",
-         "f32_range_ends_1e-2", "f32_smooth_range_hi", "f32_smooth_range_lo"]
+         "f32_range_ends_1e-2", "f32_smooth_range_hi", "f32_smooth_range_lo",
+         "pencil_thin_z", "pencil_thin_y", "pencil_long", "pencil_single_x"]
 
 
 @pytest.mark.parametrize("name", CASES)

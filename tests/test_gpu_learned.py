@@ -286,6 +286,9 @@ def _judge_case(name):
     if name == "grf_random_indep":
         return synth.lognormal_grf((37, 45, 51), seed=12, decades=6, neg_frac=0.1,
                                    zero_frac=0.01), 1e-2, 8, random_model(3, 16, 12, 0.15), True
+    if name == "grf_thin":  # one pencil row in z, ragged in every axis
+        return synth.lognormal_grf((5, 19, 61), seed=12, decades=6, neg_frac=0.1,
+                                   zero_frac=0.01), 1e-2, 8, random_model(3, 16, 12, 0.15), False
     if name == "grf_B4":
         return synth.lognormal_grf((20, 24, 44), seed=13), 1e-2, 4, random_model(3, 32, 13, 0.1), \
             False
@@ -295,7 +298,7 @@ def _judge_case(name):
     raise KeyError(name)
 
 
-JUDGE_CASES = ["grf_random", "grf_random_indep", "grf_B4", "zonal_2d"]
+JUDGE_CASES = ["grf_random", "grf_random_indep", "grf_thin", "grf_B4", "zonal_2d"]
 
 
 @pytest.mark.parametrize("name", JUDGE_CASES)
