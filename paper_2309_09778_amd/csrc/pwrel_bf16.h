@@ -12,10 +12,11 @@
 // lrelu(z) = (1 - alpha) relu(z) + alpha z:
 //   y = b2 + sum_j bf16((1-alpha) v_j) relu(bf16(z_j)) + bf16(alpha v_j) bf16(z_j).
 // Lane l holds 16 of the 32 hidden units of column l % 32 (half h = l / 32);
-// it sums them in a fixed order with FP32 fused multiply-adds (four partial
-// sums, then their sum), the two halves of a column are added, then b2.  Every point is evaluated by the
-// same instruction sequence wherever it sits in the wave, so encoder and
-// decoder agree bit for bit.
+// it packs its activations and the weights in bf16 pairs and sums them with
+// v_dot2 (two exact bf16 products and an FP32 accumulation per instruction)
+// in four partial sums in a fixed order; the two halves of a column are
+// added, then b2.  Every point is evaluated by the same instruction sequence
+// wherever it sits in the wave, so encoder and decoder agree bit for bit.
 // Every lane of the wave must execute these calls (the matrix cores work on
 // the whole wave); lanes without a point feed zero inputs.
 #pragma once
@@ -25,13 +26,14 @@
 namespace pwrel {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 struct NetBf16 {
     bf16x8 a1;      // layer-1 A operand of this lane
     floatx16 c1;    // layer-1 accumulator init: b1 of the rows this lane holds
-    float a2[16];   // bf16((1 - alpha) v) of the rows this lane holds
-    float c2[16];   // bf16(alpha v) of the same rows
+    unsigned a2[8]; // bf16((1 - alpha) v) of the rows this lane holds, in pairs
+    unsigned c2[8]; // bf16(alpha v) of the same rows, in pairs
     float b2;
 };
 
@@ -39,27 +41,6 @@ struct NetBf16 {
 __device__ __forceinline__ int d1_row(int e, int h) { return 8 * (e / 4) + 4 * h + (e % 4); }
 
 __device__ __forceinline__ float bf16_round(float f) { return (float)(__bf16)f; }
-
-__device__ __forceinline__ NetBf16 make_net_bf16(const MlpW &m, int K)
-{
-    NetBf16 n;
-    const int l = threadIdx.x & 63, h = l >> 5, i = l & 31;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int k = 8 * h + e;
-        n.a1[e] = (__bf16)(k < K ? m.w1[i][k] : 0.0f);
-    }
-    const float ar = 1.0f - m.alpha, al = m.alpha;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int row = d1_row(e, h);
-        n.c1[e] = m.b1[row];
-        n.a2[e] = bf16_round(ar * m.v[row]);
-        n.c2[e] = bf16_round(al * m.v[row]);
-    }
-    n.b2 = m.b2;
-    return n;
-}
 
 // the value of lane l ^ 32 (v_permlane32_swap: lanes 32..63 of the first
 // operand trade places with lanes 0..31 of the second)
@@ -76,22 +57,63 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
            ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
 }
 
-// this lane's half of layer 2 for one group: sum over its 16 hidden units,
-// in four partial sums (relu and linear terms of even and odd units) added
-// as (s0 + s1) + (s2 + s3)
-__device__ __forceinline__ float layer2_half(const float (&a2)[16], const float (&c2)[16],
+// layer-2 weights of the rows of elements 2q, 2q + 1 in a lane of half h
+__device__ __forceinline__ unsigned a2_pair(const MlpW &m, int q, int h)
+{
+    const float ar = 1.0f - m.alpha;
+    return pack_bf16(ar * m.v[d1_row(2 * q, h)], ar * m.v[d1_row(2 * q + 1, h)]);
+}
+__device__ __forceinline__ unsigned c2_pair(const MlpW &m, int q, int h)
+{
+    const float al = m.alpha;
+    return pack_bf16(al * m.v[d1_row(2 * q, h)], al * m.v[d1_row(2 * q + 1, h)]);
+}
+
+__device__ __forceinline__ NetBf16 make_net_bf16(const MlpW &m, int K)
+{
+    NetBf16 n;
+    const int l = threadIdx.x & 63, h = l >> 5, i = l & 31;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = 8 * h + e;
+        n.a1[e] = (__bf16)(k < K ? m.w1[i][k] : 0.0f);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+        n.c1[e] = m.b1[d1_row(e, h)];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        n.a2[q] = a2_pair(m, q, h);
+        n.c2[q] = c2_pair(m, q, h);
+    }
+    n.b2 = m.b2;
+    return n;
+}
+
+__device__ __forceinline__ float dot2_bf16(unsigned a, unsigned b, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a),
+                                           __builtin_bit_cast(bf16x2, b), c, false);
+}
+
+// this lane's half of layer 2 for one group: its 16 hidden units
+__device__ __forceinline__ float layer2_half(const unsigned (&a2)[8], const unsigned (&c2)[8],
                                              const floatx16 &d)
 {
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const unsigned pk = pack_bf16(d[2 * q], d[2 * q + 1]);  // round to bf16 (RNE)
-        const float z0 = __builtin_bit_cast(float, pk << 16);
-        const float z1 = __builtin_bit_cast(float, pk & 0xffff0000u);
-        s0 = __builtin_fmaf(a2[2 * q], __builtin_fmaxf(z0, 0.0f), s0);
-        s1 = __builtin_fmaf(c2[2 * q], z0, s1);
-        s2 = __builtin_fmaf(a2[2 * q + 1], __builtin_fmaxf(z1, 0.0f), s2);
-        s3 = __builtin_fmaf(c2[2 * q + 1], z1, s3);
+    for (int q = 0; q < 8; q += 2) {
+        // bf16(z) (round to nearest even) and relu(bf16 z) = bf16(max(z, 0))
+        const unsigned z0 = pack_bf16(d[2 * q], d[2 * q + 1]);
+        const unsigned r0 = pack_bf16(__builtin_fmaxf(d[2 * q], 0.0f),
+                                      __builtin_fmaxf(d[2 * q + 1], 0.0f));
+        const unsigned z1 = pack_bf16(d[2 * q + 2], d[2 * q + 3]);
+        const unsigned r1 = pack_bf16(__builtin_fmaxf(d[2 * q + 2], 0.0f),
+                                      __builtin_fmaxf(d[2 * q + 3], 0.0f));
+        s0 = dot2_bf16(a2[q], r0, s0);
+        s1 = dot2_bf16(c2[q], z0, s1);
+        s2 = dot2_bf16(a2[q + 1], r1, s2);
+        s3 = dot2_bf16(c2[q + 1], z1, s3);
     }
     return (s0 + s1) + (s2 + s3);
 }
@@ -99,7 +121,7 @@ __device__ __forceinline__ float layer2_half(const float (&a2)[16], const float 
 // Both groups of layer 1 (lanes 0..31 and lanes 32..63 as the 32 columns),
 // then layer 2; c1, a2, c2 as in NetBf16 for this lane's half.
 __device__ __forceinline__ float net_bf16_core(const bf16x8 &a1, const floatx16 &c1,
-                                               const float (&a2)[16], const float (&c2)[16],
+                                               const unsigned (&a2)[8], const unsigned (&c2)[8],
                                                float b2, const float (&u)[6])
 {
     const int l = threadIdx.x & 63;
@@ -136,25 +158,25 @@ __device__ __forceinline__ float net_bf16(const NetBf16 &n, const float (&u)[6])
 }
 
 // The same network with c1, a2 and c2 kept in LDS (read at each evaluation)
-// instead of registers: per half h, 48 floats at t + 48 h (c1, a2, c2).
+// instead of registers: per half h, 32 words at t + 32 h (c1 as 16 floats,
+// then the 8 a2 pairs and the 8 c2 pairs).
 struct NetBf16Lds {
     bf16x8 a1;
-    const float *t;
+    const unsigned *t;
     float b2;
 };
 
-__device__ __forceinline__ void stage_net_bf16(float *t, const MlpW &m)
+__device__ __forceinline__ void stage_net_bf16(unsigned *t, const MlpW &m)
 {
-    const float ar = 1.0f - m.alpha, al = m.alpha;
-    for (int i = threadIdx.x; i < 32; i += blockDim.x) {
-        const int h = i >> 4, e = i & 15, row = d1_row(e, h);
-        t[48 * h + e] = m.b1[row];
-        t[48 * h + 16 + e] = bf16_round(ar * m.v[row]);
-        t[48 * h + 32 + e] = bf16_round(al * m.v[row]);
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        const int h = i >> 5, k = i & 31;
+        t[i] = k < 16   ? __builtin_bit_cast(unsigned, m.b1[d1_row(k, h)])
+               : k < 24 ? a2_pair(m, k - 16, h)
+                        : c2_pair(m, k - 24, h);
     }
 }
 
-__device__ __forceinline__ NetBf16Lds make_net_bf16_lds(const MlpW &m, int K, const float *t)
+__device__ __forceinline__ NetBf16Lds make_net_bf16_lds(const MlpW &m, int K, const unsigned *t)
 {
     NetBf16Lds n;
     const int l = threadIdx.x & 63, h = l >> 5, i = l & 31;
@@ -163,20 +185,27 @@ __device__ __forceinline__ NetBf16Lds make_net_bf16_lds(const MlpW &m, int K, co
         const int k = 8 * h + e;
         n.a1[e] = (__bf16)(k < K ? m.w1[i][k] : 0.0f);
     }
-    n.t = t + 48 * h;
+    n.t = t + 32 * h;
     n.b2 = m.b2;
     return n;
 }
 
 __device__ __forceinline__ float net_bf16(const NetBf16Lds &n, const float (&u)[6])
 {
-    const float4 *t4 = reinterpret_cast<const float4 *>(n.t);
+    const uint4 *t4 = reinterpret_cast<const uint4 *>(n.t);
     floatx16 c1;
-    float a2[16], c2[16];
+    unsigned a2[8], c2[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float4 c = t4[q], a = t4[4 + q], v = t4[8 + q];
-        c1[4 * q] = c.x; c1[4 * q + 1] = c.y; c1[4 * q + 2] = c.z; c1[4 * q + 3] = c.w;
+        const uint4 c = t4[q];
+        c1[4 * q] = __builtin_bit_cast(float, c.x);
+        c1[4 * q + 1] = __builtin_bit_cast(float, c.y);
+        c1[4 * q + 2] = __builtin_bit_cast(float, c.z);
+        c1[4 * q + 3] = __builtin_bit_cast(float, c.w);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint4 a = t4[4 + q], v = t4[6 + q];
         a2[4 * q] = a.x; a2[4 * q + 1] = a.y; a2[4 * q + 2] = a.z; a2[4 * q + 3] = a.w;
         c2[4 * q] = v.x; c2[4 * q + 1] = v.y; c2[4 * q + 2] = v.z; c2[4 * q + 3] = v.w;
     }

@@ -134,7 +134,7 @@ struct BlockDecoder {
     int rp;
 
     __device__ BlockDecoder(const DecodeArgs &args, unsigned char *smem, const float4 *wl,
-                            const float *tb)
+                            const unsigned *tb)
         : a(args)
     {
         NT = blockDim.x;
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float4 wl[kWlds];
-    __shared__ float tb[PREC == 1 ? 96 : 1];
+    __shared__ unsigned tb[PREC == 1 ? 64 : 1];
     stage_weights<HP>(wl, a.mlp);
     if constexpr (PREC == 1)
         stage_net_bf16(tb, a.mlp);
@@ -440,7 +440,7 @@ k_decode_flow(DecodeArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float4 wl[kWlds];
-    __shared__ float tb[PREC == 1 ? 96 : 1];
+    __shared__ unsigned tb[PREC == 1 ? 64 : 1];
     __shared__ long long s_ticket[2];
     stage_weights<HP>(wl, a.mlp);
     if constexpr (PREC == 1)
@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
     __shared__ __align__(16) unsigned short cring[8 * 512];
     __shared__ unsigned char fring[8];
     __shared__ float4 wl[kWlds];
-    __shared__ float tb[PREC == 1 ? 96 : 1];
+    __shared__ unsigned tb[PREC == 1 ? 64 : 1];
     __shared__ long long s_ticket, rdy, cdone;
     stage_weights<HP>(wl, a.mlp);
     if constexpr (PREC == 1)
