@@ -15,6 +15,7 @@ plain path (FP32 network H = 16, no judge) is timed the same way for
 comparison.  Prints one JSON line.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -118,6 +119,9 @@ def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, 
         s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind)
         ctx.decompress(s, out=xh)
     torch.cuda.synchronize()
+    # no garbage-collector pause of this interpreter inside the timed steps
+    gc.collect()
+    gc.disable()
     ctx.set_profiling(True)
     phase_sum = {k: 0.0 for k in pwrel.PHASES}
     tc = td = 0.0
@@ -134,6 +138,7 @@ def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, 
         for k, v in ctx.phase_times().items():
             phase_sum[k] += v
     t1 = time.perf_counter()
+    gc.enable()
     ctx.set_profiling(False)
     return {"wall_s": t1 - t0, "tc": tc, "td": td,
             "phase_ms": {k: v / steps for k, v in phase_sum.items()}, "stream": s}

@@ -42,19 +42,38 @@ __device__ __forceinline__ int d1_row(int e, int h) { return 8 * (e / 4) + 4 * h
 
 __device__ __forceinline__ float bf16_round(float f) { return (float)(__bf16)f; }
 
-// the value of lane l ^ 32 (v_permlane32_swap: lanes 32..63 of the first
-// operand trade places with lanes 0..31 of the second)
+// v_permlane32_swap: lanes 32..63 of the first operand trade places with
+// lanes 0..31 of the second; the builtin returns the new first and second
+// operands.  (Where both results of one swap fed the two operands of one
+// FP32 add, hipcc 7.2 read the first result twice; the forms used here
+// compile to distinct registers.)  The value of lane l ^ 32:
 __device__ __forceinline__ unsigned xor32_lanes(unsigned x)
 {
     const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
     return (threadIdx.x & 32) ? r[0] : r[1];
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// two floats to bf16 (round to nearest even), lo in bits 0..15: one
+// v_cvt_pk_bf16_f32
 __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
 {
-    const __bf16 a = (__bf16)lo, b = (__bf16)hi;
-    return (unsigned)__builtin_bit_cast(unsigned short, a) |
-           ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
+    const f32x2 f = {lo, hi};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f, bf16x2));
+}
+
+// relu of two packed bf16 values.  A bf16 value with its sign bit set
+// (negative, or -0) is a negative 16-bit integer and every other one a
+// non-negative one, so a signed 16-bit max with 0 clears exactly the negative
+// halves (one v_pk_max_i16).  Rounding to nearest even keeps the sign, so
+// relu(bf16(z)) = bf16(max(z, 0)) (up to the sign of a zero, which no sum
+// below can see).
+__device__ __forceinline__ unsigned relu_bf16x2(unsigned z)
+{
+    const i16x2 v = __builtin_bit_cast(i16x2, z);
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_max(v, i16x2{0, 0}));
 }
 
 // layer-2 weights of the rows of elements 2q, 2q + 1 in a lane of half h
@@ -103,13 +122,11 @@ __device__ __forceinline__ float layer2_half(const unsigned (&a2)[8], const unsi
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
     for (int q = 0; q < 8; q += 2) {
-        // bf16(z) (round to nearest even) and relu(bf16 z) = bf16(max(z, 0))
+        // bf16(z) (round to nearest even) and relu(bf16 z)
         const unsigned z0 = pack_bf16(d[2 * q], d[2 * q + 1]);
-        const unsigned r0 = pack_bf16(__builtin_fmaxf(d[2 * q], 0.0f),
-                                      __builtin_fmaxf(d[2 * q + 1], 0.0f));
+        const unsigned r0 = relu_bf16x2(z0);
         const unsigned z1 = pack_bf16(d[2 * q + 2], d[2 * q + 3]);
-        const unsigned r1 = pack_bf16(__builtin_fmaxf(d[2 * q + 2], 0.0f),
-                                      __builtin_fmaxf(d[2 * q + 3], 0.0f));
+        const unsigned r1 = relu_bf16x2(z1);
         s0 = dot2_bf16(a2[q], r0, s0);
         s1 = dot2_bf16(c2[q], z0, s1);
         s2 = dot2_bf16(a2[q + 1], r1, s2);
@@ -125,19 +142,23 @@ __device__ __forceinline__ float net_bf16_core(const bf16x8 &a1, const floatx16 
                                                float b2, const float (&u)[6])
 {
     const int l = threadIdx.x & 63;
-    unsigned p[4];
+    unsigned p[3];
     p[0] = pack_bf16(u[0], u[1]);
     p[1] = pack_bf16(u[2], u[3]);
     p[2] = pack_bf16(u[4], u[5]);
-    p[3] = 0u;
-    // group 0: points of lanes 0..31; group 1: points of lanes 32..63 (moved down)
+    // group 0: points of lanes 0..31 (lanes 32..63 zero: B rows 8..15);
+    // group 1: points of lanes 32..63 moved down.  One swap with zero gives
+    // both: the first operand keeps lanes 0..31 and receives zeros above, the
+    // second receives lanes 32..63 below and keeps its zeros above.
     unsigned g0[4], g1[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const unsigned other = xor32_lanes(p[q]);
-        g0[q] = l < 32 ? p[q] : 0u;
-        g1[q] = l < 32 ? other : 0u;
+    for (int q = 0; q < 3; ++q) {
+        const auto r = __builtin_amdgcn_permlane32_swap(p[q], 0u, false, false);
+        g0[q] = r[0];
+        g1[q] = r[1];
     }
+    g0[3] = 0u;
+    g1[3] = 0u;
     const floatx16 d0 =
         __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, __builtin_bit_cast(bf16x8, g0), c1, 0, 0, 0);
     const floatx16 d1 =
