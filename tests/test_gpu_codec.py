@@ -234,6 +234,28 @@ def test_codec_bit_exact_vs_oracle(ctx, name):
     assert_bound(x, xh, eps)
 
 
+@pytest.mark.parametrize("shape", [(37, 45, 51), (24, 16, 40)])
+def test_decode_output_alignment(ctx, shape):
+    """The FP32 inverse writes four values per 16-byte store when the output is
+    16-byte aligned and one value per store otherwise; both forms (and the
+    ragged tail of n % 4 values) give the same bytes as the oracle, balance
+    points included (eps 1e-4 makes some)."""
+    x = synth.lognormal_grf(shape, seed=11, decades=10, neg_frac=0.1, zero_frac=0.01)
+    eps, B = 1e-4, 8
+    stream = ctx.compress(dev(x), eps, B, None, use_net=False)
+    ref = O.compress(x, eps, B, None, O.MODE_LORENZO)
+    assert len(ref["raw"]) > 0
+    ref_xh, _ = O.decompress(ref["codes"], ref["raw"], ref["consts"], x.shape, x.dtype, B, None,
+                             O.MODE_LORENZO)
+    n = x.size
+    buf = torch.full((n + 8,), float("nan"), dtype=torch.float32, device="cuda")
+    for off in (0, 1, 2, 3):
+        out = buf[off:off + n].view(shape)
+        assert (out.data_ptr() % 16 == 0) == (off == 0)
+        got = ctx.decompress(stream, out=out).cpu().numpy()
+        assert np.array_equal(got.view(np.uint8), ref_xh.view(np.uint8)), off
+
+
 def test_determinism_and_histogram(ctx):
     x, eps, B, model, _ = _case("grf_ragged_1e-3")
     a = ctx.compress(dev(x), eps, B, model).clone()
