@@ -134,7 +134,7 @@ k_compress(CompressArgs a)
     unsigned int *cnt = reinterpret_cast<unsigned int *>(ptile + ne);
     using V = typename std::conditional<FROM_P, int, T>::type;
     unsigned int *jh = cnt + nbt;
-    // judge only: both bins of every tile point (bit 16 marks a point)
+    // judge only: both codes of every tile point (network | Lorenzo << 16)
     unsigned *jb = jh + (a.judge ? nbt * 256 : 0);
     unsigned char *okb = reinterpret_cast<unsigned char *>(jb + (a.judge ? ntp : 0));
 
@@ -451,33 +451,27 @@ k_compress(CompressArgs a)
                     if constexpr (PREC != 1)
                         lcode = w32 ? code32(lorenzo_err32<D>(nv, amask), ok)
                                     : make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
-                    jb[okr + i] =
-                        0x10000u | (unsigned)judge_bin(code) | ((unsigned)judge_bin(lcode) << 8);
+                    jb[okr + i] = (unsigned)code | ((unsigned)lcode << 16);
                 }
             }
-            if (a.judge) {
-                for (int i = 0; i < SEG; ++i)
-                    if (!(urow && cx0 + i < limx) && u < nunits)
-                        jb[okr + i] = 0u;  // no point
-            } else if (nzero) {
+            if (!a.judge && nzero)
                 atomicAdd(&cnt[bt], nzero);
-            }
         }
         __syncthreads();
 
         if (a.judge) {
             // --- per-block judge: keep the network iff the entropy of its
             //     clamped codes is strictly below Lorenzo's (fixed-point scores).
-            // Histograms from the bins noted above (LDS atomics outside the
+            // Histograms from the codes noted above (LDS atomics outside the
             // prediction loop, where no memory operation is outstanding) ---
             for (int q = tid; q < ntp; q += NT) {
-                const unsigned v = jb[q];
-                if (v == 0u)
-                    continue;
                 const int cx = q % T2, cy = (q / T2) % T1, cz = q / (T1 * T2);
+                if (!(cz < limz && cy < limy && cx < limx))
+                    continue;  // no point
+                const unsigned v = jb[q];
                 const int bt = ((cz / bd0) * nbt1 + cy / bd1) * nbt2 + cx / bd2;
-                atomicAdd(&jh[bt * 256 + (v & 255u)], 1u);
-                atomicAdd(&jh[bt * 256 + ((v >> 8) & 255u)], 1u << 16);
+                atomicAdd(&jh[bt * 256 + judge_bin(v & 0xffffu)], 1u);
+                atomicAdd(&jh[bt * 256 + judge_bin(v >> 16)], 1u << 16);
             }
             __syncthreads();
             // scores: one wave per block, four bins per lane, then a wave sum
@@ -516,6 +510,7 @@ k_compress(CompressArgs a)
             }
             __syncthreads();
             // blocks where Lorenzo wins: overwrite the network codes written above
+            // with the Lorenzo codes noted in the prediction loop
             for (int q = tid; q < nbt * BV; q += NT) {
                 const int bt = q / BV;
                 if (jsum[2 * bt] > jsum[2 * bt + 1])
@@ -526,23 +521,10 @@ k_compress(CompressArgs a)
                 const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
                 if (!(cz < limz && cy < limy && cx < limx))
                     continue;
-                const int ei = ((cz + h0) * E1 + (cy + h1)) * E2 + (cx + h2);
-                int nv[8];
-                nv[0] = ptile[ei];
-#pragma unroll
-                for (int o = 1; o < (1 << D); ++o)
-                    nv[o] = ptile[ei - noff[o]];
-                const int pz = a.independent ? lz : cz, py = a.independent ? ly : cy,
-                          px = a.independent ? lx : cx;
-                const int amask = ((px != 0 || !(edge & 1)) ? 1 : 0) |
-                                  (D >= 2 && (py != 0 || !(edge & 2)) ? 2 : 0) |
-                                  (D >= 3 && (pz != 0 || !(edge & 4)) ? 4 : 0);
-                const bool ok = okb[(cz * T1 + cy) * T2 + cx] != 0;
                 const long long pos = bst[bt] + (long long)((lz * (int)(bext[bt] >> 16) + ly) *
                                                                 (int)(bext[bt] & 0xffffu) +
                                                             lx);
-                a.codes[pos] = w32 ? code32(lorenzo_err32<D>(nv, amask), ok)
-                                   : make_code(lorenzo_pred<D>(nv, amask), nv[0], ok);
+                a.codes[pos] = (uint16_t)(jb[(cz * T1 + cy) * T2 + cx] >> 16);
             }
             for (int bt = tid; bt < nbt; bt += NT) {
                 const bool use_n = jsum[2 * bt] > jsum[2 * bt + 1];
