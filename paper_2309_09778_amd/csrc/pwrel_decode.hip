@@ -911,7 +911,15 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                     h[k] = load_tagged(hbase + (hsrc ? c : 0));
                 }
             };
-            auto deliver = [&](unsigned long long (&h)[kPenGroup], long long tau0) {
+            // Deliver the batch h (need-steps tau0 ..); hn is the next batch, already
+            // issued.  A word not yet written by the upstream pencil is polled, and
+            // each poll also reloads the word of the next need-step (in h or hn):
+            // the upstream pencil writes it one step later, so it is often valid
+            // when the polled word lands, which saves it a round trip of its own.
+            // Reloading a valid word is harmless: a word of this call only changes
+            // from stale to valid.
+            auto deliver = [&](unsigned long long (&h)[kPenGroup], long long tau0,
+                               unsigned long long (&hn)[kPenGroup]) {
 #pragma unroll
                 for (int k = 0; k < kPenGroup; ++k) {
                     const long long tau = tau0 + k;
@@ -934,6 +942,11 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                             }
                             __builtin_amdgcn_s_sleep(1);
                             v = load_tagged(hsrc + c);
+                            const long long c1 = c + 1 < n2 ? c + 1 : n2 - 1;
+                            if (k + 1 < kPenGroup)
+                                h[k + 1 < kPenGroup ? k + 1 : 0] = load_tagged(hsrc + c1);
+                            else
+                                hn[0] = load_tagged(hsrc + c1);
                         }
                     }
                     if (need)
@@ -946,10 +959,10 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
             issue(hA, 0);
             issue(hB, kPenGroup);
             for (long long t0 = 0; t0 <= s_last; t0 += 2 * kPenGroup) {
-                deliver(hA, t0);
+                deliver(hA, t0, hB);
                 try_stage(8 * (staged + 1) <= t0 + 2 * kPenGroup);
                 issue(hA, t0 + 2 * kPenGroup);
-                deliver(hB, t0 + kPenGroup);
+                deliver(hB, t0 + kPenGroup, hA);
                 try_stage(8 * (staged + 1) <= t0 + 3 * kPenGroup);
                 issue(hB, t0 + 3 * kPenGroup);
             }
