@@ -115,6 +115,7 @@ def cpu_baseline(x, eps, block, model, side=256):
 def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, torch):
     """Warm up, then time `steps` round trips (compress + decompress) of one
     path; returns wall times, per-phase device times and the last stream."""
+    model = pwrel.model_struct(model)  # the C struct, built once
     for _ in range(warmup):
         s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind)
         ctx.decompress(s, out=xh)

@@ -166,19 +166,27 @@ def _stream(stream):
 
 
 def model_struct(model):
-    if model is None:
-        return None
+    """The C struct of a model dict (an Mlp passes through unchanged)."""
+    if model is None or isinstance(model, Mlp):
+        return model
     m = Mlp()
     w1 = np.asarray(model["w1"], dtype=np.float32)
     H = len(model["b1"])
     K = w1.shape[1] if w1.ndim == 2 else 0
+    if H > MAXH or K > MAXK:
+        raise ValueError(f"network {H}x{K} exceeds {MAXH}x{MAXK}")
     m.hidden, m.inputs = H, K
     m.alpha = float(model["alpha"])
-    for j in range(H):
-        for k in range(K):
-            m.w1[j][k] = float(w1[j, k])
-        m.b1[j] = float(model["b1"][j])
-        m.v[j] = float(model["v"][j])
+    # whole arrays at once (zero padded to the struct's fixed sizes)
+    w1p = np.zeros((MAXH, MAXK), dtype=np.float32)
+    w1p[:H, :K] = w1.reshape(H, K)
+    b1p = np.zeros(MAXH, dtype=np.float32)
+    b1p[:H] = np.asarray(model["b1"], dtype=np.float32)
+    vp = np.zeros(MAXH, dtype=np.float32)
+    vp[:H] = np.asarray(model["v"], dtype=np.float32)
+    C.memmove(C.addressof(m.w1), w1p.ctypes.data, C.sizeof(m.w1))
+    C.memmove(C.addressof(m.b1), b1p.ctypes.data, C.sizeof(m.b1))
+    C.memmove(C.addressof(m.v), vp.ctypes.data, C.sizeof(m.v))
     m.b2 = float(model["b2"])
     m.precision = int(model.get("precision", 0))
     return m
@@ -295,6 +303,11 @@ class Context:
     def decompress(self, stream_t, shape=None, dtype=None, out=None, stream=None):
         import torch
         assert stream_t.is_cuda and stream_t.dtype == torch.uint8
+        if out is not None:
+            # the library checks the output's shape and dtype against the header
+            assert out.is_cuda and out.is_contiguous()
+            shape = tuple(out.shape) if shape is None else shape
+            dtype = out.dtype if dtype is None else dtype
         if shape is None or dtype is None:
             h = header(stream_t)
             shape = tuple(h["dims"][:h["ndim"]])

@@ -291,6 +291,15 @@ def test_error_paths(ctx):
         ctx.decompress(ctx.compress(dev(x), 1e-2, 8, None, use_net=False)[:-4], x.shape,
                        torch.float32)
     assert e.value.status == pwrel.ECORRUPT
+    # an output tensor gives the shape and dtype; the library checks them against the header
+    good = ctx.compress(dev(x), 1e-2, 8, None, use_net=False).clone()
+    for wrong in (torch.empty((20, 20, 21), dtype=torch.float32, device="cuda"),
+                  torch.empty((20, 20, 20), dtype=torch.float64, device="cuda")):
+        with pytest.raises(pwrel.PwrelError) as e:
+            ctx.decompress(good, out=wrong)
+        assert e.value.status == pwrel.EINVAL
+    right = torch.empty((20, 20, 20), dtype=torch.float32, device="cuda")
+    assert torch.equal(ctx.decompress(good, out=right), ctx.decompress(good))
 
 
 # --- full size (512^3 FP32), sampled parity and whole-field invariants ------------------------
