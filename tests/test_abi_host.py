@@ -163,3 +163,32 @@ def test_create_without_gpu_fails_cleanly():
         pass
     with pytest.raises(pwrel.PwrelError):
         pwrel.Context(0)
+
+
+def test_model_struct_fills_every_field():
+    """The C struct built from a model dict by whole-array copies holds the
+    same bytes as one filled field by field; a built struct passes through;
+    networks beyond the struct's fixed sizes are refused."""
+    rng = np.random.default_rng(5)
+    for H, K in ((32, 6), (7, 2), (1, 0)):
+        m = {"alpha": 0.03, "w1": rng.standard_normal((H, K)).astype(np.float32),
+             "b1": rng.standard_normal(H).astype(np.float32),
+             "v": rng.standard_normal(H).astype(np.float32), "b2": -0.25, "precision": 1}
+        ref = pwrel.Mlp()
+        ref.hidden, ref.inputs, ref.alpha = H, K, np.float32(0.03)
+        for j in range(H):
+            for k in range(K):
+                ref.w1[j][k] = float(m["w1"][j, k])
+            ref.b1[j] = float(m["b1"][j])
+            ref.v[j] = float(m["v"][j])
+        ref.b2, ref.precision = -0.25, 1
+        s = pwrel.model_struct(m)
+        assert bytes(s) == bytes(ref)
+        assert pwrel.model_struct(s) is s
+        back = pwrel.model_dict(s)
+        for key in ("w1", "b1", "v"):
+            assert np.array_equal(back[key], m[key])
+    with pytest.raises(ValueError):
+        pwrel.model_struct({"alpha": 0.0, "w1": np.zeros((33, 6), np.float32),
+                            "b1": np.zeros(33, np.float32), "v": np.zeros(33, np.float32),
+                            "b2": 0.0})
