@@ -93,6 +93,25 @@ __device__ __forceinline__ void block_reduce(Acc &a)
     }
 }
 
+// FP32 values per thread in 32-bit accumulators, without branches: the same
+// classes and extremes as classify(float)
+struct Acc32 {
+    unsigned mn, mx, nz, nn, nf;
+};
+
+__device__ __forceinline__ void classify32(float v, Acc32 &a)
+{
+    const unsigned b = __float_as_uint(v);
+    const unsigned m = b & 0x7fffffffu;
+    const bool nonfinite = m >= 0x7f800000u, zero = m == 0u;
+    const bool normal = !nonfinite && !zero;
+    a.nf += nonfinite ? 1u : 0u;
+    a.nz += zero ? 1u : 0u;
+    a.nn += normal ? (b >> 31) : 0u;
+    a.mn = normal && m < a.mn ? m : a.mn;
+    a.mx = normal && m > a.mx ? m : a.mx;
+}
+
 template <typename T, typename V, int VW>
 __global__ void __launch_bounds__(256) k_stats(const T *__restrict__ x, long long n,
                                                DevStats *parts)
@@ -102,15 +121,34 @@ __global__ void __launch_bounds__(256) k_stats(const T *__restrict__ x, long lon
     const long long nthr = (long long)gridDim.x * blockDim.x;
     const long long nv = n / VW;
     const V *xv = reinterpret_cast<const V *>(x);
-    for (long long i = tid; i < nv; i += nthr) {
-        const V v = xv[i];
-        const T *e = reinterpret_cast<const T *>(&v);
+    if constexpr (std::is_same<T, float>::value) {
+        // fewer than 2^32 values per thread: the 32-bit counts cannot wrap
+        Acc32 b{~0u, 0u, 0u, 0u, 0u};
+        for (long long i = tid; i < nv; i += nthr) {
+            const V v = xv[i];
+            const T *e = reinterpret_cast<const T *>(&v);
 #pragma unroll
-        for (int q = 0; q < VW; ++q)
-            classify(e[q], a);
+            for (int q = 0; q < VW; ++q)
+                classify32(e[q], b);
+        }
+        for (long long i = nv * VW + tid; i < n; i += nthr)
+            classify32(x[i], b);
+        a.mn = b.mn == ~0u ? ~0ULL : (unsigned long long)b.mn;
+        a.mx = b.mx;
+        a.nz = b.nz;
+        a.nn = b.nn;
+        a.nf = b.nf;
+    } else {
+        for (long long i = tid; i < nv; i += nthr) {
+            const V v = xv[i];
+            const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+            for (int q = 0; q < VW; ++q)
+                classify(e[q], a);
+        }
+        for (long long i = nv * VW + tid; i < n; i += nthr)
+            classify(x[i], a);
     }
-    for (long long i = nv * VW + tid; i < n; i += nthr)
-        classify(x[i], a);
     block_reduce(a);
     if (threadIdx.x == 0) {
         DevStats r{};
