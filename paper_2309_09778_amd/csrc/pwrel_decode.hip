@@ -633,7 +633,11 @@ __global__ void __launch_bounds__(128) k_decode_pencil(DecodeArgs a)
                 const int xs = (int)(x & (kPenRing - 1)), xs1 = (int)((x - 1) & (kPenRing - 1));
                 const int bs = (int)((x >> 3) & 7);
                 const int lx = (int)(x & 7);
-                const unsigned code = act ? cring[bs * 512 + (lz * 8 + ly) * 8 + lx] : 0u;
+                // every lane reads its code (the ring index is in range for any x),
+                // so that the code, the flag and the neighbours below are loaded
+                // together, one LDS round trip
+                const unsigned cv = cring[bs * 512 + (lz * 8 + ly) * 8 + lx];
+                const unsigned code = act ? cv : 0u;
                 const bool flag = fring[bs] != 0;
                 // neighbours read with the code (one LDS round trip); used when coded
                 int nv[8];
