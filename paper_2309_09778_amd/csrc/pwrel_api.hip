@@ -446,9 +446,20 @@ int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, in
     if ((e = launch_consts(g, eps, ctx->ws, s)) != hipSuccess)
         return hip_fail(ctx, e, "consts");
     mark(ctx, 1, s);
-    if ((e = launch_compress(d_field, nullptr, g, tile, model, opt, ctx->ws, codes, counts,
-                             bflags, ctx->num_cus, s)) != hipSuccess)
+    if (g.dtype == PWREL_F32) {
+        // two passes: grid values and bound checks once per value into the
+        // scratch grid field, then prediction and quantization from it
+        if ((e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
+            return fail(ctx, PWREL_ENOMEM, "grid field allocation failed");
+        if ((e = launch_grid_entries(static_cast<const float *>(d_field), g, ctx->ws,
+                                     ctx->ws.pgrid, s)) != hipSuccess ||
+            (e = launch_compress(d_field, ctx->ws.pgrid, g, tile, model, opt, ctx->ws, codes,
+                                 counts, bflags, ctx->num_cus, s, true)) != hipSuccess)
+            return hip_fail(ctx, e, "compress");
+    } else if ((e = launch_compress(d_field, nullptr, g, tile, model, opt, ctx->ws, codes,
+                                    counts, bflags, ctx->num_cus, s)) != hipSuccess) {
         return hip_fail(ctx, e, "compress");
+    }
     mark(ctx, 2, s);
     if ((e = launch_scan(counts, g, ctx->ws, s)) != hipSuccess)
         return hip_fail(ctx, e, "scan");

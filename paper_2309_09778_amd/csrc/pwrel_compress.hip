@@ -29,6 +29,7 @@ struct CompressArgs {
     long long nt[3];
     long long ntiles;
     int use_net, judge, independent;
+    int entries;  // grid-field input: 2 p (+1 where the bound check failed) instead of p
     uint16_t *codes;
     uint32_t *counts;
     uint8_t *bflags;
@@ -178,8 +179,9 @@ k_compress(CompressArgs a)
     const V *src = FROM_P ? reinterpret_cast<const V *>(a.pfield) : reinterpret_cast<const V *>(a.x);
     auto point = [&](V v, bool verify, int &p, unsigned char &ok) {
         if constexpr (FROM_P) {
-            p = (int)v;
-            ok = 1;
+            const int e = (int)v;
+            p = a.entries ? (e >> 1) : e;
+            ok = (a.entries && (e & 1)) ? 0 : 1;
         } else if constexpr (std::is_same<T, float>::value) {
             const float xf = (float)v;
             bool sure;
@@ -659,14 +661,66 @@ static void by_shape(int D, int B, int HP, const CompressArgs &a, unsigned grid,
         by_hidden<T, 1, 0, FP>(HP, a, grid, lds, s);
 }
 
+// Grid value and bound check of every value of an FP32 field (the same
+// fast paths, fallbacks and order as the fused kernel's per-point step), one
+// entry per value: 2 p, plus 1 where the PW_REL bound check fails.  The fused
+// kernel then reads entries instead of values, so no extended tile computes
+// its halo's grid values a second time.
+__device__ __forceinline__ int grid_entry(float xf, const DevConsts &c, int &err)
+{
+    int p;
+    bool sure;
+    if (!grid_value_fast(xf, c, p, sure)) {
+        p = grid_value((double)xf, c, err);
+        sure = false;
+    }
+    bool ok = true;
+    if (!sure && !within_bound_fast(xf, p, c, ok))
+        ok = within_bound((double)xf, grid_inverse<float>(p, c), c.eps);
+    return (int)(((unsigned)p << 1) | (ok ? 0u : 1u));  // |p| < 2^30
+}
+
+__global__ void __launch_bounds__(256) k_grid_entries(const float *__restrict__ x, long long n,
+                                                      const DevConsts *consts, int *status,
+                                                      int *__restrict__ ent)
+{
+    if (*status != kOk)
+        return;  // every thread reads the same word: a uniform exit
+    const DevConsts c = *consts;
+    int err = kOk;
+    const long long stride = (long long)gridDim.x * 256;
+    const long long tid = blockIdx.x * 256LL + threadIdx.x;
+    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    const long long n4 = vec ? n >> 2 : 0;
+    for (long long i = tid; i < n4; i += stride) {
+        const float4 v = reinterpret_cast<const float4 *>(x)[i];
+        reinterpret_cast<int4 *>(ent)[i] = make_int4(grid_entry(v.x, c, err), grid_entry(v.y, c, err),
+                                                     grid_entry(v.z, c, err), grid_entry(v.w, c, err));
+    }
+    for (long long i = 4 * n4 + tid; i < n; i += stride)
+        ent[i] = grid_entry(x[i], c, err);
+    set_status(status, err);
+}
+
+hipError_t launch_grid_entries(const float *x, const Geom &g, Workspace &ws, int *ent,
+                               hipStream_t s)
+{
+    const long long work = (g.N + 3) / 4;
+    const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>((work + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_grid_entries, dim3(grid), dim3(256), 0, s, x, g.N, ws.consts, ws.status,
+                       ent);
+    return hipGetLastError();
+}
+
 hipError_t launch_compress(const void *x, const int *pfield, const Geom &g, const Tile &tile,
                            const pwrel_mlp *model, const pwrel_options &opt, Workspace &ws,
                            uint16_t *codes, uint32_t *counts, uint8_t *bflags, int num_cus,
-                           hipStream_t s)
+                           hipStream_t s, bool entries)
 {
     CompressArgs a{};
     a.x = x;
     a.pfield = pfield;
+    a.entries = entries ? 1 : 0;
     for (int d = 0; d < 3; ++d) {
         a.n[d] = g.n[d];
         a.bd[d] = g.bd[d];

@@ -68,10 +68,15 @@ bool pencil_mode(const Geom &g);
 hipError_t launch_stats(const void *x, const Geom &g, Workspace &ws, hipStream_t s);
 hipError_t launch_consts(const Geom &g, double eps, Workspace &ws, hipStream_t s);
 hipError_t launch_transform(const void *x, const Geom &g, Workspace &ws, int *d_p, hipStream_t s);
+// pfield: grid field input instead of x (entries: 2 p + failed-check bit, from
+// launch_grid_entries; else plain p with every check passed)
 hipError_t launch_compress(const void *x, const int *pfield, const Geom &g, const Tile &tile,
                            const pwrel_mlp *model, const pwrel_options &opt, Workspace &ws,
                            uint16_t *codes, uint32_t *counts, uint8_t *bflags, int num_cus,
-                           hipStream_t s);
+                           hipStream_t s, bool entries = false);
+// grid value and bound check of every FP32 value, one entry each (2 p + failed-check bit)
+hipError_t launch_grid_entries(const float *x, const Geom &g, Workspace &ws, int *ent,
+                               hipStream_t s);
 hipError_t launch_scan(const uint32_t *counts, const Geom &g, Workspace &ws, hipStream_t s);
 hipError_t launch_scatter(const void *x, const Geom &g, const uint16_t *codes,
                           const uint32_t *counts, Workspace &ws, void *raw,
