@@ -205,7 +205,8 @@ uint64_t pwrel_huffman_bits(const uint64_t *hist65536, uint32_t *max_len_out);
  * Device time per phase of the last pwrel_compress / pwrel_decompress on this
  * context, in milliseconds, from HIP events recorded on the caller's stream
  * while profiling is enabled (off by default; enabling adds no host sync).
- * Phases: 0 statistics + constants, 1 fused compression kernel,
+ * Phases: 0 statistics + constants, 1 compression kernels (FP32: grid
+ * values and bound checks, then the fused prediction / quantisation kernel),
  * 2 scan + raw scatter + header, 3 decoder scan, 4 decoder main kernel
  * (block levels, pencils or independent blocks), 5 decoder grid values of
  * the raw values, 6 decoder inverse map of the scratch grid field (halo

@@ -1,12 +1,17 @@
-// Fused compression kernel (steps: transform, prediction, quantisation,
+// Compression kernels (steps: transform, prediction, quantisation,
 // verification, per-block balance-point counts, per-block judge) for gfx950.
 //
-// A workgroup works on a tile of whole blocks plus the one-point halo on the
-// low side of every active axis (the "extended tile").  Its input values are
-// loaded into registers one tile ahead (coalesced rows), so the loads of the
-// next tile are in flight while the current one is predicted.  Grid values go
-// to LDS (FP32 fields: the hardware log2 / exp2 fast paths with certified
-// fallback to FP64); the tile points are bound-checked.  The tile is then
+// FP32 fields take two passes: k_grid_entries computes the grid value and
+// bound check of every value once (the hardware log2 / exp2 fast paths with
+// certified fallback to FP64) into an entry 2 p (+1 where the check fails),
+// then the fused kernel k_compress reads entries.  FP64 fields take the fused
+// kernel alone, which then computes grid values and checks itself.
+//
+// A workgroup of k_compress works on a tile of whole blocks plus the
+// one-point halo on the low side of every active axis (the "extended tile").
+// Its inputs (entries or values) are copied global -> LDS one tile ahead
+// (coalesced rows), so the loads of the next tile are in flight while the
+// current one is predicted.  Grid values and check bits go to LDS.  The tile is then
 // walked in stream order (block-major, so a wave writes 64 consecutive
 // codes), every point predicted independently from its neighbours' grid
 // values (the data selection rule that removes the serial dependency), and
