@@ -114,6 +114,8 @@ template <typename T, int D, int BB, int HP, bool FROM_P, int PREC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 4 : 6)))
 k_compress(CompressArgs a)
 {
+    static_assert(FROM_P || !std::is_same<T, float>::value,
+                  "FP32 values are read as entries (k_grid_entries)");
     using S = ShapeOf<D, BB>;
     constexpr bool CT = S::known;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -187,20 +189,8 @@ k_compress(CompressArgs a)
             const int e = (int)v;
             p = a.entries ? (e >> 1) : e;
             ok = (a.entries && (e & 1)) ? 0 : 1;
-        } else if constexpr (std::is_same<T, float>::value) {
-            const float xf = (float)v;
-            bool sure;
-            if (!grid_value_fast(xf, c, p, sure)) {
-                p = grid_value((double)xf, c, err);
-                sure = false;
-            }
-            if (verify) {
-                bool okv = true;  // certified by the grid value's position in its cell
-                if (!sure && !within_bound_fast(xf, p, c, okv))
-                    okv = within_bound((double)xf, grid_inverse<T>(p, c), c.eps);
-                ok = okv ? 1 : 0;
-            }
         } else {
+            // FP64 values (FP32 fields arrive as entries from k_grid_entries)
             const double xv = (double)v;
             p = grid_value(xv, c, err);
             if (verify)
@@ -760,7 +750,7 @@ hipError_t launch_compress(const void *x, const int *pfield, const Geom &g, cons
     if (pfield)
         by_shape<float, true>(g.D, g.B, HP, a, (unsigned)grid, lds, s);
     else if (g.dtype == PWREL_F32)
-        by_shape<float, false>(g.D, g.B, HP, a, (unsigned)grid, lds, s);
+        return hipErrorInvalidValue;  // FP32 fields take the two passes (entries)
     else
         by_shape<double, false>(g.D, g.B, HP, a, (unsigned)grid, lds, s);
     return hipGetLastError();
