@@ -256,6 +256,33 @@ def test_decode_output_alignment(ctx, shape):
         assert np.array_equal(got.view(np.uint8), ref_xh.view(np.uint8)), off
 
 
+@pytest.mark.parametrize("shape", [(37, 45, 51), (24, 16, 40)])
+def test_compress_input_alignment(ctx, shape):
+    """Statistics and grid values read four values per 16-byte load when the
+    field is 16-byte aligned and one value per load otherwise; both forms
+    (and the ragged tail of n % 4 values) give the same stream."""
+    x = synth.lognormal_grf(shape, seed=12, decades=10, neg_frac=0.1, zero_frac=0.01)
+    n = x.size
+    buf = torch.zeros(n + 8, dtype=torch.float32, device="cuda")
+    model = random_model(3, 16, 12)
+    ref = None
+    for off in (0, 1, 2, 3):
+        src = buf[off:off + n].view(shape)
+        src.copy_(dev(x))
+        assert (src.data_ptr() % 16 == 0) == (off == 0)
+        for use_net in (False, True):
+            s = ctx.compress(src, 1e-3, 8, model if use_net else None, use_net=use_net).clone()
+            if off == 0:
+                if not use_net:
+                    ref = s
+                    o = O.compress(x, 1e-3, 8, None, O.MODE_LORENZO)
+                    assert np.array_equal(host_sections(s)["codes"], o["codes"])
+                continue
+            base = ctx.compress(dev(x), 1e-3, 8, model if use_net else None, use_net=use_net)
+            assert torch.equal(s, base), (off, use_net)
+    assert ref is not None
+
+
 def test_determinism_and_histogram(ctx):
     x, eps, B, model, _ = _case("grf_ragged_1e-3")
     a = ctx.compress(dev(x), eps, B, model).clone()
