@@ -99,6 +99,11 @@ def lib():
                                     C.POINTER(_MLP), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.or_mlp_eval_many.argtypes = [C.POINTER(_MLP), P, C.c_int64, P]
         L.or_mlp_eval_bf16_many.argtypes = [C.POINTER(_MLP), P, C.c_int64, P, P]
+        L.or_mlp_eval_f64_many.argtypes = [C.POINTER(_MLP), P, C.c_int64, P, P]
+        L.or_loss_grad_abs.argtypes = [P, C.c_int, C.c_int, C.c_double, P, P, C.c_int64,
+                                       C.c_double, C.c_double, P]
+        L.or_theta_eval_many.argtypes = [P, C.c_int, C.c_int, C.c_double, P, C.c_int64,
+                                         C.c_double, P]
         L.or_bf16_rne.restype = C.c_float
         L.or_bf16_rne.argtypes = [C.c_float]
         L.or_entropy_j.restype = C.c_int64
@@ -193,6 +198,19 @@ def mlp_eval_bf16_ref(model, u):
     m = _to_c_mlp(model)
     lib().or_mlp_eval_bf16_many(C.byref(m), _ptr(u), n, _ptr(y), _ptr(s))
     return y, s
+
+
+def mlp_eval_f64(model, u):
+    """FP64 value of the network (FP32 weights, inputs as FP32 values) and the
+    bound on the error of any BF16-operand evaluation of it (the oracle's
+    mlp_bf16_bound): returns (y, bound)."""
+    u = np.ascontiguousarray(u, dtype=np.float32)
+    n = u.shape[0]
+    y = np.zeros(n)
+    b = np.zeros(n)
+    m = _to_c_mlp(model)
+    lib().or_mlp_eval_f64_many(C.byref(m), _ptr(u), n, _ptr(y), _ptr(b))
+    return y, b
 
 
 # --- deterministic math -------------------------------------------------------
@@ -365,7 +383,8 @@ def entropy_j(codes):
 
 
 def judge_j(codes):
-    """Per-block judge score of a code list (balance point and clamped errors)."""
+    """Per-block judge score of a block's codes: J of their full multiset
+    (n q(n) - J = 2^32 x the block's code entropy in bits)."""
     codes = np.ascontiguousarray(codes, dtype=np.uint16)
     return int(lib().or_judge_j(_ptr(codes), codes.size))
 
@@ -417,6 +436,28 @@ def loss_grad(theta, H, K, alpha, u, t, sigma, lam):
     loss = lib().or_loss_grad(_ptr(theta), H, K, float(alpha), _ptr(u), _ptr(t), t.size,
                               float(sigma), float(lam), _ptr(g))
     return loss, g
+
+
+def loss_grad_abs(theta, H, K, alpha, u, t, sigma, lam):
+    """Per-component sum of the magnitudes the gradient of loss_grad adds up."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    g = np.zeros_like(theta)
+    lib().or_loss_grad_abs(_ptr(theta), H, K, float(alpha), _ptr(u), _ptr(t), t.size,
+                           float(sigma), float(lam), _ptr(g))
+    return g
+
+
+def theta_eval(theta, H, K, alpha, u, sigma):
+    """FP64 output of scaled-domain parameters theta for inputs u / sigma."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, K) if K else \
+        np.zeros((np.shape(u)[0], 0))
+    y = np.zeros(u.shape[0])
+    lib().or_theta_eval_many(_ptr(theta), H, K, float(alpha), _ptr(u), u.shape[0],
+                             float(sigma), _ptr(y))
+    return y
 
 
 def train_pass(theta, H, K, alpha, u, t, sigma, lam, lr, batch, opt, adam_m=None, adam_v=None,

@@ -413,6 +413,65 @@ static double mlp_eval_bf16_ref(const or_mlp *m, const float *u, double *slack)
     return y;
 }
 
+/* The network evaluated in FP64 from its FP32 weights (the value every
+ * finite-precision evaluation approximates); u as given (FP32 values). */
+static double mlp_eval_f64(const or_mlp *m, const float *u)
+{
+    const double a = (double)m->alpha;
+    double y = (double)m->b2;
+    for (int j = 0; j < m->hidden; ++j) {
+        double z = (double)m->b1[j];
+        for (int k = 0; k < m->inputs; ++k)
+            z += (double)m->w1[j][k] * (double)u[k];
+        y += (double)m->v[j] * (z < 0.0 ? a * z : z);
+    }
+    return y;
+}
+
+/* Error bound of BF16-operand inference against mlp_eval_f64.  It covers any
+ * evaluation in which
+ *   (i)  every first-layer weight and every input is rounded once to bfloat16
+ *        (8 significant bits: relative error <= U = 2^-8), the products (exact
+ *        in FP32) and b1 summed in FP32 in any order;
+ *   (ii) every hidden pre-activation is rounded once to bfloat16 before the
+ *        leaky ReLU;
+ *   (iii) every output weight enters as bfloat16 numbers within relative
+ *        U + 2^-22 of (1 - alpha) v and alpha v (the two parts of the leaky
+ *        ReLU, v lrelu(z) = (1 - alpha) v relu(z) + alpha v z, possibly after
+ *        FP32 scalings) or of v itself, and the 2H (or H) products plus b2 are
+ *        summed in FP32 in any order.
+ * With S_j = sum_k |w_jk u_k|, Z_j = |z_j|, g_n = n 2^-24 / (1 - n 2^-24):
+ *   first layer:  d_j = (2U + U^2) S_j + g_K (|b1_j| + (1 + U)^2 S_j)
+ *   rounding z:   D_j = d_j + U (Z_j + d_j)           (|z^_j - z_j| <= D_j)
+ *   unit j:       E_j = |v_j| D_j + (U + 2^-22) |v_j| (Z_j + D_j)
+ *                 (lrelu is 1-Lipschitz and |lrelu(z)| <= |z|)
+ *   second layer: g_{2H} (|b2| + (1 + U + 2^-22) sum_j |v_j| (Z_j + D_j))
+ * The bound is the sum of the E_j and the second-layer term, plus 2^-50 of
+ * the magnitudes for the FP64 reference's own rounding. */
+static double mlp_bf16_bound(const or_mlp *m, const float *u)
+{
+    const double U = 0x1p-8, Uw = 0x1p-8 + 0x1p-22;
+    const int K = m->inputs, H = m->hidden;
+    const double gK = K * 0x1p-24 / (1.0 - K * 0x1p-24);
+    const double g2H = 2 * H * 0x1p-24 / (1.0 - 2 * H * 0x1p-24);
+    double sum_e = 0.0, mag2 = fabs((double)m->b2), magall = fabs((double)m->b2);
+    for (int j = 0; j < H; ++j) {
+        double z = (double)m->b1[j], S = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double t = (double)m->w1[j][k] * (double)u[k];
+            z += t;
+            S += fabs(t);
+        }
+        const double Z = fabs(z), av = fabs((double)m->v[j]);
+        const double d = (2.0 * U + U * U) * S + gK * (fabs((double)m->b1[j]) + (1.0 + U) * (1.0 + U) * S);
+        const double D = d + U * (Z + d);
+        sum_e += av * D + Uw * av * (Z + D);
+        mag2 += (1.0 + Uw) * av * (Z + D);
+        magall += av * Z + fabs((double)m->b1[j]) + S;
+    }
+    return sum_e + g2H * mag2 + 0x1p-50 * magall;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry: C-order dims n[0..D-1] (axis D-1 fastest), blocks of edge B     */
 /* clipped at the high faces, blocks in raster order, points in local raster */
@@ -645,28 +704,19 @@ static int64_t entropy_j(uint16_t *tmp, int64_t n)
     return J;
 }
 
-/* Per-block judge score: J over bins, bin 0 = the balance point (code 0),
- * else 1 + (error clamped to [-127, 127]) + 127. */
+/* Per-block judge score: J of the block's codes taken as they are, every
+ * distinct code (code 0, the balance point, included) one symbol of the
+ * multiset, so that n q(n) - J is 2^32 times the block's empirical code
+ * entropy in bits (Sec. 4.3 picks the predictor whose codes are cheapest to
+ * entropy-code).  The caller's codes are left in their order. */
 static int64_t judge_j(const uint16_t *codes, int64_t n)
 {
-    int64_t cnt[256];
-    memset(cnt, 0, sizeof cnt);
-    for (int64_t i = 0; i < n; ++i) {
-        int bin = 0;
-        if (codes[i] != 0) {
-            int64_t e = (int64_t)codes[i] - OR_R;
-            if (e < -127)
-                e = -127;
-            if (e > 127)
-                e = 127;
-            bin = (int)(e + 128);
-        }
-        cnt[bin]++;
-    }
-    int64_t J = 0;
-    for (int b = 0; b < 256; ++b)
-        if (cnt[b])
-            J += cnt[b] * qlog(cnt[b]);
+    uint16_t *tmp = (uint16_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint16_t));
+    if (!tmp)
+        return INT64_MIN;
+    memcpy(tmp, codes, (size_t)n * sizeof(uint16_t));
+    int64_t J = entropy_j(tmp, n);
+    free(tmp);
     return J;
 }
 
@@ -1104,6 +1154,65 @@ double or_loss_grad(const double *theta, int H, int K, double alpha, const doubl
     return loss;
 }
 
+/* Magnitudes behind each gradient component of or_loss_grad: the sum over
+ * samples of |each sample's contribution| / n, plus |lambda w|.  A summation
+ * in finite precision is off by at most a small multiple of its unit
+ * roundoff times this sum, whatever the order (used for tolerances). */
+void or_loss_grad_abs(const double *theta, int H, int K, double alpha, const double *u,
+                      const double *t, int64_t n, double sigma, double lambda, double *gabs)
+{
+    const double *W = theta, *b1 = theta + H * K, *v = theta + H * K + H;
+    double b2 = theta[H * K + 2 * H];
+    int64_t np = nparams(H, K);
+    for (int64_t q = 0; q < np; ++q)
+        gabs[q] = 0.0;
+    double z[OR_MAXH], h[OR_MAXH], us[OR_MAXK];
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < K; ++k)
+            us[k] = u[i * K + k] / sigma;
+        double y = b2;
+        for (int j = 0; j < H; ++j) {
+            double a = b1[j];
+            for (int k = 0; k < K; ++k)
+                a += W[j * K + k] * us[k];
+            z[j] = a;
+            h[j] = (a < 0.0) ? alpha * a : a;
+            y += v[j] * h[j];
+        }
+        double gy = fabs(y - t[i] / sigma) / (double)n;
+        for (int j = 0; j < H; ++j) {
+            gabs[H * K + H + j] += gy * fabs(h[j]);
+            double gz = gy * fabs(v[j]) * ((z[j] < 0.0) ? alpha : 1.0);
+            gabs[H * K + j] += gz;
+            for (int k = 0; k < K; ++k)
+                gabs[j * K + k] += gz * fabs(us[k]);
+        }
+        gabs[H * K + 2 * H] += gy;
+    }
+    for (int q = 0; q < H * K; ++q)
+        gabs[q] += fabs(lambda * W[q]);
+    for (int j = 0; j < H; ++j)
+        gabs[H * K + H + j] += fabs(lambda * v[j]);
+}
+
+/* Network value in the scaled domain of the trainer (FP64): the output for
+ * the inputs u / sigma, parameters theta = [w1 | b1 | v | b2]. */
+void or_theta_eval_many(const double *theta, int H, int K, double alpha, const double *u,
+                        int64_t n, double sigma, double *y)
+{
+    const double *W = theta, *b1 = theta + H * K, *v = theta + H * K + H;
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = theta[H * K + 2 * H];
+        for (int j = 0; j < H; ++j) {
+            double a = b1[j];
+            for (int k = 0; k < K; ++k)
+                a += W[j * K + k] * (u[i * K + k] / sigma);
+            acc += v[j] * ((a < 0.0) ? alpha * a : a);
+        }
+        y[i] = acc;
+    }
+}
+
 /* One pass over [0, n) in minibatches of `batch`, in index order.
  * opt 0 = SGD, 1 = Adam (beta1 0.9, beta2 0.999, eps 1e-8).
  * theta is updated in place; adam_m/adam_v/step carry Adam state. */
@@ -1289,6 +1398,16 @@ void or_mlp_eval_bf16_many(const or_mlp *m, const float *u, int64_t n, double *y
 }
 
 float or_bf16_rne(float f) { return bf16_rne(f); }
+
+/* FP64 value of the network and the BF16 error bound of mlp_bf16_bound. */
+void or_mlp_eval_f64_many(const or_mlp *m, const float *u, int64_t n, double *y, double *bound)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        y[i] = mlp_eval_f64(m, u + i * m->inputs);
+        if (bound)
+            bound[i] = mlp_bf16_bound(m, u + i * m->inputs);
+    }
+}
 
 size_t or_sizeof_mlp(void) { return sizeof(or_mlp); }
 size_t or_sizeof_consts(void) { return sizeof(or_consts); }

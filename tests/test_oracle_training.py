@@ -117,3 +117,34 @@ def test_training_rule_selects_no_worse_than_untrained(kind):
     if kind == "grf":
         # log-normal k^-3 field: one SGD pass buys a large entropy drop
         assert idx > 0 and gain > 0.3, gain
+
+
+@pytest.mark.parametrize("K,H,sigma", [(6, 16, 7.3), (6, 32, 0.37), (2, 8, 123.0)])
+def test_fold_is_scale_equivariant(K, H, sigma):
+    """The exported network (scale folded in: w1 / s, b1, v s, b2 s) is the
+    trained one moved back to grid units: y_raw(u) = s y_scaled(u / s) for
+    every u.  Any other placement of s (b1 s, w1 s, v / s, b2 unscaled)
+    breaks the identity by far more than the FP32 rounding of the weights."""
+    rng = np.random.default_rng(K * 1000 + H)
+    th = rng.normal(0, 0.5, H * K + 2 * H + 1)
+    tmpl = O.mlp_init(3 if K == 6 else 2, H, seed=1)
+    m = O.model_from_theta(tmpl, th, sigma)
+    u = rng.integers(-500, 501, size=(400, K)).astype(np.float32)
+    y_raw, _ = O.mlp_eval_f64(m, u)
+    y_scaled = O.theta_eval(th, H, K, 0.01, u, sigma)
+    W, b1, v, b2 = th[:H * K].reshape(H, K), th[H * K:H * K + H], th[H * K + H:-1], th[-1]
+    mag = sigma * ((np.abs(u.astype(np.float64)) / sigma @ np.abs(W).T + np.abs(b1)) @ np.abs(v)
+                   + abs(b2))
+    # each folded weight is one FP32 rounding away from its exact value
+    tol = 2.0 ** -21 * mag
+    assert np.all(np.abs(y_raw - sigma * y_scaled) <= tol)
+    # and the identity is not satisfied by accident: every weight group matters
+    for name in ("w1", "b1", "v"):
+        bad = dict(m)
+        bad[name] = (np.asarray(m[name], np.float64) * (sigma if name != "v" else 1 / sigma)
+                     ).astype(np.float32)
+        yb, _ = O.mlp_eval_f64(bad, u)
+        assert np.max(np.abs(yb - sigma * y_scaled) / tol) > 10, name
+    bad = dict(m, b2=float(np.float32(th[-1])))
+    yb, _ = O.mlp_eval_f64(bad, u)
+    assert np.max(np.abs(yb - sigma * y_scaled) / tol) > 10
