@@ -83,12 +83,12 @@ typedef struct {
     int32_t use_net;            /* 0: one-layer Lorenzo everywhere; 1: network where all
                                    neighbours exist (needs a model) */
     int32_t judge;              /* 1 (needs use_net): per block keep the network only if the
-                                   entropy of its codes is strictly below that of Lorenzo's
-                                   codes (flag per block in the stream).  Entropy of a block's
-                                   codes with every code mapped to a bin: 0 for the balance
-                                   point, else the error clamped to [-127, 127]; compared as
-                                   J = sum over bins of c rint(2^32 log2 c), higher J = lower
-                                   entropy (Sec. 4.3) */
+                                   empirical entropy of its codes is strictly below that of
+                                   Lorenzo's codes (flag per block in the stream).  Every
+                                   distinct code of the block (code 0 included) is a symbol;
+                                   compared as J = sum over symbols of c rint(2^32 log2 c),
+                                   higher J = lower entropy (Sec. 4.3: the codes are
+                                   entropy-coded) */
     int32_t independent_blocks; /* 0: the prediction surface crosses block faces (halo mode);
                                    1: neighbours outside the block count as missing, so every
                                    block decodes on its own (Sec. 4.4.2) */
@@ -172,6 +172,48 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
 
 /* Validate a header held in host memory (no GPU work). */
 int pwrel_read_header(const void *buf, uint64_t size, pwrel_header *out);
+
+/*
+ * pwrel_compress_raw: the computation of pwrel_compress (Algorithm 1) with
+ * the stream's sections returned in separate caller buffers instead of one
+ * stream, for inspection and bit-exact checking:
+ *   d_codes  uint16 [n]        block-major codes (as the stream's codes section)
+ *   d_counts uint32 [nblocks]  code-0 points per block
+ *   d_bflags uint8  [nblocks]  per-block predictor flag (needed iff opt->judge;
+ *                              else may be NULL)
+ *   d_raw    dtype  [raw_capacity] raw values of the code-0 points, stream order
+ *   header_out (host)          the header the stream would carry (constants,
+ *                              n_raw, section offsets, total_size, status)
+ * Synchronizes `stream` once.  Errors as pwrel_compress; PWREL_ENOSPC when
+ * more than raw_capacity values are unpredictable.
+ */
+int pwrel_compress_raw(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                       int dtype, double rel_error_bound, int block_size,
+                       const pwrel_mlp *model, const pwrel_options *opt, uint16_t *d_codes,
+                       uint32_t *d_counts, uint8_t *d_bflags, void *d_raw,
+                       uint64_t raw_capacity, pwrel_header *header_out, void *stream);
+
+/*
+ * A trained network kept for later fields (Sec. 5: the model trained in the
+ * training phase is retained and used to compress; Sec. 4.3).  pwrel_mlp is a
+ * plain value owned by the caller, so nothing is allocated or freed here.
+ *  pwrel_model_save - serialise *m (host) into buf (host, cap bytes): magic
+ *      "PWMD", version 1, hidden, inputs, alpha, precision, then w1 [H][K],
+ *      b1 [H], v [H], b2 as little-endian FP32, then an FNV-1a 64-bit checksum
+ *      of everything before it.  *size receives the byte count (also when
+ *      buf is NULL or cap is too small: then PWREL_ENOSPC).  PWREL_EINVAL for
+ *      an invalid network.
+ *  pwrel_model_load - parse and validate such bytes into *out; PWREL_ECORRUPT
+ *      if the magic, version, sizes or checksum do not match or the network
+ *      is invalid.
+ *  pwrel_stream_model - the network stored in a stream (device memory,
+ *      in_size bytes) into *out (host); PWREL_EINVAL if the stream has none,
+ *      PWREL_ECORRUPT if its header or model is invalid.  Synchronizes.
+ */
+int pwrel_model_save(const pwrel_mlp *m, void *buf, uint64_t cap, uint64_t *size);
+int pwrel_model_load(const void *buf, uint64_t size, pwrel_mlp *out);
+int pwrel_stream_model(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, pwrel_mlp *out,
+                       void *stream);
 
 /*
  * Inspection entry points (same kernels as the codec):

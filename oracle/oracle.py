@@ -76,7 +76,7 @@ def lib():
         L.or_decompress.argtypes = [P, P, C.c_uint64, C.POINTER(_Consts), P, C.c_int, C.c_int,
                                     C.c_int, C.c_int, C.POINTER(_MLP), C.c_int, P, P, P]
         L.or_codes_at.argtypes = [P, P, C.c_int, C.c_int, C.POINTER(_Consts), C.c_int, C.c_int,
-                                  C.POINTER(_MLP), C.c_int, P, C.c_uint64, P, P, P, P, P]
+                                  C.POINTER(_MLP), C.c_int, P, C.c_uint64, P, P, P, P, P, P, P]
         L.or_block_start.restype = C.c_int64
         L.or_block_start.argtypes = [P, C.c_int, C.c_int, P]
         L.or_mlp_init.argtypes = [C.POINTER(_MLP), C.c_int, C.c_int, C.c_float, C.c_uint64]
@@ -101,7 +101,7 @@ def lib():
         L.or_mlp_eval_bf16_many.argtypes = [C.POINTER(_MLP), P, C.c_int64, P, P]
         L.or_mlp_eval_f64_many.argtypes = [C.POINTER(_MLP), P, C.c_int64, P, P]
         L.or_loss_grad_abs.argtypes = [P, C.c_int, C.c_int, C.c_double, P, P, C.c_int64,
-                                       C.c_double, C.c_double, P]
+                                       C.c_double, C.c_double, P, P]
         L.or_theta_eval_many.argtypes = [P, C.c_int, C.c_int, C.c_double, P, C.c_int64,
                                          C.c_double, P]
         L.or_bf16_rne.restype = C.c_float
@@ -350,14 +350,17 @@ def codes_at(x, c, B, idx, model=None, mode=MODE_PLAIN, independent=False):
     p = np.zeros(n, dtype=np.int32)
     yref = np.zeros(n)
     slack = np.zeros(n)
+    y64 = np.zeros(n)
+    bound = np.zeros(n)
     cs = _consts_struct(c)
     m = _to_c_mlp(model)
     st = lib().or_codes_at(_ptr(x), _ptr(dims), x.ndim, _dtype_code(x), C.byref(cs), B,
                            int(bool(independent)), C.byref(m) if m is not None else None, mode,
                            _ptr(idx), n, _ptr(codes), _ptr(pos), _ptr(p), _ptr(yref),
-                           _ptr(slack))
+                           _ptr(slack), _ptr(y64), _ptr(bound))
     _check(st, "codes_at")
-    return {"codes": codes, "pos": pos, "p": p, "yref": yref, "slack": slack}
+    return {"codes": codes, "pos": pos, "p": p, "yref": yref, "slack": slack, "y64": y64,
+            "bound": bound}
 
 
 def encode_p(p, B, model=None, use_net=True, independent=False):
@@ -439,14 +442,17 @@ def loss_grad(theta, H, K, alpha, u, t, sigma, lam):
 
 
 def loss_grad_abs(theta, H, K, alpha, u, t, sigma, lam):
-    """Per-component sum of the magnitudes the gradient of loss_grad adds up."""
+    """Per-component magnitudes behind loss_grad's gradient: (gabs, gres) --
+    the sum of |terms| and the residual magnitudes times |dy/dtheta| (see
+    or_loss_grad_abs)."""
     theta = np.ascontiguousarray(theta, dtype=np.float64)
     u = np.ascontiguousarray(u, dtype=np.float64)
     t = np.ascontiguousarray(t, dtype=np.float64)
     g = np.zeros_like(theta)
+    r = np.zeros_like(theta)
     lib().or_loss_grad_abs(_ptr(theta), H, K, float(alpha), _ptr(u), _ptr(t), t.size,
-                           float(sigma), float(lam), _ptr(g))
-    return g
+                           float(sigma), float(lam), _ptr(g), _ptr(r))
+    return g, r
 
 
 def theta_eval(theta, H, K, alpha, u, sigma):

@@ -904,12 +904,13 @@ int or_decompress(const uint16_t *codes, const void *raw, uint64_t n_raw, const 
 
 /* Stream position and code of selected points, computed point by point from
  * the field alone (for sampled comparisons on large fields).  mode 0/1 as in
- * or_compress (no judge).  yref/slack (optional) receive the BF16 reference
- * network value where the network applies (precision 1), else NaN. */
+ * or_compress (no judge).  Where the network applies (else NaN): yref/slack
+ * (optional) receive the BF16 reference network value (precision 1 only),
+ * y64/bound (optional) the FP64 network value and the BF16 error bound. */
 int or_codes_at(const void *x, const uint64_t *dims, int ndim, int dtype, const or_consts *c,
                 int B, int independent, const or_mlp *m, int mode, const uint64_t *idx,
                 uint64_t n_idx, uint16_t *codes_out, uint64_t *pos_out, int32_t *p_out,
-                double *yref, double *slack)
+                double *yref, double *slack, double *y64, double *bound)
 {
     geom g;
     int st = geom_init(&g, dims, ndim, B);
@@ -946,13 +947,15 @@ int or_codes_at(const void *x, const uint64_t *dims, int ndim, int dtype, const 
         if (status)
             return status;
         int64_t pred = 0;
-        double yr = NAN, sl = NAN;
+        double yr = NAN, sl = NAN, ye = NAN, bd = NAN;
         if (mode != 0 && m && all) {
             float u[OR_MAXK];
             for (int k = 0; k < m->inputs; ++k)
                 u[k] = (float)(int32_t)(nbv[k + 2] - nbv[1]);
             if (m->precision == 1)
                 yr = mlp_eval_bf16_ref(m, u, &sl);
+            ye = mlp_eval_f64(m, u);
+            bd = mlp_bf16_bound(m, u);
             float y = mlp_eval_f32(m, u);
             if (y > 0x1p30f)
                 y = 0x1p30f;
@@ -968,6 +971,10 @@ int or_codes_at(const void *x, const uint64_t *dims, int ndim, int dtype, const 
         codes_out[s] = code_of(pred, pv, ok);
         if (yref)
             yref[s] = yr;
+        if (y64)
+            y64[s] = ye;
+        if (bound)
+            bound[s] = bd;
         if (slack)
             slack[s] = sl;
         if (p_out)
@@ -1154,40 +1161,60 @@ double or_loss_grad(const double *theta, int H, int K, double alpha, const doubl
     return loss;
 }
 
-/* Magnitudes behind each gradient component of or_loss_grad: the sum over
- * samples of |each sample's contribution| / n, plus |lambda w|.  A summation
- * in finite precision is off by at most a small multiple of its unit
- * roundoff times this sum, whatever the order (used for tolerances). */
+/* Magnitudes behind each gradient component of or_loss_grad, for error
+ * bounds of finite-precision evaluations of the same sums:
+ *   gabs[q] = sum over samples of |the sample's contribution| / n, plus
+ *             |lambda w| (the terms of the sum itself);
+ *   gres[q] = sum over samples of F_i |d y_i / d theta_q| / n, with
+ *             F_i = |b2| + sum_j |v_j| (|b1_j| + sum_k |w_jk u_ik / s|) + |t_i / s|
+ *             the magnitudes the residual y_i - t_i / s is computed from
+ *             (its rounding error is a small multiple of F_i).
+ * gres may be NULL. */
 void or_loss_grad_abs(const double *theta, int H, int K, double alpha, const double *u,
-                      const double *t, int64_t n, double sigma, double lambda, double *gabs)
+                      const double *t, int64_t n, double sigma, double lambda, double *gabs,
+                      double *gres)
 {
     const double *W = theta, *b1 = theta + H * K, *v = theta + H * K + H;
     double b2 = theta[H * K + 2 * H];
     int64_t np = nparams(H, K);
-    for (int64_t q = 0; q < np; ++q)
+    for (int64_t q = 0; q < np; ++q) {
         gabs[q] = 0.0;
+        if (gres)
+            gres[q] = 0.0;
+    }
     double z[OR_MAXH], h[OR_MAXH], us[OR_MAXK];
     for (int64_t i = 0; i < n; ++i) {
         for (int k = 0; k < K; ++k)
             us[k] = u[i * K + k] / sigma;
-        double y = b2;
+        double y = b2, F = fabs(b2) + fabs(t[i] / sigma);
         for (int j = 0; j < H; ++j) {
-            double a = b1[j];
-            for (int k = 0; k < K; ++k)
+            double a = b1[j], m = fabs(b1[j]);
+            for (int k = 0; k < K; ++k) {
                 a += W[j * K + k] * us[k];
+                m += fabs(W[j * K + k] * us[k]);
+            }
             z[j] = a;
             h[j] = (a < 0.0) ? alpha * a : a;
             y += v[j] * h[j];
+            F += fabs(v[j]) * m;
         }
-        double gy = fabs(y - t[i] / sigma) / (double)n;
+        const double gy = fabs(y - t[i] / sigma) / (double)n, fr = F / (double)n;
         for (int j = 0; j < H; ++j) {
+            const double dz = fabs(v[j]) * ((z[j] < 0.0) ? alpha : 1.0);
             gabs[H * K + H + j] += gy * fabs(h[j]);
-            double gz = gy * fabs(v[j]) * ((z[j] < 0.0) ? alpha : 1.0);
-            gabs[H * K + j] += gz;
+            gabs[H * K + j] += gy * dz;
             for (int k = 0; k < K; ++k)
-                gabs[j * K + k] += gz * fabs(us[k]);
+                gabs[j * K + k] += gy * dz * fabs(us[k]);
+            if (gres) {
+                gres[H * K + H + j] += fr * fabs(h[j]);
+                gres[H * K + j] += fr * dz;
+                for (int k = 0; k < K; ++k)
+                    gres[j * K + k] += fr * dz * fabs(us[k]);
+            }
         }
         gabs[H * K + 2 * H] += gy;
+        if (gres)
+            gres[H * K + 2 * H] += fr;
     }
     for (int q = 0; q < H * K; ++q)
         gabs[q] += fabs(lambda * W[q]);

@@ -42,6 +42,7 @@ struct pwrel_ctx {
     long long order_nb[3] = {-1, -1, -1};
     int order_pen = -1;  // the cached order is of pencils (1) or of blocks (0)
     unsigned epoch = 0;
+    void *hdr = nullptr;  // header of pwrel_compress_raw (PWREL_HEADER_BYTES)
 };
 
 namespace {
@@ -74,82 +75,10 @@ int hip_fail(pwrel_ctx *ctx, hipError_t e, const char *what)
     return fail(ctx, PWREL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-uint64_t align256(uint64_t v) { return (v + 255u) & ~uint64_t(255u); }
-
-int max_block(int ndim) { return ndim == 1 ? 4096 : (ndim == 2 ? 64 : 16); }
-
-bool make_geom(const uint64_t *dims, int ndim, int dtype, int B, Geom &g)
-{
-    if (!dims || ndim < 1 || ndim > 3 || B < 2 || B > max_block(ndim))
-        return false;
-    if (dtype != PWREL_F32 && dtype != PWREL_F64)
-        return false;
-    g.D = ndim;
-    g.B = B;
-    g.dtype = dtype;
-    g.N = 1;
-    g.nblocks = 1;
-    for (int d = 0; d < 3; ++d) {
-        const int src = d - (3 - ndim);
-        const uint64_t nd = src >= 0 ? dims[src] : 1;
-        if (nd < 1 || nd > (uint64_t(1) << 40))
-            return false;
-        g.n[d] = (long long)nd;
-        g.bd[d] = src >= 0 ? B : 1;
-        g.nb[d] = (g.n[d] + g.bd[d] - 1) / g.bd[d];
-        if (g.N > (1LL << 42) / g.n[d])
-            return false;
-        g.N *= g.n[d];
-        g.nblocks *= g.nb[d];
-    }
-    return true;
-}
-
-struct Layout {
-    uint64_t off[5];  // model, bflags, counts, codes, raw
-};
-
-Layout layout_for(const Geom &g, int flags)
-{
-    Layout L;
-    uint64_t o = PWREL_HEADER_BYTES;
-    L.off[0] = o;
-    if (flags & PWREL_HF_NET)
-        o = align256(o + sizeof(pwrel_mlp));
-    L.off[1] = o;
-    if (flags & PWREL_HF_JUDGE)
-        o = align256(o + (uint64_t)g.nblocks);
-    L.off[2] = o;
-    o = align256(o + 4ull * (uint64_t)g.nblocks);
-    L.off[3] = o;
-    o = align256(o + 2ull * (uint64_t)g.N);
-    L.off[4] = o;
-    return L;
-}
-
 int check_model(pwrel_ctx *ctx, const pwrel_mlp *m, int ndim)
 {
-    if (!m)
-        return fail(ctx, PWREL_EINVAL, "model is NULL but use_net is set");
-    if (m->hidden < 2 || m->hidden > PWREL_MAX_HIDDEN)
-        return fail(ctx, PWREL_EINVAL, "model hidden width must be 2..32");
-    if (m->inputs != (1 << ndim) - 2)
-        return fail(ctx, PWREL_EINVAL, "model inputs must equal 2^ndim - 2");
-    if (m->precision != 0 && m->precision != 1)
-        return fail(ctx, PWREL_EINVAL, "model precision must be 0 (FP32) or 1 (BF16 matrix cores)");
-    if (!(m->alpha >= 0.0f && m->alpha <= 1.0f))
-        return fail(ctx, PWREL_EINVAL, "leaky-ReLU slope must lie in [0, 1]");
-    auto bad = [](float v) { return !std::isfinite(v) || std::fabs(v) > 65536.0f; };
-    if (bad(m->b2))
-        return fail(ctx, PWREL_EINVAL, "model weights must be finite and below 2^16");
-    for (int j = 0; j < m->hidden; ++j) {
-        if (bad(m->b1[j]) || bad(m->v[j]))
-            return fail(ctx, PWREL_EINVAL, "model weights must be finite and below 2^16");
-        for (int k = 0; k < m->inputs; ++k)
-            if (bad(m->w1[j][k]))
-                return fail(ctx, PWREL_EINVAL, "model weights must be finite and below 2^16");
-    }
-    return PWREL_OK;
+    const char *why = model_problem(m, ndim);
+    return why ? fail(ctx, PWREL_EINVAL, why) : PWREL_OK;
 }
 
 template <typename P>
@@ -381,7 +310,7 @@ void pwrel_destroy(pwrel_ctx *ctx)
                     ws.offsets,     ws.partials,    ws.pgrid,      ws.qtab,        ctx->counts_scratch,
                     ctx->chunk_cnt, ctx->chunk_off, ctx->pairs,    ctx->theta,     ctx->nets,
                     ctx->vhist,     ctx->scal,      ctx->scores,   ws.done,        ws.ticket,
-                    ctx->order,     ws.praw,        ws.zf,         ws.yf};
+                    ctx->order,     ws.praw,        ws.zf,         ws.yf,          ctx->hdr};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -396,6 +325,100 @@ const char *pwrel_last_error(const pwrel_ctx *ctx)
     return ctx ? ctx->err.c_str() : "no context";
 }
 
+}  // extern "C"
+
+namespace {
+
+bool check_compress_args(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                         int dtype, double eps, int block_size, const pwrel_mlp *model,
+                         const pwrel_options &opt, Geom &g, Tile &tile, int &st)
+{
+    st = PWREL_OK;
+    if (pwrel_check_args(dims, ndim, dtype, eps, block_size) != PWREL_OK) {
+        st = fail(ctx, PWREL_EINVAL, "bad dims/ndim/dtype/bound/block size");
+        return false;
+    }
+    if (!d_field) {
+        st = fail(ctx, PWREL_EINVAL, "NULL field");
+        return false;
+    }
+    if (opt.judge && !opt.use_net) {
+        st = fail(ctx, PWREL_EINVAL, "the per-block judge needs a network (use_net)");
+        return false;
+    }
+    if (opt.use_net && (st = check_model(ctx, model, ndim)) != PWREL_OK)
+        return false;
+    make_geom(dims, ndim, dtype, block_size, g);
+    if (!tile_for(g, tile)) {
+        st = fail(ctx, PWREL_EINVAL, "block too large for the LDS tile");
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+namespace pwrel {
+
+// The compression launches (Algorithm 1): reset, statistics, constants, grid
+// values and bound checks (FP32), prediction / quantisation / judge, scan,
+// raw scatter, model, header.  Queued on s; nothing is synchronised or
+// allocated here.  ws.pgrid must hold g.N entries for FP32 fields.
+hipError_t compress_launches(Workspace &ws, int num_cus, const void *d_field, const Geom &g,
+                             const Tile &tile, double eps, const pwrel_mlp *model,
+                             const pwrel_options &opt, const Sections &sec, hipStream_t s,
+                             void (*mark_fn)(void *, int, hipStream_t), void *mark_arg)
+{
+    auto mark_at = [&](int i) {
+        if (mark_fn)
+            mark_fn(mark_arg, i, s);
+    };
+    const int flags = flags_of(opt);
+    const Layout L = layout_for(g, flags);
+    hipError_t e;
+    if ((e = launch_reset(ws, s)) != hipSuccess)
+        return e;
+    mark_at(0);
+    if ((e = launch_stats(d_field, g, ws, s)) != hipSuccess ||
+        (e = launch_consts(g, eps, ws, s)) != hipSuccess)
+        return e;
+    mark_at(1);
+    if (g.dtype == PWREL_F32) {
+        // two passes: grid values and bound checks once per value into the
+        // grid scratch field, then prediction and quantisation from it
+        if ((e = launch_grid_entries(static_cast<const float *>(d_field), g, ws, ws.pgrid, s)) !=
+                hipSuccess ||
+            (e = launch_compress(d_field, ws.pgrid, g, tile, model, opt, ws, sec.codes,
+                                 sec.counts, sec.bflags, num_cus, s, true)) != hipSuccess)
+            return e;
+    } else if ((e = launch_compress(d_field, nullptr, g, tile, model, opt, ws, sec.codes,
+                                    sec.counts, sec.bflags, num_cus, s)) != hipSuccess) {
+        return e;
+    }
+    mark_at(2);
+    if ((e = launch_scan(sec.counts, g, ws, s)) != hipSuccess ||
+        (e = launch_scatter(d_field, g, sec.codes, sec.counts, ws, sec.raw, sec.raw_cap, s)) !=
+            hipSuccess)
+        return e;
+    if (opt.use_net && sec.model && (e = launch_write_model(*model, sec.model, s)) != hipSuccess)
+        return e;
+    if ((e = launch_header(g, flags, L.off, ws, sec.header, sec.header_capacity,
+                           sec.stream_gaps, s)) != hipSuccess)
+        return e;
+    mark_at(3);
+    return hipSuccess;
+}
+
+}  // namespace pwrel
+
+namespace {
+
+void mark_cb(void *ctx, int i, hipStream_t s) { mark(static_cast<pwrel_ctx *>(ctx), i, s); }
+
+}  // namespace
+
+extern "C" {
+
 int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
                    int dtype, double eps, int block_size, const pwrel_mlp *model,
                    const pwrel_options *opt_in, void *d_out, uint64_t out_capacity,
@@ -406,74 +429,41 @@ int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, in
     pwrel_options opt{1, 0, 0, 0};
     if (opt_in)
         opt = *opt_in;
-    if (pwrel_check_args(dims, ndim, dtype, eps, block_size) != PWREL_OK)
-        return fail(ctx, PWREL_EINVAL, "bad dims/ndim/dtype/bound/block size");
-    if (!d_field || !d_out || !out_size)
-        return fail(ctx, PWREL_EINVAL, "NULL field, output or size pointer");
-    if (opt.judge && !opt.use_net)
-        return fail(ctx, PWREL_EINVAL, "the per-block judge needs a network (use_net)");
-    if (opt.use_net) {
-        const int st = check_model(ctx, model, ndim);
-        if (st)
-            return st;
-    }
     Geom g;
-    make_geom(dims, ndim, dtype, block_size, g);
     Tile tile;
-    if (!tile_for(g, tile))
-        return fail(ctx, PWREL_EINVAL, "block too large for the LDS tile");
-    const int flags = (opt.use_net ? PWREL_HF_NET : 0) | (opt.judge ? PWREL_HF_JUDGE : 0) |
-                      (opt.independent_blocks ? PWREL_HF_INDEPENDENT : 0);
+    int st;
+    if (!check_compress_args(ctx, d_field, dims, ndim, dtype, eps, block_size, model, opt, g,
+                             tile, st))
+        return st;
+    if (!d_out || !out_size)
+        return fail(ctx, PWREL_EINVAL, "NULL output or size pointer");
+    const int flags = flags_of(opt);
     const Layout L = layout_for(g, flags);
     if (out_capacity < L.off[4])
         return fail(ctx, PWREL_ENOSPC, "output capacity below header + codes");
     DeviceGuard guard(ctx->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int st = ensure_scan(ctx, g);
-    if (st)
+    if ((st = ensure_scan(ctx, g)) != PWREL_OK)
         return st;
-    unsigned char *out = static_cast<unsigned char *>(d_out);
-    uint16_t *codes = reinterpret_cast<uint16_t *>(out + L.off[3]);
-    uint32_t *counts = reinterpret_cast<uint32_t *>(out + L.off[2]);
-    uint8_t *bflags = (flags & PWREL_HF_JUDGE) ? out + L.off[1] : nullptr;
-    const unsigned tsize = dtype == PWREL_F32 ? 4u : 8u;
     hipError_t e;
-    if ((e = launch_reset(ctx->ws, s)) != hipSuccess)
-        return hip_fail(ctx, e, "reset");
-    mark(ctx, 0, s);
-    if ((e = launch_stats(d_field, g, ctx->ws, s)) != hipSuccess)
-        return hip_fail(ctx, e, "stats");
-    if ((e = launch_consts(g, eps, ctx->ws, s)) != hipSuccess)
-        return hip_fail(ctx, e, "consts");
-    mark(ctx, 1, s);
-    if (g.dtype == PWREL_F32) {
-        // two passes: grid values and bound checks once per value into the
-        // scratch grid field, then prediction and quantization from it
-        if ((e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
-            return fail(ctx, PWREL_ENOMEM, "grid field allocation failed");
-        if ((e = launch_grid_entries(static_cast<const float *>(d_field), g, ctx->ws,
-                                     ctx->ws.pgrid, s)) != hipSuccess ||
-            (e = launch_compress(d_field, ctx->ws.pgrid, g, tile, model, opt, ctx->ws, codes,
-                                 counts, bflags, ctx->num_cus, s, true)) != hipSuccess)
-            return hip_fail(ctx, e, "compress");
-    } else if ((e = launch_compress(d_field, nullptr, g, tile, model, opt, ctx->ws, codes,
-                                    counts, bflags, ctx->num_cus, s)) != hipSuccess) {
+    if (g.dtype == PWREL_F32 &&
+        (e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, "grid field allocation failed");
+    unsigned char *out = static_cast<unsigned char *>(d_out);
+    const unsigned tsize = dtype == PWREL_F32 ? 4u : 8u;
+    Sections sec{};
+    sec.codes = reinterpret_cast<uint16_t *>(out + L.off[3]);
+    sec.counts = reinterpret_cast<uint32_t *>(out + L.off[2]);
+    sec.bflags = (flags & PWREL_HF_JUDGE) ? out + L.off[1] : nullptr;
+    sec.raw = out + L.off[4];
+    sec.raw_cap = (out_capacity - L.off[4]) / tsize;
+    sec.header = out;
+    sec.stream_gaps = true;
+    sec.model = out + L.off[0];
+    sec.header_capacity = out_capacity;
+    if ((e = compress_launches(ctx->ws, ctx->num_cus, d_field, g, tile, eps, model, opt, sec, s,
+                               mark_cb, ctx)) != hipSuccess)
         return hip_fail(ctx, e, "compress");
-    }
-    mark(ctx, 2, s);
-    if ((e = launch_scan(counts, g, ctx->ws, s)) != hipSuccess)
-        return hip_fail(ctx, e, "scan");
-    if ((e = launch_scatter(d_field, g, codes, counts, ctx->ws, out + L.off[4],
-                            (out_capacity - L.off[4]) / tsize, s)) != hipSuccess)
-        return hip_fail(ctx, e, "scatter");
-    if (opt.use_net) {
-        if ((e = hipMemcpyAsync(out + L.off[0], model, sizeof(pwrel_mlp), hipMemcpyHostToDevice,
-                                s)) != hipSuccess)
-            return hip_fail(ctx, e, "model copy");
-    }
-    if ((e = launch_header(g, flags, L.off, ctx->ws, out, out_capacity, s)) != hipSuccess)
-        return hip_fail(ctx, e, "header");
-    mark(ctx, 3, s);
     pwrel_header h;
     if ((e = hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(ctx, e, "header copy");
@@ -484,6 +474,215 @@ int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, in
     if (h.status != PWREL_OK)
         return finish_status(ctx, h.status);
     *out_size = h.total_size;
+    return PWREL_OK;
+}
+
+int pwrel_compress_raw(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                       int dtype, double eps, int block_size, const pwrel_mlp *model,
+                       const pwrel_options *opt_in, uint16_t *d_codes, uint32_t *d_counts,
+                       uint8_t *d_bflags, void *d_raw, uint64_t raw_capacity,
+                       pwrel_header *header_out, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    pwrel_options opt{1, 0, 0, 0};
+    if (opt_in)
+        opt = *opt_in;
+    Geom g;
+    Tile tile;
+    int st;
+    if (!check_compress_args(ctx, d_field, dims, ndim, dtype, eps, block_size, model, opt, g,
+                             tile, st))
+        return st;
+    if (!d_codes || !d_counts || !header_out || (opt.judge && !d_bflags) ||
+        (raw_capacity && !d_raw))
+        return fail(ctx, PWREL_EINVAL, "NULL section pointer");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((st = ensure_scan(ctx, g)) != PWREL_OK)
+        return st;
+    hipError_t e;
+    if (g.dtype == PWREL_F32 &&
+        (e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, "grid field allocation failed");
+    if (!ctx->hdr && (e = hipMalloc(&ctx->hdr, PWREL_HEADER_BYTES)) != hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, "header scratch allocation failed");
+    const Layout L = layout_for(g, flags_of(opt));
+    const unsigned tsize = dtype == PWREL_F32 ? 4u : 8u;
+    Sections sec{};
+    sec.codes = d_codes;
+    sec.counts = d_counts;
+    sec.bflags = opt.judge ? d_bflags : nullptr;
+    sec.raw = d_raw;
+    sec.raw_cap = raw_capacity;
+    sec.header = ctx->hdr;
+    sec.stream_gaps = false;
+    sec.model = nullptr;
+    // the header checks the stream size against this capacity: the stream
+    // these sections form fits iff the raw values do
+    sec.header_capacity = L.off[4] + raw_capacity * tsize;
+    if ((e = compress_launches(ctx->ws, ctx->num_cus, d_field, g, tile, eps, model, opt, sec, s,
+                               mark_cb, ctx)) != hipSuccess)
+        return hip_fail(ctx, e, "compress_raw");
+    pwrel_header h;
+    if ((e = hipMemcpyAsync(&h, ctx->hdr, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    if (h.status != PWREL_OK)
+        return finish_status(ctx, h.status);
+    *header_out = h;
+    return PWREL_OK;
+}
+
+// --- a trained network kept between fields (Sec. 5 retains the trained model) -----
+namespace {
+
+constexpr uint32_t kModelMagic = 0x444D5750u;  // "PWMD"
+constexpr uint32_t kModelVersion = 1u;
+
+uint64_t fnv1a64(const unsigned char *p, uint64_t n)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (uint64_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+uint64_t model_bytes(int H, int K) { return 24 + 4ull * (H * K + 2 * H + 1) + 8; }
+
+void put32(unsigned char *&p, uint32_t v)
+{
+    std::memcpy(p, &v, 4);
+    p += 4;
+}
+void putf(unsigned char *&p, float v)
+{
+    std::memcpy(p, &v, 4);
+    p += 4;
+}
+uint32_t get32(const unsigned char *&p)
+{
+    uint32_t v;
+    std::memcpy(&v, p, 4);
+    p += 4;
+    return v;
+}
+float getf(const unsigned char *&p)
+{
+    float v;
+    std::memcpy(&v, p, 4);
+    p += 4;
+    return v;
+}
+
+}  // namespace
+
+int pwrel_model_save(const pwrel_mlp *m, void *buf, uint64_t cap, uint64_t *size)
+{
+    if (!m || !size)
+        return PWREL_EINVAL;
+    if (m->inputs != 0 && m->inputs != 2 && m->inputs != 6)
+        return PWREL_EINVAL;
+    if (model_problem(m, m->inputs == 6 ? 3 : (m->inputs == 2 ? 2 : 1)))
+        return PWREL_EINVAL;
+    const int H = m->hidden, K = m->inputs;
+    const uint64_t need = model_bytes(H, K);
+    *size = need;
+    if (!buf || cap < need)
+        return PWREL_ENOSPC;
+    unsigned char *p = static_cast<unsigned char *>(buf), *p0 = p;
+    put32(p, kModelMagic);
+    put32(p, kModelVersion);
+    put32(p, (uint32_t)H);
+    put32(p, (uint32_t)K);
+    putf(p, m->alpha);
+    put32(p, (uint32_t)m->precision);
+    for (int j = 0; j < H; ++j)
+        for (int k = 0; k < K; ++k)
+            putf(p, m->w1[j][k]);
+    for (int j = 0; j < H; ++j)
+        putf(p, m->b1[j]);
+    for (int j = 0; j < H; ++j)
+        putf(p, m->v[j]);
+    putf(p, m->b2);
+    const uint64_t h = fnv1a64(p0, (uint64_t)(p - p0));
+    std::memcpy(p, &h, 8);
+    return PWREL_OK;
+}
+
+int pwrel_model_load(const void *buf, uint64_t size, pwrel_mlp *out)
+{
+    if (!buf || !out)
+        return PWREL_EINVAL;
+    if (size < 24)
+        return PWREL_ECORRUPT;
+    const unsigned char *p = static_cast<const unsigned char *>(buf), *p0 = p;
+    if (get32(p) != kModelMagic || get32(p) != kModelVersion)
+        return PWREL_ECORRUPT;
+    const uint32_t H = get32(p), K = get32(p);
+    if (H < 2 || H > PWREL_MAX_HIDDEN || (K != 0 && K != 2 && K != 6))
+        return PWREL_ECORRUPT;
+    const uint64_t need = model_bytes((int)H, (int)K);
+    if (size != need)
+        return PWREL_ECORRUPT;
+    uint64_t h;
+    std::memcpy(&h, p0 + need - 8, 8);
+    if (h != fnv1a64(p0, need - 8))
+        return PWREL_ECORRUPT;
+    pwrel_mlp m;
+    std::memset(&m, 0, sizeof m);
+    m.hidden = (int32_t)H;
+    m.inputs = (int32_t)K;
+    m.alpha = getf(p);
+    m.precision = (int32_t)get32(p);
+    for (uint32_t j = 0; j < H; ++j)
+        for (uint32_t k = 0; k < K; ++k)
+            m.w1[j][k] = getf(p);
+    for (uint32_t j = 0; j < H; ++j)
+        m.b1[j] = getf(p);
+    for (uint32_t j = 0; j < H; ++j)
+        m.v[j] = getf(p);
+    m.b2 = getf(p);
+    if (model_problem(&m, K == 6 ? 3 : (K == 2 ? 2 : 1)))
+        return PWREL_ECORRUPT;
+    *out = m;
+    return PWREL_OK;
+}
+
+int pwrel_stream_model(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, pwrel_mlp *out,
+                       void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!d_in || !out)
+        return fail(ctx, PWREL_EINVAL, "NULL stream or output");
+    if (in_size < PWREL_HEADER_BYTES)
+        return fail(ctx, PWREL_ECORRUPT, "stream shorter than its header");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    pwrel_header h;
+    hipError_t e = hipMemcpyAsync(&h, d_in, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    pwrel_header v;
+    if (pwrel_read_header(&h, in_size, &v) != PWREL_OK)
+        return fail(ctx, PWREL_ECORRUPT, "stream header is corrupt or truncated");
+    if (!(v.flags & PWREL_HF_NET))
+        return fail(ctx, PWREL_EINVAL, "the stream holds no network");
+    pwrel_mlp m;
+    e = hipMemcpyAsync(&m, static_cast<const unsigned char *>(d_in) + v.off_model, sizeof m,
+                       hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "model copy");
+    if (model_problem(&m, v.ndim))
+        return fail(ctx, PWREL_ECORRUPT, "stream model is invalid");
+    *out = m;
     return PWREL_OK;
 }
 

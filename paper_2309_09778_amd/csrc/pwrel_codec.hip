@@ -684,7 +684,7 @@ hipError_t launch_scatter(const void *x, const Geom &g, const uint16_t *codes,
 }
 
 hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspace &ws,
-                         void *d_header, uint64_t capacity, hipStream_t s)
+                         void *d_header, uint64_t capacity, bool stream_gaps, hipStream_t s)
 {
     HeaderArgs h{};
     h.dtype = g.dtype;
@@ -712,9 +712,25 @@ hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspa
     for (int r = 0; r < 5; ++r) {
         h.pad_lo[r] = ends[r];
         h.pad_hi[r] = nexts[r] > ends[r] ? nexts[r] : ends[r];
+        if (!stream_gaps && r > 0)  // a lone header: only its own tail
+            h.pad_hi[r] = h.pad_lo[r];
     }
+    if (!stream_gaps)
+        h.pad_hi[0] = PWREL_HEADER_BYTES;
     hipLaunchKernelGGL(k_header, dim3(1), dim3(256), 0, s, h, ws.consts, ws.n_raw, ws.status,
                        (pwrel_header *)d_header);
+    return hipGetLastError();
+}
+
+__global__ void k_write_model(pwrel_mlp m, pwrel_mlp *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *dst = m;
+}
+
+hipError_t launch_write_model(const pwrel_mlp &m, void *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_write_model, dim3(1), dim3(64), 0, s, m, static_cast<pwrel_mlp *>(dst));
     return hipGetLastError();
 }
 

@@ -44,15 +44,25 @@ struct CompressArgs {
     MlpW mlp;
 };
 
-// Judge bins: code 0 (balance point) and the prediction error clamped to
-// [-127, 127] (Sec. 4.3 judge reading: entropy of the clamped code).
+// Per-block judge (Sec. 4.3: the codes are entropy-coded, so a block keeps the
+// network only if its codes have the lower empirical entropy).  J = sum over the
+// block's points of q(c), c = the number of the block's points that carry the
+// same code, q(c) = rint(2^32 log2 c); n q(n) - J is 2^32 times the entropy in
+// bits.  Counts come from a histogram over a window of errors (kJudgeWin bins:
+// bin 0 = code 0, the balance point; bin e + kJudgeHalf for |e| < kJudgeHalf);
+// codes outside the window go to a short per-block list (kJudgeList entries per
+// predictor) and are counted in it, or, when the list is full, by a scan of the
+// block's codes.
+constexpr int kJudgeHalf = 256;
+constexpr int kJudgeWin = 2 * kJudgeHalf;  // bins per block
+constexpr int kJudgeList = 64;             // listed out-of-window codes per block and predictor
+
 __device__ __forceinline__ int judge_bin(unsigned code)
 {
     if (code == 0)
         return 0;
-    int e = (int)code - kR;
-    e = e < -127 ? -127 : (e > 127 ? 127 : e);
-    return e + 128;
+    const int e = (int)code - kR;
+    return (e > -kJudgeHalf && e < kJudgeHalf) ? e + kJudgeHalf : -1;
 }
 
 __device__ __forceinline__ unsigned short code32(int e, bool ok)
@@ -133,7 +143,8 @@ k_compress(CompressArgs a)
     const int BV = bd0 * bd1 * bd2;
 
     // LDS: [judge: per-block scores] [block stream starts] [block extents]
-    // [grid tile] [balance counts] [judge: per-block histograms] [bound bits]
+    // [grid tile] [balance counts] [judge: per-block histograms, both codes of
+    // every point, out-of-window list counts and lists] [bound bits]
     // (the 64-bit arrays first for alignment)
     unsigned long long *jsum = reinterpret_cast<unsigned long long *>(smem);
     long long *bst = reinterpret_cast<long long *>(jsum + (a.judge ? 2 * nbt : 0));
@@ -141,10 +152,13 @@ k_compress(CompressArgs a)
     int *ptile = reinterpret_cast<int *>(bext + nbt);
     unsigned int *cnt = reinterpret_cast<unsigned int *>(ptile + ne);
     using V = typename std::conditional<FROM_P, int, T>::type;
-    unsigned int *jh = cnt + nbt;
+    unsigned int *jh = cnt + nbt;  // [nbt][kJudgeWin]: network count | Lorenzo count << 16
     // judge only: both codes of every tile point (network | Lorenzo << 16)
-    unsigned *jb = jh + (a.judge ? nbt * 256 : 0);
-    unsigned char *okb = reinterpret_cast<unsigned char *>(jb + (a.judge ? ntp : 0));
+    unsigned *jb = jh + (a.judge ? nbt * kJudgeWin : 0);
+    unsigned *jlc = jb + (a.judge ? ntp : 0);  // [nbt][2] list lengths
+    unsigned short *jl = reinterpret_cast<unsigned short *>(jlc + (a.judge ? 2 * nbt : 0));
+    unsigned char *okb =
+        reinterpret_cast<unsigned char *>(jl + (a.judge ? 2 * nbt * kJudgeList : 0));
 
     __shared__ int s_status;
     __shared__ float4 wl[kWlds];
@@ -156,10 +170,12 @@ k_compress(CompressArgs a)
     for (int i = tid; i < nbt; i += NT)
         cnt[i] = 0u;
     if (a.judge) {
-        for (int i = tid; i < nbt * 256; i += NT)
+        for (int i = tid; i < nbt * kJudgeWin; i += NT)
             jh[i] = 0u;
-        for (int i = tid; i < 2 * nbt; i += NT)
+        for (int i = tid; i < 2 * nbt; i += NT) {
             jsum[i] = 0ULL;
+            jlc[i] = 0u;
+        }
     }
     if (tid == 0)
         s_status = *a.status;
@@ -457,52 +473,90 @@ k_compress(CompressArgs a)
         __syncthreads();
 
         if (a.judge) {
-            // --- per-block judge: keep the network iff the entropy of its
-            //     clamped codes is strictly below Lorenzo's (fixed-point scores).
-            // Histograms from the codes noted above (LDS atomics outside the
-            // prediction loop, where no memory operation is outstanding) ---
+            // --- per-block judge: keep the network iff the entropy of its codes
+            //     is strictly below Lorenzo's (fixed-point scores).  Histograms
+            //     and out-of-window lists from the codes noted above (LDS
+            //     atomics outside the prediction loop, where no memory
+            //     operation is outstanding) ---
             for (int q = tid; q < ntp; q += NT) {
                 const int cx = q % T2, cy = (q / T2) % T1, cz = q / (T1 * T2);
                 if (!(cz < limz && cy < limy && cx < limx))
                     continue;  // no point
                 const unsigned v = jb[q];
                 const int bt = ((cz / bd0) * nbt1 + cy / bd1) * nbt2 + cx / bd2;
-                atomicAdd(&jh[bt * 256 + judge_bin(v & 0xffffu)], 1u);
-                atomicAdd(&jh[bt * 256 + judge_bin(v >> 16)], 1u << 16);
+#pragma unroll
+                for (int pr = 0; pr < 2; ++pr) {
+                    const unsigned code = pr ? v >> 16 : v & 0xffffu;
+                    const int bin = judge_bin(code);
+                    if (bin >= 0) {
+                        atomicAdd(&jh[bt * kJudgeWin + bin], pr ? 1u << 16 : 1u);
+                    } else {
+                        const unsigned slot = atomicAdd(&jlc[2 * bt + pr], 1u);
+                        if (slot < (unsigned)kJudgeList)
+                            jl[(2 * bt + pr) * kJudgeList + slot] = (unsigned short)code;
+                    }
+                }
             }
             __syncthreads();
-            // scores: one wave per block, four bins per lane, then a wave sum
-            for (int bt = tid >> 6; bt < nbt; bt += NT / 64) {
-                const int ln = tid & 63;
-                unsigned *h = jh + bt * 256 + 4 * ln;
-                unsigned w[4];
-                long long qn[4], ql[4];
+            // scores J = sum over points of q(count of the point's code), points
+            // in block-major order (a wave's points share a block where the
+            // block size is a multiple of 64: one wave sum, one LDS add)
+            const bool wave_blocks = BV % 64 == 0;
+            for (int q0 = 0; q0 < nbt * BV; q0 += NT) {
+                const int q = q0 + tid;
+                const int bt = q < nbt * BV ? q / BV : nbt - 1;
+                const int li = q - bt * BV;
+                const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
+                const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
+                const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
+                const bool pt = q < nbt * BV && cz < limz && cy < limy && cx < limx;
+                unsigned long long s2[2] = {0ULL, 0ULL};
+                if (pt) {
+                    const unsigned v = jb[(cz * T1 + cy) * T2 + cx];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    w[k] = h[k];
-                    h[k] = 0u;
+                    for (int pr = 0; pr < 2; ++pr) {
+                        const unsigned code = pr ? v >> 16 : v & 0xffffu;
+                        const int bin = judge_bin(code);
+                        unsigned c = 0;
+                        if (bin >= 0) {
+                            const unsigned w = jh[bt * kJudgeWin + bin];
+                            c = pr ? w >> 16 : w & 0xffffu;
+                        } else {
+                            const unsigned nl = jlc[2 * bt + pr];
+                            if (nl <= (unsigned)kJudgeList) {
+                                const unsigned short *lst = jl + (2 * bt + pr) * kJudgeList;
+                                for (unsigned k = 0; k < nl; ++k)
+                                    c += lst[k] == code ? 1u : 0u;
+                            } else {
+                                // list full: count over the block's points
+                                const int ex = (int)(bext[bt] & 0xffffu), ey = (int)(bext[bt] >> 16);
+                                const int ez = std::min(bd0, limz - btz * bd0);
+                                for (int kz = 0; kz < ez; ++kz)
+                                    for (int ky = 0; ky < ey; ++ky)
+                                        for (int kx = 0; kx < ex; ++kx) {
+                                            const unsigned w = jb[((btz * bd0 + kz) * T1 +
+                                                                   bty * bd1 + ky) * T2 +
+                                                                  btx * bd2 + kx];
+                                            c += (pr ? w >> 16 : w & 0xffffu) == code ? 1u : 0u;
+                                        }
+                            }
+                        }
+                        s2[pr] = (unsigned long long)a.qtab[c];  // q(c), c >= 1
+                    }
                 }
+                if (wave_blocks) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    qn[k] = a.qtab[w[k] & 0xffffu];  // q(0) = 0
-                    ql[k] = a.qtab[w[k] >> 16];
-                }
-                unsigned long long sn = 0, sl = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    sn += (unsigned long long)(w[k] & 0xffffu) * (unsigned long long)qn[k];
-                    sl += (unsigned long long)(w[k] >> 16) * (unsigned long long)ql[k];
-                }
-                if (ln == 0)
-                    cnt[bt] = w[0];  // bin 0 holds the balance points of both
-#pragma unroll
-                for (int d = 32; d > 0; d >>= 1) {
-                    sn += (unsigned long long)__shfl_xor((long long)sn, d, 64);
-                    sl += (unsigned long long)__shfl_xor((long long)sl, d, 64);
-                }
-                if (ln == 0) {
-                    jsum[2 * bt] = sn;
-                    jsum[2 * bt + 1] = sl;
+                    for (int d = 32; d > 0; d >>= 1) {
+                        s2[0] += (unsigned long long)__shfl_xor((long long)s2[0], d, 64);
+                        s2[1] += (unsigned long long)__shfl_xor((long long)s2[1], d, 64);
+                    }
+                    if ((tid & 63) == 0 && q < nbt * BV) {
+                        atomicAdd(&jsum[2 * bt], s2[0]);
+                        atomicAdd(&jsum[2 * bt + 1], s2[1]);
+                    }
+                } else if (pt) {
+                    atomicAdd(&jsum[2 * bt], s2[0]);
+                    atomicAdd(&jsum[2 * bt + 1], s2[1]);
                 }
             }
             __syncthreads();
@@ -525,9 +579,15 @@ k_compress(CompressArgs a)
             }
             for (int bt = tid; bt < nbt; bt += NT) {
                 const bool use_n = jsum[2 * bt] > jsum[2 * bt + 1];
-                cnt[bt] = use_n ? (cnt[bt] & 0xffffu) : (cnt[bt] >> 16);
+                const unsigned w = jh[bt * kJudgeWin];  // bin 0: the balance points of both
+                cnt[bt] = use_n ? (w & 0xffffu) : (w >> 16);
             }
             __syncthreads();
+            // clear the histograms and lists for the next tile
+            for (int i = tid; i < nbt * kJudgeWin; i += NT)
+                jh[i] = 0u;
+            for (int i = tid; i < 2 * nbt; i += NT)
+                jlc[i] = 0u;
         }
 
         // --- per-block balance-point counts ------------------------------------
@@ -559,8 +619,8 @@ static size_t compress_lds(const Geom &g, const int *t, bool judge = true)
     const size_t nbt = (size_t)(t[0] / g.bd[0]) * (t[1] / g.bd[1]) * (t[2] / g.bd[2]);
     const size_t ntp = (size_t)t[0] * t[1] * t[2];
     size_t n = nbt * 8 + nbt * 4 + ne * 4 + nbt * 4;  // starts, extents, tile, counts
-    if (judge)
-        n += nbt * 256 * 4 + 2 * nbt * 8 + ntp * 4;  // histograms, scores, bins
+    if (judge)  // histograms, scores, both codes per point, list lengths, lists
+        n += nbt * kJudgeWin * 4 + 2 * nbt * 8 + ntp * 4 + 2 * nbt * 4 + 2 * nbt * kJudgeList * 2;
     return n + ntp;  // bound bits
 }
 

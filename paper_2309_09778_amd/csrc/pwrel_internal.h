@@ -81,8 +81,11 @@ hipError_t launch_scan(const uint32_t *counts, const Geom &g, Workspace &ws, hip
 hipError_t launch_scatter(const void *x, const Geom &g, const uint16_t *codes,
                           const uint32_t *counts, Workspace &ws, void *raw,
                           unsigned long long raw_cap, hipStream_t s);
+// stream_gaps: zero the alignment gaps between the sections that follow d_header
 hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspace &ws,
-                         void *d_header, uint64_t capacity, hipStream_t s);
+                         void *d_header, uint64_t capacity, bool stream_gaps, hipStream_t s);
+// the network into the stream's model section (a kernel, no host copy)
+hipError_t launch_write_model(const pwrel_mlp &m, void *dst, hipStream_t s);
 hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *model, int flags,
                          const uint8_t *bflags, const uint16_t *codes, const uint32_t *counts,
                          const void *raw, unsigned long long n_raw, Workspace &ws,
@@ -98,5 +101,114 @@ hipError_t launch_hist(const uint16_t *codes, long long n, unsigned long long *h
                        hipStream_t s);
 
 bool tile_for(const Geom &g, Tile &tile);
+
+// --- host helpers shared by the entry points --------------------------------------
+constexpr uint64_t align256(uint64_t v) { return (v + 255u) & ~uint64_t(255u); }
+
+inline int max_block(int ndim) { return ndim == 1 ? 4096 : (ndim == 2 ? 64 : 16); }
+
+// C-order dims padded to three axes (false if the arguments are invalid)
+inline bool make_geom(const uint64_t *dims, int ndim, int dtype, int B, Geom &g)
+{
+    if (!dims || ndim < 1 || ndim > 3 || B < 2 || B > max_block(ndim))
+        return false;
+    if (dtype != PWREL_F32 && dtype != PWREL_F64)
+        return false;
+    g.D = ndim;
+    g.B = B;
+    g.dtype = dtype;
+    g.N = 1;
+    g.nblocks = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int src = d - (3 - ndim);
+        const uint64_t nd = src >= 0 ? dims[src] : 1;
+        if (nd < 1 || nd > (uint64_t(1) << 40))
+            return false;
+        g.n[d] = (long long)nd;
+        g.bd[d] = src >= 0 ? B : 1;
+        g.nb[d] = (g.n[d] + g.bd[d] - 1) / g.bd[d];
+        if (g.N > (1LL << 42) / g.n[d])
+            return false;
+        g.N *= g.n[d];
+        g.nblocks *= g.nb[d];
+    }
+    return true;
+}
+
+// byte offsets of the stream sections (model, bflags, counts, codes, raw)
+struct Layout {
+    uint64_t off[5];
+};
+
+inline Layout layout_for(const Geom &g, int flags)
+{
+    Layout L;
+    uint64_t o = PWREL_HEADER_BYTES;
+    L.off[0] = o;
+    if (flags & PWREL_HF_NET)
+        o = align256(o + sizeof(pwrel_mlp));
+    L.off[1] = o;
+    if (flags & PWREL_HF_JUDGE)
+        o = align256(o + (uint64_t)g.nblocks);
+    L.off[2] = o;
+    o = align256(o + 4ull * (uint64_t)g.nblocks);
+    L.off[3] = o;
+    o = align256(o + 2ull * (uint64_t)g.N);
+    L.off[4] = o;
+    return L;
+}
+
+inline int flags_of(const pwrel_options &opt)
+{
+    return (opt.use_net ? PWREL_HF_NET : 0) | (opt.judge ? PWREL_HF_JUDGE : 0) |
+           (opt.independent_blocks ? PWREL_HF_INDEPENDENT : 0);
+}
+
+// why a network cannot be used on an ndim field, or nullptr
+inline const char *model_problem(const pwrel_mlp *m, int ndim)
+{
+    if (!m)
+        return "model is NULL but use_net is set";
+    if (m->hidden < 2 || m->hidden > PWREL_MAX_HIDDEN)
+        return "model hidden width must be 2..32";
+    if (m->inputs != (1 << ndim) - 2)
+        return "model inputs must equal 2^ndim - 2";
+    if (m->precision != 0 && m->precision != 1)
+        return "model precision must be 0 (FP32) or 1 (BF16 matrix cores)";
+    if (!(m->alpha >= 0.0f && m->alpha <= 1.0f))
+        return "leaky-ReLU slope must lie in [0, 1]";
+    auto bad = [](float v) { return !(v == v) || v > 65536.0f || v < -65536.0f; };
+    if (bad(m->b2))
+        return "model weights must be finite and below 2^16";
+    for (int j = 0; j < m->hidden; ++j) {
+        if (bad(m->b1[j]) || bad(m->v[j]))
+            return "model weights must be finite and below 2^16";
+        for (int k = 0; k < m->inputs; ++k)
+            if (bad(m->w1[j][k]))
+                return "model weights must be finite and below 2^16";
+    }
+    return nullptr;
+}
+
+// Where the sections of one compression go (device pointers), and how the
+// header is written.
+struct Sections {
+    uint16_t *codes;
+    uint32_t *counts;
+    uint8_t *bflags;           // judge only
+    void *raw;
+    uint64_t raw_cap;          // values
+    void *header;              // device, PWREL_HEADER_BYTES
+    bool stream_gaps;          // header is the start of a stream: zero its alignment gaps
+    void *model;               // device destination of the model, or nullptr
+    uint64_t header_capacity;  // stream capacity (raw overflow -> ENOSPC in the header)
+};
+
+// the compression launches of one field (pwrel_api.hip); mark_fn (optional)
+// is called with phase marks 0..3 between them
+hipError_t compress_launches(Workspace &ws, int num_cus, const void *d_field, const Geom &g,
+                             const Tile &tile, double eps, const pwrel_mlp *model,
+                             const pwrel_options &opt, const Sections &sec, hipStream_t s,
+                             void (*mark_fn)(void *, int, hipStream_t), void *mark_arg);
 
 }  // namespace pwrel

@@ -94,6 +94,12 @@ _SIGS = {
                                  C.POINTER(C.c_uint64), _P]),
     "pwrel_decompress": (C.c_int, [_P, _P, C.c_uint64, _P, _P, C.c_int, C.c_int, _P]),
     "pwrel_read_header": (C.c_int, [_P, C.c_uint64, C.POINTER(Header)]),
+    "pwrel_compress_raw": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
+                                     C.POINTER(Mlp), C.POINTER(Options), _P, _P, _P, _P,
+                                     C.c_uint64, C.POINTER(Header), _P]),
+    "pwrel_model_save": (C.c_int, [C.POINTER(Mlp), _P, C.c_uint64, C.POINTER(C.c_uint64)]),
+    "pwrel_model_load": (C.c_int, [_P, C.c_uint64, C.POINTER(Mlp)]),
+    "pwrel_stream_model": (C.c_int, [_P, _P, C.c_uint64, C.POINTER(Mlp), _P]),
     "pwrel_transform": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, _P,
                                   C.POINTER(Header), _P]),
     "pwrel_encode_grid": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.POINTER(Mlp),
@@ -239,6 +245,31 @@ def read_header_bytes(buf, size=None):
     return header_dict(h)
 
 
+def model_save(model):
+    """Serialise a network (dict or Mlp) to bytes (pwrel_model_save)."""
+    m = model_struct(model)
+    size = C.c_uint64(0)
+    st = lib().pwrel_model_save(C.byref(m), None, 0, C.byref(size))
+    if st not in (OK, ENOSPC):
+        raise PwrelError(st, "model_save")
+    buf = C.create_string_buffer(size.value)
+    st = lib().pwrel_model_save(C.byref(m), C.cast(buf, _P), size.value, C.byref(size))
+    if st:
+        raise PwrelError(st, "model_save")
+    return buf.raw[:size.value]
+
+
+def model_load(data):
+    """Parse bytes written by model_save into a network dict (pwrel_model_load)."""
+    data = bytes(data)
+    buf = C.create_string_buffer(data, max(len(data), 1))
+    m = Mlp()
+    st = lib().pwrel_model_load(C.cast(buf, _P), len(data), C.byref(m))
+    if st:
+        raise PwrelError(st, "model_load")
+    return model_dict(m)
+
+
 def huffman_bits(hist):
     hist = np.ascontiguousarray(hist, dtype=np.uint64)
     assert hist.size == 65536
@@ -319,6 +350,46 @@ class Context:
                                       _dtype_code(dtype), _stream(stream))
         self._check(st, "decompress")
         return out
+
+    def compress_raw(self, x, eps, block=8, model=None, use_net=True, judge=False,
+                     independent=False, raw_capacity=None, stream=None):
+        """pwrel_compress_raw: the sections of a compression in separate device
+        tensors; returns dict(header, codes int16 [n], counts int32 [nblocks],
+        bflags uint8 [nblocks] | None, raw [n_raw])."""
+        import torch
+        assert x.is_cuda and x.is_contiguous()
+        dt = _dtype_code(x.dtype)
+        n = x.numel()
+        nb = 1
+        for d in x.shape:
+            nb *= -(-int(d) // int(block))
+        cap = n if raw_capacity is None else int(raw_capacity)
+        codes = torch.empty(max(n, 1), dtype=torch.int16, device=x.device)
+        counts = torch.empty(max(nb, 1), dtype=torch.int32, device=x.device)
+        bflags = torch.empty(max(nb, 1), dtype=torch.uint8, device=x.device) if judge else None
+        raw = torch.empty(max(cap, 1), dtype=x.dtype, device=x.device)
+        m = model_struct(model) if use_net else None
+        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
+        h = Header()
+        st = self._L.pwrel_compress_raw(
+            self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(), dt, float(eps),
+            int(block), C.byref(m) if m is not None else None, C.byref(opt),
+            C.c_void_p(codes.data_ptr()), C.c_void_p(counts.data_ptr()),
+            C.c_void_p(bflags.data_ptr()) if bflags is not None else None,
+            C.c_void_p(raw.data_ptr()), cap, C.byref(h), _stream(stream))
+        self._check(st, "compress_raw")
+        hd = header_dict(h)
+        return {"header": hd, "codes": codes[:n], "counts": counts[:nb],
+                "bflags": bflags[:nb] if bflags is not None else None,
+                "raw": raw[:hd["n_raw"]]}
+
+    def stream_model(self, stream_t, stream=None):
+        """The network stored in a device stream (pwrel_stream_model)."""
+        m = Mlp()
+        st = self._L.pwrel_stream_model(self.h, C.c_void_p(stream_t.data_ptr()),
+                                        stream_t.numel(), C.byref(m), _stream(stream))
+        self._check(st, "stream_model")
+        return model_dict(m)
 
     # learned part ------------------------------------------------------------
     def train(self, x, eps, block=8, init=None, rho=0.01, seed=0, hidden=32, alpha=0.01,
@@ -473,10 +544,12 @@ def header(stream_t):
 
 
 def sections(stream_t):
-    """Header dict plus the sections of a device stream, as device tensor views."""
+    """Header dict plus the sections of a device stream, as device tensor views
+    (only the header and the model are copied to the host)."""
     import torch
-    raw = stream_t.cpu().numpy().tobytes()
-    h = read_header_bytes(raw)
+    head = stream_t[:HEADER_BYTES + C.sizeof(Mlp)].cpu().numpy().tobytes()
+    h = read_header_bytes(head, size=stream_t.numel())
+    raw = head
     n, nb, nr = h["n"], h["nblocks"], h["n_raw"]
     tdt = torch.float32 if h["dtype"] == F32 else torch.float64
     tsz = 4 if h["dtype"] == F32 else 8

@@ -17,6 +17,8 @@ Recipes (seed fixed per call):
                      (connected regions), then an exact fraction of zeros.
   zonal_bands_2d  -- sum_j (1/j) cos(2 pi j (i_lat + 1/2) / n_lat), j = 1..4,
                      plus 0.1 x a standardised 2-D k^-2 random field.
+  lognormal_grf_device -- the lognormal_grf recipe drawn with torch on the
+                     GPU, for multi-gigabyte fields (the FP64 volume).
 """
 import numpy as np
 
@@ -125,3 +127,65 @@ def batch_shapes(n_fields=2000, seed=3000, lo2=128, hi2=1024, lo3=32, hi3=256):
         else:
             out.append(tuple(int(v) for v in rng.integers(lo3, hi3 + 1, size=3)))
     return out
+
+
+def lognormal_grf_device(shape, seed=0, decades=8.0, neg_frac=0.10, zero_frac=0.005, slope=3.0,
+                         dtype=None, device="cuda"):
+    """The lognormal_grf recipe drawn on the GPU with torch (for fields of
+    gigabytes, where the host FFT would take minutes).  The numbers differ
+    from lognormal_grf's (another generator) but follow the same recipe; the
+    sign threshold is the (1 - neg_frac) quantile of a 2^24-value subsample of
+    its field.  Returns a torch tensor on `device`."""
+    import torch
+    dtype = torch.float32 if dtype is None else dtype
+    shape = tuple(int(s) for s in shape)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+
+    def grf():
+        white = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+        spec = torch.fft.rfftn(white)
+        del white
+        k2 = None
+        for ax, n in enumerate(shape):
+            if ax == len(shape) - 1:
+                f = torch.fft.rfftfreq(n, device=device, dtype=torch.float64) * n
+            else:
+                f = torch.fft.fftfreq(n, device=device, dtype=torch.float64) * n
+            sh = [1] * len(shape)
+            sh[ax] = f.numel()
+            term = (f * f).reshape(sh)
+            k2 = term if k2 is None else k2 + term
+        amp = torch.where(k2 > 0, k2.clamp_min(1e-300) ** (-slope / 4.0),
+                          torch.zeros((), dtype=torch.float64, device=device))
+        spec *= amp
+        del amp, k2
+        g = torch.fft.irfftn(spec, s=shape)
+        del spec
+        g -= g.mean()
+        sd = g.std()
+        if sd > 0:
+            g /= sd
+        return g
+
+    g = grf()
+    gm = g.abs().max()
+    if gm > 0:
+        g *= (decades / 2.0) / gm
+    mag = torch.pow(10.0, g)
+    del g
+    if neg_frac > 0:
+        s = grf()
+        flat = s.reshape(-1)
+        pick = torch.randint(0, flat.numel(), (min(flat.numel(), 1 << 24),), generator=gen,
+                             device=device)
+        thr = torch.quantile(flat[pick].float(), 1.0 - neg_frac).double()
+        mag[s > thr] *= -1.0
+        del s, flat, pick
+    x = mag.to(dtype)
+    del mag
+    nz = int(round(zero_frac * x.numel()))
+    if nz > 0:
+        idx = torch.randperm(x.numel(), generator=gen, device=device)[:nz]
+        x.view(-1)[idx] = 0
+    return x

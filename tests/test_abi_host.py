@@ -192,3 +192,70 @@ def test_model_struct_fills_every_field():
         pwrel.model_struct({"alpha": 0.0, "w1": np.zeros((33, 6), np.float32),
                             "b1": np.zeros(33, np.float32), "v": np.zeros(33, np.float32),
                             "b2": 0.0})
+
+
+# --- trained network kept between fields (Sec. 5): save / load ---------------------------
+
+def _trained_like(ndim, H, seed):
+    rng = np.random.default_rng(seed)
+    m = pwrel.mlp_init(ndim, H, 0.01, seed)
+    K = (1 << ndim) - 2
+    m["w1"] = (m["w1"] + rng.normal(0, 0.3, (H, K))).astype(np.float32)
+    m["b1"] = rng.normal(0, 1, H).astype(np.float32)
+    m["v"] = rng.normal(0, 1, H).astype(np.float32)
+    m["b2"] = float(np.float32(rng.normal()))
+    m["precision"] = 1
+    return m
+
+
+@pytest.mark.parametrize("ndim,H", [(3, 32), (2, 16), (1, 4)])
+def test_model_save_load_round_trip(ndim, H):
+    m = _trained_like(ndim, H, ndim * 10 + H)
+    data = pwrel.model_save(m)
+    K = (1 << ndim) - 2
+    assert len(data) == 24 + 4 * (H * K + 2 * H + 1) + 8
+    assert data[:4] == b"PWMD" and struct.unpack("<I", data[4:8])[0] == 1
+    back = pwrel.model_load(data)
+    for k in ("w1", "b1", "v"):
+        assert np.array_equal(np.asarray(back[k]).view(np.uint32),
+                              np.asarray(m[k], np.float32).view(np.uint32)), k
+    assert np.float32(back["b2"]) == np.float32(m["b2"])
+    assert back["precision"] == 1 and back["alpha"] == np.float32(0.01)
+    # the bytes are a fixed function of the network
+    assert pwrel.model_save(back) == data
+
+
+def test_model_load_rejects_damage():
+    data = pwrel.model_save(_trained_like(3, 16, 5))
+    for i in (0, 5, 9, 30, len(data) - 20, len(data) - 1):
+        bad = bytearray(data)
+        bad[i] ^= 0x10
+        with pytest.raises(pwrel.PwrelError) as e:
+            pwrel.model_load(bytes(bad))
+        assert e.value.status == pwrel.ECORRUPT, i
+    for cut in (0, 10, len(data) - 1):
+        with pytest.raises(pwrel.PwrelError) as e:
+            pwrel.model_load(data[:cut])
+        assert e.value.status == pwrel.ECORRUPT
+    with pytest.raises(pwrel.PwrelError) as e:
+        pwrel.model_load(data + b"\0")
+    assert e.value.status == pwrel.ECORRUPT
+
+
+def test_model_save_capacity_and_invalid_network():
+    L = pwrel.lib()
+    m = pwrel.model_struct(_trained_like(3, 8, 1))
+    size = C.c_uint64(0)
+    assert L.pwrel_model_save(C.byref(m), None, 0, C.byref(size)) == pwrel.ENOSPC
+    need = size.value
+    buf = C.create_string_buffer(need)
+    assert L.pwrel_model_save(C.byref(m), C.cast(buf, C.c_void_p), need - 1,
+                              C.byref(size)) == pwrel.ENOSPC
+    assert L.pwrel_model_save(C.byref(m), C.cast(buf, C.c_void_p), need, C.byref(size)) == 0
+    m.hidden = 40
+    assert L.pwrel_model_save(C.byref(m), C.cast(buf, C.c_void_p), need,
+                              C.byref(size)) == pwrel.EINVAL
+    m.hidden = 8
+    m.w1[0][0] = float("nan")
+    assert L.pwrel_model_save(C.byref(m), C.cast(buf, C.c_void_p), need,
+                              C.byref(size)) == pwrel.EINVAL

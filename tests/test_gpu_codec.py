@@ -192,6 +192,14 @@ def _case(name):
         shape = {"pencil_thin_z": (3, 17, 40), "pencil_thin_y": (17, 3, 40),
                  "pencil_long": (9, 10, 203), "pencil_single_x": (20, 19, 7)}[name]
         return synth.lognormal_grf(shape, seed=13), 1e-2, 8, random_model(3, 16, 13), False
+    if name == "flow_96cubed_B16":
+        # block-flow halo decoder (non-pencil shape) with 216 blocks: the size
+        # at which a bounded wait of an earlier decoder gave up
+        return synth.lognormal_grf((96, 96, 96), seed=15), 1e-2, 16, random_model(3, 16, 15), \
+            False
+    if name == "flow_B4_1320_blocks":
+        return synth.lognormal_grf((48, 40, 44), seed=16), 1e-2, 4, random_model(3, 16, 16), \
+            False
     if name == "lorenzo_only":
         return synth.lognormal_grf((30, 31, 66), seed=10), 1e-2, 8, None, False
     if name == "single_point":
@@ -211,7 +219,8 @@ CASES = ["config0_bumps64", "grf_ragged_1e-3", "grf_ragged_indep", "grf_B4_H32",
          "grf_B5", "zonal_2d", "grf_2d_B64", "grf_1d_halo", "grf_1d_indep", "f64_1e-4",
          "lorenzo_only", "single_point", "all_zero", "tiny_1d", "sign_gap_delta",
          "f32_range_ends_1e-2", "f32_smooth_range_hi", "f32_smooth_range_lo",
-         "pencil_thin_z", "pencil_thin_y", "pencil_long", "pencil_single_x"]
+         "pencil_thin_z", "pencil_thin_y", "pencil_long", "pencil_single_x",
+         "flow_96cubed_B16", "flow_B4_1320_blocks"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -437,3 +446,40 @@ def test_fast_path_boundaries(ctx, eps):
     assert_bound(x, xh, eps)
     # the sweep reaches both verdicts of the bound check
     assert 0 < g["h"]["n_raw"] < x.size
+
+
+# --- sections in separate buffers (pwrel_compress_raw) and the stored network -----------------
+
+@pytest.mark.parametrize("judge", [False, True])
+def test_compress_raw_equals_stream_sections(ctx, judge):
+    x = synth.lognormal_grf((37, 45, 51), seed=21, decades=10, neg_frac=0.1, zero_frac=0.01)
+    model = random_model(3, 16, 21)
+    xd = dev(x)
+    stream = ctx.compress(xd, 1e-3, 8, model, judge=judge)
+    sec = pwrel.sections(stream)
+    r = ctx.compress_raw(xd, 1e-3, 8, model, judge=judge)
+    h, hr = sec["header"], r["header"]
+    assert h["n_raw"] > 0
+    for k in h:
+        assert hr[k] == h[k], k
+    assert torch.equal(r["codes"], sec["codes"])
+    assert torch.equal(r["counts"], sec["counts"])
+    assert torch.equal(r["raw"], sec["raw"])
+    if judge:
+        assert torch.equal(r["bflags"], sec["bflags"])
+    # too small a raw capacity is reported, not overrun
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.compress_raw(xd, 1e-3, 8, model, judge=judge, raw_capacity=h["n_raw"] - 1)
+    assert e.value.status == pwrel.ENOSPC
+
+
+def test_stream_model_and_saved_model_compress_alike(ctx):
+    x = synth.lognormal_grf((40, 40, 48), seed=22)
+    model, _ = ctx.train(dev(x), 1e-2, 8, rho=0.05, seed=22, hidden=16, precision=1)
+    a = ctx.compress(dev(x), 1e-2, 8, model, judge=True).clone()
+    kept = pwrel.model_load(pwrel.model_save(ctx.stream_model(a)))
+    b = ctx.compress(dev(x), 1e-2, 8, kept, judge=True)
+    assert torch.equal(a, b)
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.stream_model(ctx.compress(dev(x), 1e-2, 8, None, use_net=False))
+    assert e.value.status == pwrel.EINVAL

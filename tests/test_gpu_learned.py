@@ -10,14 +10,18 @@
   scores of those networks, the choice is the best score, and it pays;
 - the matrix-core (BF16) network inside the codec: points without a full
   stencil carry exactly the oracle's Lorenzo codes; at every other point the
-  integer prediction the code implies lies within 1/2 + slack of the oracle's
-  FP64 reference of the BF16 network; the stream decodes bit-exactly to the
-  value its codes define (the inverse transform of the grid value, or the
-  stored raw value);
+  integer prediction the code implies lies within 1/2 + B(u) of the network's
+  FP64 value (the FP32-weight network of Sec. 4.2 evaluated exactly), B(u) the
+  oracle's error bound for BF16-operand inference derived from bf16 unit
+  roundoff and the weight and input magnitudes; as a secondary check, within
+  1/2 + slack of the oracle's reference of the kernel's own rounding points;
+  the stream decodes bit-exactly to the value its codes define (the inverse
+  transform of the grid value, or the stored raw value);
 - the per-block judge: with FP32 networks every output equals the oracle's
-  learned mode; with the BF16 network every block's flag is the comparison of
-  the two scores of that block (network codes of the plain run, Lorenzo codes
-  of the oracle) and the block carries the winner's codes;
+  learned mode (entropy of each block's full code multiset); with the BF16
+  network every block's flag is the comparison of the two scores of that
+  block (network codes of the plain run, Lorenzo codes of the oracle) and the
+  block carries the winner's codes;
 - 512^3 FP32: train, compress with the judge, decode; bound on every point,
   sampled codes against the oracle.
 """
@@ -111,13 +115,19 @@ def check_bf16_stream(x, eps, B, model, indep, stream):
     net = net_points(x.shape, B, indep)
     # no full stencil: Lorenzo with missing neighbours as zero, exactly
     assert np.array_equal(codes[~net], rc[~net])
-    # full stencil: the implied integer prediction against the BF16 reference
+    # full stencil: the implied integer prediction against the network's FP64
+    # value, within the derived BF16 bound (primary), and against the
+    # reference of the kernel's rounding points (secondary)
     u, n1 = stencil_inputs(p)
-    yref, slack = O.mlp_eval_bf16_ref(model, u[net].astype(np.float32))
+    un = u[net].astype(np.float32)
+    y64, bound = O.mlp_eval_f64(model, un)
+    yref, slack = O.mlp_eval_bf16_ref(model, un)
     c = codes[net].astype(np.int64)
     pn, n1n = p[net].astype(np.int64), n1[net]
     coded = c != 0
     y_int = c - R + pn - n1n
+    dev64 = np.abs(y_int[coded] - y64[coded])
+    assert np.all(dev64 <= 0.5 + bound[coded]), (dev64 - bound[coded]).max()
     dev_ = np.abs(y_int[coded] - yref[coded])
     assert np.all(dev_ <= 0.5 + slack[coded] + 1e-9), dev_.max()
     # balance points at full stencils: failed verification or an error near 2^15
@@ -187,11 +197,21 @@ def test_loss_grad_matches_oracle(ctx, ndim, H):
     th = rng.normal(0, 0.3, H * K + 2 * H + 1).astype(np.float32)
     sigma, lam, alpha = 7.3, 1e-3, 0.01
     loss, g = ctx.loss_grad(dev(th), H, K, alpha, dev(u), dev(t), sigma, lam)
-    loss_r, g_r = O.loss_grad(th.astype(np.float64), H, K, alpha, u.astype(np.float64),
-                              t.astype(np.float64), sigma, lam)
+    th64, u64, t64 = th.astype(np.float64), u.astype(np.float64), t.astype(np.float64)
+    loss_r, g_r = O.loss_grad(th64, H, K, alpha, u64, t64, sigma, lam)
+    gabs, gres = O.loss_grad_abs(th64, H, K, alpha, u64, t64, sigma, lam)
     assert abs(loss - loss_r) <= 1e-5 * abs(loss_r)
     g = g.cpu().numpy().astype(np.float64)
-    assert np.allclose(g, g_r, rtol=1e-3, atol=1e-4 * np.abs(g_r).max())
+    # FP32 attainable: each component is a serial FP32 sum of n terms (error
+    # <= gamma_n sum |terms|, the recursive-summation bound), each term a few
+    # roundings off, and the residual it multiplies off by a small multiple of
+    # the magnitudes it was computed from
+    n, u32 = t.size, 2.0 ** -24
+    tol = u32 * ((n + 16) * gabs + (H + K + 16) * gres)
+    d = np.abs(g - g_r)
+    assert np.all(d <= tol), (d / tol).max()
+    # and typically far inside it (rounding errors do not all line up)
+    assert np.median(d / tol) <= 0.05, np.median(d / tol)
 
 
 @pytest.mark.parametrize("ndim,H", [(3, 16), (2, 8)])
@@ -204,16 +224,30 @@ def test_adam_steps_match_oracle(ctx, ndim, H):
     lrs, lams = [1e-3, 3e-3], [1e-4, 0.0]
     out = ctx.train_pairs(dev(u), dev(t), H, K, alpha, sigma, dev(th0), lrs, lams, batch=256,
                           epochs=1).cpu().numpy().astype(np.float64)
+    u64, t64 = u.astype(np.float64), t.astype(np.float64)
     for c in range(2):
-        ref, *_ = O.train_pass(th0.astype(np.float64), H, K, alpha, u.astype(np.float64),
-                               t.astype(np.float64), sigma, lams[c], lrs[c], 256, 1)
+        ref, *_ = O.train_pass(th0.astype(np.float64), H, K, alpha, u64, t64, sigma, lams[c],
+                               lrs[c], 256, 1)
         d = np.abs(out[c] - ref)
-        # Adam's normalised steps move each parameter by ~lr per step; FP32
-        # gradients change that by a tiny fraction except where a gradient
-        # component is itself at the rounding level
-        assert np.median(d) <= 1e-3 * lrs[c]
-        assert np.mean(d <= 0.01 * lrs[c]) >= 0.98
-        assert np.all(d <= 6 * lrs[c])
+        # Adam's step lr m^ / (sqrt(v^) + eps) depends on gradient ratios, not
+        # sizes: a parameter whose gradient stays well above its FP32 error at
+        # every step follows the oracle to a small fraction of lr; one whose
+        # gradient is at the rounding level may take another sign.  Replay the
+        # oracle step by step and split the parameters that way.
+        th, am, av, st = th0.astype(np.float64), None, None, 0
+        clear = np.ones(th.size, dtype=bool)
+        for s0 in range(0, t.size, 256):
+            ub, tb = u64[s0:s0 + 256], t64[s0:s0 + 256]
+            _, gs = O.loss_grad(th, H, K, alpha, ub, tb, sigma, lams[c])
+            ga, gr = O.loss_grad_abs(th, H, K, alpha, ub, tb, sigma, lams[c])
+            tol = 2.0 ** -24 * ((tb.size + 16) * ga + (H + K + 16) * gr)
+            clear &= np.abs(gs) > 20 * tol
+            th, am, av, st = O.train_pass(th, H, K, alpha, ub, tb, sigma, lams[c], lrs[c], 256,
+                                          1, am, av, st)
+        assert np.array_equal(th, ref)
+        assert clear.mean() >= 0.9, clear.mean()
+        assert np.all(d[clear] <= 1e-3 * lrs[c]), d[clear].max() / lrs[c]
+        assert np.median(d) <= 1e-4 * lrs[c]
 
 
 # --- training entry point ----------------------------------------------------------------------
@@ -385,6 +419,8 @@ def test_learned_full_size_512cubed(ctx):
     cg = codes[net["pos"].astype(np.int64)].astype(np.int64)
     coded = cg != 0
     y_int = cg - R + net["p"].astype(np.int64) - left["p"].astype(np.int64)
+    d64 = np.abs(y_int[coded] - net["y64"][coded])
+    assert np.all(d64 <= 0.5 + net["bound"][coded]), (d64 - net["bound"][coded]).max()
     d = np.abs(y_int[coded] - net["yref"][coded])
     assert np.all(d <= 0.5 + net["slack"][coded] + 1e-9), d.max()
     # network blocks at faces (no full stencil) use Lorenzo with missing neighbours as zero
