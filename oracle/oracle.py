@@ -104,6 +104,12 @@ def lib():
                                        C.c_double, C.c_double, P, P]
         L.or_theta_eval_many.argtypes = [P, C.c_int, C.c_int, C.c_double, P, C.c_int64,
                                          C.c_double, P]
+        L.or_huff_lengths.argtypes = [P, C.c_int, C.c_int, P]
+        L.or_huff_canonical.argtypes = [P, C.c_int, C.c_int, P]
+        L.or_huff_encode.restype = C.c_int64
+        L.or_huff_encode.argtypes = [P, C.c_int64, P, P, P]
+        L.or_huff_decode.restype = C.c_int64
+        L.or_huff_decode.argtypes = [P, C.c_int64, C.c_int64, P, C.c_int, C.c_int, P]
         L.or_bf16_rne.restype = C.c_float
         L.or_bf16_rne.argtypes = [C.c_float]
         L.or_entropy_j.restype = C.c_int64
@@ -211,6 +217,54 @@ def mlp_eval_f64(model, u):
     m = _to_c_mlp(model)
     lib().or_mlp_eval_f64_many(C.byref(m), _ptr(u), n, _ptr(y), _ptr(b))
     return y, b
+
+
+# --- Huffman stage (Sec. 4.1 coding of the codes) --------------------------------------
+
+HUFF_LMAX = 24
+
+
+def huff_lengths(hist, lmax=HUFF_LMAX):
+    """Optimal code lengths with no codeword longer than lmax (package-merge)."""
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    ln = np.zeros(hist.size, dtype=np.uint8)
+    st = lib().or_huff_lengths(_ptr(hist), hist.size, int(lmax), _ptr(ln))
+    if st:
+        raise OracleError(st, "huff_lengths")
+    return ln
+
+
+def huff_canonical(lengths, lmax=HUFF_LMAX):
+    ln = np.ascontiguousarray(lengths, dtype=np.uint8)
+    code = np.zeros(ln.size, dtype=np.uint32)
+    st = lib().or_huff_canonical(_ptr(ln), ln.size, int(lmax), _ptr(code))
+    if st:
+        raise OracleError(st, "huff_canonical")
+    return code
+
+
+def huff_encode(codes, lengths, lmax=HUFF_LMAX):
+    """Bitstream (uint32 words, MSB first) of the codes and its bit count."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    ln = np.ascontiguousarray(lengths, dtype=np.uint8)
+    cw = huff_canonical(ln, lmax)
+    nbits = int(ln[codes].astype(np.int64).sum())
+    words = np.zeros(max((nbits + 31) // 32, 1), dtype=np.uint32)
+    got = lib().or_huff_encode(_ptr(codes), codes.size, _ptr(ln), _ptr(cw), _ptr(words))
+    assert got == nbits
+    return words, nbits
+
+
+def huff_decode(words, n, lengths, start=0, lmax=HUFF_LMAX):
+    """n codes decoded from bit `start` of the stream; returns (codes, end bit)."""
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    ln = np.ascontiguousarray(lengths, dtype=np.uint8)
+    out = np.zeros(max(int(n), 1), dtype=np.uint16)
+    end = lib().or_huff_decode(_ptr(words), int(start), int(n), _ptr(ln), ln.size, int(lmax),
+                               _ptr(out))
+    if end < 0:
+        raise OracleError(-5, "huff_decode")
+    return out[:n], end
 
 
 # --- deterministic math -------------------------------------------------------

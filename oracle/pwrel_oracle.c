@@ -1426,6 +1426,220 @@ void or_mlp_eval_bf16_many(const or_mlp *m, const float *u, int64_t n, double *y
 
 float or_bf16_rne(float f) { return bf16_rne(f); }
 
+/* ------------------------------------------------------------------------ */
+/* Entropy coding of the codes (Sec. 4.1: the quantised codes go through a   */
+/* Huffman coding stage; Algorithm 1's Huffman step; Sec. 5 rebuilds the     */
+/* tree to decode).  Code lengths: optimal prefix code with no codeword      */
+/* longer than Lmax, by package-merge (Larmore and Hirschberg 1990);         */
+/* codewords: canonical assignment (shorter codes first, equal lengths in    */
+/* symbol order; the convention of RFC 1951, Sec. 3.2.2).  Bitstream: the    */
+/* codewords of the codes in stream order, concatenated; bit i of the stream */
+/* is bit 31 - (i mod 32) of 32-bit word i / 32 (most significant first).    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t w;
+    int32_t a, b; /* leaf: a = symbol, b = -1; package: the two item indices (previous row) */
+} pm_item;
+
+static int pm_cmp(const void *x, const void *y)
+{
+    const pm_item *p = (const pm_item *)x, *q = (const pm_item *)y;
+    return (p->w > q->w) - (p->w < q->w);
+}
+
+/* add 1 to the length of every leaf under item k of row r */
+static void pm_count(pm_item **rows, int r, int k, uint8_t *len)
+{
+    const pm_item *it = &rows[r][k];
+    if (it->b < 0) {
+        len[it->a]++;
+        return;
+    }
+    pm_count(rows, r - 1, it->a, len);
+    pm_count(rows, r - 1, it->b, len);
+}
+
+/* Code lengths of the nsym symbols with counts hist (0 = unused, length 0).
+ * One used symbol gets length 1.  Returns 0, or -1 if Lmax is too small for
+ * the number of used symbols (2^Lmax < n) or memory runs out. */
+int or_huff_lengths(const uint64_t *hist, int nsym, int Lmax, uint8_t *len)
+{
+    int n = 0;
+    for (int s = 0; s < nsym; ++s) {
+        len[s] = 0;
+        n += hist[s] != 0;
+    }
+    if (n == 0)
+        return 0;
+    if (n == 1) {
+        for (int s = 0; s < nsym; ++s)
+            if (hist[s])
+                len[s] = 1;
+        return 0;
+    }
+    if (Lmax < 1 || Lmax > 62 || ((uint64_t)1 << Lmax) < (uint64_t)n)
+        return -1;
+    /* leaves sorted by count (ties: symbol order, by a stable sort of the
+     * symbol-ordered list) */
+    pm_item *leaves = (pm_item *)malloc((size_t)n * sizeof(pm_item));
+    pm_item **rows = (pm_item **)calloc((size_t)Lmax, sizeof(pm_item *));
+    int *rn = (int *)calloc((size_t)Lmax, sizeof(int));
+    if (!leaves || !rows || !rn) {
+        free(leaves); free(rows); free(rn);
+        return -1;
+    }
+    int k = 0;
+    for (int s = 0; s < nsym; ++s)
+        if (hist[s]) {
+            leaves[k].w = hist[s];
+            leaves[k].a = s;
+            leaves[k].b = -1;
+            k++;
+        }
+    /* insertion sort keeps equal counts in symbol order (stable) */
+    for (int i = 1; i < n; ++i) {
+        pm_item t = leaves[i];
+        int j = i - 1;
+        while (j >= 0 && leaves[j].w > t.w) {
+            leaves[j + 1] = leaves[j];
+            j--;
+        }
+        leaves[j + 1] = t;
+    }
+    (void)pm_cmp;
+    /* row 0: the leaves; row r: the leaves merged with the packages (pairs)
+     * of row r - 1, in weight order (a leaf before a package of equal weight) */
+    int st = 0;
+    for (int r = 0; r < Lmax && st == 0; ++r) {
+        int np = r == 0 ? 0 : rn[r - 1] / 2;
+        rows[r] = (pm_item *)malloc((size_t)(n + np) * sizeof(pm_item));
+        if (!rows[r]) {
+            st = -1;
+            break;
+        }
+        int i = 0, j = 0, o = 0;
+        while (i < n || j < np) {
+            uint64_t pw = 0;
+            if (j < np)
+                pw = rows[r - 1][2 * j].w + rows[r - 1][2 * j + 1].w;
+            if (j >= np || (i < n && leaves[i].w <= pw)) {
+                rows[r][o++] = leaves[i++];
+            } else {
+                rows[r][o].w = pw;
+                rows[r][o].a = 2 * j;
+                rows[r][o].b = 2 * j + 1;
+                o++;
+                j++;
+            }
+        }
+        rn[r] = o;
+    }
+    if (st == 0 && rn[Lmax - 1] < 2 * n - 2)
+        st = -1;
+    if (st == 0) {
+        /* the 2n - 2 lightest items of the last row; every leaf occurrence
+         * inside them adds one to that leaf's length */
+        int take = 2 * n - 2;
+        for (int q = 0; q < take; ++q)
+            pm_count(rows, Lmax - 1, q, len);
+    }
+    for (int r = 0; r < Lmax; ++r)
+        free(rows[r]);
+    free(rows); free(rn); free(leaves);
+    return st;
+}
+
+/* Canonical codewords of the lengths (RFC 1951, Sec. 3.2.2): returns 0, or
+ * -1 if the lengths over-subscribe the code space (Kraft sum > 1). */
+int or_huff_canonical(const uint8_t *len, int nsym, int Lmax, uint32_t *code)
+{
+    uint32_t bl_count[64] = {0}, next_code[64] = {0};
+    for (int s = 0; s < nsym; ++s) {
+        if (len[s] > Lmax)
+            return -1;
+        if (len[s])
+            bl_count[len[s]]++;
+    }
+    uint64_t c = 0;
+    for (int b = 1; b <= Lmax; ++b) {
+        c = (c + bl_count[b - 1]) << 1;
+        next_code[b] = (uint32_t)c;
+        if (c + bl_count[b] > ((uint64_t)1 << b))
+            return -1;
+    }
+    for (int s = 0; s < nsym; ++s)
+        code[s] = len[s] ? next_code[len[s]]++ : 0;
+    return 0;
+}
+
+/* The bitstream of n codes (stream order): word i/32, bit 31 - i%32.
+ * words must hold ceil(total bits / 32) zeroed words.  Returns the bit count. */
+int64_t or_huff_encode(const uint16_t *codes, int64_t n, const uint8_t *len, const uint32_t *code,
+                       uint32_t *words)
+{
+    int64_t pos = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int l = len[codes[i]];
+        uint32_t c = code[codes[i]];
+        for (int k = l - 1; k >= 0; --k) {
+            if ((c >> k) & 1u)
+                words[pos >> 5] |= 1u << (31 - (pos & 31));
+            pos++;
+        }
+    }
+    return pos;
+}
+
+/* Decode n codes from a bitstream starting at bit `start`, bit by bit down
+ * the canonical code (a codeword of length l is the l-th bit prefix whose
+ * value lies in [first[l], first[l] + count[l]) ).  Returns the bit position
+ * after the last code, or -1 if the bits match no codeword. */
+int64_t or_huff_decode(const uint32_t *words, int64_t start, int64_t n, const uint8_t *len,
+                       int nsym, int Lmax, uint16_t *out)
+{
+    uint32_t bl_count[64] = {0}, first[64] = {0};
+    int32_t index[64] = {0};
+    for (int s = 0; s < nsym; ++s)
+        if (len[s])
+            bl_count[len[s]]++;
+    /* symbols in canonical order: by length, then symbol */
+    int32_t *sorted = (int32_t *)malloc((size_t)(nsym > 0 ? nsym : 1) * sizeof(int32_t));
+    if (!sorted)
+        return -1;
+    int m = 0;
+    uint32_t c = 0;
+    for (int b = 1; b <= Lmax; ++b) {
+        c = (c + bl_count[b - 1]) << 1;
+        first[b] = c;
+        index[b] = m;
+        for (int s = 0; s < nsym; ++s)
+            if (len[s] == b)
+                sorted[m++] = s;
+    }
+    int64_t pos = start;
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t v = 0;
+        int b = 0, found = 0;
+        while (b < Lmax) {
+            v = (v << 1) | ((words[pos >> 5] >> (31 - (pos & 31))) & 1u);
+            pos++;
+            b++;
+            if (v - first[b] < bl_count[b]) {
+                out[i] = (uint16_t)sorted[index[b] + (int32_t)(v - first[b])];
+                found = 1;
+                break;
+            }
+        }
+        if (!found) {
+            free(sorted);
+            return -1;
+        }
+    }
+    free(sorted);
+    return pos;
+}
+
 /* FP64 value of the network and the BF16 error bound of mlp_bf16_bound. */
 void or_mlp_eval_f64_many(const or_mlp *m, const float *u, int64_t n, double *y, double *bound)
 {
