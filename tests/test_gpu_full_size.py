@@ -83,10 +83,10 @@ def test_fp64_volume_4gib(ctx):
     print(f"[full] FP64 {shape} eps {eps}: generating", flush=True)
     xd = synth.lognormal_grf_device(shape, seed=1004, decades=12, neg_frac=0.10, zero_frac=0.01,
                                     dtype=torch.float64)
-    assert xd.numel() * 8 == 4 << 30
+    assert xd.numel() * 8 == 4 << 30  # byte offsets into the field pass 2^32
     model = fp32_model(3, 16, 1004)
     stream = ctx.compress(xd, eps, B, model)
-    assert stream.numel() > (1 << 32)  # offsets beyond 2^32 bytes are in use
+    assert stream.numel() > (1 << 30)  # the codes alone are 1 GiB
     xh = ctx.decompress(stream)
     torch.cuda.synchronize()
     print("[full] FP64 compressed and decompressed", flush=True)
@@ -136,18 +136,19 @@ def test_zonal_2d_learned_full_size(ctx):
     codes_s = sec["codes"].cpu().numpy().view(np.uint16)
     flags = sec["bflags"].cpu().numpy()
     c = O.consts(x, eps)
-    # stream order -> field order (all blocks full: 1800 and 3600 are multiples of 16)
-    nby, nbx = shape[0] // B, shape[1] // B
-    q = np.arange(x.size)
-    blk, loc = q // (B * B), q % (B * B)
-    fy = (blk // nbx) * B + loc // B
-    fx = (blk % nbx) * B + loc % B
-    codes = np.empty(shape, dtype=np.uint16)
-    codes[fy, fx] = codes_s
-    bflag = np.repeat(np.repeat(flags.reshape(nby, nbx), B, 0), B, 1).astype(bool)
+    # stream position of every field point: block rows of height hb = min(B, 1800 - by*B)
+    # (the last one is ragged), blocks of width B (3600 = 225 * 16), local raster order
+    nby, nbx = -(-shape[0] // B), -(-shape[1] // B)
+    yy, xx = np.meshgrid(np.arange(shape[0]), np.arange(shape[1]), indexing="ij")
+    by, bx = yy // B, xx // B
+    hb = np.minimum(B, shape[0] - by * B)
+    bw = np.minimum(B, shape[1] - bx * B)
+    pos = by * B * shape[1] + bx * B * hb + (yy % B) * bw + (xx % B)
+    assert np.array_equal(np.sort(pos.reshape(-1)), np.arange(x.size))
+    codes = codes_s[pos]
     lor = O.compress(x, eps, B, None, O.MODE_LORENZO)
-    lcodes = np.empty(shape, dtype=np.uint16)
-    lcodes[fy, fx] = lor["codes"]
+    lcodes = lor["codes"][pos]
+    bflag = flags[by * nbx + bx].astype(bool)
     assert 0 < flags.mean() < 1
     assert np.array_equal(codes[~bflag], lcodes[~bflag])
     p = lor["p"]
