@@ -194,6 +194,30 @@ int pwrel_compress_raw(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims
                        uint64_t raw_capacity, pwrel_header *header_out, void *stream);
 
 /*
+ * pwrel_compress_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels, stream and errors as pwrel_compress,
+ * but every device scratch buffer (statistics records, constants, status,
+ * raw counter, judge table, per-block scan, the FP32 grid-value field) lies
+ * in one static device array of the library (about 24 MiB per GPU, held by
+ * each GPU the library runs on until the process ends); nothing is allocated
+ * or freed, and the context's own workspace is not touched.  The array's
+ * address is looked up, and its constant table filled, by pwrel_create on
+ * the context's device.  Limits: at most 2^22 values and 2^20 blocks per
+ * field, else PWREL_EINVAL (with a message) before any GPU work.  Every call
+ * on one GPU shares that GPU's array (it keeps the last call's contents;
+ * each call clears what must start at zero), so calls that overlap on one
+ * GPU, from any context or stream, race: the caller serialises them.
+ * Synchronises `stream` once to read the stream length.
+ */
+int pwrel_compress_noalloc(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                           int dtype, double rel_error_bound, int block_size,
+                           const pwrel_mlp *model, const pwrel_options *opt, void *d_out,
+                           uint64_t out_capacity, uint64_t *out_size, void *stream);
+#define PWREL_NOALLOC_MAX_VALUES (1ull << 22)
+#define PWREL_NOALLOC_MAX_BLOCKS (1ull << 20)
+
+/*
  * A trained network kept for later fields (Sec. 5: the model trained in the
  * training phase is retained and used to compress; Sec. 4.3).  pwrel_mlp is a
  * plain value owned by the caller, so nothing is allocated or freed here.

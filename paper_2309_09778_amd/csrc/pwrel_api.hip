@@ -292,6 +292,8 @@ int pwrel_create(pwrel_ctx **out, int device)
         e = launch_qtable(ws.qtab, kQtab, nullptr);
     if (e == hipSuccess)
         e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = noalloc_setup(device);  // the static scratch of pwrel_compress_noalloc
     if (e != hipSuccess) {
         pwrel_destroy(ctx);
         return PWREL_ENOMEM;
@@ -359,6 +361,19 @@ bool check_compress_args(pwrel_ctx *ctx, const void *d_field, const uint64_t *di
 }  // namespace
 
 namespace pwrel {
+
+bool api_check_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                        int dtype, double eps, int block_size, const pwrel_mlp *model,
+                        const pwrel_options &opt, Geom &g, Tile &tile, int &st)
+{
+    return check_compress_args(ctx, d_field, dims, ndim, dtype, eps, block_size, model, opt, g,
+                               tile, st);
+}
+
+int api_fail(pwrel_ctx *ctx, int code, const char *msg) { return fail(ctx, code, msg); }
+int api_status(pwrel_ctx *ctx, int device_status) { return finish_status(ctx, device_status); }
+int api_device(const pwrel_ctx *ctx) { return ctx->device; }
+int api_num_cus(const pwrel_ctx *ctx) { return ctx->num_cus; }
 
 // The compression launches (Algorithm 1): reset, statistics, constants, grid
 // values and bound checks (FP32), prediction / quantisation / judge, scan,

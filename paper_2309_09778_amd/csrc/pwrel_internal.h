@@ -211,4 +211,18 @@ hipError_t compress_launches(Workspace &ws, int num_cus, const void *d_field, co
                              const pwrel_options &opt, const Sections &sec, hipStream_t s,
                              void (*mark_fn)(void *, int, hipStream_t), void *mark_arg);
 
+// --- entry-point helpers (pwrel_api.hip) used by entry points in other files -----
+// argument checks of pwrel_compress (the message goes to the context)
+bool api_check_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                        int dtype, double eps, int block_size, const pwrel_mlp *model,
+                        const pwrel_options &opt, Geom &g, Tile &tile, int &st);
+int api_fail(pwrel_ctx *ctx, int code, const char *msg);
+int api_status(pwrel_ctx *ctx, int device_status);  // status of a finished call, with message
+int api_device(const pwrel_ctx *ctx);
+int api_num_cus(const pwrel_ctx *ctx);
+
+// static scratch of pwrel_compress_noalloc (pwrel_noalloc.hip): set up once
+// per device by pwrel_create, with that device current
+hipError_t noalloc_setup(int device);
+
 }  // namespace pwrel

@@ -92,6 +92,9 @@ _SIGS = {
     "pwrel_compress": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
                                  C.POINTER(Mlp), C.POINTER(Options), _P, C.c_uint64,
                                  C.POINTER(C.c_uint64), _P]),
+    "pwrel_compress_noalloc": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
+                                         C.POINTER(Mlp), C.POINTER(Options), _P, C.c_uint64,
+                                         C.POINTER(C.c_uint64), _P]),
     "pwrel_decompress": (C.c_int, [_P, _P, C.c_uint64, _P, _P, C.c_int, C.c_int, _P]),
     "pwrel_read_header": (C.c_int, [_P, C.c_uint64, C.POINTER(Header)]),
     "pwrel_compress_raw": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
@@ -329,6 +332,27 @@ class Context:
                                     C.c_void_p(out.data_ptr()), out.numel(), C.byref(size),
                                     _stream(stream))
         self._check(st, "compress")
+        return out[:size.value]
+
+    def compress_noalloc(self, x, eps, block=8, model=None, use_net=True, judge=False,
+                         independent=False, out=None, stream=None):
+        """pwrel_compress_noalloc: as compress(), with the library's static
+        device scratch instead of the context's workspace (the output tensor
+        is the caller's: pass `out` to allocate nothing at all)."""
+        import torch
+        assert x.is_cuda and x.is_contiguous()
+        dt = _dtype_code(x.dtype)
+        cap = compress_bound(x.shape, dt, block)
+        if out is None:
+            out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
+        m = model_struct(model) if use_net else None
+        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
+        size = C.c_uint64(0)
+        st = self._L.pwrel_compress_noalloc(
+            self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(), dt, float(eps),
+            int(block), C.byref(m) if m is not None else None, C.byref(opt),
+            C.c_void_p(out.data_ptr()), out.numel(), C.byref(size), _stream(stream))
+        self._check(st, "compress_noalloc")
         return out[:size.value]
 
     def decompress(self, stream_t, shape=None, dtype=None, out=None, stream=None):
