@@ -92,7 +92,12 @@ typedef struct {
     int32_t independent_blocks; /* 0: the prediction surface crosses block faces (halo mode);
                                    1: neighbours outside the block count as missing, so every
                                    block decodes on its own (Sec. 4.4.2) */
-    int32_t reserved;
+    int32_t entropy;            /* 0: the stream stores 16-bit codes; 1: the codes are
+                                   Huffman coded (Sec. 4.1 coding stage, Algorithm 1: optimal
+                                   codeword lengths of at most 32 bits from this field's code
+                                   histogram, canonical codewords); where the codebook would
+                                   cost more than it saves, the stream keeps the 16-bit codes
+                                   (no PWREL_HF_HUFFMAN flag).  pwrel_compress only */
 } pwrel_options;
 
 /*
@@ -105,10 +110,24 @@ typedef struct {
  *                               local raster order; code = e + 2^15 with
  *                               e = prediction - grid value, 0 = balance point
  *   raw    : dtype  [n_raw]     input values of the code-0 points, same order
+ * With PWREL_HF_HUFFMAN the codes section is replaced by three sections
+ * (off_codes = 0), and raw follows them:
+ *   huff   : uint32 count[33]    count[l] = codewords of l bits (count[0] = 0),
+ *            uint16 syms[n_sym]  the coded symbols in canonical order (by
+ *                                length, then value); codeword of the i-th
+ *                                symbol of length l = first[l] + its rank among
+ *                                them, first[1] = 0, first[l] = (first[l-1] +
+ *                                count[l-1]) << 1 (RFC 1951 canonical code)
+ *   sizes  : uint16 (size_bytes = 2) or uint32 (4) [nblocks]  bits of each block
+ *   bits   : uint32 [ceil(n_bits / 32)]  the blocks' codewords in stream order,
+ *                                most significant bit first, no padding between
+ *                                blocks (block b starts at the sum of the sizes
+ *                                before it)
  */
 #define PWREL_HF_NET 1
 #define PWREL_HF_JUDGE 2
 #define PWREL_HF_INDEPENDENT 4
+#define PWREL_HF_HUFFMAN 8
 typedef struct {
     uint32_t magic, version;
     int32_t dtype, ndim;
@@ -129,6 +148,11 @@ typedef struct {
     uint64_t n_zero, n_neg;
     int32_t status; /* device-side status of the producing call (0 = ok) */
     int32_t pad0;
+    /* Huffman sections (PWREL_HF_HUFFMAN; else all 0) */
+    uint64_t off_huff, off_sizes, off_bits;
+    uint64_t n_bits;      /* coded bits of all blocks */
+    uint32_t n_sym;       /* symbols of the codebook */
+    uint32_t size_bytes;  /* bytes per block bit size (2 or 4) */
 } pwrel_header;
 
 typedef struct pwrel_ctx pwrel_ctx;
@@ -268,12 +292,27 @@ int pwrel_histogram(pwrel_ctx *ctx, const uint16_t *d_codes, uint64_t n, uint64_
 uint64_t pwrel_huffman_bits(const uint64_t *hist65536, uint32_t *max_len_out);
 
 /*
+ * The codebook a Huffman stream stores for a code histogram (host only; Sec.
+ * 4.1 Huffman stage): count33[l] = symbols given l-bit codewords (l = 0..32,
+ * count33[0] = 0), syms (capacity 65,536) = the used symbols in canonical
+ * order (by length, then value), *n_sym their number, *n_bits = sum over
+ * symbols of count * length.  Lengths are those of an optimal prefix code
+ * whenever its longest codeword has at most 32 bits (else a valid code with
+ * lengths capped at 32).  Returns PWREL_OK, or PWREL_EINVAL for a NULL
+ * argument.
+ */
+int pwrel_huffman_codebook(const uint64_t *hist65536, uint32_t *count33, uint16_t *syms,
+                           uint32_t *n_sym, uint64_t *n_bits);
+
+/*
  * Device time per phase of the last pwrel_compress / pwrel_decompress on this
  * context, in milliseconds, from HIP events recorded on the caller's stream
  * while profiling is enabled (off by default; enabling adds no host sync).
  * Phases: 0 statistics + constants, 1 compression kernels (FP32: grid
  * values and bound checks, then the fused prediction / quantisation kernel),
- * 2 scan + raw scatter + header, 3 decoder scan, 4 decoder main kernel
+ * 2 scan + raw scatter + header (and, for Huffman streams, the histogram,
+ * the host codebook and the encoder), 3 decoder scan (and Huffman decoding),
+ * 4 decoder main kernel
  * (block levels, pencils or independent blocks), 5 decoder grid values of
  * the raw values, 6 decoder inverse map of the scratch grid field (halo
  * mode; 0 otherwise).  Returns the number of phases written (<= n).

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "pwrel_huffman.h"
 #include "pwrel_internal.h"
 #include "pwrel_train.h"
 
@@ -105,6 +106,45 @@ int ensure_scan(pwrel_ctx *ctx, const Geom &g)
     if (e != hipSuccess)
         return fail(ctx, PWREL_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
     return PWREL_OK;
+}
+
+// buffers of the Huffman stage: 16-bit codes (N), encoder tables, per-block
+// bit offsets
+int ensure_huffman(pwrel_ctx *ctx, const Geom &g)
+{
+    Workspace &ws = ctx->ws;
+    hipError_t e = grow(ws.codes16, ws.codes16_cap, (size_t)std::max<long long>(g.N, 1));
+    if (e == hipSuccess)
+        e = grow(ws.boffsets, ws.boffsets_cap, (size_t)g.nblocks);
+    if (e == hipSuccess)
+        e = grow(ws.bpartials, ws.bpartials_cap,
+                 (size_t)((g.nblocks + kScanChunk - 1) / kScanChunk));
+    if (e == hipSuccess && !ws.enc_len)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.enc_len), 65536);
+    if (e == hipSuccess && !ws.enc_code)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.enc_code), 65536 * sizeof(uint32_t));
+    if (e == hipSuccess && !ws.bits_total)
+        e = hipMalloc(reinterpret_cast<void **>(&ws.bits_total), 256);
+    if (e != hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, std::string("Huffman workspace: ") + hipGetErrorString(e));
+    return PWREL_OK;
+}
+
+// where the Huffman sections of a stream go (after the counts section)
+HuffLayout huff_layout(const Geom &g, const Layout &L, uint64_t n_sym, uint64_t n_bits,
+                       uint64_t n_raw, uint64_t tsize, uint64_t &total)
+{
+    HuffLayout h{};
+    h.n_sym = (uint32_t)n_sym;
+    h.n_bits = n_bits;
+    h.size_bytes = (uint32_t)huff_size_bytes(g);
+    h.table_bytes = huff_table_bytes(n_sym);
+    h.off_huff = L.off[3];
+    h.off_sizes = align256(h.off_huff + h.table_bytes);
+    h.off_bits = align256(h.off_sizes + (uint64_t)h.size_bytes * (uint64_t)g.nblocks);
+    const uint64_t off_raw = align256(h.off_bits + 4ull * ((n_bits + 31) / 32));
+    total = off_raw + n_raw * tsize;
+    return h;
 }
 
 int finish_status(pwrel_ctx *ctx, int st)
@@ -245,7 +285,11 @@ uint64_t pwrel_compress_bound(const uint64_t *dims, int ndim, int dtype, int blo
     if (!make_geom(dims, ndim, dtype, block_size, g))
         return 0;
     const Layout L = layout_for(g, PWREL_HF_NET | PWREL_HF_JUDGE);
-    return L.off[4] + (uint64_t)g.N * (dtype == PWREL_F32 ? 4u : 8u);
+    // a Huffman stream holds at most 16 bits per code (else the codes are
+    // stored as they are), plus its codebook and per-block sizes
+    const uint64_t huff_extra = align256(huff_table_bytes(65536)) +
+                                align256(4ull * (uint64_t)g.nblocks) + 256;
+    return L.off[4] + huff_extra + (uint64_t)g.N * (dtype == PWREL_F32 ? 4u : 8u);
 }
 
 int pwrel_create(pwrel_ctx **out, int device)
@@ -312,7 +356,9 @@ void pwrel_destroy(pwrel_ctx *ctx)
                     ws.offsets,     ws.partials,    ws.pgrid,      ws.qtab,        ctx->counts_scratch,
                     ctx->chunk_cnt, ctx->chunk_off, ctx->pairs,    ctx->theta,     ctx->nets,
                     ctx->vhist,     ctx->scal,      ctx->scores,   ws.done,        ws.ticket,
-                    ctx->order,     ws.praw,        ws.zf,         ws.yf,          ctx->hdr};
+                    ctx->order,     ws.praw,        ws.zf,         ws.yf,          ctx->hdr,
+                    ws.codes16,     ws.enc_len,     ws.enc_code,   ws.boffsets,    ws.bpartials,
+                    ws.bits_total};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -430,6 +476,127 @@ namespace {
 
 void mark_cb(void *ctx, int i, hipStream_t s) { mark(static_cast<pwrel_ctx *>(ctx), i, s); }
 
+// pwrel_compress with the Huffman stage (Sec. 4.1 coding stage; Algorithm 1
+// writes the Huffman codes).  Pass 1 on the device: statistics, constants,
+// grid values, prediction and quantisation into the context's 16-bit code
+// buffer, the balance-point scan and the code histogram.  The host then
+// builds the codebook from the histogram and lays the stream out (the coded
+// size is sum count * length, known before any bit is written).  Pass 2:
+// raw values, codebook, per-block bit sizes, packed bits, model, header.
+int compress_huffman(pwrel_ctx *ctx, const void *d_field, const Geom &g, const Tile &tile,
+                     double eps, const pwrel_mlp *model, const pwrel_options &opt,
+                     unsigned char *out, uint64_t out_capacity, uint64_t *out_size, hipStream_t s)
+{
+    Workspace &ws = ctx->ws;
+    int st;
+    if ((st = ensure_huffman(ctx, g)) != PWREL_OK)
+        return st;
+    const int flags = flags_of(opt);
+    const Layout L = layout_for(g, flags);
+    const uint64_t tsize = g.dtype == PWREL_F32 ? 4u : 8u;
+    uint32_t *counts = reinterpret_cast<uint32_t *>(out + L.off[2]);
+    uint8_t *bflags = (flags & PWREL_HF_JUDGE) ? out + L.off[1] : nullptr;
+    hipError_t e;
+    mark(ctx, 0, s);
+    if ((e = launch_reset(ws, s)) != hipSuccess || (e = launch_stats(d_field, g, ws, s)) != hipSuccess ||
+        (e = launch_consts(g, eps, ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "compress (statistics)");
+    mark(ctx, 1, s);
+    if (g.dtype == PWREL_F32) {
+        if ((e = launch_grid_entries(static_cast<const float *>(d_field), g, ws, ws.pgrid, s)) !=
+                hipSuccess ||
+            (e = launch_compress(d_field, ws.pgrid, g, tile, model, opt, ws, ws.codes16, counts,
+                                 bflags, ctx->num_cus, s, true)) != hipSuccess)
+            return hip_fail(ctx, e, "compress");
+    } else if ((e = launch_compress(d_field, nullptr, g, tile, model, opt, ws, ws.codes16, counts,
+                                    bflags, ctx->num_cus, s)) != hipSuccess) {
+        return hip_fail(ctx, e, "compress");
+    }
+    mark(ctx, 2, s);
+    std::vector<uint64_t> hist(65536);
+    unsigned long long n_raw = 0;
+    int dst = 0;
+    if ((e = launch_scan(counts, g, ws, s)) != hipSuccess ||
+        (e = launch_hist(ws.codes16, g.N, ws.hist, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(hist.data(), ws.hist, 65536 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&n_raw, ws.n_raw, sizeof n_raw, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&dst, ws.status, sizeof dst, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "compress (histogram)");
+    if (dst != PWREL_OK)
+        return finish_status(ctx, dst);
+    HuffTable t;
+    if (!huff_build(hist.data(), t))
+        return fail(ctx, PWREL_EHIP, "internal: Huffman lengths fail the Kraft inequality");
+    if (t.n_bits > 16ull * (uint64_t)g.N)
+        return fail(ctx, PWREL_EHIP, "internal: Huffman code longer than the 16-bit codes");
+    uint64_t total = 0;
+    const HuffLayout hl = huff_layout(g, L, t.syms.size(), t.n_bits, n_raw, tsize, total);
+    if (total >= L.off[4] + n_raw * tsize) {
+        // the codebook costs more than it saves (codes spread over many
+        // values in a small field): the stream keeps the 16-bit codes
+        const int pflags = flags & ~PWREL_HF_HUFFMAN;
+        if ((e = hipMemcpyAsync(out + L.off[3], ws.codes16, 2ull * (uint64_t)g.N,
+                                hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+            (e = launch_scatter(d_field, g, ws.codes16, counts, ws, out + L.off[4],
+                                (out_capacity - L.off[4]) / tsize, s)) != hipSuccess ||
+            (opt.use_net && (e = launch_write_model(*model, out + L.off[0], s)) != hipSuccess) ||
+            (e = launch_header(g, pflags, L.off, ws, out, out_capacity, true, s)) != hipSuccess)
+            return hip_fail(ctx, e, "compress (16-bit codes)");
+        mark(ctx, 3, s);
+        pwrel_header h;
+        if ((e = hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(ctx, e, "header copy");
+        static const int spans16[3][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}};
+        collect(ctx, spans16, 3);
+        if (h.status != PWREL_OK)
+            return finish_status(ctx, h.status);
+        *out_size = h.total_size;
+        return PWREL_OK;
+    }
+    if (total > out_capacity)
+        return fail(ctx, PWREL_ENOSPC, "output capacity too small");
+    // codebook section: count[0..32], then the symbols in canonical order
+    std::vector<uint32_t> tab((hl.table_bytes + 3) / 4, 0u);
+    std::memcpy(tab.data(), t.count.data(), t.count.size() * sizeof(uint32_t));
+    std::memcpy(reinterpret_cast<unsigned char *>(tab.data()) + 4 * (kHuffMaxLen + 1),
+                t.syms.data(), t.syms.size() * sizeof(uint16_t));
+    const uint64_t off_raw = align256(hl.off_bits + 4ull * ((hl.n_bits + 31) / 32));
+    const uint64_t offs[5] = {L.off[0], L.off[1], L.off[2], 0, off_raw};
+    uint32_t *d_tab = reinterpret_cast<uint32_t *>(out + hl.off_huff);
+    if ((e = hipMemcpyAsync(d_tab, tab.data(), hl.table_bytes, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = launch_scatter(d_field, g, ws.codes16, counts, ws, out + off_raw,
+                            (out_capacity - off_raw) / tsize, s)) != hipSuccess ||
+        (e = launch_huff_encode(g, ws.codes16, d_tab, out + hl.off_sizes,
+                                reinterpret_cast<uint32_t *>(out + hl.off_bits),
+                                (hl.n_bits + 31) / 32, ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "compress (Huffman stage)");
+    if (opt.use_net && (e = launch_write_model(*model, out + L.off[0], s)) != hipSuccess)
+        return hip_fail(ctx, e, "model");
+    if ((e = launch_header(g, flags, offs, ws, out, out_capacity, true, s, &hl)) != hipSuccess)
+        return hip_fail(ctx, e, "header");
+    mark(ctx, 3, s);
+    pwrel_header h;
+    unsigned long long bits_dev = 0;
+    if ((e = hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&bits_dev, ws.bits_total, sizeof bits_dev, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    static const int spans[3][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}};
+    collect(ctx, spans, 3);
+    if (h.status != PWREL_OK)
+        return finish_status(ctx, h.status);
+    if (bits_dev != t.n_bits)
+        return fail(ctx, PWREL_EHIP, "internal: coded size differs from the codebook's");
+    *out_size = h.total_size;
+    return PWREL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -465,6 +632,9 @@ int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, in
         (e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
         return fail(ctx, PWREL_ENOMEM, "grid field allocation failed");
     unsigned char *out = static_cast<unsigned char *>(d_out);
+    if (opt.entropy)
+        return compress_huffman(ctx, d_field, g, tile, eps, model, opt, out, out_capacity,
+                                out_size, s);
     const unsigned tsize = dtype == PWREL_F32 ? 4u : 8u;
     Sections sec{};
     sec.codes = reinterpret_cast<uint16_t *>(out + L.off[3]);
@@ -512,6 +682,8 @@ int pwrel_compress_raw(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims
     if (!d_codes || !d_counts || !header_out || (opt.judge && !d_bflags) ||
         (raw_capacity && !d_raw))
         return fail(ctx, PWREL_EINVAL, "NULL section pointer");
+    if (opt.entropy)
+        return fail(ctx, PWREL_EINVAL, "compress_raw returns the 16-bit codes (entropy = 0)");
     DeviceGuard guard(ctx->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if ((st = ensure_scan(ctx, g)) != PWREL_OK)
@@ -716,14 +888,29 @@ int pwrel_read_header(const void *buf, uint64_t size, pwrel_header *out)
         return PWREL_ECORRUPT;
     if ((uint64_t)g.N != h.n || (uint64_t)g.nblocks != h.nblocks || h.status != PWREL_OK)
         return PWREL_ECORRUPT;
-    if (h.flags & ~(PWREL_HF_NET | PWREL_HF_JUDGE | PWREL_HF_INDEPENDENT))
+    if (h.flags & ~(PWREL_HF_NET | PWREL_HF_JUDGE | PWREL_HF_INDEPENDENT | PWREL_HF_HUFFMAN))
         return PWREL_ECORRUPT;
     const Layout L = layout_for(g, h.flags);
-    if (h.off_model != L.off[0] || h.off_bflags != L.off[1] || h.off_counts != L.off[2] ||
-        h.off_codes != L.off[3] || h.off_raw != L.off[4])
+    if (h.off_model != L.off[0] || h.off_bflags != L.off[1] || h.off_counts != L.off[2])
         return PWREL_ECORRUPT;
     const uint64_t tsize = h.dtype == PWREL_F32 ? 4u : 8u;
-    if (h.n_raw > h.n || h.total_size != h.off_raw + h.n_raw * tsize || h.total_size > size)
+    if (h.n_raw > h.n)
+        return PWREL_ECORRUPT;
+    if (h.flags & PWREL_HF_HUFFMAN) {
+        if (h.off_codes != 0 || h.n_sym < 1 || h.n_sym > 65536 || h.n_bits > 16ull * h.n ||
+            h.size_bytes != (uint32_t)huff_size_bytes(g))
+            return PWREL_ECORRUPT;
+        uint64_t total = 0;
+        const HuffLayout hl = huff_layout(g, L, h.n_sym, h.n_bits, h.n_raw, tsize, total);
+        if (h.off_huff != hl.off_huff || h.off_sizes != hl.off_sizes ||
+            h.off_bits != hl.off_bits || h.off_raw != align256(hl.off_bits + 4ull * ((h.n_bits + 31) / 32)))
+            return PWREL_ECORRUPT;
+    } else {
+        if (h.off_codes != L.off[3] || h.off_raw != L.off[4] || h.off_huff || h.off_sizes ||
+            h.off_bits || h.n_bits || h.n_sym || h.size_bytes)
+            return PWREL_ECORRUPT;
+    }
+    if (h.total_size != h.off_raw + h.n_raw * tsize || h.total_size > size)
         return PWREL_ECORRUPT;
     if (!(h.w > 0.0) || !std::isfinite(h.w) || !std::isfinite(h.Lp) || !std::isfinite(h.Ln) ||
         !(h.eps > 0.0 && h.eps < 1.0) || !(h.p_zero <= h.b_sign) || h.delta < 0)
@@ -845,13 +1032,36 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
     c.b_sign = h.b_sign;
     c.n_lo = h.n_lo;
     c.delta = h.delta;
-    const unsigned char *in = static_cast<const unsigned char *>(d_in);
-    const uint32_t *counts = reinterpret_cast<const uint32_t *>(in + h.off_counts);
-    const uint16_t *codes = reinterpret_cast<const uint16_t *>(in + h.off_codes);
-    const uint8_t *bflags = (h.flags & PWREL_HF_JUDGE) ? in + h.off_bflags : nullptr;
     if ((e = launch_reset(ctx->ws, s)) != hipSuccess)
         return hip_fail(ctx, e, "reset");
     mark(ctx, 4, s);
+    const unsigned char *in = static_cast<const unsigned char *>(d_in);
+    const uint32_t *counts = reinterpret_cast<const uint32_t *>(in + h.off_counts);
+    const uint16_t *codes = reinterpret_cast<const uint16_t *>(in + h.off_codes);
+    if (h.flags & PWREL_HF_HUFFMAN) {
+        // the codebook's length counts must describe a prefix code of n_sym symbols
+        uint32_t cnt[kHuffMaxLen + 1];
+        if ((e = hipMemcpyAsync(cnt, in + h.off_huff, sizeof cnt, hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(ctx, e, "codebook copy");
+        uint64_t nsym = 0, kraft = 0;
+        for (int l = 1; l <= kHuffMaxLen; ++l) {
+            nsym += cnt[l];
+            kraft += (uint64_t)cnt[l] << (kHuffMaxLen - l);
+        }
+        if (cnt[0] != 0 || nsym != h.n_sym || kraft > (uint64_t(1) << kHuffMaxLen))
+            return fail(ctx, PWREL_ECORRUPT, "stream codebook is corrupt");
+        if ((st = ensure_huffman(ctx, g)) != PWREL_OK)
+            return st;
+        if ((e = launch_huff_decode(g, reinterpret_cast<const uint32_t *>(in + h.off_huff),
+                                    reinterpret_cast<const uint32_t *>(in + h.off_bits),
+                                    (h.n_bits + 31) / 32, in + h.off_sizes, ctx->ws.codes16,
+                                    ctx->ws, s)) != hipSuccess)
+            return hip_fail(ctx, e, "Huffman decode");
+        codes = ctx->ws.codes16;
+    }
+    const uint8_t *bflags = (h.flags & PWREL_HF_JUDGE) ? in + h.off_bflags : nullptr;
     if ((e = launch_scan(counts, g, ctx->ws, s)) != hipSuccess)
         return hip_fail(ctx, e, "scan");
     mark(ctx, 5, s);
@@ -1052,6 +1262,21 @@ int pwrel_histogram(pwrel_ctx *ctx, const uint16_t *d_codes, uint64_t n, uint64_
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     return e == hipSuccess ? PWREL_OK : hip_fail(ctx, e, "histogram");
+}
+
+int pwrel_huffman_codebook(const uint64_t *hist, uint32_t *count33, uint16_t *syms,
+                           uint32_t *n_sym, uint64_t *n_bits)
+{
+    if (!hist || !count33 || !syms || !n_sym || !n_bits)
+        return PWREL_EINVAL;
+    HuffTable t;
+    if (!huff_build(hist, t))
+        return PWREL_EHIP;
+    std::memcpy(count33, t.count.data(), (kHuffMaxLen + 1) * sizeof(uint32_t));
+    std::memcpy(syms, t.syms.data(), t.syms.size() * sizeof(uint16_t));
+    *n_sym = (uint32_t)t.syms.size();
+    *n_bits = t.n_bits;
+    return PWREL_OK;
 }
 
 uint64_t pwrel_huffman_bits(const uint64_t *hist, uint32_t *max_len_out)

@@ -296,7 +296,8 @@ __device__ __forceinline__ unsigned wave_incl_scan(unsigned v)
     return v;
 }
 
-__global__ void __launch_bounds__(256) k_scan_local(const uint32_t *__restrict__ counts,
+template <typename C>
+__global__ void __launch_bounds__(256) k_scan_local(const C *__restrict__ counts,
                                                     long long nb,
                                                     unsigned long long *__restrict__ offs,
                                                     unsigned long long *__restrict__ partials)
@@ -361,12 +362,7 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long *part
 // a7: raw values of balance points in stream order (one wave per block, wave
 // ballot + popcount for the in-block rank).
 // ---------------------------------------------------------------------------
-struct GeoArgs {
-    long long n[3];
-    int bd[3];
-    long long nb[3];
-    long long nblocks;
-};
+
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter(const T *__restrict__ x, GeoArgs g,
@@ -422,7 +418,10 @@ struct HeaderArgs {
     unsigned long long off_model, off_bflags, off_counts, off_codes, off_raw;
     unsigned long long capacity;
     int raw_size;
-    unsigned long long pad_lo[5], pad_hi[5];  // alignment gaps between sections
+    unsigned long long pad_lo[kHeaderGaps], pad_hi[kHeaderGaps];  // gaps between sections
+    // Huffman sections (0 without them)
+    unsigned long long off_huff, off_sizes, off_bits, n_bits;
+    unsigned n_sym, size_bytes;
 };
 
 // Writes the header and zeroes every alignment gap, so that equal inputs give
@@ -432,7 +431,7 @@ __global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *c
                                                 pwrel_header *out)
 {
     unsigned char *bytes = reinterpret_cast<unsigned char *>(out);
-    for (int r = 0; r < 5; ++r)
+    for (int r = 0; r < kHeaderGaps; ++r)
         for (unsigned long long i = h.pad_lo[r] + threadIdx.x; i < h.pad_hi[r]; i += blockDim.x)
             bytes[i] = 0;
     if (threadIdx.x != 0 || blockIdx.x != 0)
@@ -472,6 +471,12 @@ __global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *c
     o.abs_max = c.abs_max;
     o.n_zero = c.n_zero;
     o.n_neg = c.n_neg;
+    o.off_huff = h.off_huff;
+    o.off_sizes = h.off_sizes;
+    o.off_bits = h.off_bits;
+    o.n_bits = h.n_bits;
+    o.n_sym = h.n_sym;
+    o.size_bytes = h.size_bytes;
     int st = *status;
     if (st == kOk && o.total_size > h.capacity)
         st = kENoSpc;
@@ -647,10 +652,25 @@ hipError_t launch_transform(const void *x, const Geom &g, Workspace &ws, int *d_
 hipError_t launch_scan(const uint32_t *counts, const Geom &g, Workspace &ws, hipStream_t s)
 {
     const long long nparts = (g.nblocks + kScanChunk - 1) / kScanChunk;
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nparts), dim3(256), 0, s, counts, g.nblocks,
-                       ws.offsets, ws.partials);
+    hipLaunchKernelGGL(k_scan_local<uint32_t>, dim3((unsigned)nparts), dim3(256), 0, s, counts,
+                       g.nblocks, ws.offsets, ws.partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, ws.partials, nparts,
                        ws.n_raw);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_sizes(const void *sizes, int elem_bytes, long long n,
+                             unsigned long long *offs, unsigned long long *partials,
+                             unsigned long long *total, hipStream_t s)
+{
+    const long long nparts = (n + kScanChunk - 1) / kScanChunk;
+    if (elem_bytes == 2)
+        hipLaunchKernelGGL(k_scan_local<uint16_t>, dim3((unsigned)nparts), dim3(256), 0, s,
+                           static_cast<const uint16_t *>(sizes), n, offs, partials);
+    else
+        hipLaunchKernelGGL(k_scan_local<uint32_t>, dim3((unsigned)nparts), dim3(256), 0, s,
+                           static_cast<const uint32_t *>(sizes), n, offs, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nparts, total);
     return hipGetLastError();
 }
 
@@ -684,7 +704,8 @@ hipError_t launch_scatter(const void *x, const Geom &g, const uint16_t *codes,
 }
 
 hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspace &ws,
-                         void *d_header, uint64_t capacity, bool stream_gaps, hipStream_t s)
+                         void *d_header, uint64_t capacity, bool stream_gaps, hipStream_t s,
+                         const HuffLayout *hl)
 {
     HeaderArgs h{};
     h.dtype = g.dtype;
@@ -698,20 +719,39 @@ hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspa
     h.off_model = offs[0];
     h.off_bflags = offs[1];
     h.off_counts = offs[2];
-    h.off_codes = offs[3];
+    h.off_codes = hl ? 0ULL : offs[3];
     h.off_raw = offs[4];
     h.capacity = capacity;
     h.raw_size = g.dtype == PWREL_F32 ? 4 : 8;
-    const unsigned long long ends[5] = {
-        sizeof(pwrel_header),
-        (flags & PWREL_HF_NET) ? offs[0] + sizeof(pwrel_mlp) : offs[0],
-        (flags & PWREL_HF_JUDGE) ? offs[1] + (unsigned long long)g.nblocks : offs[1],
-        offs[2] + 4ull * (unsigned long long)g.nblocks,
-        offs[3] + 2ull * (unsigned long long)g.N};
-    const unsigned long long nexts[5] = {offs[0], offs[1], offs[2], offs[3], offs[4]};
-    for (int r = 0; r < 5; ++r) {
-        h.pad_lo[r] = ends[r];
-        h.pad_hi[r] = nexts[r] > ends[r] ? nexts[r] : ends[r];
+    // each section's end and the next section's start: the gap between them is zeroed
+    unsigned long long ends[kHeaderGaps], nexts[kHeaderGaps];
+    int ng = 0;
+    auto gap = [&](unsigned long long e, unsigned long long n) {
+        ends[ng] = e;
+        nexts[ng] = n;
+        ++ng;
+    };
+    gap(sizeof(pwrel_header), offs[0]);
+    gap((flags & PWREL_HF_NET) ? offs[0] + sizeof(pwrel_mlp) : offs[0], offs[1]);
+    gap((flags & PWREL_HF_JUDGE) ? offs[1] + (unsigned long long)g.nblocks : offs[1], offs[2]);
+    if (hl) {
+        h.off_huff = hl->off_huff;
+        h.off_sizes = hl->off_sizes;
+        h.off_bits = hl->off_bits;
+        h.n_bits = hl->n_bits;
+        h.n_sym = hl->n_sym;
+        h.size_bytes = hl->size_bytes;
+        gap(offs[2] + 4ull * (unsigned long long)g.nblocks, hl->off_huff);
+        gap(hl->off_huff + hl->table_bytes, hl->off_sizes);
+        gap(hl->off_sizes + (unsigned long long)hl->size_bytes * g.nblocks, hl->off_bits);
+        gap(hl->off_bits + 4ull * ((hl->n_bits + 31) / 32), offs[4]);
+    } else {
+        gap(offs[2] + 4ull * (unsigned long long)g.nblocks, offs[3]);
+        gap(offs[3] + 2ull * (unsigned long long)g.N, offs[4]);
+    }
+    for (int r = 0; r < kHeaderGaps; ++r) {
+        h.pad_lo[r] = r < ng ? ends[r] : 0;
+        h.pad_hi[r] = r < ng ? std::max(ends[r], nexts[r]) : 0;
         if (!stream_gaps && r > 0)  // a lone header: only its own tail
             h.pad_hi[r] = h.pad_lo[r];
     }

@@ -1,0 +1,498 @@
+// Huffman coding of the quantisation codes (Sec. 4.1: the codes go through a
+// Huffman coding stage after quantisation; Algorithm 1 writes Huffman codes to
+// the stream; Sec. 5 rebuilds the Huffman tree to decompress).
+//
+// Codebook: optimal code lengths from the field's 65,536-bin code histogram
+// (host; at most kHuffMaxLen bits), canonical codewords (shorter codes first,
+// equal lengths in symbol order), stored in the stream as the number of
+// symbols of each length and the symbols in canonical order.
+//
+// Encoder (device): per-block bit sizes (one wave per block, a wave sum of
+// code lengths), an exclusive scan of the sizes, then one wave per block packs
+// its codewords MSB-first into 32-bit words: each lane places its codeword at
+// the wave prefix of the lengths in an LDS copy of the block's words, and the
+// wave stores them (its two boundary words, shared with the neighbouring
+// blocks, by atomic OR into a zeroed bit section).
+//
+// Decoder (device): one thread per block from its own bit offset, a 64-bit
+// bit buffer refilled one word at a time; codewords of up to kLutBits bits in
+// one LDS table lookup, longer ones by the canonical limits of each length.
+#include <algorithm>
+#include <vector>
+
+#include "pwrel_huffman.h"
+#include "pwrel_kernels.h"
+
+namespace pwrel {
+
+// ---------------------------------------------------------------------------
+// host: code lengths and canonical order
+// ---------------------------------------------------------------------------
+namespace {
+
+// Huffman lengths by merging the two lightest subtrees (two sorted queues:
+// leaves by weight, then merged nodes in the order they are made, which is
+// non-decreasing in weight).  Returns the largest length.
+uint32_t huffman_depths(const std::vector<std::pair<uint64_t, uint32_t>> &leaves,
+                        std::vector<uint32_t> &depth)
+{
+    const size_t n = leaves.size();
+    depth.assign(n, 0);
+    if (n == 1) {
+        depth[0] = 1;
+        return 1;
+    }
+    std::vector<uint64_t> iw(n - 1);
+    std::vector<uint32_t> iparent(n - 1, 0), lparent(n, 0);
+    size_t li = 0, ii = 0;
+    for (size_t k = 0; k + 1 < n; ++k) {
+        uint32_t pick[2];
+        uint64_t wsum = 0;
+        for (int t = 0; t < 2; ++t) {
+            const bool leaf = li < n && (ii >= k || leaves[li].first <= iw[ii]);
+            if (leaf) {
+                wsum += leaves[li].first;
+                pick[t] = (uint32_t)li++;
+                lparent[pick[t]] = (uint32_t)k;
+            } else {
+                wsum += iw[ii];
+                pick[t] = (uint32_t)(n + ii);
+                iparent[ii++] = (uint32_t)k;
+            }
+        }
+        iw[k] = wsum;
+    }
+    // the last merged node is the root; parents are made after their children
+    std::vector<uint32_t> idepth(n - 1, 0);
+    for (size_t k = n - 1; k-- > 0;)
+        if (k + 2 < n)
+            idepth[k] = idepth[iparent[k]] + 1;
+    uint32_t mx = 0;
+    for (size_t i = 0; i < n; ++i) {
+        depth[i] = idepth[lparent[i]] + 1;
+        mx = std::max(mx, depth[i]);
+    }
+    return mx;
+}
+
+// Lengths above lmax: move leaves up in pairs until the Kraft sum fits (the
+// classic bit-length adjustment), then hand the lengths out again by weight
+// (heaviest symbol, shortest code).  A valid prefix code, not always optimal;
+// only used when the optimal code has a codeword longer than lmax.
+void limit_depths(const std::vector<std::pair<uint64_t, uint32_t>> &leaves,
+                  std::vector<uint32_t> &depth, uint32_t maxd, uint32_t lmax)
+{
+    std::vector<uint64_t> cnt(maxd + 2, 0);
+    for (uint32_t d : depth)
+        cnt[d]++;
+    for (uint32_t i = maxd; i > lmax; --i) {
+        while (cnt[i] > 0) {
+            uint32_t j = i - 2;
+            while (cnt[j] == 0)
+                --j;
+            cnt[i] -= 2;
+            cnt[i - 1] += 1;
+            cnt[j + 1] += 2;
+            cnt[j] -= 1;
+        }
+    }
+    // leaves are in increasing weight: the lightest take the longest codes
+    size_t i = 0;
+    for (uint32_t d = lmax; d >= 1 && i < depth.size(); --d)
+        for (uint64_t c = 0; c < cnt[d] && i < depth.size(); ++c)
+            depth[i++] = d;
+}
+
+}  // namespace
+
+bool huff_build(const uint64_t *hist, HuffTable &t)
+{
+    std::vector<std::pair<uint64_t, uint32_t>> leaves;
+    for (uint32_t s = 0; s < 65536u; ++s)
+        if (hist[s])
+            leaves.push_back({hist[s], s});
+    t.count.assign(kHuffMaxLen + 1, 0);
+    t.syms.clear();
+    t.n_bits = 0;
+    t.max_len = 0;
+    if (leaves.empty())
+        return true;
+    std::sort(leaves.begin(), leaves.end());
+    std::vector<uint32_t> depth;
+    uint32_t mx = huffman_depths(leaves, depth);
+    if (mx > kHuffMaxLen) {
+        limit_depths(leaves, depth, mx, kHuffMaxLen);
+        mx = kHuffMaxLen;
+    }
+    std::vector<std::pair<uint32_t, uint32_t>> order(leaves.size());  // (length, symbol)
+    for (size_t i = 0; i < leaves.size(); ++i) {
+        order[i] = {depth[i], leaves[i].second};
+        t.count[depth[i]]++;
+        t.n_bits += leaves[i].first * depth[i];
+    }
+    std::sort(order.begin(), order.end());
+    t.syms.resize(order.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        t.syms[i] = (uint16_t)order[i].second;
+    t.max_len = mx;
+    // Kraft check (the canonical construction needs sum 2^-l <= 1)
+    uint64_t kraft = 0;
+    for (uint32_t l = 1; l <= kHuffMaxLen; ++l)
+        kraft += (uint64_t)t.count[l] << (kHuffMaxLen - l);
+    return kraft <= (uint64_t(1) << kHuffMaxLen);
+}
+
+// ---------------------------------------------------------------------------
+// device
+// ---------------------------------------------------------------------------
+
+// canonical first codeword and first canonical index of every length
+struct Canon {
+    unsigned first[kHuffMaxLen + 2];
+    unsigned index[kHuffMaxLen + 2];
+    unsigned count[kHuffMaxLen + 2];
+};
+
+__device__ __forceinline__ void canon_from(const uint32_t *cnt, Canon &c)
+{
+    unsigned code = 0, idx = 0;
+    c.first[0] = 0;
+    c.index[0] = 0;
+    c.count[0] = 0;
+    for (int l = 1; l <= kHuffMaxLen; ++l) {
+        code = (code + c.count[l - 1]) << 1;
+        c.count[l] = cnt[l];
+        c.first[l] = code;
+        c.index[l] = idx;
+        idx += cnt[l];
+    }
+    c.count[kHuffMaxLen + 1] = 0;
+}
+
+__global__ void k_fill_u32(uint32_t *p, unsigned long long n, uint32_t v)
+{
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += stride)
+        p[i] = v;
+}
+
+// encoder table: length and codeword of every symbol (0 = unused)
+__global__ void k_huff_enc(const uint32_t *__restrict__ tab, uint8_t *__restrict__ enc_len,
+                           uint32_t *__restrict__ enc_code)
+{
+    const uint32_t *cnt = tab;
+    const uint16_t *syms = reinterpret_cast<const uint16_t *>(tab + kHuffMaxLen + 1);
+    unsigned nsym = 0;
+    for (int l = 1; l <= kHuffMaxLen; ++l)
+        nsym += cnt[l];
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsym)
+        return;
+    unsigned code = 0, idx = 0, prev = 0;
+    for (int l = 1; l <= kHuffMaxLen; ++l) {
+        code = (code + prev) << 1;
+        prev = cnt[l];
+        if (i < idx + cnt[l]) {
+            const unsigned s = syms[i];
+            enc_len[s] = (uint8_t)l;
+            enc_code[s] = code + (i - idx);
+            return;
+        }
+        idx += cnt[l];
+    }
+}
+
+// per-block bit sizes: one wave per block
+template <typename S>
+__global__ void __launch_bounds__(256) k_huff_sizes(const uint16_t *__restrict__ codes, GeoArgs g,
+                                                    const uint8_t *__restrict__ enc_len,
+                                                    S *__restrict__ sizes, int *status)
+{
+    const int lane = threadIdx.x & 63;
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    int err = kOk;
+    for (long long b = wave; b < g.nblocks; b += nwaves) {
+        const long long bx = b % g.nb[2], by = (b / g.nb[2]) % g.nb[1],
+                        bz = b / (g.nb[1] * g.nb[2]);
+        const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
+        const long long bsize = (long long)q.ez * q.ey * q.ex;
+        unsigned s = 0;
+        for (long long i = lane; i < bsize; i += 64) {
+            const unsigned l = enc_len[codes[q.start + i]];
+            if (l == 0)
+                err = kECorrupt;  // a code the codebook does not hold
+            s += l;
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1)
+            s += __shfl_xor(s, d, 64);
+        if (lane == 0)
+            sizes[b] = (S)s;
+    }
+    set_status(status, err);
+}
+
+// bit packing: one wave per block, the block's words assembled in LDS
+template <typename S>
+__global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ codes, GeoArgs g,
+                                                   const uint8_t *__restrict__ enc_len,
+                                                   const uint32_t *__restrict__ enc_code,
+                                                   const S *__restrict__ sizes,
+                                                   const unsigned long long *__restrict__ boffs,
+                                                   const unsigned long long *__restrict__ bparts,
+                                                   uint32_t *__restrict__ bits, int wave_words,
+                                                   const int *status)
+{
+    extern __shared__ uint32_t lw[];
+    if (*status != kOk)
+        return;
+    const int lane = threadIdx.x & 63;
+    uint32_t *w = lw + (threadIdx.x >> 6) * wave_words;
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long b = wave; b < g.nblocks; b += nwaves) {
+        const long long bx = b % g.nb[2], by = (b / g.nb[2]) % g.nb[1],
+                        bz = b / (g.nb[1] * g.nb[2]);
+        const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
+        const long long bsize = (long long)q.ez * q.ey * q.ex;
+        const unsigned long long start = boffs[b] + bparts[b / kScanChunk];
+        const unsigned s0 = (unsigned)(start & 31u);
+        const unsigned nbits = (unsigned)sizes[b];
+        const int nw = (int)((s0 + nbits + 31u) >> 5);
+        for (int k = lane; k < nw; k += 64)
+            w[k] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        unsigned run = s0;
+        for (long long c0 = 0; c0 < bsize; c0 += 64) {
+            const long long i = c0 + lane;
+            unsigned l = 0, cw = 0;
+            if (i < bsize) {
+                const unsigned sym = codes[q.start + i];
+                l = enc_len[sym];
+                cw = enc_code[sym];
+            }
+            unsigned incl = l;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const unsigned o = __shfl_up(incl, d, 64);
+                if (lane >= d)
+                    incl += o;
+            }
+            const unsigned pos = run + incl - l;
+            if (l) {
+                const unsigned long long t = ((unsigned long long)cw << (64 - l)) >> (pos & 31u);
+                atomicOr(&w[pos >> 5], (uint32_t)(t >> 32));
+                if ((pos & 31u) + l > 32u)
+                    atomicOr(&w[(pos >> 5) + 1], (uint32_t)t);
+            }
+            run += __shfl(incl, 63, 64);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long w0 = start >> 5;
+        const bool part_lo = s0 != 0, part_hi = ((s0 + nbits) & 31u) != 0;
+        for (int k = lane; k < nw; k += 64) {
+            const bool shared = (k == 0 && part_lo) || (k == nw - 1 && part_hi);
+            if (shared)
+                atomicOr(&bits[w0 + k], w[k]);
+            else
+                bits[w0 + k] = w[k];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// decoder: one thread per block
+constexpr int kLutBits = 12;
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_huff_unpack(const uint32_t *__restrict__ tab,
+                                                     const uint32_t *__restrict__ bits,
+                                                     unsigned long long nwords, GeoArgs g,
+                                                     const S *__restrict__ sizes,
+                                                     const unsigned long long *__restrict__ boffs,
+                                                     const unsigned long long *__restrict__ bparts,
+                                                     uint16_t *__restrict__ codes, int *status)
+{
+    __shared__ uint32_t lut[1 << kLutBits];  // symbol | length << 16 (length 0: longer code)
+    __shared__ Canon cs;
+    const uint32_t *cnt = tab;
+    const uint16_t *syms = reinterpret_cast<const uint16_t *>(tab + kHuffMaxLen + 1);
+    if (threadIdx.x == 0)
+        canon_from(cnt, cs);
+    __syncthreads();
+    for (int e = threadIdx.x; e < (1 << kLutBits); e += blockDim.x) {
+        uint32_t v = 0;
+        for (int l = 1; l <= kLutBits; ++l) {
+            const unsigned pre = (unsigned)e >> (kLutBits - l);
+            if (pre - cs.first[l] < cs.count[l]) {
+                v = syms[cs.index[l] + (pre - cs.first[l])] | ((uint32_t)l << 16);
+                break;
+            }
+        }
+        lut[e] = v;
+    }
+    __syncthreads();
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= g.nblocks)
+        return;
+    const long long bx = b % g.nb[2], by = (b / g.nb[2]) % g.nb[1], bz = b / (g.nb[1] * g.nb[2]);
+    const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
+    const long long bsize = (long long)q.ez * q.ey * q.ex;
+    const unsigned long long start = boffs[b] + bparts[b / kScanChunk];
+    const unsigned long long end = start + (unsigned long long)sizes[b];
+    int err = kOk;
+    if (end > nwords * 32ull) {
+        set_status(status, kECorrupt);
+        return;
+    }
+    // bit buffer: the next nb bits of the stream, left-aligned in buf
+    unsigned long long wi = start >> 5;
+    unsigned long long buf = 0;
+    int nb = 0;
+    auto refill = [&]() {
+        while (nb <= 32) {
+            const uint32_t v = wi < nwords ? bits[wi] : 0u;
+            buf |= (unsigned long long)v << (32 - nb);
+            nb += 32;
+            ++wi;
+        }
+    };
+    refill();
+    const unsigned sk = (unsigned)(start & 31u);
+    buf <<= sk;
+    nb -= (int)sk;
+    unsigned long long used = 0;
+    uint16_t *dst = codes + q.start;
+    for (long long i = 0; i < bsize; ++i) {
+        refill();
+        const unsigned win = (unsigned)(buf >> 32);
+        uint32_t e = lut[win >> (32 - kLutBits)];
+        unsigned l = e >> 16, sym = e & 0xFFFFu;
+        if (l == 0) {
+            for (l = kLutBits + 1; l <= kHuffMaxLen; ++l) {
+                const unsigned pre = win >> (32 - l);
+                if (pre - cs.first[l] < cs.count[l])
+                    break;
+            }
+            if (l > kHuffMaxLen) {
+                err = kECorrupt;
+                break;
+            }
+            sym = syms[cs.index[l] + ((win >> (32 - l)) - cs.first[l])];
+        }
+        buf <<= l;
+        nb -= (int)l;
+        used += l;
+        dst[i] = (uint16_t)sym;
+    }
+    if (used != end - start)
+        err = kECorrupt;
+    set_status(status, err);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+GeoArgs geo_of(const Geom &g)
+{
+    GeoArgs a{};
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = g.n[d];
+        a.bd[d] = g.bd[d];
+        a.nb[d] = g.nb[d];
+    }
+    a.nblocks = g.nblocks;
+    return a;
+}
+
+unsigned wave_grid(long long nblocks)
+{
+    const long long g = (nblocks + 3) / 4;
+    return (unsigned)std::max<long long>(1, std::min<long long>(g, 16384));
+}
+
+}  // namespace
+
+int huff_size_bytes(const Geom &g)
+{
+    const long long bv = (long long)g.bd[0] * g.bd[1] * g.bd[2];
+    return bv * kHuffMaxLen <= 65535 ? 2 : 4;
+}
+
+hipError_t launch_huff_encode(const Geom &g, const uint16_t *codes, const uint32_t *d_tab,
+                              void *d_sizes, uint32_t *d_bits, unsigned long long nwords,
+                              Workspace &ws, hipStream_t s)
+{
+    const GeoArgs ga = geo_of(g);
+    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t *>(ws.enc_len), 65536ull / 4, 0u);
+    hipLaunchKernelGGL(k_huff_enc, dim3(256), dim3(256), 0, s, d_tab, ws.enc_len, ws.enc_code);
+    const unsigned grid = wave_grid(g.nblocks);
+    const long long bv = (long long)g.bd[0] * g.bd[1] * g.bd[2];
+    const int wave_words = (int)((bv * kHuffMaxLen + 31) / 32 + 2);
+    // waves per workgroup of the packer: each holds its block's words in LDS
+    const int wpg = (int)std::max<long long>(1, std::min<long long>(4, 65536 / (4 * wave_words)));
+    const size_t lds = wpg * sizeof(uint32_t) * (size_t)wave_words;
+    const unsigned pgrid =
+        (unsigned)std::max<long long>(1, std::min<long long>((g.nblocks + wpg - 1) / wpg, 16384));
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<unsigned long long>(
+                                       std::max<unsigned long long>(1, (nwords + 255) / 256), 8192)),
+                       dim3(256), 0, s, d_bits, nwords, 0u);
+    if (huff_size_bytes(g) == 2) {
+        uint16_t *sz = static_cast<uint16_t *>(d_sizes);
+        hipLaunchKernelGGL(k_huff_sizes<uint16_t>, dim3(grid), dim3(256), 0, s, codes, ga,
+                           ws.enc_len, sz, ws.status);
+        hipError_t e = launch_scan_sizes(sz, 2, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
+                                         s);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_huff_pack<uint16_t>, dim3(pgrid), dim3(64 * wpg), lds, s, codes, ga,
+                           ws.enc_len, ws.enc_code, sz, ws.boffsets, ws.bpartials, d_bits,
+                           wave_words, ws.status);
+    } else {
+        uint32_t *sz = static_cast<uint32_t *>(d_sizes);
+        hipLaunchKernelGGL(k_huff_sizes<uint32_t>, dim3(grid), dim3(256), 0, s, codes, ga,
+                           ws.enc_len, sz, ws.status);
+        hipError_t e = launch_scan_sizes(sz, 4, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
+                                         s);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_huff_pack<uint32_t>, dim3(pgrid), dim3(64 * wpg), lds, s, codes, ga,
+                           ws.enc_len, ws.enc_code, sz, ws.boffsets, ws.bpartials, d_bits,
+                           wave_words, ws.status);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32_t *d_bits,
+                              unsigned long long nwords, const void *d_sizes, uint16_t *codes,
+                              Workspace &ws, hipStream_t s)
+{
+    const GeoArgs ga = geo_of(g);
+    const unsigned grid = (unsigned)((g.nblocks + 255) / 256);
+    hipError_t e;
+    if (huff_size_bytes(g) == 2) {
+        const uint16_t *sz = static_cast<const uint16_t *>(d_sizes);
+        if ((e = launch_scan_sizes(sz, 2, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
+                                   s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_huff_unpack<uint16_t>, dim3(grid), dim3(256), 0, s, d_tab, d_bits,
+                           nwords, ga, sz, ws.boffsets, ws.bpartials, codes, ws.status);
+    } else {
+        const uint32_t *sz = static_cast<const uint32_t *>(d_sizes);
+        if ((e = launch_scan_sizes(sz, 4, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
+                                   s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_huff_unpack<uint32_t>, dim3(grid), dim3(256), 0, s, d_tab, d_bits,
+                           nwords, ga, sz, ws.boffsets, ws.bpartials, codes, ws.status);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pwrel

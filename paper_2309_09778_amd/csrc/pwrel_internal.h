@@ -55,6 +55,16 @@ struct Workspace {
     // pencil decoder: tagged z faces (nb0 x n1 x n2) and y faces (nb1 x n0 x n2)
     unsigned long long *zf = nullptr, *yf = nullptr;
     size_t zf_cap = 0, yf_cap = 0;
+    // Huffman stage: 16-bit codes between the coder and the predictor stage
+    // (N), encoder tables (65,536 lengths and codewords), per-block bit
+    // offsets (exclusive scan: per block and per scan chunk) and total bits
+    uint16_t *codes16 = nullptr;
+    size_t codes16_cap = 0;
+    uint8_t *enc_len = nullptr;
+    uint32_t *enc_code = nullptr;
+    unsigned long long *boffsets = nullptr, *bpartials = nullptr;
+    size_t boffsets_cap = 0, bpartials_cap = 0;
+    unsigned long long *bits_total = nullptr;
 };
 
 constexpr int kQtab = 4097;
@@ -78,12 +88,25 @@ hipError_t launch_compress(const void *x, const int *pfield, const Geom &g, cons
 hipError_t launch_grid_entries(const float *x, const Geom &g, Workspace &ws, int *ent,
                                hipStream_t s);
 hipError_t launch_scan(const uint32_t *counts, const Geom &g, Workspace &ws, hipStream_t s);
+// exclusive scan of n per-block sizes (uint16 or uint32): offsets per block
+// relative to their scan chunk, chunk bases in partials, the sum in *total
+hipError_t launch_scan_sizes(const void *sizes, int elem_bytes, long long n,
+                             unsigned long long *offs, unsigned long long *partials,
+                             unsigned long long *total, hipStream_t s);
 hipError_t launch_scatter(const void *x, const Geom &g, const uint16_t *codes,
                           const uint32_t *counts, Workspace &ws, void *raw,
                           unsigned long long raw_cap, hipStream_t s);
-// stream_gaps: zero the alignment gaps between the sections that follow d_header
+// Placement of the Huffman sections of a stream (host-computed)
+struct HuffLayout {
+    uint64_t off_huff, off_sizes, off_bits, n_bits, table_bytes;
+    uint32_t n_sym, size_bytes;
+};
+constexpr int kHeaderGaps = 8;
+// stream_gaps: zero the alignment gaps between the sections that follow
+// d_header; hl: the Huffman sections (offs[3], the codes offset, unused)
 hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspace &ws,
-                         void *d_header, uint64_t capacity, bool stream_gaps, hipStream_t s);
+                         void *d_header, uint64_t capacity, bool stream_gaps, hipStream_t s,
+                         const HuffLayout *hl = nullptr);
 // the network into the stream's model section (a kernel, no host copy)
 hipError_t launch_write_model(const pwrel_mlp &m, void *dst, hipStream_t s);
 hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *model, int flags,
@@ -161,7 +184,8 @@ inline Layout layout_for(const Geom &g, int flags)
 inline int flags_of(const pwrel_options &opt)
 {
     return (opt.use_net ? PWREL_HF_NET : 0) | (opt.judge ? PWREL_HF_JUDGE : 0) |
-           (opt.independent_blocks ? PWREL_HF_INDEPENDENT : 0);
+           (opt.independent_blocks ? PWREL_HF_INDEPENDENT : 0) |
+           (opt.entropy ? PWREL_HF_HUFFMAN : 0);
 }
 
 // why a network cannot be used on an ndim field, or nullptr

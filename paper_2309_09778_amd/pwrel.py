@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libpwrel.so")
 
 F32, F64 = 0, 1
 OK, EINVAL, ERANGE, ENONFINITE, ENOSPC, ECORRUPT, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
-HF_NET, HF_JUDGE, HF_INDEPENDENT = 1, 2, 4
+HF_NET, HF_JUDGE, HF_INDEPENDENT, HF_HUFFMAN = 1, 2, 4, 8
+HUFF_MAX_LEN = 32
 HEADER_BYTES = 512
 MAXH, MAXK = 32, 6
 R = 32768
@@ -39,7 +40,7 @@ class Mlp(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("use_net", C.c_int32), ("judge", C.c_int32),
-                ("independent_blocks", C.c_int32), ("reserved", C.c_int32)]
+                ("independent_blocks", C.c_int32), ("entropy", C.c_int32)]
 
 
 class Header(C.Structure):
@@ -54,7 +55,9 @@ class Header(C.Structure):
                 ("off_counts", C.c_uint64), ("off_codes", C.c_uint64), ("off_raw", C.c_uint64),
                 ("total_size", C.c_uint64), ("abs_min", C.c_double), ("abs_max", C.c_double),
                 ("n_zero", C.c_uint64), ("n_neg", C.c_uint64), ("status", C.c_int32),
-                ("pad0", C.c_int32)]
+                ("pad0", C.c_int32), ("off_huff", C.c_uint64), ("off_sizes", C.c_uint64),
+                ("off_bits", C.c_uint64), ("n_bits", C.c_uint64), ("n_sym", C.c_uint32),
+                ("size_bytes", C.c_uint32)]
 
 
 MAX_CANDIDATES = 17
@@ -110,6 +113,8 @@ _SIGS = {
     "pwrel_detmath": (C.c_int, [_P, _P, _P, _P, C.c_uint64, _P]),
     "pwrel_histogram": (C.c_int, [_P, _P, C.c_uint64, _P, _P]),
     "pwrel_huffman_bits": (C.c_uint64, [_P, C.POINTER(C.c_uint32)]),
+    "pwrel_huffman_codebook": (C.c_int, [_P, _P, _P, C.POINTER(C.c_uint32),
+                                         C.POINTER(C.c_uint64)]),
     "pwrel_mlp_init": (C.c_int, [C.POINTER(Mlp), C.c_int, C.c_int, C.c_float, C.c_uint64]),
     "pwrel_set_profiling": (C.c_int, [_P, C.c_int]),
     "pwrel_phase_times": (C.c_int, [_P, _P, C.c_int]),
@@ -281,6 +286,33 @@ def huffman_bits(hist):
     return int(bits), int(ml.value)
 
 
+def huffman_codebook(hist):
+    """The library's codebook for a 65,536-bin histogram: (count[33], syms in
+    canonical order, total coded bits)."""
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    assert hist.size == 65536
+    cnt = np.zeros(HUFF_MAX_LEN + 1, dtype=np.uint32)
+    syms = np.zeros(65536, dtype=np.uint16)
+    ns, nb = C.c_uint32(0), C.c_uint64(0)
+    st = lib().pwrel_huffman_codebook(hist.ctypes.data_as(_P), cnt.ctypes.data_as(_P),
+                                      syms.ctypes.data_as(_P), C.byref(ns), C.byref(nb))
+    if st:
+        raise PwrelError(st, "huffman_codebook")
+    return cnt, syms[:ns.value].copy(), int(nb.value)
+
+
+def codebook_lengths(count, syms):
+    """Per-symbol codeword lengths (65,536 entries, 0 = unused) of a codebook
+    given as length counts and canonical-order symbols."""
+    ln = np.zeros(65536, dtype=np.uint8)
+    i = 0
+    for l in range(1, len(count)):
+        c = int(count[l])
+        ln[np.asarray(syms[i:i + c], dtype=np.int64)] = l
+        i += c
+    return ln
+
+
 # --- context ----------------------------------------------------------------------
 
 class Context:
@@ -313,8 +345,9 @@ class Context:
 
     # codec -------------------------------------------------------------------
     def compress(self, x, eps, block=8, model=None, use_net=True, judge=False,
-                 independent=False, out=None, stream=None):
-        """Compress a contiguous CUDA tensor; returns a uint8 CUDA tensor view."""
+                 independent=False, entropy=False, out=None, stream=None):
+        """Compress a contiguous CUDA tensor; returns a uint8 CUDA tensor view.
+        entropy=True: the codes are Huffman coded in the stream."""
         import torch
         assert x.is_cuda and x.is_contiguous()
         dt = _dtype_code(x.dtype)
@@ -324,7 +357,8 @@ class Context:
         if out is None:
             out = torch.empty(cap, dtype=torch.uint8, device=x.device)
         m = model_struct(model) if use_net else None
-        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
+        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)),
+                      int(bool(entropy)))
         size = C.c_uint64(0)
         st = self._L.pwrel_compress(self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(),
                                     dt, float(eps), int(block),
@@ -583,8 +617,18 @@ def sections(stream_t):
 
     out = {"header": h,
            "counts": view(h["off_counts"], nb, torch.int32, 4),
-           "codes": view(h["off_codes"], n, torch.int16, 2),
            "raw": view(h["off_raw"], nr, tdt, tsz)}
+    if h["flags"] & HF_HUFFMAN:
+        # codebook: counts of each length, symbols in canonical order; per-block
+        # bit sizes; the packed words
+        out["huff_count"] = view(h["off_huff"], HUFF_MAX_LEN + 1, torch.int32, 4)
+        out["huff_syms"] = view(h["off_huff"] + 4 * (HUFF_MAX_LEN + 1), h["n_sym"],
+                                torch.int16, 2)
+        out["sizes"] = view(h["off_sizes"], nb, torch.int16 if h["size_bytes"] == 2
+                            else torch.int32, h["size_bytes"])
+        out["bits"] = view(h["off_bits"], (h["n_bits"] + 31) // 32, torch.int32, 4)
+    else:
+        out["codes"] = view(h["off_codes"], n, torch.int16, 2)
     if h["flags"] & HF_JUDGE:
         out["bflags"] = stream_t[h["off_bflags"]:h["off_bflags"] + nb]
     if h["flags"] & HF_NET:

@@ -56,8 +56,12 @@ def test_compress_bound_covers_every_section():
     n = 512 ** 3
     nb = 64 ** 3
     b = pwrel.compress_bound((512, 512, 512), pwrel.F32, 8)
-    assert b >= 512 + C.sizeof(pwrel.Mlp) + nb + 4 * nb + 2 * n + 4 * n
-    assert b < 512 + 4096 + nb + 4 * nb + 2 * n + 4 * n
+    # every section of a 16-bit-code stream, or of a Huffman stream: a codebook of at most
+    # 65,536 symbols (33 length counts + 2 bytes a symbol), 4 bytes of bit size a block and
+    # at most 16 bits a code
+    huff = 4 * 33 + 2 * 65536 + 4 * nb
+    assert b >= 512 + C.sizeof(pwrel.Mlp) + nb + 4 * nb + 2 * n + 4 * n + huff
+    assert b < 512 + 4096 + nb + 4 * nb + 2 * n + 4 * n + huff
     assert pwrel.compress_bound((8, 8, 8), 3, 8) == 0
 
 
@@ -259,3 +263,93 @@ def test_model_save_capacity_and_invalid_network():
     m.w1[0][0] = float("nan")
     assert L.pwrel_model_save(C.byref(m), C.cast(buf, C.c_void_p), need,
                               C.byref(size)) == pwrel.EINVAL
+
+
+def _oracle_cost(hist, lmax):
+    ln = O.huff_lengths(hist, lmax)
+    return int((hist.astype(np.int64) * ln.astype(np.int64)).sum())
+
+
+@pytest.mark.parametrize("kind", ["uniform", "zipf", "geometric", "one", "two", "wide"])
+def test_library_codebook_is_optimal_and_canonical(kind):
+    """The stream's codebook (library host code) costs exactly the optimum
+    that the oracle's package-merge reaches with the same 32-bit limit, its
+    lengths satisfy Kraft, and its symbols are in canonical order."""
+    rng = np.random.default_rng(hash(kind) % 1000)
+    hist = np.zeros(65536, dtype=np.uint64)
+    if kind == "uniform":
+        idx = rng.choice(65536, 500, replace=False)
+        hist[idx] = rng.integers(1, 1000, 500)
+    elif kind == "zipf":
+        idx = rng.choice(65536, 3000, replace=False)
+        hist[idx] = (1e7 / np.arange(1, 3001) ** 1.3).astype(np.uint64) + 1
+    elif kind == "geometric":   # deep tree (lengths in the twenties)
+        idx = 32768 + np.arange(-30, 31)
+        hist[idx] = (2.0 ** (30 - np.abs(np.arange(-30, 31)))).astype(np.uint64)
+    elif kind == "one":
+        hist[32768] = 12345
+    elif kind == "two":
+        hist[0], hist[65535] = 3, 7
+    else:
+        hist[:] = rng.integers(0, 50, 65536)
+    cnt, syms, nbits = pwrel.huffman_codebook(hist)
+    used = np.flatnonzero(hist)
+    assert cnt[0] == 0 and int(cnt.sum()) == used.size == syms.size
+    ln = pwrel.codebook_lengths(cnt, syms)
+    assert np.array_equal(np.flatnonzero(ln), used)
+    assert sum(int(cnt[l]) * 2.0 ** -l for l in range(1, 33)) <= 1.0
+    assert int((hist.astype(np.int64) * ln.astype(np.int64)).sum()) == nbits
+    keys = [(int(ln[s]), int(s)) for s in syms]
+    assert keys == sorted(keys)
+    assert nbits == _oracle_cost(hist, 32)
+    if used.size > 1:
+        assert nbits == pwrel.huffman_bits(hist)[0]   # the 32-bit limit did not bind
+
+
+def test_library_codebook_caps_lengths_at_32_bits():
+    """Fibonacci counts make the optimal unlimited code 39 bits deep; the
+    stream's codebook caps every length at 32 and stays a prefix code, at a
+    cost no lower than the limited optimum of the oracle."""
+    fib = [1, 1]
+    while len(fib) < 40:
+        fib.append(fib[-1] + fib[-2])
+    hist = np.zeros(65536, dtype=np.uint64)
+    hist[100:140] = fib
+    assert pwrel.huffman_bits(hist)[1] == 39
+    cnt, syms, nbits = pwrel.huffman_codebook(hist)
+    ln = pwrel.codebook_lengths(cnt, syms)
+    assert ln.max() <= 32 and sum(int(cnt[l]) * 2.0 ** -l for l in range(1, 33)) <= 1.0
+    assert nbits >= _oracle_cost(hist, 32)
+    assert nbits == int((hist.astype(np.int64) * ln.astype(np.int64)).sum())
+
+
+def test_huffman_header_validation():
+    """A Huffman stream's header: sections after the counts in the stated order,
+    256-byte aligned; inconsistent offsets, sizes or symbol counts are corrupt."""
+    n, block, nraw, nsym, nbits = (10, 12), 4, 3, 7, 333
+    h = _valid_header(n=n, block=block, n_raw=nraw)
+    al = lambda v: (v + 255) // 256 * 256
+    nb = h.nblocks
+    h.flags = pwrel.HF_HUFFMAN
+    h.off_huff = h.off_codes
+    h.off_codes = 0
+    h.n_sym, h.n_bits, h.size_bytes = nsym, nbits, 2
+    h.off_sizes = al(h.off_huff + 4 * 33 + 2 * nsym)
+    h.off_bits = al(h.off_sizes + 2 * nb)
+    h.off_raw = al(h.off_bits + 4 * ((nbits + 31) // 32))
+    h.total_size = h.off_raw + 4 * nraw
+    d = pwrel.read_header_bytes(_bytes(h), size=h.total_size)
+    assert d["n_sym"] == nsym and d["off_bits"] == h.off_bits
+    for field, val in [("off_codes", 512), ("off_sizes", h.off_sizes + 256), ("n_sym", 0),
+                       ("size_bytes", 4), ("n_bits", 16 * 120 + 1), ("off_raw", h.off_raw + 256),
+                       ("off_huff", h.off_huff + 256)]:
+        hh = pwrel.Header.from_buffer_copy(bytes(h))
+        setattr(hh, field, val)
+        with pytest.raises(pwrel.PwrelError) as e:
+            pwrel.read_header_bytes(_bytes(hh), size=h.total_size + 4096)
+        assert e.value.status == pwrel.ECORRUPT, field
+    # Huffman fields in a 16-bit-code stream are corrupt too
+    hh = _valid_header(n=n, block=block, n_raw=nraw)
+    hh.n_sym = 5
+    with pytest.raises(pwrel.PwrelError):
+        pwrel.read_header_bytes(_bytes(hh), size=hh.total_size)
