@@ -113,12 +113,14 @@ def cpu_baseline(x, eps, block, model, side=256):
             "decompress_GBps": round(gb / (t2 - t1), 5)}
 
 
-def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, torch):
+def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, torch,
+             entropy=False):
     """Warm up, then time `steps` round trips (compress + decompress) of one
     path; returns wall times, per-phase device times and the last stream."""
     model = pwrel.model_struct(model)  # the C struct, built once
     for _ in range(warmup):
-        s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind)
+        s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind,
+                         entropy=entropy)
         ctx.decompress(s, out=xh)
     torch.cuda.synchronize()
     # no garbage-collector pause of this interpreter inside the timed steps
@@ -130,7 +132,8 @@ def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, 
     t0 = time.perf_counter()
     for _ in range(steps):
         a = time.perf_counter()
-        s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind)
+        s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind,
+                         entropy=entropy)
         b = time.perf_counter()
         ctx.decompress(s, out=xh)
         torch.cuda.synchronize()
@@ -203,6 +206,7 @@ def main():
     ap.add_argument("--no-alt", action="store_true",
                     help="skip the learned path with independent blocks (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--entropy", action="store_true", help="Huffman-coded streams")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the codec has no multi-GPU path "
@@ -235,7 +239,8 @@ def main():
           f"{train_wall_ms:.1f} ms", file=sys.stderr, flush=True)
 
     # timed: the learned path (BF16 matrix-core network + per-block Lorenzo judge)
-    L = run_path(ctx, xd, eps, B, learned, True, ind, out, xh, K, args.warmup, pwrel, torch)
+    L = run_path(ctx, xd, eps, B, learned, True, ind, out, xh, K, args.warmup, pwrel, torch,
+                 entropy=args.entropy)
     ok_l = bound_ok(xd, xh, eps, torch)
     st_l = stream_stats(ctx, L["stream"], x.nbytes, pwrel)
     st_l.update(error_stats(ctx, xd, xh, L["stream"], torch, pwrel))

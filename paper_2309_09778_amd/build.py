@@ -9,10 +9,11 @@ OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pwrel_codec.hip", "pwrel_compress.hip",
                                                    "pwrel_decode.hip", "pwrel_train.hip",
                                                    "pwrel_api.hip", "pwrel_noalloc.hip",
-                                                   "pwrel_huffman.hip")]
+                                                   "pwrel_huffman.hip", "pwrel_decode_lanes.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("pwrel_device.h", "pwrel_internal.h",
                                                    "pwrel_kernels.h", "pwrel_bf16.h",
-                                                   "pwrel_train.h", "pwrel_huffman.h")] + \
+                                                   "pwrel_train.h", "pwrel_huffman.h",
+                                                   "pwrel_decode.h")] + \
     [os.path.join(ROOT, "include", "pwrel.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -48,14 +48,194 @@ struct CompressArgs {
 // network only if its codes have the lower empirical entropy).  J = sum over the
 // block's points of q(c), c = the number of the block's points that carry the
 // same code, q(c) = rint(2^32 log2 c); n q(n) - J is 2^32 times the entropy in
-// bits.  Counts come from a histogram over a window of errors (kJudgeWin bins:
-// bin 0 = code 0, the balance point; bin e + kJudgeHalf for |e| < kJudgeHalf);
-// codes outside the window go to a short per-block list (kJudgeList entries per
-// predictor) and are counted in it, or, when the list is full, by a scan of the
-// block's codes.
+// bits.  One wave per block.  Blocks of up to 1,024 points of the compiled
+// shapes: the wave sorts the block's codes of each predictor (a bitonic network
+// in registers and lane exchanges) and reads the multiplicities off the runs.
+// Other blocks: codes within a window of errors are counted in a histogram
+// (kJudgeWin bins: bin 0 = code 0, the balance point; bin e + kJudgeHalf for
+// |e| < kJudgeHalf), the others in a per-block hash table of each predictor
+// (open addressing, as many slots as the block has points rounded up to a
+// power of two, so it never fills).  Either way J = the sum over the distinct
+// codes of c q(c).
 constexpr int kJudgeHalf = 256;
 constexpr int kJudgeWin = 2 * kJudgeHalf;  // bins per block
-constexpr int kJudgeList = 64;             // listed out-of-window codes per block and predictor
+
+__host__ __device__ constexpr int judge_slots(int bv)
+{
+    int h = 1;
+    while (h < bv)
+        h <<= 1;
+    return h;
+}
+
+// the judge sorts in registers: compiled shape with at most 1,024 points a block
+__host__ __device__ constexpr bool judge_sorts(bool known, int bv) { return known && bv <= 1024; }
+__host__ __device__ constexpr int judge_epl(int bv) { return bv <= 64 ? 1 : judge_slots(bv) / 64; }
+
+// count one more of `code` (non-zero, outside the window) in a table of hc
+// slots: entry = code << 16 | count, 0 = empty
+__device__ __forceinline__ void judge_hash_add(unsigned *tab, int hc, unsigned code)
+{
+    unsigned h = (code * 2654435761u) >> 16;
+    for (int probe = 0; probe < hc; ++probe) {
+        h &= (unsigned)(hc - 1);
+        const unsigned old = atomicCAS(&tab[h], 0u, (code << 16) | 1u);
+        if (old == 0u)
+            return;
+        if ((old >> 16) == code) {
+            atomicAdd(&tab[h], 1u);
+            return;
+        }
+        ++h;
+    }
+}
+
+// Lane exchanges of the judge's sort, all on the vector ALU (DPP and the
+// gfx950 lane swaps): the value of lane ^ d.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+template <int CTRL> __device__ __forceinline__ unsigned dpp(unsigned v)
+{
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int D> __device__ __forceinline__ unsigned lane_xor(unsigned v)
+{
+    const int lane = threadIdx.x & 63;
+    if constexpr (D == 1) {
+        return dpp<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    } else if constexpr (D == 2) {
+        return dpp<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    } else if constexpr (D == 4) {
+        const unsigned up = dpp<0x104>(v), dn = dpp<0x114>(v);  // row_shl:4 (lane + 4), row_shr:4
+        return (lane & 4) ? dn : up;
+    } else if constexpr (D == 8) {
+        return dpp<0x128>(v);  // row_ror:8 (lane + 8 mod 16 = lane ^ 8)
+    } else if constexpr (D == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
+}
+
+__device__ __forceinline__ unsigned pk_min16(unsigned a, unsigned b)
+{
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                   __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ unsigned pk_max16(unsigned a, unsigned b)
+{
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                   __builtin_bit_cast(u16x2, b)));
+}
+
+// one compare-exchange stage of the bitonic network at distance D < 64 in lanes
+template <int EPL, int D>
+__device__ __forceinline__ void bitonic_lanes(unsigned (&a)[EPL], int sz)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+        const int i = k * 64 + lane;
+        const unsigned b = lane_xor<D>(a[k]);
+        const bool keep_lo = ((i & D) == 0) == ((i & sz) == 0);
+        a[k] = keep_lo ? pk_min16(a[k], b) : pk_max16(a[k], b);
+    }
+}
+
+// The judge's scores of one block held by a wave: each 32-bit key carries the
+// network's code (low half) and Lorenzo's (high half) of one point; elements
+// i = k 64 + lane, k < EPL; nsent of them are stand-ins (0xFFFF in both
+// halves) for positions outside the field.  Returns, for each half, the sum
+// over its distinct codes of c q(c), c = the code's multiplicity.  The two
+// halves are sorted at once by one bitonic network on packed 16-bit
+// minima/maxima (pairs i, i ^ d: in a lane's registers for d >= 64, by lane
+// exchanges below); a run of equal codes then ends where the successor
+// differs and starts at the last run start at or before it (the highest set
+// bit of a ballot of run starts).  Stand-ins sort last and are taken off the
+// last run of each half.
+template <int EPL>
+__device__ __forceinline__ void wave_multiset_score(unsigned (&a)[EPL], unsigned nsent,
+                                                    const long long *qtab,
+                                                    unsigned long long &s0,
+                                                    unsigned long long &s1)
+{
+    constexpr int N = EPL * 64;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int sz = 2; sz <= N; sz <<= 1) {
+#pragma unroll
+        for (int d = sz >> 1; d > 0; d >>= 1) {
+            if (d >= 64) {
+                const int dk = d >> 6;
+#pragma unroll
+                for (int k = 0; k < EPL; ++k) {
+                    if (k & dk)
+                        continue;
+                    const bool asc = ((k * 64) & sz) == 0;
+                    const unsigned x = a[k], y = a[k | dk];
+                    const unsigned lo = pk_min16(x, y), hi = pk_max16(x, y);
+                    a[k] = asc ? lo : hi;
+                    a[k | dk] = asc ? hi : lo;
+                }
+            } else if (d == 32) {
+                bitonic_lanes<EPL, 32>(a, sz);
+            } else if (d == 16) {
+                bitonic_lanes<EPL, 16>(a, sz);
+            } else if (d == 8) {
+                bitonic_lanes<EPL, 8>(a, sz);
+            } else if (d == 4) {
+                bitonic_lanes<EPL, 4>(a, sz);
+            } else if (d == 2) {
+                bitonic_lanes<EPL, 2>(a, sz);
+            } else {
+                bitonic_lanes<EPL, 1>(a, sz);
+            }
+        }
+    }
+    const unsigned long long lowmask = lane == 63 ? ~0ULL : ((2ULL << lane) - 1ULL);
+    unsigned long long J[2] = {0ULL, 0ULL};
+    int carry[2] = {-1, -1};
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+        const int i = k * 64 + lane;
+        const unsigned pw = dpp<0x138>(a[k]);  // wave_shr:1: lane - 1
+        const unsigned nw = dpp<0x130>(a[k]);  // wave_shl:1: lane + 1
+        const unsigned lp = k > 0 ? __builtin_amdgcn_readlane(a[k > 0 ? k - 1 : 0], 63) : 0u;
+        const unsigned fn = k + 1 < EPL ? __builtin_amdgcn_readlane(a[k + 1 < EPL ? k + 1 : k], 0)
+                                        : 0u;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const unsigned key = (a[k] >> (16 * h)) & 0xFFFFu;
+            unsigned pk = (pw >> (16 * h)) & 0xFFFFu, nk = (nw >> (16 * h)) & 0xFFFFu;
+            if (lane == 0)
+                pk = k > 0 ? (lp >> (16 * h)) & 0xFFFFu : key ^ 1u;
+            if (lane == 63)
+                nk = k + 1 < EPL ? (fn >> (16 * h)) & 0xFFFFu : key ^ 1u;
+            const unsigned long long sm = __ballot(key != pk);
+            const unsigned long long m = sm & lowmask;
+            const int st = m ? k * 64 + 63 - __clzll((long long)m) : carry[h];
+            if (sm)
+                carry[h] = k * 64 + 63 - __clzll((long long)sm);
+            if (key != nk) {
+                int c = i - st + 1;
+                if (key == 0xFFFFu)
+                    c -= (int)nsent;
+                if (c > 0)
+                    J[h] += (unsigned long long)c * (unsigned long long)qtab[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        J[0] += (unsigned long long)__shfl_xor((long long)J[0], o, 64);
+        J[1] += (unsigned long long)__shfl_xor((long long)J[1], o, 64);
+    }
+    s0 = J[0];
+    s1 = J[1];
+}
 
 __device__ __forceinline__ int judge_bin(unsigned code)
 {
@@ -154,11 +334,18 @@ k_compress(CompressArgs a)
     using V = typename std::conditional<FROM_P, int, T>::type;
     unsigned int *jh = cnt + nbt;  // [nbt][kJudgeWin]: network count | Lorenzo count << 16
     // judge only: both codes of every tile point (network | Lorenzo << 16)
-    unsigned *jb = jh + (a.judge ? nbt * kJudgeWin : 0);
-    unsigned *jlc = jb + (a.judge ? ntp : 0);  // [nbt][2] list lengths
-    unsigned short *jl = reinterpret_cast<unsigned short *>(jlc + (a.judge ? 2 * nbt : 0));
-    unsigned char *okb =
-        reinterpret_cast<unsigned char *>(jl + (a.judge ? 2 * nbt * kJudgeList : 0));
+    // the judge's path (sort in registers, or window + hash tables)
+    constexpr int BVc = BB * (D >= 2 ? BB : 1) * (D >= 3 ? BB : 1);  // 0: runtime shape
+    constexpr bool JS = judge_sorts(CT, BVc);
+    constexpr int JEPL = JS ? judge_epl(BVc) : 1;
+    const int HC = judge_slots(BV);
+    const bool jwin = a.judge && !JS;
+    unsigned *jb = jh + (jwin ? nbt * kJudgeWin : 0);
+    // judge: [nbt][2] code-0 counts of each predictor; window path: [nbt][2][HC]
+    // hash tables of the out-of-window codes
+    unsigned *jz = jb + (a.judge ? ntp : 0);
+    unsigned *jht = jz + (a.judge ? 2 * nbt : 0);
+    unsigned char *okb = reinterpret_cast<unsigned char *>(jht + (jwin ? 2 * nbt * HC : 0));
 
     __shared__ int s_status;
     __shared__ float4 wl[kWlds];
@@ -170,12 +357,14 @@ k_compress(CompressArgs a)
     for (int i = tid; i < nbt; i += NT)
         cnt[i] = 0u;
     if (a.judge) {
-        for (int i = tid; i < nbt * kJudgeWin; i += NT)
-            jh[i] = 0u;
-        for (int i = tid; i < 2 * nbt; i += NT) {
-            jsum[i] = 0ULL;
-            jlc[i] = 0u;
+        if (jwin) {
+            for (int i = tid; i < nbt * kJudgeWin; i += NT)
+                jh[i] = 0u;
+            for (int i = tid; i < 2 * nbt * HC; i += NT)
+                jht[i] = 0u;
         }
+        for (int i = tid; i < 2 * nbt; i += NT)
+            jsum[i] = 0ULL;
     }
     if (tid == 0)
         s_status = *a.status;
@@ -474,89 +663,85 @@ k_compress(CompressArgs a)
 
         if (a.judge) {
             // --- per-block judge: keep the network iff the entropy of its codes
-            //     is strictly below Lorenzo's (fixed-point scores).  Histograms
-            //     and out-of-window lists from the codes noted above (LDS
-            //     atomics outside the prediction loop, where no memory
-            //     operation is outstanding) ---
-            for (int q = tid; q < ntp; q += NT) {
-                const int cx = q % T2, cy = (q / T2) % T1, cz = q / (T1 * T2);
-                if (!(cz < limz && cy < limy && cx < limx))
-                    continue;  // no point
-                const unsigned v = jb[q];
-                const int bt = ((cz / bd0) * nbt1 + cy / bd1) * nbt2 + cx / bd2;
-#pragma unroll
-                for (int pr = 0; pr < 2; ++pr) {
-                    const unsigned code = pr ? v >> 16 : v & 0xffffu;
-                    const int bin = judge_bin(code);
-                    if (bin >= 0) {
-                        atomicAdd(&jh[bt * kJudgeWin + bin], pr ? 1u << 16 : 1u);
-                    } else {
-                        const unsigned slot = atomicAdd(&jlc[2 * bt + pr], 1u);
-                        if (slot < (unsigned)kJudgeList)
-                            jl[(2 * bt + pr) * kJudgeList + slot] = (unsigned short)code;
-                    }
-                }
-            }
-            __syncthreads();
-            // scores J = sum over points of q(count of the point's code), points
-            // in block-major order (a wave's points share a block where the
-            // block size is a multiple of 64: one wave sum, one LDS add)
-            const bool wave_blocks = BV % 64 == 0;
-            for (int q0 = 0; q0 < nbt * BV; q0 += NT) {
-                const int q = q0 + tid;
-                const int bt = q < nbt * BV ? q / BV : nbt - 1;
-                const int li = q - bt * BV;
-                const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
+            //     is strictly below Lorenzo's (fixed-point scores), one wave per
+            //     block (LDS atomics outside the prediction loop, where no
+            //     memory operation is outstanding) ---
+            const int lane = tid & 63;
+            for (int bt = tid >> 6; bt < nbt; bt += NT / 64) {
                 const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
-                const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
-                const bool pt = q < nbt * BV && cz < limz && cy < limy && cx < limx;
-                unsigned long long s2[2] = {0ULL, 0ULL};
-                if (pt) {
-                    const unsigned v = jb[(cz * T1 + cy) * T2 + cx];
+                unsigned long long s0 = 0ULL, s1 = 0ULL;
+                unsigned z0 = 0, z1 = 0;
+                if constexpr (JS) {
+                    unsigned kv[JEPL];
+                    unsigned nsent = 0;
 #pragma unroll
-                    for (int pr = 0; pr < 2; ++pr) {
-                        const unsigned code = pr ? v >> 16 : v & 0xffffu;
-                        const int bin = judge_bin(code);
-                        unsigned c = 0;
-                        if (bin >= 0) {
-                            const unsigned w = jh[bt * kJudgeWin + bin];
-                            c = pr ? w >> 16 : w & 0xffffu;
-                        } else {
-                            const unsigned nl = jlc[2 * bt + pr];
-                            if (nl <= (unsigned)kJudgeList) {
-                                const unsigned short *lst = jl + (2 * bt + pr) * kJudgeList;
-                                for (unsigned k = 0; k < nl; ++k)
-                                    c += lst[k] == code ? 1u : 0u;
-                            } else {
-                                // list full: count over the block's points
-                                const int ex = (int)(bext[bt] & 0xffffu), ey = (int)(bext[bt] >> 16);
-                                const int ez = std::min(bd0, limz - btz * bd0);
-                                for (int kz = 0; kz < ez; ++kz)
-                                    for (int ky = 0; ky < ey; ++ky)
-                                        for (int kx = 0; kx < ex; ++kx) {
-                                            const unsigned w = jb[((btz * bd0 + kz) * T1 +
-                                                                   bty * bd1 + ky) * T2 +
-                                                                  btx * bd2 + kx];
-                                            c += (pr ? w >> 16 : w & 0xffffu) == code ? 1u : 0u;
-                                        }
-                            }
-                        }
-                        s2[pr] = (unsigned long long)a.qtab[c];  // q(c), c >= 1
+                    for (int k = 0; k < JEPL; ++k) {
+                        const int li = k * 64 + lane;
+                        const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
+                        const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
+                        const bool pt = li < BV && cz < limz && cy < limy && cx < limx;
+                        const unsigned v = pt ? jb[(cz * T1 + cy) * T2 + cx] : 0xFFFFFFFFu;
+                        kv[k] = v;
+                        nsent += (unsigned)__popcll(__ballot(!pt));
+                        z0 += (unsigned)__popcll(__ballot(pt && (v & 0xffffu) == 0u));
+                        z1 += (unsigned)__popcll(__ballot(pt && (v >> 16) == 0u));
                     }
-                }
-                if (wave_blocks) {
+                    wave_multiset_score<JEPL>(kv, nsent, a.qtab, s0, s1);
+                } else {
+                    unsigned *hb = jh + bt * kJudgeWin;
+                    unsigned *t0 = jht + (2 * bt) * HC, *t1 = t0 + HC;
+                    for (int q0 = 0; q0 < BV; q0 += 64) {
+                        const int li = q0 + lane;
+                        const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
+                        const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
+                        const bool pt = li < BV && cz < limz && cy < limy && cx < limx;
+                        const unsigned v = pt ? jb[(cz * T1 + cy) * T2 + cx] : 0u;
+                        const unsigned c0 = v & 0xffffu, c1 = v >> 16;
+                        const int b0 = judge_bin(c0), b1 = judge_bin(c1);
+                        if (pt) {
+                            if (b0 >= 0)
+                                atomicAdd(&hb[b0], 1u);
+                            else
+                                judge_hash_add(t0, HC, c0);
+                            if (b1 >= 0)
+                                atomicAdd(&hb[b1], 1u << 16);
+                            else
+                                judge_hash_add(t1, HC, c1);
+                        }
+                        z0 += (unsigned)__popcll(__ballot(pt && c0 == 0u));
+                        z1 += (unsigned)__popcll(__ballot(pt && c1 == 0u));
+                    }
+                    // this wave's LDS atomics above complete before its reads below
+                    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+                    for (int k = lane; k < kJudgeWin; k += 64) {
+                        const unsigned w = hb[k];
+                        const unsigned cn = w & 0xffffu, cl = w >> 16;
+                        if (cn)
+                            s0 += (unsigned long long)cn * (unsigned long long)a.qtab[cn];
+                        if (cl)
+                            s1 += (unsigned long long)cl * (unsigned long long)a.qtab[cl];
+                        hb[k] = 0u;  // cleared for the next tile
+                    }
+                    for (int k = lane; k < HC; k += 64) {
+                        const unsigned cn = t0[k] & 0xffffu, cl = t1[k] & 0xffffu;
+                        if (cn)
+                            s0 += (unsigned long long)cn * (unsigned long long)a.qtab[cn];
+                        if (cl)
+                            s1 += (unsigned long long)cl * (unsigned long long)a.qtab[cl];
+                        t0[k] = 0u;
+                        t1[k] = 0u;
+                    }
 #pragma unroll
                     for (int d = 32; d > 0; d >>= 1) {
-                        s2[0] += (unsigned long long)__shfl_xor((long long)s2[0], d, 64);
-                        s2[1] += (unsigned long long)__shfl_xor((long long)s2[1], d, 64);
+                        s0 += (unsigned long long)__shfl_xor((long long)s0, d, 64);
+                        s1 += (unsigned long long)__shfl_xor((long long)s1, d, 64);
                     }
-                    if ((tid & 63) == 0 && q < nbt * BV) {
-                        atomicAdd(&jsum[2 * bt], s2[0]);
-                        atomicAdd(&jsum[2 * bt + 1], s2[1]);
-                    }
-                } else if (pt) {
-                    atomicAdd(&jsum[2 * bt], s2[0]);
-                    atomicAdd(&jsum[2 * bt + 1], s2[1]);
+                }
+                if (lane == 0) {
+                    jsum[2 * bt] = s0;
+                    jsum[2 * bt + 1] = s1;
+                    jz[2 * bt] = z0;
+                    jz[2 * bt + 1] = z1;
                 }
             }
             __syncthreads();
@@ -579,15 +764,9 @@ k_compress(CompressArgs a)
             }
             for (int bt = tid; bt < nbt; bt += NT) {
                 const bool use_n = jsum[2 * bt] > jsum[2 * bt + 1];
-                const unsigned w = jh[bt * kJudgeWin];  // bin 0: the balance points of both
-                cnt[bt] = use_n ? (w & 0xffffu) : (w >> 16);
+                cnt[bt] = use_n ? jz[2 * bt] : jz[2 * bt + 1];  // balance points of the winner
             }
             __syncthreads();
-            // clear the histograms and lists for the next tile
-            for (int i = tid; i < nbt * kJudgeWin; i += NT)
-                jh[i] = 0u;
-            for (int i = tid; i < 2 * nbt; i += NT)
-                jlc[i] = 0u;
         }
 
         // --- per-block balance-point counts ------------------------------------
@@ -619,8 +798,13 @@ static size_t compress_lds(const Geom &g, const int *t, bool judge = true)
     const size_t nbt = (size_t)(t[0] / g.bd[0]) * (t[1] / g.bd[1]) * (t[2] / g.bd[2]);
     const size_t ntp = (size_t)t[0] * t[1] * t[2];
     size_t n = nbt * 8 + nbt * 4 + ne * 4 + nbt * 4;  // starts, extents, tile, counts
-    if (judge)  // histograms, scores, both codes per point, list lengths, lists
-        n += nbt * kJudgeWin * 4 + 2 * nbt * 8 + ntp * 4 + 2 * nbt * 4 + 2 * nbt * kJudgeList * 2;
+    if (judge) {  // scores, both codes per point, code-0 counts; window path: bins, tables
+        const int bv = g.bd[0] * g.bd[1] * g.bd[2];
+        int kt[3];
+        n += 2 * nbt * 8 + ntp * 4 + 2 * nbt * 4;
+        if (!judge_sorts(known_shape(g.D, g.B, kt), bv))
+            n += nbt * kJudgeWin * 4 + 2 * nbt * (size_t)judge_slots(bv) * 4;
+    }
     return n + ntp;  // bound bits
 }
 

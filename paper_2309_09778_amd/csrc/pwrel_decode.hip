@@ -27,36 +27,11 @@
 #include <type_traits>
 
 #include "pwrel_bf16.h"
+#include "pwrel_decode.h"
 
 namespace pwrel {
 
-struct DecodeArgs {
-    long long n[3];
-    int bd[3];
-    long long nb[3];
-    long long nblocks;
-    int use_net, judge, independent;
-    const uint8_t *bflags;
-    const uint16_t *codes;
-    const uint32_t *counts;
-    const unsigned long long *offs;
-    const unsigned long long *partials;
-    const void *raw;
-    unsigned long long n_raw;
-    void *xh;
-    int *pgrid;
-    const int *praw;  // grid values of the raw values
-    int *status;
-    // halo mode: block order, done flags, ticket counter, this call's flag value
-    const unsigned *order;
-    unsigned *done;
-    unsigned *ticket;
-    unsigned epoch;
-    // pencil decoder: tagged face buffers
-    unsigned long long *zf, *yf;
-    DevConsts c;
-    MlpW mlp;
-};
+
 
 constexpr unsigned kSpinLimit = 1u << 20;  // polls of one flag before giving up
 // Scratch grid field entry: 2 p + 1 for a balance point, 2 p for a coded
@@ -422,7 +397,7 @@ __global__ void __launch_bounds__(256) k_decode(DecodeArgs a)
         stage_net_bf16(tb, a.mlp);
     __syncthreads();
     BlockDecoder<T, D, BB, HP, PREC, false> d(a, smem, wl, tb);
-    d.begin(blockIdx.x);
+    d.begin(a.partial_only ? partial_block(blockIdx.x, a) : (long long)blockIdx.x);
     __syncthreads();
     d.balance_points();
     __syncthreads();
@@ -1188,8 +1163,22 @@ hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *mod
     const long long nlines = (long long)g.bd[0] * g.bd[1];
     const unsigned nt = (unsigned)std::min(256LL, std::max(64LL, (nlines + 63) / 64 * 64));
     const bool flow = !a.independent;
-    const unsigned grid = flow ? (unsigned)std::max(num_cus, 1) : (unsigned)g.nblocks;
+    unsigned grid = flow ? (unsigned)std::max(num_cus, 1) : (unsigned)g.nblocks;
     const bool pencils = flow && pencil_mode(g);
+    if (!flow && lanes_shape(g.D, g.B)) {
+        // whole blocks one per lane; the blocks clipped by the high faces one per workgroup
+        long long nfull = 1;
+        for (int d = 0; d < 3; ++d) {
+            a.nf[d] = g.n[d] / g.bd[d];
+            nfull *= a.nf[d];
+        }
+        launch_decode_lanes(g, HP, a, s);
+        const long long npart = g.nblocks - nfull;
+        if (npart == 0)
+            return hipGetLastError();
+        a.partial_only = 1;
+        grid = (unsigned)npart;
+    }
     if (g.dtype == PWREL_F32) {
         if (pencils)
             pencil_by_hidden<float>(HP, a, grid, s);

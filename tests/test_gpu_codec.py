@@ -200,6 +200,24 @@ def _case(name):
     if name == "flow_B4_1320_blocks":
         return synth.lognormal_grf((48, 40, 44), seed=16), 1e-2, 4, random_model(3, 16, 16), \
             False
+    if name.startswith("lanes_"):
+        # independent blocks: whole blocks one per lane (several waves, a ragged
+        # last wave), clipped blocks one per workgroup
+        if name == "lanes_f32_B8":
+            return synth.lognormal_grf((72, 64, 136), seed=17), 1e-2, 8, random_model(3, 16, 17), \
+                True
+        if name == "lanes_B4_ragged":
+            return synth.lognormal_grf((30, 41, 53), seed=18), 1e-2, 4, random_model(3, 8, 18), \
+                True
+        if name == "lanes_2d_B16":
+            return synth.zonal_bands_2d((150, 301), seed=19), 1e-2, 16, random_model(2, 32, 19), \
+                True
+        if name == "lanes_f64":
+            x = synth.lognormal_grf((24, 40, 50), seed=20, decades=12, neg_frac=0.1,
+                                    zero_frac=0.01, dtype=np.float64)
+            return x, 1e-4, 8, random_model(3, 16, 20), True
+        if name == "lanes_lorenzo":
+            return synth.lognormal_grf((40, 48, 64), seed=22), 1e-2, 8, None, True
     if name == "lorenzo_only":
         return synth.lognormal_grf((30, 31, 66), seed=10), 1e-2, 8, None, False
     if name == "single_point":
@@ -220,7 +238,8 @@ CASES = ["config0_bumps64", "grf_ragged_1e-3", "grf_ragged_indep", "grf_B4_H32",
          "lorenzo_only", "single_point", "all_zero", "tiny_1d", "sign_gap_delta",
          "f32_range_ends_1e-2", "f32_smooth_range_hi", "f32_smooth_range_lo",
          "pencil_thin_z", "pencil_thin_y", "pencil_long", "pencil_single_x",
-         "flow_96cubed_B16", "flow_B4_1320_blocks"]
+         "flow_96cubed_B16", "flow_B4_1320_blocks", "lanes_f32_B8", "lanes_B4_ragged",
+         "lanes_2d_B16", "lanes_f64", "lanes_lorenzo"]
 
 
 @pytest.mark.parametrize("name", CASES)

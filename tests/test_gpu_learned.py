@@ -297,6 +297,17 @@ BF16_CASES = {
     "f64_1e-4": (lambda: synth.lognormal_grf((24, 40, 50), seed=9, decades=12, neg_frac=0.1,
                                               zero_frac=0.01, dtype=np.float64), 1e-4, 8, False,
                  (3, 16, 9)),
+    # independent blocks decoded one per lane (matrix cores for 64 blocks at once)
+    "lanes_B8_indep": (lambda: synth.lognormal_grf((72, 64, 136), seed=23), 1e-2, 8, True,
+                       (3, 32, 23)),
+    "lanes_B4_indep": (lambda: synth.lognormal_grf((30, 41, 53), seed=24), 1e-2, 4, True,
+                       (3, 32, 24)),
+    "lanes_2d_indep": (lambda: synth.zonal_bands_2d((150, 301), seed=25), 1e-2, 16, True,
+                       (2, 32, 25)),
+    "lanes_f64_indep": (lambda: synth.lognormal_grf((24, 40, 50), seed=26, decades=12,
+                                                     neg_frac=0.1, zero_frac=0.01,
+                                                     dtype=np.float64), 1e-4, 8, True,
+                        (3, 16, 26)),
 }
 
 
