@@ -13,7 +13,7 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pwrel_codec.hip", "pwrel_com
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("pwrel_device.h", "pwrel_internal.h",
                                                    "pwrel_kernels.h", "pwrel_bf16.h",
                                                    "pwrel_train.h", "pwrel_huffman.h",
-                                                   "pwrel_decode.h")] + \
+                                                   "pwrel_decode.h", "pwrel_wavesort.h")] + \
     [os.path.join(ROOT, "include", "pwrel.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -4,6 +4,7 @@
 // Compression:   reset -> stats -> consts -> compress -> scan -> scatter -> header
 // Decompression: reset -> scan -> decode (per block level, or all blocks at once)
 #include "pwrel_kernels.h"
+#include "pwrel_wavesort.h"
 
 namespace pwrel {
 
@@ -485,28 +486,47 @@ __global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *c
 }
 
 // ---------------------------------------------------------------------------
-// code histogram (on demand, not on the codec path): LDS window around the
-// zero-error code, global atomics outside it, one flush per workgroup.
+// code histogram (inspection, and the Huffman stage's codebook): LDS window
+// around the zero-error code, global atomics outside it, one flush per
+// workgroup.
 // ---------------------------------------------------------------------------
-constexpr int kHistWin = 8192;
+constexpr int kHistWin = 32768;  // 128 KiB of LDS
 
-__global__ void __launch_bounds__(256) k_hist(const uint16_t *__restrict__ codes, long long n,
-                                              unsigned long long *hist)
+// Per workgroup (1024 threads, one or two per CU): a histogram of kHistWin
+// codes around the zero-error code in LDS (128 KiB), global atomics outside it
+// (the rare large errors), one flush of the non-zero bins at the end.  Each
+// thread counts a contiguous run of codes (16-byte loads), so the lanes of an
+// atomic instruction mostly address different bins.
+__global__ void __launch_bounds__(1024) k_hist(const uint16_t *__restrict__ codes, long long n,
+                                               unsigned long long *hist)
 {
-    __shared__ unsigned win[kHistWin];
+    extern __shared__ unsigned win[];
     for (int i = threadIdx.x; i < kHistWin; i += blockDim.x)
         win[i] = 0u;
     __syncthreads();
     const int lo = kR - kHistWin / 2;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int cd = codes[i];
-        const int k = cd - lo;
+    auto add = [&](unsigned code) {
+        const int k = (int)code - lo;
         if (k >= 0 && k < kHistWin)
             atomicAdd(&win[k], 1u);
         else
-            atomicAdd(&hist[cd], 1ULL);
+            atomicAdd(&hist[code], 1ULL);
+    };
+    const long long nth = (long long)gridDim.x * blockDim.x;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool al = (reinterpret_cast<uintptr_t>(codes) & 15) == 0;
+    const long long n8 = al ? n / 8 : 0;
+    for (long long i = t; i < n8; i += nth) {
+        const uint4 v = reinterpret_cast<const uint4 *>(codes)[i];
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            add(w[k] & 0xFFFFu);
+            add(w[k] >> 16);
+        }
     }
+    for (long long i = 8 * n8 + t; i < n; i += nth)
+        add(codes[i]);
     __syncthreads();
     for (int i = threadIdx.x; i < kHistWin; i += blockDim.x)
         if (win[i])
@@ -779,8 +799,8 @@ hipError_t launch_hist(const uint16_t *codes, long long n, unsigned long long *h
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, hist, 65536LL);
     if (n > 0)
-        hipLaunchKernelGGL(k_hist, dim3(grid_for(n, 256 * 64, 1024)), dim3(256), 0, s, codes, n,
-                           hist);
+        hipLaunchKernelGGL(k_hist, dim3(grid_for(n, 1024 * 64, 256)), dim3(1024),
+                           kHistWin * sizeof(unsigned), s, codes, n, hist);
     return hipGetLastError();
 }
 

@@ -107,33 +107,53 @@ void limit_depths(const std::vector<std::pair<uint64_t, uint32_t>> &leaves,
 
 bool huff_build(const uint64_t *hist, HuffTable &t)
 {
-    std::vector<std::pair<uint64_t, uint32_t>> leaves;
+    // used symbols in increasing (count, symbol): least-significant-digit radix
+    // passes of 11 bits over the counts, stable, starting from symbol order
+    std::vector<std::pair<uint64_t, uint32_t>> leaves, tmp;
+    uint64_t cmax = 0;
     for (uint32_t s = 0; s < 65536u; ++s)
-        if (hist[s])
+        if (hist[s]) {
             leaves.push_back({hist[s], s});
+            cmax = std::max(cmax, hist[s]);
+        }
     t.count.assign(kHuffMaxLen + 1, 0);
     t.syms.clear();
     t.n_bits = 0;
     t.max_len = 0;
     if (leaves.empty())
         return true;
-    std::sort(leaves.begin(), leaves.end());
+    tmp.resize(leaves.size());
+    for (int shift = 0; shift < 64 && (cmax >> shift) != 0; shift += 11) {
+        uint32_t bucket[2049] = {0};
+        for (const auto &l : leaves)
+            bucket[((l.first >> shift) & 2047u) + 1]++;
+        for (int k = 0; k < 2048; ++k)
+            bucket[k + 1] += bucket[k];
+        for (const auto &l : leaves)
+            tmp[bucket[(l.first >> shift) & 2047u]++] = l;
+        leaves.swap(tmp);
+    }
     std::vector<uint32_t> depth;
     uint32_t mx = huffman_depths(leaves, depth);
     if (mx > kHuffMaxLen) {
         limit_depths(leaves, depth, mx, kHuffMaxLen);
         mx = kHuffMaxLen;
     }
-    std::vector<std::pair<uint32_t, uint32_t>> order(leaves.size());  // (length, symbol)
+    // canonical order (length, then symbol): per symbol its length, then the
+    // symbols in value order bucketed by length
+    std::vector<uint8_t> len(65536, 0);
     for (size_t i = 0; i < leaves.size(); ++i) {
-        order[i] = {depth[i], leaves[i].second};
+        len[leaves[i].second] = (uint8_t)depth[i];
         t.count[depth[i]]++;
         t.n_bits += leaves[i].first * depth[i];
     }
-    std::sort(order.begin(), order.end());
-    t.syms.resize(order.size());
-    for (size_t i = 0; i < order.size(); ++i)
-        t.syms[i] = (uint16_t)order[i].second;
+    uint32_t pos[kHuffMaxLen + 2] = {0};
+    for (int l = 1; l <= kHuffMaxLen; ++l)
+        pos[l + 1] = pos[l] + t.count[l];
+    t.syms.resize(leaves.size());
+    for (uint32_t s = 0; s < 65536u; ++s)
+        if (len[s])
+            t.syms[pos[len[s]]++] = (uint16_t)s;
     t.max_len = mx;
     // Kraft check (the canonical construction needs sum 2^-l <= 1)
     uint64_t kraft = 0;
@@ -203,7 +223,8 @@ __global__ void k_huff_enc(const uint32_t *__restrict__ tab, uint8_t *__restrict
     }
 }
 
-// per-block bit sizes: one wave per block
+// per-block bit sizes: one wave per block, eight codes per lane (one 16-byte
+// load) where the block's codes are 16-byte aligned
 template <typename S>
 __global__ void __launch_bounds__(256) k_huff_sizes(const uint16_t *__restrict__ codes, GeoArgs g,
                                                     const uint8_t *__restrict__ enc_len,
@@ -218,13 +239,28 @@ __global__ void __launch_bounds__(256) k_huff_sizes(const uint16_t *__restrict__
                         bz = b / (g.nb[1] * g.nb[2]);
         const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
         const long long bsize = (long long)q.ez * q.ey * q.ex;
-        unsigned s = 0;
-        for (long long i = lane; i < bsize; i += 64) {
-            const unsigned l = enc_len[codes[q.start + i]];
-            if (l == 0)
-                err = kECorrupt;  // a code the codebook does not hold
+        const uint16_t *src = codes + q.start;
+        unsigned s = 0, zl = 0;
+        long long i0 = 0;
+        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            for (; i0 + 512 <= bsize; i0 += 512) {
+                const uint4 v = reinterpret_cast<const uint4 *>(src + i0)[lane];
+                const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const unsigned l0 = enc_len[w[k] & 0xFFFFu], l1 = enc_len[w[k] >> 16];
+                    zl |= (l0 == 0 ? 1u : 0u) | (l1 == 0 ? 1u : 0u);
+                    s += l0 + l1;
+                }
+            }
+        }
+        for (long long i = i0 + lane; i < bsize; i += 64) {
+            const unsigned l = enc_len[src[i]];
+            zl |= l == 0 ? 1u : 0u;
             s += l;
         }
+        if (zl)
+            err = kECorrupt;  // a code the codebook does not hold
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1)
             s += __shfl_xor(s, d, 64);
@@ -234,7 +270,12 @@ __global__ void __launch_bounds__(256) k_huff_sizes(const uint16_t *__restrict__
     set_status(status, err);
 }
 
-// bit packing: one wave per block, the block's words assembled in LDS
+// Bit packing: one wave per block, the block's words assembled in LDS.  Each
+// lane packs a run of consecutive codes (eight, from one 16-byte load, where
+// aligned; else one) into its own bit span: whole words by plain LDS stores,
+// the first and last word of its span (shared with the neighbouring lanes) by
+// atomic OR.  The wave then stores the block's words, the two boundary words
+// (shared with the neighbouring blocks) by atomic OR into the zeroed section.
 template <typename S>
 __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ codes, GeoArgs g,
                                                    const uint8_t *__restrict__ enc_len,
@@ -252,6 +293,30 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
     uint32_t *w = lw + (threadIdx.x >> 6) * wave_words;
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    // append n codes (lengths l[], codewords c[]) at bit `pos` of w
+    auto emit = [&](unsigned pos, const unsigned *l, const unsigned *c, int n) {
+        unsigned long long acc = 0;
+        int nacc = (int)(pos & 31u);
+        unsigned wp = pos >> 5;
+        bool first = true;
+        for (int j = 0; j < n; ++j) {
+            acc |= (unsigned long long)c[j] << (64 - nacc - (int)l[j]);
+            nacc += (int)l[j];
+            if (nacc >= 32) {
+                const uint32_t word = (uint32_t)(acc >> 32);
+                if (first)
+                    atomicOr(&w[wp], word);
+                else
+                    w[wp] = word;
+                first = false;
+                ++wp;
+                acc <<= 32;
+                nacc -= 32;
+            }
+        }
+        if (nacc > 0)
+            atomicOr(&w[wp], (uint32_t)(acc >> 32));
+    };
     for (long long b = wave; b < g.nblocks; b += nwaves) {
         const long long bx = b % g.nb[2], by = (b / g.nb[2]) % g.nb[1],
                         bz = b / (g.nb[1] * g.nb[2]);
@@ -264,13 +329,37 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
         for (int k = lane; k < nw; k += 64)
             w[k] = 0u;
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         unsigned run = s0;
-        for (long long c0 = 0; c0 < bsize; c0 += 64) {
+        const uint16_t *src = codes + q.start;
+        long long i0 = 0;
+        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            for (; i0 + 512 <= bsize; i0 += 512) {
+                const uint4 v = reinterpret_cast<const uint4 *>(src + i0)[lane];
+                const unsigned cw[4] = {v.x, v.y, v.z, v.w};
+                unsigned l[8], c[8], t = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const unsigned sym = (cw[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+                    l[j] = enc_len[sym];
+                    c[j] = enc_code[sym];
+                    t += l[j];
+                }
+                unsigned incl = t;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const unsigned o = __shfl_up(incl, d, 64);
+                    if (lane >= d)
+                        incl += o;
+                }
+                emit(run + incl - t, l, c, 8);
+                run += __shfl(incl, 63, 64);
+            }
+        }
+        for (long long c0 = i0; c0 < bsize; c0 += 64) {
             const long long i = c0 + lane;
             unsigned l = 0, cw = 0;
             if (i < bsize) {
-                const unsigned sym = codes[q.start + i];
+                const unsigned sym = src[i];
                 l = enc_len[sym];
                 cw = enc_code[sym];
             }
@@ -281,16 +370,12 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
                 if (lane >= d)
                     incl += o;
             }
-            const unsigned pos = run + incl - l;
-            if (l) {
-                const unsigned long long t = ((unsigned long long)cw << (64 - l)) >> (pos & 31u);
-                atomicOr(&w[pos >> 5], (uint32_t)(t >> 32));
-                if ((pos & 31u) + l > 32u)
-                    atomicOr(&w[(pos >> 5) + 1], (uint32_t)t);
-            }
+            if (l)
+                emit(run + incl - l, &l, &cw, 1);
             run += __shfl(incl, 63, 64);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // this wave's LDS writes above are complete before its reads below
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
         __builtin_amdgcn_wave_barrier();
         const unsigned long long w0 = start >> 5;
         const bool part_lo = s0 != 0, part_hi = ((s0 + nbits) & 31u) != 0;
@@ -349,16 +434,36 @@ __global__ void __launch_bounds__(256) k_huff_unpack(const uint32_t *__restrict_
         set_status(status, kECorrupt);
         return;
     }
-    // bit buffer: the next nb bits of the stream, left-aligned in buf
-    unsigned long long wi = start >> 5;
+    // the stream's words come four at a time (16-byte aligned loads, the next
+    // group in flight); buf holds the next nb bits left-aligned
+    const uint4 *w4 = reinterpret_cast<const uint4 *>(bits);
+    const unsigned long long n4 = nwords >> 2;
+    unsigned long long gi = (start >> 5) >> 2;  // current group
+    auto load4 = [&](unsigned long long k) -> uint4 {
+        if (k < n4)
+            return w4[k];
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        const unsigned long long w = 4 * k;
+        if (w < nwords) v.x = bits[w];
+        if (w + 1 < nwords) v.y = bits[w + 1];
+        if (w + 2 < nwords) v.z = bits[w + 2];
+        return v;
+    };
+    uint4 cur = load4(gi), nxt = load4(gi + 1);
+    int wk = (int)((start >> 5) & 3u);  // next word of cur
     unsigned long long buf = 0;
     int nb = 0;
     auto refill = [&]() {
         while (nb <= 32) {
-            const uint32_t v = wi < nwords ? bits[wi] : 0u;
+            const uint32_t v = wk == 0 ? cur.x : wk == 1 ? cur.y : wk == 2 ? cur.z : cur.w;
             buf |= (unsigned long long)v << (32 - nb);
             nb += 32;
-            ++wi;
+            if (++wk == 4) {
+                wk = 0;
+                cur = nxt;
+                ++gi;
+                nxt = load4(gi + 1);
+            }
         }
     };
     refill();
@@ -366,11 +471,10 @@ __global__ void __launch_bounds__(256) k_huff_unpack(const uint32_t *__restrict_
     buf <<= sk;
     nb -= (int)sk;
     unsigned long long used = 0;
-    uint16_t *dst = codes + q.start;
-    for (long long i = 0; i < bsize; ++i) {
+    auto next_sym = [&]() -> unsigned {
         refill();
         const unsigned win = (unsigned)(buf >> 32);
-        uint32_t e = lut[win >> (32 - kLutBits)];
+        const uint32_t e = lut[win >> (32 - kLutBits)];
         unsigned l = e >> 16, sym = e & 0xFFFFu;
         if (l == 0) {
             for (l = kLutBits + 1; l <= kHuffMaxLen; ++l) {
@@ -380,15 +484,34 @@ __global__ void __launch_bounds__(256) k_huff_unpack(const uint32_t *__restrict_
             }
             if (l > kHuffMaxLen) {
                 err = kECorrupt;
-                break;
+                l = 1;
+                sym = 0;
+            } else {
+                sym = syms[cs.index[l] + ((win >> (32 - l)) - cs.first[l])];
             }
-            sym = syms[cs.index[l] + ((win >> (32 - l)) - cs.first[l])];
         }
         buf <<= l;
         nb -= (int)l;
         used += l;
-        dst[i] = (uint16_t)sym;
+        return sym;
+    };
+    uint16_t *dst = codes + q.start;
+    long long i = 0;
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        // eight codes per 16-byte store
+        for (; i + 8 <= bsize && err == kOk; i += 8) {
+            unsigned wv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const unsigned lo = next_sym();
+                const unsigned hi = next_sym();
+                wv[k] = lo | (hi << 16);
+            }
+            *reinterpret_cast<uint4 *>(dst + i) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        }
     }
+    for (; i < bsize && err == kOk; ++i)
+        dst[i] = (uint16_t)next_sym();
     if (used != end - start)
         err = kECorrupt;
     set_status(status, err);
