@@ -153,6 +153,8 @@ typedef struct {
     uint64_t n_bits;      /* coded bits of all blocks */
     uint32_t n_sym;       /* symbols of the codebook */
     uint32_t size_bytes;  /* bytes per block bit size (2 or 4) */
+    int64_t p_max;        /* bound on every grid value: b_sign, or the grid value of the
+                             largest-magnitude negative, plus one step */
 } pwrel_header;
 
 typedef struct pwrel_ctx pwrel_ctx;

@@ -323,6 +323,8 @@ int pwrel_create(pwrel_ctx **out, int device)
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&ws.qtab), kQtab * sizeof(long long));
     if (e == hipSuccess)
+        e = hipMalloc(&ws.invtab, kInvTable * sizeof(double));
+    if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&ctx->theta),
                       (PWREL_MAX_CANDIDATES + 1) * kMaxParams * sizeof(float));
     if (e == hipSuccess)
@@ -358,7 +360,7 @@ void pwrel_destroy(pwrel_ctx *ctx)
                     ctx->vhist,     ctx->scal,      ctx->scores,   ws.done,        ws.ticket,
                     ctx->order,     ws.praw,        ws.zf,         ws.yf,          ctx->hdr,
                     ws.codes16,     ws.enc_len,     ws.enc_code,   ws.boffsets,    ws.bpartials,
-                    ws.bits_total};
+                    ws.bits_total,  ws.invtab};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -913,7 +915,8 @@ int pwrel_read_header(const void *buf, uint64_t size, pwrel_header *out)
     if (h.total_size != h.off_raw + h.n_raw * tsize || h.total_size > size)
         return PWREL_ECORRUPT;
     if (!(h.w > 0.0) || !std::isfinite(h.w) || !std::isfinite(h.Lp) || !std::isfinite(h.Ln) ||
-        !(h.eps > 0.0 && h.eps < 1.0) || !(h.p_zero <= h.b_sign) || h.delta < 0)
+        !(h.eps > 0.0 && h.eps < 1.0) || !(h.p_zero <= h.b_sign) || h.delta < 0 ||
+        h.p_max <= h.b_sign)
         return PWREL_ECORRUPT;
     *out = h;
     return PWREL_OK;
@@ -1032,6 +1035,8 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
     c.b_sign = h.b_sign;
     c.n_lo = h.n_lo;
     c.delta = h.delta;
+    c.p_max = h.p_max;
+    c.w32 = (h.p_max - h.p_zero) < (1LL << 27) ? 1 : 0;
     if ((e = launch_reset(ctx->ws, s)) != hipSuccess)
         return hip_fail(ctx, e, "reset");
     mark(ctx, 4, s);

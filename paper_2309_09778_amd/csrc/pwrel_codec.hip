@@ -249,6 +249,7 @@ __global__ void __launch_bounds__(256) k_consts(const DevStats *parts, int npart
                 qmax = qn > qmax ? qn : qmax;
             }
             k.w32 = (qmax - k.p_zero) < (1LL << 27) ? 1 : 0;
+            k.p_max = qmax + 1;
         }
         // fast-path margins: |t_fast - t| <= (err(log2) + 2^-52 (|log2 x| + |L| + 1))
         // r + 2^-52 |t| with |log2 x| < 129 and |t| < 2^30, enlarged by 1/64
@@ -472,6 +473,7 @@ __global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *c
     o.abs_max = c.abs_max;
     o.n_zero = c.n_zero;
     o.n_neg = c.n_neg;
+    o.p_max = c.p_max;
     o.off_huff = h.off_huff;
     o.off_sizes = h.off_sizes;
     o.off_bits = h.off_bits;

@@ -35,7 +35,21 @@ struct DecodeArgs {
     // workgroup-per-block kernel then takes only the clipped blocks
     long long nf[3];
     int partial_only;
+    // x^ of every grid value q in [inv_lo, inv_lo + inv_n) (dtype of the field),
+    // or nullptr: then x^ = grid_inverse(q) per point
+    const void *invtab;
+    long long inv_lo, inv_n;
 };
+
+// x^ of grid value q: from the table where it holds q, else computed
+template <typename T>
+__device__ __forceinline__ T inverse_of(int q, const DecodeArgs &a)
+{
+    const long long k = (long long)q - a.inv_lo;
+    if (a.invtab && k >= 0 && k < a.inv_n)
+        return reinterpret_cast<const T *>(a.invtab)[k];
+    return (T)grid_inverse<T>(q, a.c);
+}
 
 // The k-th block clipped by a high face of the field (blocks outside the
 // nf[0] x nf[1] x nf[2] grid of whole blocks): first the clipped z planes of

@@ -974,28 +974,46 @@ __global__ void __launch_bounds__(256) k_raw_grid(const T *raw, unsigned long lo
 
 // x^ of the coded points from the scratch grid field of the halo-mode
 // decoder (a balance point's x^ is already written)
+// x^ of every grid value in [lo, lo + n) (the decoders' lookup table)
+template <typename T>
+__global__ void __launch_bounds__(256) k_inv_table(DevConsts c, long long lo, long long n, T *tab)
+{
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        tab[i] = (T)grid_inverse<T>((int)(lo + i), c);
+}
+
+template <typename T>
+__device__ __forceinline__ T inverse_tab(int q, const DevConsts &c, const T *tab, long long lo,
+                                         long long nt)
+{
+    const long long k = (long long)q - lo;
+    return (tab && k >= 0 && k < nt) ? tab[k] : (T)grid_inverse<T>(q, c);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_inverse(const int *pgrid, long long n, DevConsts c,
-                                                 T *xh)
+                                                 const T *tab, long long lo, long long nt, T *xh)
 {
     const long long stride = (long long)gridDim.x * 256;
     for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
         const int v = pgrid[i];
         if (!(v & 1))
-            xh[i] = (T)grid_inverse<T>(scratch_grid(v), c);
+            xh[i] = inverse_tab<T>(scratch_grid(v), c, tab, lo, nt);
     }
 }
 
 // The same for FP32 fields with x^ 16-byte aligned: four values per thread
 // (one 16-byte load, one 16-byte store where all four are coded), two groups
 // of four in flight per thread; the tail n % 4 in scalar form.
-__device__ __forceinline__ void inverse4(const int4 &v, const DevConsts &c, float *dst)
+__device__ __forceinline__ void inverse4(const int4 &v, const DevConsts &c, const float *tab,
+                                         long long lo, long long nt, float *dst)
 {
     const int e[4] = {v.x, v.y, v.z, v.w};
     float o[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        o[k] = (float)grid_inverse<float>(scratch_grid(e[k]), c);
+        o[k] = inverse_tab<float>(scratch_grid(e[k]), c, tab, lo, nt);
     if (((e[0] | e[1] | e[2] | e[3]) & 1) == 0) {
         *reinterpret_cast<float4 *>(dst) = make_float4(o[0], o[1], o[2], o[3]);
     } else {
@@ -1007,7 +1025,8 @@ __device__ __forceinline__ void inverse4(const int4 &v, const DevConsts &c, floa
 }
 
 __global__ void __launch_bounds__(256) k_inverse_f32x4(const int *pgrid, long long n,
-                                                       DevConsts c, float *xh)
+                                                       DevConsts c, const float *tab, long long lo,
+                                                       long long nt, float *xh)
 {
     const long long n4 = n >> 2;
     const int4 *p4 = reinterpret_cast<const int4 *>(pgrid);
@@ -1015,16 +1034,16 @@ __global__ void __launch_bounds__(256) k_inverse_f32x4(const int *pgrid, long lo
     long long i = blockIdx.x * 256LL + threadIdx.x;
     for (; i + stride < n4; i += 2 * stride) {
         const int4 a = p4[i], b = p4[i + stride];
-        inverse4(a, c, xh + 4 * i);
-        inverse4(b, c, xh + 4 * (i + stride));
+        inverse4(a, c, tab, lo, nt, xh + 4 * i);
+        inverse4(b, c, tab, lo, nt, xh + 4 * (i + stride));
     }
     if (i < n4)
-        inverse4(p4[i], c, xh + 4 * i);
+        inverse4(p4[i], c, tab, lo, nt, xh + 4 * i);
     const long long r = 4 * n4 + blockIdx.x * 256LL + threadIdx.x;
     if (r < n) {
         const int v = pgrid[r];
         if (!(v & 1))
-            xh[r] = (float)grid_inverse<float>(scratch_grid(v), c);
+            xh[r] = inverse_tab<float>(scratch_grid(v), c, tab, lo, nt);
     }
 }
 
@@ -1154,6 +1173,20 @@ hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *mod
     a.yf = ws.yf;
     a.c = c;
     a.mlp = pack_mlp(a.use_net ? model : nullptr);
+    // the inverse of every grid value the field can hold, where few enough
+    const long long ntab = inv_table_size(c);
+    if (ntab) {
+        const unsigned tg = (unsigned)((ntab + 255) / 256);
+        if (g.dtype == PWREL_F32)
+            hipLaunchKernelGGL(k_inv_table<float>, dim3(tg), dim3(256), 0, s, c,
+                               (long long)c.p_zero, ntab, static_cast<float *>(ws.invtab));
+        else
+            hipLaunchKernelGGL(k_inv_table<double>, dim3(tg), dim3(256), 0, s, c,
+                               (long long)c.p_zero, ntab, static_cast<double *>(ws.invtab));
+        a.invtab = ws.invtab;
+        a.inv_lo = c.p_zero;
+        a.inv_n = ntab;
+    }
     const bool mfma = a.use_net && model && model->precision == 1;
     const int HP = mfma ? 0 : hidden_pad(a.use_net ? model : nullptr);
     const int h0 = g.D >= 3 ? 1 : 0, h1 = g.D >= 2 ? 1 : 0;
@@ -1165,7 +1198,7 @@ hipError_t launch_decode(const Geom &g, const DevConsts &c, const pwrel_mlp *mod
     const bool flow = !a.independent;
     unsigned grid = flow ? (unsigned)std::max(num_cus, 1) : (unsigned)g.nblocks;
     const bool pencils = flow && pencil_mode(g);
-    if (!flow && lanes_shape(g.D, g.B)) {
+    if (!flow && lanes_shape(g.D, g.B) && c.w32) {
         // whole blocks one per lane; the blocks clipped by the high faces one per workgroup
         long long nfull = 1;
         for (int d = 0; d < 3; ++d) {
@@ -1216,15 +1249,19 @@ hipError_t launch_inverse(const Geom &g, const DevConsts &c, Workspace &ws, void
     const unsigned grid = (unsigned)std::min<long long>((g.N + 255) / 256, 8192);
     const bool vec = (reinterpret_cast<uintptr_t>(xh) & 15) == 0 &&
                      (reinterpret_cast<uintptr_t>(ws.pgrid) & 15) == 0;
+    const long long nt = inv_table_size(c);
     if (g.dtype == PWREL_F32 && vec)
         hipLaunchKernelGGL(k_inverse_f32x4, dim3(std::max(1u, grid / 4)), dim3(256), 0, s,
-                           ws.pgrid, g.N, c, static_cast<float *>(xh));
+                           ws.pgrid, g.N, c, nt ? static_cast<const float *>(ws.invtab) : nullptr,
+                           (long long)c.p_zero, nt, static_cast<float *>(xh));
     else if (g.dtype == PWREL_F32)
         hipLaunchKernelGGL(k_inverse<float>, dim3(grid), dim3(256), 0, s, ws.pgrid, g.N, c,
-                           static_cast<float *>(xh));
+                           nt ? static_cast<const float *>(ws.invtab) : nullptr,
+                           (long long)c.p_zero, nt, static_cast<float *>(xh));
     else
         hipLaunchKernelGGL(k_inverse<double>, dim3(grid), dim3(256), 0, s, ws.pgrid, g.N, c,
-                           static_cast<double *>(xh));
+                           nt ? static_cast<const double *>(ws.invtab) : nullptr,
+                           (long long)c.p_zero, nt, static_cast<double *>(xh));
     return hipGetLastError();
 }
 

@@ -13,8 +13,11 @@
 // rows per lane, and x^ of the row is written as one contiguous run (64 lanes
 // = 64 neighbouring blocks = one coalesced stretch of the field).
 //
-// Only whole blocks go here; blocks clipped by the field's high faces are
-// decoded by the workgroup-per-block kernel.
+// Only whole blocks go here, of fields whose grid values span less than 2^27
+// (prediction arithmetic in 32 bits); blocks clipped by the field's high faces
+// are decoded by the workgroup-per-block kernel.  A decoded grid value must
+// lie in [p_zero, p_max] (else the stream is corrupt); x^ comes from the
+// table of every grid value's inverse where the decompression built one.
 #include "pwrel_bf16.h"
 #include "pwrel_decode.h"
 
@@ -47,6 +50,29 @@ template <int B> struct RowCodes {
         return (k & 1) ? (w[k >> 1] >> 16) : (w[k >> 1] & 0xFFFFu);
     }
 };
+
+// Lorenzo prediction over the available neighbours in 32-bit arithmetic
+// (wrapping sums are exact where the result fits, which it does for a valid
+// stream's grid values)
+template <int D>
+__device__ __forceinline__ int lorenzo32(const int (&nv)[8], int amask)
+{
+    unsigned s = 0;
+#pragma unroll
+    for (int o = 1; o < (1 << D); ++o)
+        if ((o & ~amask) == 0)
+            s += lorenzo_sign(o) > 0 ? (unsigned)nv[o] : 0u - (unsigned)nv[o];
+    return (int)s;
+}
+
+__device__ __forceinline__ int net_pred32(float y, int n1)
+{
+    if (y > 0x1p30f)
+        y = 0x1p30f;
+    if (!(y >= -0x1p30f))
+        y = -0x1p30f;
+    return n1 + (int)__builtin_rintf(y);
+}
 
 template <typename T, int B>
 __device__ __forceinline__ void store_row(T *dst, const T (&v)[B], bool vec)
@@ -160,27 +186,33 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_decode_lanes(DecodeArgs a)
                 nv[5] = lx > 0 ? zr[lx > 0 ? lx - 1 : 0] : 0;
                 nv[6] = zry[lx];
                 nv[7] = lx > 0 ? zry[lx > 0 ? lx - 1 : 0] : 0;
-                long long pred;
-                if constexpr (PREC == 1) {
-                    if (amask == NO)  // wave-uniform: every lane runs the matrix cores
-                        pred = predict_bf16<D>(nv, amask, netb, n16);
-                    else
-                        pred = predict<D, 8>(nv, amask, false, wt, b2, alpha);
+                int pred;
+                if (amask == NO) {  // wave-uniform
+                    if constexpr (PREC == 1) {
+                        // every lane runs the matrix cores (Lorenzo lanes feed zeros)
+                        float u[6];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            u[k] = (k < K && netb) ? (float)(nv[k + 2] - nv[1]) : 0.0f;
+                        const float y = net_bf16(n16, u);
+                        pred = netb ? net_pred32(y, nv[1]) : lorenzo32<D>(nv, amask);
+                    } else {
+                        pred = netb ? net_pred32(net_f32<D, HP>(nv, wt, b2, alpha), nv[1])
+                                    : lorenzo32<D>(nv, amask);
+                    }
                 } else {
-                    pred = predict<D, HP>(nv, amask, netb, wt, b2, alpha);
+                    pred = lorenzo32<D>(nv, amask);
                 }
                 const unsigned code = rc.get(lx);
                 int p;
                 T x;
                 if (code != 0u) {
-                    const long long pv = pred - ((long long)code - kR);
-                    if (!(pv > -(long long)kGridLimit && pv < (long long)kGridLimit)) {
+                    p = pred - ((int)code - kR);
+                    if (p < c.p_zero || p > c.p_max) {
                         err = kECorrupt;
-                        p = 0;
-                    } else {
-                        p = (int)pv;
+                        p = (int)c.p_zero;
                     }
-                    x = (T)grid_inverse<T>(p, c);
+                    x = inverse_of<T>(p, a);
                 } else {
                     // balance point: its raw value and that value's grid value
                     if (zc < nzero) {

@@ -32,6 +32,8 @@ struct DevConsts {
     int w32;            // grid values span < 2^27: prediction errors fit 32-bit arithmetic
     int pad2;
     double vm;          // bound certified when t is this far inside its grid cell (below)
+    long long p_max;    // no point's grid value exceeds this (the largest |x| of a negative,
+                        // else b_sign, plus one grid step against ulp-level log2 errors)
 };
 
 // Running statistics of a field (reduced with integer atomics).

@@ -65,7 +65,18 @@ struct Workspace {
     unsigned long long *boffsets = nullptr, *bpartials = nullptr;
     size_t boffsets_cap = 0, bpartials_cap = 0;
     unsigned long long *bits_total = nullptr;
+    // decoders: x^ of every grid value in [p_zero, p_max] (kInvTable entries of
+    // the field's dtype at most; allocated with the context)
+    void *invtab = nullptr;
 };
+
+constexpr long long kInvTable = 1 << 16;
+// entries of the decoders' inverse table for these constants (0: none)
+inline long long inv_table_size(const DevConsts &c)
+{
+    const long long n = c.p_max - c.p_zero + 1;
+    return (n > 0 && n <= kInvTable) ? n : 0;
+}
 
 constexpr int kQtab = 4097;
 

@@ -57,7 +57,7 @@ class Header(C.Structure):
                 ("n_zero", C.c_uint64), ("n_neg", C.c_uint64), ("status", C.c_int32),
                 ("pad0", C.c_int32), ("off_huff", C.c_uint64), ("off_sizes", C.c_uint64),
                 ("off_bits", C.c_uint64), ("n_bits", C.c_uint64), ("n_sym", C.c_uint32),
-                ("size_bytes", C.c_uint32)]
+                ("size_bytes", C.c_uint32), ("p_max", C.c_int64)]
 
 
 MAX_CANDIDATES = 17

@@ -73,6 +73,7 @@ def _valid_header(n=(10, 12), block=4, flags=0, dtype=pwrel.F32, n_raw=3):
     h.block, h.flags = block, flags
     h.eps, h.w, h.r, h.b_a = 1e-2, 0.0287, 34.8, 0.01435
     h.Lp, h.Ln, h.p_zero, h.b_sign, h.delta = 0.0, 2.0, -4389, 70, 0
+    h.p_max = 141
     N = int(np.prod(n))
     nb = int(np.prod([-(-v // block) for v in n]))
     h.n, h.nblocks, h.n_raw = N, nb, n_raw
@@ -107,7 +108,7 @@ def test_header_validation_accepts_consistent_and_rejects_corrupt():
     corruptions = [("magic", 0x12345678), ("version", 2), ("dtype", 5), ("ndim", 4),
                    ("n", 121), ("nblocks", 8), ("off_codes", 1024), ("n_raw", 4),
                    ("total_size", 10 ** 9), ("w", -1.0), ("eps", 2.0), ("status", -5),
-                   ("delta", -1), ("flags", 64)]
+                   ("delta", -1), ("flags", 64), ("p_max", 70)]
     for field, val in corruptions:
         hh = _valid_header()
         setattr(hh, field, val)
