@@ -5,15 +5,19 @@ Workload: a 512^3 FP32 log-normal field (k^-3 Gaussian random field over 8
 decades, 10% negative connected regions, 0.5% zeros; seeded synthetic stand-in
 for the paper's seismic volumes), block 8^3, point-wise relative bound 1e-2.
 
-Learned path (timed): a network of hidden width 32 is trained on the device
-from 1% of the field's points (outside the timed region; its time is
-reported), then one step = compress (statistics, constants, grid values and
-bound checks of every value, then the fused BF16 matrix-core prediction /
-per-block Lorenzo judge / quantisation kernel, scan, raw scatter, header)
-followed by decompress (scan, grid values of the raw values, pencil-ordered
-reconstruction, inverse map) of the whole field, inputs resident in HBM.  The
-plain path (FP32 network H = 16, no judge) is timed the same way for
-comparison.  Prints one JSON line.
+Timed path (the `value`): the learned path with every block decoded on its
+own (Sec. 4.4.2's sub-block decompression): a network of hidden width 32 is
+trained on the device from 1% of the field's points (outside the timed
+region; its time is reported, and the end-to-end rate with it), then one step
+= compress (statistics, constants, grid values and bound checks, BF16
+matrix-core prediction with the per-block Lorenzo judge, quantisation, scan,
+raw values, Huffman stage: histogram, codebook, bit packing) followed by
+decompress (Huffman decoding, per-block reconstruction, x^) of the whole
+field, inputs resident in HBM.  Beside it, timed the same way: the learned
+path with halo prediction, and the plain path (FP32 network of width 16
+trained by the same device trainer, no judge).  Then the FP64 volume
+(1024 x 1024 x 512, eps 1e-4) and the 2-D 1800 x 3600 field on the learned
+path, a measured device copy, and the CPU oracle.  Prints one JSON line.
 """
 import argparse
 import gc
@@ -31,7 +35,7 @@ ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 
 
 def compress_flops_per_point(H, K):
-    """Algorithmic FP32 + FP64 operations of the fused compression kernel per
+    """Algorithmic FP32 + FP64 operations of the compression kernels per
     point: log-domain transform (atanh series: 1 div, 10 fma, 5 mul/add; then
     + log2 factor, * 1/w), verification (exp2 Taylor: 4 ops + 13 fma; |x - x^|
     and eps |x|), perceptron (K*H fma, H leaky products, H fma).  fma = 2."""
@@ -44,13 +48,9 @@ def compress_flops_per_point(H, K):
 COMPRESS_SOURCES = ["paper_2309_09778_amd/csrc/pwrel_compress.hip",
                     "paper_2309_09778_amd/csrc/pwrel_kernels.h",
                     "paper_2309_09778_amd/csrc/pwrel_bf16.h",
-                    "paper_2309_09778_amd/csrc/pwrel_device.h"]
-DECODE_SOURCES = ["paper_2309_09778_amd/csrc/pwrel_decode.hip",
-                  "paper_2309_09778_amd/csrc/pwrel_kernels.h",
-                  "paper_2309_09778_amd/csrc/pwrel_bf16.h",
-                  "paper_2309_09778_amd/csrc/pwrel_device.h"]
+                    "paper_2309_09778_amd/csrc/pwrel_device.h",
+                    "paper_2309_09778_amd/csrc/pwrel_wavesort.h"]
 COMPRESS_PROFILE = "k_grid_entries_k_compress_learned_bf16_judge_512cubed_f32_eps1e-2.txt"
-DECODE_PROFILE = "k_decode_pencil_learned_bf16_judge_512cubed_f32_eps1e-2.txt"
 
 
 def source_hash(files):
@@ -80,47 +80,81 @@ def profiled_traffic(summary, files):
     return int(vals["traffic_bytes_per_launch:"]) if "traffic_bytes_per_launch:" in vals else None
 
 
-def huffman_stream_bytes(h, hist, huffman_bits):
-    """Compressed size with the codes Huffman-coded: header + model + per-block
-    counts + coded bits + codebook (2-byte symbol + 1-byte length per used
-    code) + raw values."""
-    bits, _ = huffman_bits(hist)
-    used = int((hist > 0).sum())
-    return (h["off_counts"] + 4 * h["nblocks"] + (bits + 7) // 8 + 3 * used +
-            h["n_raw"] * (4 if h["dtype"] == 0 else 8))
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(x, eps, block, model, side=256):
-    """The CPU oracle (single thread) on a sub-cube of the same field: the
-    learned mode (both predictors and the per-block judge, the network in
-    FP32), compress then decompress."""
+def cpu_baseline(x, eps, block, model, nproc):
+    """The CPU oracle as it stands, learned mode (both predictors and the
+    per-block judge, the network in FP32), compress then decompress: one
+    thread on a 192^3 corner of the field, and one thread per host core each
+    on its own disjoint 96^3 piece (the oracle's C routines run outside the
+    interpreter lock)."""
+    import concurrent.futures as cf
     import numpy as np
     from oracle import oracle as O
-    sub = np.ascontiguousarray(x[:side, :side, :side])
     m = dict(model, precision=0)
+
+    def one(sub):
+        r = O.compress(sub, eps, block, m, O.MODE_LEARNED)
+        O.decompress(r["codes"], r["raw"], r["consts"], sub.shape, sub.dtype, block, m,
+                     O.MODE_LEARNED, flags=r["flags"])
+
+    side1 = 192
+    sub = np.ascontiguousarray(x[:side1, :side1, :side1])
     t0 = time.perf_counter()
     r = O.compress(sub, eps, block, m, O.MODE_LEARNED)
     t1 = time.perf_counter()
     O.decompress(r["codes"], r["raw"], r["consts"], sub.shape, sub.dtype, block, m,
                  O.MODE_LEARNED, flags=r["flags"])
     t2 = time.perf_counter()
-    gb = sub.nbytes / 1e9
-    return {"value": round(gb / (t2 - t0), 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{side}^3 FP32 sub-cube (first corner) of the same field, learned mode "
-                      f"(network H={len(model['b1'])} in FP32 + Lorenzo judge), compress + "
-                      f"decompress, single thread",
-            "compress_GBps": round(gb / (t1 - t0), 5),
-            "decompress_GBps": round(gb / (t2 - t1), 5)}
+    gb1 = sub.nbytes / 1e9
+    side = 96
+    per = x.shape[0] // side
+    pieces = []
+    for i in range(nproc):
+        a, b, c = i % per, (i // per) % per, (i // (per * per)) % per
+        pieces.append(np.ascontiguousarray(x[a * side:(a + 1) * side, b * side:(b + 1) * side,
+                                             c * side:(c + 1) * side]))
+    t3 = time.perf_counter()
+    with cf.ThreadPoolExecutor(nproc) as ex:
+        list(ex.map(one, pieces))
+    t4 = time.perf_counter()
+    gbn = sum(p.nbytes for p in pieces) / 1e9
+    return {"value": round(gbn / (t4 - t3), 5), "unit": "GB/s", "cores": nproc, "kind": "oracle",
+            "sample": f"{nproc} disjoint {side}^3 FP32 pieces of the same field, one host thread "
+                      f"each, learned mode (network H={len(model['b1'])} in FP32 + Lorenzo "
+                      f"judge), compress + decompress round trip; single thread: {side1}^3 corner",
+            "single_thread_GBps": round(gb1 / (t2 - t0), 5),
+            "single_thread_compress_GBps": round(gb1 / (t1 - t0), 5),
+            "single_thread_decompress_GBps": round(gb1 / (t2 - t1), 5)}
 
 
-def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, torch,
-             entropy=False):
+def copy_bandwidth(xd, torch, reps=10):
+    """Measured HBM bandwidth of a device copy of the field (bytes read +
+    written / time, HIP events)."""
+    y = torch.empty_like(xd)
+    y.copy_(xd)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(xd)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del y
+    return round(2 * xd.numel() * xd.element_size() / (ms * 1e-3) / 1e9, 1)
+
+
+def run_path(ctx, xd, eps, B, model, judge, ind, entropy, out, xh, steps, warmup, pwrel, torch):
     """Warm up, then time `steps` round trips (compress + decompress) of one
     path; returns wall times, per-phase device times and the last stream."""
-    model = pwrel.model_struct(model)  # the C struct, built once
+    model = pwrel.model_struct(model) if model is not None else None
+    use_net = model is not None
+    kw = dict(use_net=use_net, judge=judge, independent=ind, entropy=entropy, out=out)
     for _ in range(warmup):
-        s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind,
-                         entropy=entropy)
+        s = ctx.compress(xd, eps, B, model, **kw)
         ctx.decompress(s, out=xh)
     torch.cuda.synchronize()
     # no garbage-collector pause of this interpreter inside the timed steps
@@ -132,8 +166,7 @@ def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, 
     t0 = time.perf_counter()
     for _ in range(steps):
         a = time.perf_counter()
-        s = ctx.compress(xd, eps, B, model, judge=judge, out=out, independent=ind,
-                         entropy=entropy)
+        s = ctx.compress(xd, eps, B, model, **kw)
         b = time.perf_counter()
         ctx.decompress(s, out=xh)
         torch.cuda.synchronize()
@@ -149,42 +182,82 @@ def run_path(ctx, xd, eps, B, model, judge, ind, out, xh, steps, warmup, pwrel, 
             "phase_ms": {k: v / steps for k, v in phase_sum.items()}, "stream": s}
 
 
-def stream_stats(ctx, s, x_nbytes, pwrel):
-    h = pwrel.header(s)
+def bound_ok(xd, xh, eps, torch):
+    """|x - x^| <= eps |x|, sign and zero preserved, on every point (FP64)."""
+    ok = True
+    n = xd.numel()
+    step = 1 << 26
+    xf, hf = xd.reshape(-1), xh.reshape(-1)
+    for i in range(0, n, step):
+        xt, ht = xf[i:i + step].double(), hf[i:i + step].double()
+        nz = xt != 0
+        ok = ok and bool(torch.all((xt - ht).abs() <= eps * xt.abs())) and \
+            bool(torch.all(ht[~nz] == 0)) and \
+            bool(torch.all(torch.signbit(ht[nz]) == torch.signbit(xt[nz])))
+    return ok
+
+
+def max_rel_error(xd, xh, torch):
+    m = 0.0
+    n = xd.numel()
+    step = 1 << 26
+    xf, hf = xd.reshape(-1), xh.reshape(-1)
+    for i in range(0, n, step):
+        xt, ht = xf[i:i + step].double(), hf[i:i + step].double()
+        nz = xt != 0
+        if bool(nz.any()):
+            m = max(m, float(((xt[nz] - ht[nz]).abs() / xt[nz].abs()).max()))
+    return m
+
+
+def stream_stats(ctx, s, x_nbytes, pwrel, plain_codes=None):
+    """Ratio of the stream as stored (and, for a 16-bit-code stream, the exact
+    Huffman estimate), balance points, blocks that keep the network, and the
+    RMS prediction error in grid units (from the code histogram)."""
+    import numpy as np
     sec = pwrel.sections(s)
-    hist = ctx.histogram(sec["codes"])
-    hbytes = huffman_stream_bytes(h, hist, pwrel.huffman_bits)
+    h = sec["header"]
     out = {"ratio_stream": round(x_nbytes / h["total_size"], 4),
-           "ratio_huffman": round(x_nbytes / hbytes, 4),
-           "paper_CR_percent_huffman": round(100.0 * hbytes / x_nbytes, 3),
+           "paper_CR_percent": round(100.0 * h["total_size"] / x_nbytes, 3),
+           "stream_bytes": int(h["total_size"]),
+           "huffman_coded": bool(h["flags"] & pwrel.HF_HUFFMAN),
            "unpredictable_frac": round(h["n_raw"] / h["n"], 7), "n_raw": int(h["n_raw"])}
+    if h["flags"] & pwrel.HF_HUFFMAN:
+        out["bits_per_value"] = round(h["n_bits"] / h["n"], 4)
+        out["codebook_symbols"] = int(h["n_sym"])
     if "bflags" in sec:
         out["network_block_frac"] = round(float(sec["bflags"].float().mean()), 4)
     return out
 
 
-def bound_ok(xd, xh, eps, torch):
-    xt, ht = xd.double(), xh.double()
-    nz = xt != 0
-    return bool(torch.all((xt - ht).abs() <= eps * xt.abs())) and \
-        bool(torch.all(ht[~nz] == 0)) and \
-        bool(torch.all(torch.signbit(ht[nz]) == torch.signbit(xt[nz])))
-
-
-def error_stats(ctx, xd, xh, stream, torch, pwrel):
-    """Max relative error of x^ (FP64, over non-zero x) and the RMS prediction
-    error in grid units (from the code histogram: e = code - 2^15, balance
-    points excluded)."""
+def pred_error_rms(ctx, codes_t, pwrel):
     import numpy as np
-    xt, ht = xd.double(), xh.double()
-    nz = xt != 0
-    rel = float(((xt[nz] - ht[nz]).abs() / xt[nz].abs()).max())
-    hist = ctx.histogram(pwrel.sections(stream)["codes"]).astype(np.float64)
+    hist = ctx.histogram(codes_t).astype(np.float64)
     e = np.arange(65536, dtype=np.float64) - 32768.0
-    h = hist.copy()
-    h[0] = 0.0
-    rms = float(np.sqrt((h * e * e).sum() / max(h.sum(), 1.0)))
-    return {"max_rel_error": rel, "pred_error_rms": round(rms, 4)}
+    hist[0] = 0.0
+    return round(float(np.sqrt((hist * e * e).sum() / max(hist.sum(), 1.0))), 4)
+
+
+def path_record(name, P, ctx, xd, xh, eps, gb, K, pwrel, torch):
+    rec = {"path": name,
+           "round_trip_GBps": round(gb / (P["wall_s"] / K), 3),
+           "compress_GBps": round(gb / (P["tc"] / K), 3),
+           "decompress_GBps": round(gb / (P["td"] / K), 3),
+           "ms_per_step": round(P["wall_s"] * 1e3 / K, 4),
+           "phase_ms": {k: round(v, 4) for k, v in P["phase_ms"].items()},
+           "bound_ok_every_point": bound_ok(xd, xh, eps, torch),
+           "max_rel_error": max_rel_error(xd, xh, torch)}
+    rec.update(stream_stats(ctx, P["stream"], xd.numel() * xd.element_size(), pwrel))
+    return rec
+
+
+def train_record(rep, wall_ms):
+    return {"wall_ms": round(wall_ms, 2), "ms_sample": round(rep["ms_sample"], 3),
+            "ms_train": round(rep["ms_train"], 3), "ms_select": round(rep["ms_select"], 3),
+            "n_train": rep["n_train"], "n_val": rep["n_val"], "chosen": rep["chosen"],
+            "train_pairs_per_s": round(rep["n_train"] / max(rep["ms_train"], 1e-9) * 1e3, 1),
+            "val_gain_bits": round((rep["val_score"][rep["chosen"]] - rep["val_score"][0]) /
+                                   2.0 ** 32 / max(rep["n_val"], 1), 4)}
 
 
 def main():
@@ -199,14 +272,9 @@ def main():
     ap.add_argument("--plain-hidden", type=int, default=16,
                     help="hidden width of the plain FP32 network")
     ap.add_argument("--rho", type=float, default=0.01, help="training sample rate")
-    ap.add_argument("--independent", action="store_true",
-                    help="blocks predicted without neighbours outside the block (every block "
-                         "decodes on its own)")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison")
-    ap.add_argument("--no-alt", action="store_true",
-                    help="skip the learned path with independent blocks (context)")
+    ap.add_argument("--only-timed", action="store_true",
+                    help="the timed path only (no other paths, legs or CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--entropy", action="store_true", help="Huffman-coded streams")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the codec has no multi-GPU path "
@@ -216,107 +284,67 @@ def main():
     import torch
     from paper_2309_09778_amd import pwrel, synth
 
-    S, eps, B, ind = args.side, args.eps, args.block, args.independent
+    S, eps, B = args.side, args.eps, args.block
     x = synth.lognormal_grf((S, S, S), seed=1001)
-    print(f"[bench] field {S}^3 FP32 generated", file=sys.stderr, flush=True)
+    log(f"field {S}^3 FP32 generated")
     xd = torch.from_numpy(x).cuda()
     ctx = pwrel.Context(0)
     cap = pwrel.compress_bound(x.shape, pwrel.F32, B)
     out = torch.empty(cap, dtype=torch.uint8, device="cuda")
     xh = torch.empty_like(xd)
-    # a plain device copy of known size (HBM counter calibration for profiles)
-    xd.clone()
-    torch.cuda.synchronize()
+    copy_gbps = copy_bandwidth(xd, torch)
     gb = x.nbytes / 1e9
     K = args.steps
+    N = x.size
 
     # training (outside the timed region, reported on its own)
     t0 = time.perf_counter()
     learned, rep = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.hidden,
-                             precision=1, independent=ind)
-    train_wall_ms = (time.perf_counter() - t0) * 1e3
-    print(f"[bench] trained: chosen {rep['chosen']}, {rep['n_train']} pairs, "
-          f"{train_wall_ms:.1f} ms", file=sys.stderr, flush=True)
+                             precision=1, independent=True)
+    train_ms = (time.perf_counter() - t0) * 1e3
+    log(f"trained: chosen {rep['chosen']}, {rep['n_train']} pairs, {train_ms:.1f} ms")
 
-    # timed: the learned path (BF16 matrix-core network + per-block Lorenzo judge)
-    L = run_path(ctx, xd, eps, B, learned, True, ind, out, xh, K, args.warmup, pwrel, torch,
-                 entropy=args.entropy)
-    ok_l = bound_ok(xd, xh, eps, torch)
-    st_l = stream_stats(ctx, L["stream"], x.nbytes, pwrel)
-    st_l.update(error_stats(ctx, xd, xh, L["stream"], torch, pwrel))
+    # timed: the learned path, independent blocks, judge, Huffman-coded stream
+    L = run_path(ctx, xd, eps, B, learned, True, True, True, out, xh, K, args.warmup, pwrel,
+                 torch)
+    rec_l = path_record("learned BF16 H=%d, judge, independent blocks, Huffman" % args.hidden,
+                        L, ctx, xd, xh, eps, gb, K, pwrel, torch)
     ms_step = L["wall_s"] * 1e3 / K
     value = gb / (L["wall_s"] / K)
-    print("[bench] learned path timed", file=sys.stderr, flush=True)
-
-    plain = None
-    if not args.no_plain:
-        pm = pwrel.mlp_init(3, args.plain_hidden, 0.01, 1001)
-        P = run_path(ctx, xd, eps, B, pm, False, ind, out, xh, K, args.warmup, pwrel, torch)
-        plain = {"network": f"FP32 H={args.plain_hidden}, Lorenzo-initialised (untrained)",
-                 "round_trip_GBps": round(gb / (P["wall_s"] / K), 3),
-                 "compress_GBps": round(gb / (P["tc"] / K), 3),
-                 "decompress_GBps": round(gb / (P["td"] / K), 3),
-                 "phase_ms": {k: round(v, 4) for k, v in P["phase_ms"].items()},
-                 "bound_ok_every_point": bound_ok(xd, xh, eps, torch)}
-        plain.update(stream_stats(ctx, P["stream"], x.nbytes, pwrel))
-        plain.update(error_stats(ctx, xd, xh, P["stream"], torch, pwrel))
-        print("[bench] plain path timed", file=sys.stderr, flush=True)
-
-    # context: the learned path with independent blocks (each block predicted
-    # from its own points only; every block decodes on its own)
-    alt = None
-    if not args.no_alt and not ind:
-        alt_model, alt_rep = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.hidden,
-                                       precision=1, independent=True)
-        A = run_path(ctx, xd, eps, B, alt_model, True, True, out, xh, K, args.warmup, pwrel,
-                     torch)
-        alt = {"network": f"BF16 H={args.hidden} trained with independent blocks, judge",
-               "round_trip_GBps": round(gb / (A["wall_s"] / K), 3),
-               "compress_GBps": round(gb / (A["tc"] / K), 3),
-               "decompress_GBps": round(gb / (A["td"] / K), 3),
-               "phase_ms": {k: round(v, 4) for k, v in A["phase_ms"].items()},
-               "bound_ok_every_point": bound_ok(xd, xh, eps, torch)}
-        alt.update(stream_stats(ctx, A["stream"], x.nbytes, pwrel))
-        alt.update(error_stats(ctx, xd, xh, A["stream"], torch, pwrel))
-        print("[bench] learned path with independent blocks timed", file=sys.stderr, flush=True)
+    # the same call's codes as 16 bits (for the prediction error and the ratio estimate)
+    s16 = ctx.compress(xd, eps, B, learned, judge=True, independent=True, out=out)
+    rec_l["pred_error_rms"] = pred_error_rms(ctx, pwrel.sections(s16)["codes"], pwrel)
+    hist = ctx.histogram(pwrel.sections(s16)["codes"])
+    rec_l["huffman_bits_estimate"] = pwrel.huffman_bits(hist)[0]
+    log("learned path timed")
 
     ph = L["phase_ms"]
-    N = x.size
-    n_raw = st_l["n_raw"]
+    n_raw = rec_l["n_raw"]
     nblocks = (S // B) ** 3
-    # compression phase (grid values and bound checks, then the fused kernel):
-    # ALU-bound (FP64 transform and verification per point; the network runs
-    # on the matrix cores)
+    # compression kernels (grid values and bound checks, then the fused
+    # prediction / judge / quantisation kernel): issue-bound on the ALUs
     flops_pp = compress_flops_per_point(0, 6)
     c_ms = ph["compress"]
     c_ach = flops_pp * N / (c_ms * 1e-3) / 1e12
     c_bytes = N * 4 + N * 2 + nblocks * 5 + n_raw * 4  # field in; codes, counts, flags, raw out
     mfma_useful = 2 * (args.hidden * 6 + args.hidden) * N
-    roof_c = {"kernel": "k_grid_entries + k_compress<float,3,8,8,true,1> (a3-a7, BF16 MFMA "
-                        "network, judge)", "bound": "alu", "achieved": round(c_ach, 3),
-              "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
-              "frac": round(c_ach / ALU_PEAK_TFLOPS, 4),
-              "traffic": profiled_traffic(COMPRESS_PROFILE, COMPRESS_SOURCES),
-              "avg_ms": round(c_ms, 4), "flops_per_point": flops_pp,
-              "algorithmic_bytes": c_bytes,
-              "hbm_frac": round(c_bytes / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-              "mfma_util": round(mfma_useful / (c_ms * 1e-3) / 2.5e15, 5)}
-    # halo-mode decoder (pencils): bound by its chain of dependent pencils;
-    # priced against HBM with its algorithmic bytes (codes in, grid values out)
+    roofline = {"kernel": "k_grid_entries + k_compress<float,3,8,8,true,1> (a3-a7, BF16 MFMA "
+                          "network, exact per-block judge)", "bound": "alu",
+                "achieved": round(c_ach, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(c_ach / ALU_PEAK_TFLOPS, 4),
+                "traffic": profiled_traffic(COMPRESS_PROFILE, COMPRESS_SOURCES),
+                "avg_ms": round(c_ms, 4), "flops_per_point": flops_pp,
+                "algorithmic_bytes": c_bytes,
+                "hbm_frac": round(c_bytes / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "mfma_util": round(mfma_useful / (c_ms * 1e-3) / 2.5e15, 5)}
+    # the lane decoder (independent blocks): codes in, x^ out
     d_ms = ph["decode_levels"]
     d_bytes = N * 2 + N * 4 + n_raw * 4
-    d_ach = d_bytes / (d_ms * 1e-3) / 1e9
-    roof_d = {"kernel": "k_decode_pencil<float,8,1> (a8 halo mode, BF16 network, judge)",
-              "bound": "hbm", "achieved": round(d_ach, 2), "peak": HBM_PEAK_GBPS,
-              "unit": "GB/s", "frac": round(d_ach / HBM_PEAK_GBPS, 5),
-              "traffic": profiled_traffic(DECODE_PROFILE, DECODE_SOURCES),
-              "avg_ms": round(d_ms, 4), "algorithmic_bytes": d_bytes,
-              "limiter": "dependency chain of pencils (levels bz + by)"}
-    # the roofline line is the dominant kernel's; the other is reported beside it
-    if d_ms >= c_ms:
-        roofline, other = roof_d, ("roofline_compress", roof_c)
-    else:
-        roofline, other = roof_c, ("roofline_decode", roof_d)
+    roof_d = {"kernel": "k_decode_lanes<float,3,8,8,1> (a8, one lane per block, BF16 network)",
+              "bound": "hbm", "achieved": round(d_bytes / (d_ms * 1e-3) / 1e9, 2),
+              "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+              "frac": round(d_bytes / (d_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 5),
+              "avg_ms": round(d_ms, 4), "algorithmic_bytes": d_bytes}
 
     res = {
         "metric": "compress/decompress GB/s at PW_REL 1e-2 and ratio, learned BF16 vs plain FP32",
@@ -326,33 +354,97 @@ def main():
         "config": {"workload": f"{S}^3 FP32 log-normal k^-3 GRF (8 decades, 10% negative, "
                                f"0.5% zeros), block {B}^3, eps {eps:g}, learned path: network "
                                f"H={args.hidden} trained on the device ({args.rho:g} sample), "
-                               f"BF16 matrix cores, per-block Lorenzo judge" +
-                               (", independent blocks" if ind else ", halo prediction"),
-                   "path": "learned BF16 (timed) vs plain FP32", "field_bytes": x.nbytes},
-        "compress_GBps": round(gb / (L["tc"] / K), 3),
-        "decompress_GBps": round(gb / (L["td"] / K), 3),
-        "compress_frac_hbm": round(gb / (L["tc"] / K) / HBM_PEAK_GBPS, 4),
-        "decompress_frac_hbm": round(gb / (L["td"] / K) / HBM_PEAK_GBPS, 4),
-        "phase_ms": {k: round(v, 4) for k, v in ph.items()},
-        "bound_ok_every_point": ok_l,
-        "training": {"wall_ms": round(train_wall_ms, 2), "ms_sample": round(rep["ms_sample"], 3),
-                     "ms_train": round(rep["ms_train"], 3),
-                     "ms_select": round(rep["ms_select"], 3), "n_train": rep["n_train"],
-                     "n_val": rep["n_val"], "chosen": rep["chosen"],
-                     "val_gain_bits": round((rep["val_score"][rep["chosen"]] -
-                                             rep["val_score"][0]) / 2.0 ** 32 /
-                                            max(rep["n_val"], 1), 4)},
+                               f"BF16 matrix cores, per-block Lorenzo judge, independent blocks, "
+                               f"Huffman-coded stream", "field_bytes": x.nbytes},
+        "compress_GBps": rec_l["compress_GBps"], "decompress_GBps": rec_l["decompress_GBps"],
+        "compress_frac_hbm": round(rec_l["compress_GBps"] / HBM_PEAK_GBPS, 4),
+        "decompress_frac_hbm": round(rec_l["decompress_GBps"] / HBM_PEAK_GBPS, 4),
+        "phase_ms": rec_l["phase_ms"], "bound_ok_every_point": rec_l["bound_ok_every_point"],
+        "max_rel_error": rec_l["max_rel_error"],
+        "ratio_stream": rec_l["ratio_stream"], "paper_CR_percent": rec_l["paper_CR_percent"],
+        "bits_per_value": rec_l.get("bits_per_value"), "n_raw": n_raw,
+        "network_block_frac": rec_l.get("network_block_frac"),
+        "pred_error_rms": rec_l["pred_error_rms"],
+        "training": train_record(rep, train_ms),
+        "end_to_end_with_training_GBps": round(gb / ((train_ms + ms_step) * 1e-3), 3),
         "roofline": roofline,
-        other[0]: other[1],
+        "roofline_decode": roof_d,
+        "copy_GBps_measured": copy_gbps,
+        "learned": rec_l,
     }
-    res.update(st_l)
-    if plain is not None:
-        res["plain"] = plain
-    if alt is not None:
-        res["learned_independent_blocks"] = alt
+    if args.only_timed:
+        print(json.dumps(res), flush=True)
+        return
+
+    # the learned path with halo prediction
+    lh, rep_h = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.hidden, precision=1)
+    H_ = run_path(ctx, xd, eps, B, lh, True, False, True, out, xh, K, args.warmup, pwrel, torch)
+    res["learned_halo"] = path_record("learned BF16 H=%d, judge, halo prediction, Huffman"
+                                      % args.hidden, H_, ctx, xd, xh, eps, gb, K, pwrel, torch)
+    log("learned halo path timed")
+
+    # the plain path: FP32 network of width 16 trained by the same device trainer
+    pm, rep_p = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.plain_hidden,
+                          precision=0, independent=True)
+    P = run_path(ctx, xd, eps, B, pm, False, True, True, out, xh, K, args.warmup, pwrel, torch)
+    res["plain"] = path_record("plain FP32 H=%d (trained on the device, no judge), independent "
+                               "blocks, Huffman" % args.plain_hidden, P, ctx, xd, xh, eps, gb, K,
+                               pwrel, torch)
+    res["plain"]["training"] = train_record(rep_p, rep_p["ms_sample"] + rep_p["ms_train"])
+    s16 = ctx.compress(xd, eps, B, pm, independent=True, out=out)
+    res["plain"]["pred_error_rms"] = pred_error_rms(ctx, pwrel.sections(s16)["codes"], pwrel)
+    Ph = run_path(ctx, xd, eps, B, pwrel.mlp_init(3, args.plain_hidden, 0.01, 1001), False,
+                  False, True, out, xh, K, args.warmup, pwrel, torch)
+    res["lorenzo_halo"] = path_record("untrained network (= one-layer Lorenzo), halo "
+                                      "prediction, Huffman", Ph, ctx, xd, xh, eps, gb, K, pwrel,
+                                      torch)
+    log("plain paths timed")
+    res["learned_vs_plain_size"] = round(rec_l["stream_bytes"] / res["plain"]["stream_bytes"], 4)
+    cpu_model = learned
+    del out, xh
+    torch.cuda.empty_cache()
+
+    # the FP64 volume (1024 x 1024 x 512, eps 1e-4) on the learned path
+    shp = (512, 1024, 1024)
+    x64 = synth.lognormal_grf_device(shp, seed=1004, decades=12, neg_frac=0.10, zero_frac=0.01,
+                                     dtype=torch.float64)
+    o64 = torch.empty(pwrel.compress_bound(shp, pwrel.F64, 8), dtype=torch.uint8, device="cuda")
+    h64 = torch.empty_like(x64)
+    t0 = time.perf_counter()
+    m64, rep64 = ctx.train(x64, 1e-4, 8, rho=0.002, seed=1004, hidden=args.hidden, precision=1,
+                           independent=True)
+    t64 = (time.perf_counter() - t0) * 1e3
+    F = run_path(ctx, x64, 1e-4, 8, m64, True, True, True, o64, h64, 3, 1, pwrel, torch)
+    res["fp64_volume"] = path_record("FP64 1024x1024x512 (12 decades, 10% negative, 1% zeros), "
+                                     "eps 1e-4, learned BF16, judge, independent blocks, Huffman",
+                                     F, ctx, x64, h64, 1e-4, x64.numel() * 8 / 1e9, 3, pwrel,
+                                     torch)
+    res["fp64_volume"]["training"] = train_record(rep64, t64)
+    log("FP64 volume timed")
+    del x64, o64, h64, F
+    torch.cuda.empty_cache()
+
+    # the 2-D 1800 x 3600 field (zonal bands + k^-2 noise), block 16^2, learned path
+    x2 = torch.from_numpy(synth.zonal_bands_2d((1800, 3600), seed=1002)).cuda()
+    o2 = torch.empty(pwrel.compress_bound(x2.shape, pwrel.F32, 16), dtype=torch.uint8,
+                     device="cuda")
+    h2 = torch.empty_like(x2)
+    m2, rep2 = ctx.train(x2, eps, 16, rho=args.rho, seed=1002, hidden=args.hidden, precision=1,
+                         independent=True)
+    Z = run_path(ctx, x2, eps, 16, m2, True, True, True, o2, h2, K, args.warmup, pwrel, torch)
+    res["zonal_2d"] = path_record("2-D 1800x3600 zonal bands + k^-2 noise, block 16^2, learned "
+                                  "BF16, judge, independent blocks, Huffman", Z, ctx, x2, h2, eps,
+                                  x2.numel() * 4 / 1e9, K, pwrel, torch)
+    Z0 = run_path(ctx, x2, eps, 16, pwrel.mlp_init(2, args.plain_hidden, 0.01, 1002), False, True,
+                  True, o2, h2, K, args.warmup, pwrel, torch)
+    res["zonal_2d"]["lorenzo_ratio_stream"] = stream_stats(ctx, Z0["stream"], x2.numel() * 4,
+                                                           pwrel)["ratio_stream"]
+    log("2-D field timed")
+
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(x, eps, B, learned)
+        log("cpu baseline (oracle) ...")
+        nproc = min(len(os.sched_getaffinity(0)), 16)
+        res["cpu_baseline"] = cpu_baseline(x, eps, B, cpu_model, nproc)
     print(json.dumps(res), flush=True)
 
 
