@@ -492,47 +492,70 @@ __global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *c
 // around the zero-error code, global atomics outside it, one flush per
 // workgroup.
 // ---------------------------------------------------------------------------
-constexpr int kHistWin = 32768;  // 128 KiB of LDS
+constexpr int kHistWin = 32768;  // half the code space: 128 KiB of LDS
 
-// Per workgroup (1024 threads, one or two per CU): a histogram of kHistWin
-// codes around the zero-error code in LDS (128 KiB), global atomics outside it
-// (the rare large errors), one flush of the non-zero bins at the end.  Each
-// thread counts a contiguous run of codes (16-byte loads), so the lanes of an
-// atomic instruction mostly address different bins.
+// Per workgroup (1024 threads, one or two per CU) over its share of the codes:
+// a histogram of half the code space at a time in LDS (128 KiB): first the
+// central half (errors within +-2^14), then, only if the workgroup met any
+// code outside it, the outer half; each pass ends with one flush of the
+// non-zero bins.  No code goes to a global atomic on its own, however wide
+// the errors.  Each thread counts a contiguous run of codes (16-byte loads),
+// so the lanes of an atomic instruction mostly address different bins.
 __global__ void __launch_bounds__(1024) k_hist(const uint16_t *__restrict__ codes, long long n,
                                                unsigned long long *hist)
 {
     extern __shared__ unsigned win[];
-    for (int i = threadIdx.x; i < kHistWin; i += blockDim.x)
-        win[i] = 0u;
-    __syncthreads();
-    const int lo = kR - kHistWin / 2;
-    auto add = [&](unsigned code) {
-        const int k = (int)code - lo;
-        if (k >= 0 && k < kHistWin)
-            atomicAdd(&win[k], 1u);
-        else
-            atomicAdd(&hist[code], 1ULL);
-    };
+    __shared__ int s_outer;
     const long long nth = (long long)gridDim.x * blockDim.x;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool al = (reinterpret_cast<uintptr_t>(codes) & 15) == 0;
     const long long n8 = al ? n / 8 : 0;
-    for (long long i = t; i < n8; i += nth) {
-        const uint4 v = reinterpret_cast<const uint4 *>(codes)[i];
-        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    constexpr unsigned lo = kR - kHistWin / 2, hi = kR + kHistWin / 2;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = threadIdx.x; i < kHistWin; i += blockDim.x)
+            win[i] = 0u;
+        if (threadIdx.x == 0 && pass == 0)
+            s_outer = 0;
+        __syncthreads();
+        bool outer = false;
+        // bin of a code in this pass's half, or -1
+        auto bin = [&](unsigned code) -> int {
+            const bool central = code >= lo && code < hi;
+            if (pass == 0) {
+                outer |= !central;
+                return central ? (int)(code - lo) : -1;
+            }
+            return central ? -1 : (int)(code < lo ? code : code - kHistWin);
+        };
+        auto add = [&](unsigned code) {
+            const int k = bin(code);
+            if (k >= 0)
+                atomicAdd(&win[k], 1u);
+        };
+        for (long long i = t; i < n8; i += nth) {
+            const uint4 v = reinterpret_cast<const uint4 *>(codes)[i];
+            const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            add(w[k] & 0xFFFFu);
-            add(w[k] >> 16);
+            for (int k = 0; k < 4; ++k) {
+                add(w[k] & 0xFFFFu);
+                add(w[k] >> 16);
+            }
         }
+        for (long long i = 8 * n8 + t; i < n; i += nth)
+            add(codes[i]);
+        if (pass == 0 && outer)
+            s_outer = 1;
+        __syncthreads();
+        for (int i = threadIdx.x; i < kHistWin; i += blockDim.x)
+            if (win[i]) {
+                const unsigned code = pass == 0 ? lo + i : (i < (int)lo ? i : i + kHistWin);
+                atomicAdd(&hist[code], (unsigned long long)win[i]);
+            }
+        const bool again = s_outer != 0;
+        __syncthreads();
+        if (!again)
+            break;  // uniform: every thread read the same shared flag
     }
-    for (long long i = 8 * n8 + t; i < n; i += nth)
-        add(codes[i]);
-    __syncthreads();
-    for (int i = threadIdx.x; i < kHistWin; i += blockDim.x)
-        if (win[i])
-            atomicAdd(&hist[lo + i], (unsigned long long)win[i]);
 }
 
 __global__ void k_zero_u64(unsigned long long *p, long long n)
