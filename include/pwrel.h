@@ -244,6 +244,48 @@ int pwrel_compress_noalloc(pwrel_ctx *ctx, const void *d_field, const uint64_t *
 #define PWREL_NOALLOC_MAX_BLOCKS (1ull << 20)
 
 /*
+ * pwrel_compress_batch: n FP32 fields, each compressed into its own stream
+ * exactly as pwrel_compress would (Algorithm 1 per field: the field's own
+ * statistics and constants, Eq. 8-12, its codes, counts, raw values and
+ * header; byte-identical streams), by one fixed sequence of about ten
+ * launches whatever n and the shapes: one persistent compression launch per
+ * class over every tile of its fields, and one launch per per-field stage
+ * over a field table.  Classes: 3-D fields with block 8 and 2-D fields with
+ * block 16 (the compiled batched tile shapes).
+ *   fields[i]       (host) d_field (device, C order), dims/ndim (2 or 3),
+ *                   reserved = 0, d_out (device, out_capacity bytes; at
+ *                   least the header + codes part, else PWREL_ENOSPC)
+ *   block_size[3]   (host, or NULL) block edge by ndim - 1; 0 = default
+ *                   (16 for 2-D, 8 for 3-D); others give PWREL_EINVAL
+ *   models[3]       (host, or NULL) network by ndim - 1, needed for every
+ *                   dimensionality present when opt->use_net; copied
+ *   opt             as pwrel_compress; entropy must be 0 (16-bit codes)
+ *   d_out_sizes[n]  (device) each stream's length, 0 where that field
+ *                   failed; the field's status is in its stream header
+ * Ordered on `stream`; no synchronisation and no device allocation once the
+ * request was seen.  The context keeps the field table of the last request
+ * (fields, bound, blocks, models, options, d_out_sizes): a call that repeats
+ * it launches kernels only, so it may run under HIP graph capture and be
+ * replayed; a new request builds the table (host work, allocation on growth,
+ * one asynchronous copy) and is refused with PWREL_EINVAL under capture.
+ * Calls sharing a context run in stream order; concurrent calls on one
+ * context from different streams race on its workspace.
+ */
+typedef struct {
+    const void *d_field;
+    uint64_t dims[3];
+    int32_t ndim;
+    int32_t reserved;
+    void *d_out;
+    uint64_t out_capacity;
+} pwrel_field_desc;
+
+int pwrel_compress_batch(pwrel_ctx *ctx, int n, const pwrel_field_desc *fields, int dtype,
+                         double rel_error_bound, const int *block_size,
+                         const pwrel_mlp *const *models, const pwrel_options *opt,
+                         uint64_t *d_out_sizes, void *stream);
+
+/*
  * A trained network kept for later fields (Sec. 5: the model trained in the
  * training phase is retained and used to compress; Sec. 4.3).  pwrel_mlp is a
  * plain value owned by the caller, so nothing is allocated or freed here.

@@ -9,7 +9,8 @@ OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pwrel_codec.hip", "pwrel_compress.hip",
                                                    "pwrel_decode.hip", "pwrel_train.hip",
                                                    "pwrel_api.hip", "pwrel_noalloc.hip",
-                                                   "pwrel_huffman.hip", "pwrel_decode_lanes.hip")]
+                                                   "pwrel_huffman.hip", "pwrel_decode_lanes.hip",
+                                                   "pwrel_batch.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("pwrel_device.h", "pwrel_internal.h",
                                                    "pwrel_kernels.h", "pwrel_bf16.h",
                                                    "pwrel_train.h", "pwrel_huffman.h",

@@ -44,6 +44,7 @@ struct pwrel_ctx {
     int order_pen = -1;  // the cached order is of pencils (1) or of blocks (0)
     unsigned epoch = 0;
     void *hdr = nullptr;  // header of pwrel_compress_raw (PWREL_HEADER_BYTES)
+    pwrel::BatchState *batch = nullptr;  // pwrel_compress_batch's workspace and table
 };
 
 namespace {
@@ -367,6 +368,7 @@ void pwrel_destroy(pwrel_ctx *ctx)
     if (ctx->ev_ok)
         for (hipEvent_t &e : ctx->ev)
             (void)hipEventDestroy(e);
+    batch_release(ctx->batch);
     delete ctx;
 }
 
@@ -422,6 +424,8 @@ int api_fail(pwrel_ctx *ctx, int code, const char *msg) { return fail(ctx, code,
 int api_status(pwrel_ctx *ctx, int device_status) { return finish_status(ctx, device_status); }
 int api_device(const pwrel_ctx *ctx) { return ctx->device; }
 int api_num_cus(const pwrel_ctx *ctx) { return ctx->num_cus; }
+const long long *api_qtab(const pwrel_ctx *ctx) { return ctx->ws.qtab; }
+BatchState *&api_batch_state(pwrel_ctx *ctx) { return ctx->batch; }
 
 // The compression launches (Algorithm 1): reset, statistics, constants, grid
 // values and bound checks (FP32), prediction / quantisation / judge, scan,

@@ -113,13 +113,14 @@ __device__ __forceinline__ void classify32(float v, Acc32 &a)
     a.mx = normal && m > a.mx ? m : a.mx;
 }
 
+// part `part` of nparts of a field's statistics (a workgroup's share) into *out
 template <typename T, typename V, int VW>
-__global__ void __launch_bounds__(256) k_stats(const T *__restrict__ x, long long n,
-                                               DevStats *parts)
+__device__ __forceinline__ void stats_part(const T *__restrict__ x, long long n, int part,
+                                           int nparts, DevStats *out)
 {
     Acc a{~0ULL, 0ULL, 0ULL, 0ULL, 0ULL};
-    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long nthr = (long long)gridDim.x * blockDim.x;
+    const long long tid = (long long)part * blockDim.x + threadIdx.x;
+    const long long nthr = (long long)nparts * blockDim.x;
     const long long nv = n / VW;
     const V *xv = reinterpret_cast<const V *>(x);
     if constexpr (std::is_same<T, float>::value) {
@@ -158,8 +159,15 @@ __global__ void __launch_bounds__(256) k_stats(const T *__restrict__ x, long lon
         r.n_zero = a.nz;
         r.n_neg = a.nn;
         r.n_nonfinite = a.nf;
-        parts[blockIdx.x] = r;
+        *out = r;
     }
+}
+
+template <typename T, typename V, int VW>
+__global__ void __launch_bounds__(256) k_stats(const T *__restrict__ x, long long n,
+                                               DevStats *parts)
+{
+    stats_part<T, V, VW>(x, n, blockIdx.x, gridDim.x, parts + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,8 +188,8 @@ __device__ __forceinline__ double from_abs_bits<double>(unsigned long long b)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_consts(const DevStats *parts, int nparts, double eps,
-                                                DevConsts *c, int *status)
+__device__ __forceinline__ void consts_reduce(const DevStats *parts, int nparts, double eps,
+                                              DevConsts *c, int *status)
 {
     Acc a{~0ULL, 0ULL, 0ULL, 0ULL, 0ULL};
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
@@ -265,6 +273,13 @@ __global__ void __launch_bounds__(256) k_consts(const DevStats *parts, int npart
     set_status(status, err);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_consts(const DevStats *parts, int nparts, double eps,
+                                                DevConsts *c, int *status)
+{
+    consts_reduce<T>(parts, nparts, eps, c, status);
+}
+
 // ---------------------------------------------------------------------------
 // a3 alone: grid value of every point (inspection entry point).
 // ---------------------------------------------------------------------------
@@ -298,15 +313,16 @@ __device__ __forceinline__ unsigned wave_incl_scan(unsigned v)
     return v;
 }
 
+// chunk `chunk` (kScanChunk counts) of an exclusive scan: offsets relative to
+// the chunk, the chunk's total into partials[chunk]
 template <typename C>
-__global__ void __launch_bounds__(256) k_scan_local(const C *__restrict__ counts,
-                                                    long long nb,
-                                                    unsigned long long *__restrict__ offs,
-                                                    unsigned long long *__restrict__ partials)
+__device__ __forceinline__ void scan_chunk(const C *__restrict__ counts, long long nb, long long chunk,
+                                           unsigned long long *__restrict__ offs,
+                                           unsigned long long *__restrict__ partials)
 {
     __shared__ unsigned wsum[4];
     constexpr int PER = kScanChunk / 256;
-    const long long base = (long long)blockIdx.x * kScanChunk + threadIdx.x * PER;
+    const long long base = chunk * kScanChunk + threadIdx.x * PER;
     unsigned v[PER];
     unsigned s = 0;
 #pragma unroll
@@ -330,12 +346,20 @@ __global__ void __launch_bounds__(256) k_scan_local(const C *__restrict__ counts
         run += v[q];
     }
     if (threadIdx.x == 255)
-        partials[blockIdx.x] = (unsigned long long)(wbase + incl);
+        partials[chunk] = (unsigned long long)(wbase + incl);
 }
 
-__global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long *partials,
-                                                        long long np,
-                                                        unsigned long long *total)
+template <typename C>
+__global__ void __launch_bounds__(256) k_scan_local(const C *__restrict__ counts,
+                                                    long long nb,
+                                                    unsigned long long *__restrict__ offs,
+                                                    unsigned long long *__restrict__ partials)
+{
+    scan_chunk<C>(counts, nb, blockIdx.x, offs, partials);
+}
+
+__device__ __forceinline__ void scan_partials(unsigned long long *partials, long long np,
+                                              unsigned long long *total)
 {
     __shared__ unsigned long long sh[1024];
     unsigned long long carry = 0;
@@ -360,31 +384,35 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long *part
         *total = carry;
 }
 
+__global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long *partials,
+                                                        long long np,
+                                                        unsigned long long *total)
+{
+    scan_partials(partials, np, total);
+}
+
 // ---------------------------------------------------------------------------
 // a7: raw values of balance points in stream order (one wave per block, wave
 // ballot + popcount for the in-block rank).
 // ---------------------------------------------------------------------------
 
 
+// the raw values of block b's balance points (one wave)
 template <typename T>
-__global__ void __launch_bounds__(256) k_scatter(const T *__restrict__ x, GeoArgs g,
-                                                 const uint16_t *__restrict__ codes,
-                                                 const uint32_t *__restrict__ counts,
-                                                 const unsigned long long *offs,
-                                                 const unsigned long long *partials,
-                                                 T *__restrict__ raw, unsigned long long raw_cap,
-                                                 int *status)
+__device__ __forceinline__ void scatter_block(const T *__restrict__ x, const GeoArgs &g,
+                                              const uint16_t *__restrict__ codes,
+                                              const uint32_t *__restrict__ counts,
+                                              const unsigned long long *offs,
+                                              const unsigned long long *partials,
+                                              T *__restrict__ raw, unsigned long long raw_cap,
+                                              int *status, long long b)
 {
-    if (*status != kOk)
-        return;  // wave-level work only: a per-thread exit is safe
     const int lane = threadIdx.x & 63;
-    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
     const unsigned long long below = (1ULL << lane) - 1ULL;
-    for (long long b = wave; b < g.nblocks; b += nwaves) {
+    {
         const unsigned cnt = counts[b];
         if (cnt == 0)
-            continue;
+            return;
         const long long bx = b % g.nb[2], by = (b / g.nb[2]) % g.nb[1],
                         bz = b / (g.nb[1] * g.nb[2]);
         const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
@@ -410,33 +438,39 @@ __global__ void __launch_bounds__(256) k_scatter(const T *__restrict__ x, GeoArg
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter(const T *__restrict__ x, GeoArgs g,
+                                                 const uint16_t *__restrict__ codes,
+                                                 const uint32_t *__restrict__ counts,
+                                                 const unsigned long long *offs,
+                                                 const unsigned long long *partials,
+                                                 T *__restrict__ raw, unsigned long long raw_cap,
+                                                 int *status)
+{
+    if (*status != kOk)
+        return;  // wave-level work only: a per-thread exit is safe
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long b = wave; b < g.nblocks; b += nwaves)
+        scatter_block<T>(x, g, codes, counts, offs, partials, raw, raw_cap, status, b);
+}
+
 // ---------------------------------------------------------------------------
 // stream header (one thread)
 // ---------------------------------------------------------------------------
-struct HeaderArgs {
-    int dtype, ndim, block, flags;
-    unsigned long long dims[3];
-    unsigned long long n, nblocks;
-    unsigned long long off_model, off_bflags, off_counts, off_codes, off_raw;
-    unsigned long long capacity;
-    int raw_size;
-    unsigned long long pad_lo[kHeaderGaps], pad_hi[kHeaderGaps];  // gaps between sections
-    // Huffman sections (0 without them)
-    unsigned long long off_huff, off_sizes, off_bits, n_bits;
-    unsigned n_sym, size_bytes;
-};
+
 
 // Writes the header and zeroes every alignment gap, so that equal inputs give
 // byte-identical streams.
-__global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *cp,
-                                                const unsigned long long *n_raw, int *status,
-                                                pwrel_header *out)
+__device__ __forceinline__ void write_header(const HeaderArgs &h, const DevConsts *cp,
+                                             const unsigned long long *n_raw, int *status,
+                                             pwrel_header *out, unsigned long long *out_size)
 {
     unsigned char *bytes = reinterpret_cast<unsigned char *>(out);
     for (int r = 0; r < kHeaderGaps; ++r)
         for (unsigned long long i = h.pad_lo[r] + threadIdx.x; i < h.pad_hi[r]; i += blockDim.x)
             bytes[i] = 0;
-    if (threadIdx.x != 0 || blockIdx.x != 0)
+    if (threadIdx.x != 0)
         return;
     pwrel_header o{};
     const DevConsts c = *cp;
@@ -485,6 +519,15 @@ __global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *c
         st = kENoSpc;
     o.status = st;
     *out = o;
+    if (out_size)
+        *out_size = st == kOk ? o.total_size : 0ULL;
+}
+
+__global__ void __launch_bounds__(256) k_header(HeaderArgs h, const DevConsts *cp,
+                                                const unsigned long long *n_raw, int *status,
+                                                pwrel_header *out)
+{
+    write_header(h, cp, n_raw, status, out, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -748,9 +791,8 @@ hipError_t launch_scatter(const void *x, const Geom &g, const uint16_t *codes,
     return hipGetLastError();
 }
 
-hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspace &ws,
-                         void *d_header, uint64_t capacity, bool stream_gaps, hipStream_t s,
-                         const HuffLayout *hl)
+HeaderArgs make_header_args(const Geom &g, int flags, const uint64_t *offs, uint64_t capacity,
+                            bool stream_gaps, const HuffLayout *hl)
 {
     HeaderArgs h{};
     h.dtype = g.dtype;
@@ -802,6 +844,14 @@ hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspa
     }
     if (!stream_gaps)
         h.pad_hi[0] = PWREL_HEADER_BYTES;
+    return h;
+}
+
+hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspace &ws,
+                         void *d_header, uint64_t capacity, bool stream_gaps, hipStream_t s,
+                         const HuffLayout *hl)
+{
+    const HeaderArgs h = make_header_args(g, flags, offs, capacity, stream_gaps, hl);
     hipLaunchKernelGGL(k_header, dim3(1), dim3(256), 0, s, h, ws.consts, ws.n_raw, ws.status,
                        (pwrel_header *)d_header);
     return hipGetLastError();
@@ -843,6 +893,158 @@ hipError_t launch_detmath(const double *x, double *l2, double *e2, uint64_t n, h
         return hipSuccess;
     hipLaunchKernelGGL(k_detmath, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, l2, e2,
                        (unsigned long long)n);
+    return hipGetLastError();
+}
+
+}  // namespace pwrel
+
+// ===========================================================================
+// batched compression: the per-field stages over a table of fields, one
+// launch each whatever the number of fields (workgroups find their field by
+// a binary search of the fields' first parts, chunks or blocks)
+// ===========================================================================
+namespace pwrel {
+
+template <typename K>
+__device__ __forceinline__ int batch_field_of(const BatchField *f, int nf, long long k, K key)
+{
+    int lo = 0, hi = nf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (key(f[mid]) <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_batch_reset(const BatchField *f, int nf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nf) {
+        *f[i].status = kOk;
+        *f[i].n_raw = 0ULL;
+    }
+}
+
+// statistics: workgroup k = part k - part0 of its field
+template <typename T, typename V, int VW>
+__global__ void __launch_bounds__(256) k_batch_stats(const BatchField *f, int nf,
+                                                     DevStats *records)
+{
+    const long long k = blockIdx.x;
+    const int i = batch_field_of(f, nf, k, [](const BatchField &b) { return b.part0; });
+    const BatchField &b = f[i];
+    const T *x = static_cast<const T *>(b.x);
+    if (b.vec)
+        stats_part<T, V, VW>(x, b.N, (int)(k - b.part0), (int)b.nparts, records + k);
+    else
+        stats_part<T, T, 1>(x, b.N, (int)(k - b.part0), (int)b.nparts, records + k);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_consts(const BatchField *f,
+                                                      const DevStats *records)
+{
+    const BatchField &b = f[blockIdx.x];
+    consts_reduce<T>(records + b.part0, (int)b.nparts, b.eps, b.consts, b.status);
+}
+
+hipError_t launch_batch_front(const BatchField *d_fields, int nf, int dtype, long long nparts,
+                              DevStats *records, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3((nf + 255) / 256), dim3(256), 0, s, d_fields, nf);
+    if (dtype == PWREL_F32) {
+        hipLaunchKernelGGL((k_batch_stats<float, float4, 4>), dim3((unsigned)nparts), dim3(256),
+                           0, s, d_fields, nf, records);
+        hipLaunchKernelGGL(k_batch_consts<float>, dim3(nf), dim3(256), 0, s, d_fields, records);
+    } else {
+        hipLaunchKernelGGL((k_batch_stats<double, double2, 2>), dim3((unsigned)nparts),
+                           dim3(256), 0, s, d_fields, nf, records);
+        hipLaunchKernelGGL(k_batch_consts<double>, dim3(nf), dim3(256), 0, s, d_fields, records);
+    }
+    return hipGetLastError();
+}
+
+// scan: workgroup k = chunk k - chunk0 of its field; offsets and chunk
+// partials at the field's own base (blk0, chunk0)
+__global__ void __launch_bounds__(256) k_batch_scan_local(const BatchField *f, int nf,
+                                                          unsigned long long *offs,
+                                                          unsigned long long *partials)
+{
+    const long long k = blockIdx.x;
+    const int i = batch_field_of(f, nf, k, [](const BatchField &b) { return b.chunk0; });
+    const BatchField &b = f[i];
+    scan_chunk<uint32_t>(b.counts, b.g.nblocks, k - b.chunk0, offs + b.blk0,
+                         partials + b.chunk0);
+}
+
+__global__ void __launch_bounds__(1024) k_batch_scan_partials(const BatchField *f,
+                                                              unsigned long long *partials)
+{
+    const BatchField &b = f[blockIdx.x];
+    scan_partials(partials + b.chunk0, b.nchunks, b.n_raw);
+}
+
+// raw values: one wave per block of the batch's block numbering
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_scatter(const BatchField *f, int nf,
+                                                       long long nblocks,
+                                                       const unsigned long long *offs,
+                                                       const unsigned long long *partials)
+{
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long k = wave; k < nblocks; k += nwaves) {
+        const int i = batch_field_of(f, nf, k, [](const BatchField &b) { return b.blk0; });
+        const BatchField &b = f[i];
+        if (*b.status != kOk)
+            continue;  // wave-uniform
+        scatter_block<T>(static_cast<const T *>(b.x), b.g, b.codes, b.counts, offs + b.blk0,
+                         partials + b.chunk0, static_cast<T *>(b.raw), b.raw_cap, b.status,
+                         k - b.blk0);
+    }
+}
+
+// the model section of each field that carries one: the network of the
+// field's dimensionality (models[ndim - 1], device)
+__global__ void __launch_bounds__(256) k_batch_model(const BatchField *f, const pwrel_mlp *models)
+{
+    const BatchField &b = f[blockIdx.x];
+    if (!b.model_dst)
+        return;
+    const unsigned *src = reinterpret_cast<const unsigned *>(models + (b.h.ndim - 1));
+    unsigned *dst = static_cast<unsigned *>(b.model_dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(pwrel_mlp) / 4); i += blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(256) k_batch_header(const BatchField *f)
+{
+    const BatchField &b = f[blockIdx.x];
+    write_header(b.h, b.consts, b.n_raw, b.status, static_cast<pwrel_header *>(b.header),
+                 b.out_size);
+}
+
+hipError_t launch_batch_back(const BatchField *d_fields, int nf, int dtype, long long nchunks,
+                             long long nblocks, unsigned long long *offsets,
+                             unsigned long long *partials, const pwrel_mlp *models,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_scan_local, dim3((unsigned)nchunks), dim3(256), 0, s, d_fields,
+                       nf, offsets, partials);
+    hipLaunchKernelGGL(k_batch_scan_partials, dim3(nf), dim3(1024), 0, s, d_fields, partials);
+    const unsigned grid = grid_for(nblocks, 4, 16384);
+    if (dtype == PWREL_F32)
+        hipLaunchKernelGGL(k_batch_scatter<float>, dim3(grid), dim3(256), 0, s, d_fields, nf,
+                           nblocks, offsets, partials);
+    else
+        hipLaunchKernelGGL(k_batch_scatter<double>, dim3(grid), dim3(256), 0, s, d_fields, nf,
+                           nblocks, offsets, partials);
+    if (models)
+        hipLaunchKernelGGL(k_batch_model, dim3(nf), dim3(256), 0, s, d_fields, models);
+    hipLaunchKernelGGL(k_batch_header, dim3(nf), dim3(256), 0, s, d_fields);
     return hipGetLastError();
 }
 

@@ -26,6 +26,11 @@
 namespace pwrel {
 
 struct CompressArgs {
+    // batch: nfields fields (fields[], ordered by tile0; every field of the
+    // same dimensionality, dtype, block and tile), ntiles over all of them;
+    // else nfields = 0 and the single field below
+    const FieldDesc *fields;
+    int nfields;
     const void *x;
     const int *pfield;
     long long n[3];
@@ -184,7 +189,7 @@ __device__ __forceinline__ void wait_vmem()
 // Occupancy bound (measured at 512^3): six waves per SIMD for the FP32 and
 // Lorenzo variants, four for the BF16 one; the registers the bound takes away
 // cost a few spills, far less than the latency the extra waves hide.
-template <typename T, int D, int BB, int HP, bool FROM_P, int PREC>
+template <typename T, int D, int BB, int HP, bool FROM_P, int PREC, bool BATCH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 4 : 6)))
 k_compress(CompressArgs a)
 {
@@ -251,13 +256,65 @@ k_compress(CompressArgs a)
             jsum[i] = 0ULL;
     }
     if (tid == 0)
-        s_status = *a.status;
+        s_status = BATCH ? kOk : *a.status;
     __syncthreads();
     if (s_status != kOk)  // uniform: every thread reads the same shared value
         return;
-    const DevConsts c = *a.consts;
-    const long long n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-    const bool w32 = c.w32 != 0;
+    // the field of a tile (batch: binary search of the fields' first tiles)
+    struct Fld {
+        const V *src;
+        long long n[3], nb[3], nt[3], tile0;
+        uint16_t *codes;
+        uint32_t *counts;
+        uint8_t *bflags;
+        const DevConsts *consts;
+        int *status;
+    };
+    auto field_of = [&](long long t) {
+        Fld F;
+        if constexpr (!BATCH) {
+            F.src = FROM_P ? reinterpret_cast<const V *>(a.pfield)
+                           : reinterpret_cast<const V *>(a.x);
+            for (int d = 0; d < 3; ++d) {
+                F.n[d] = a.n[d];
+                F.nb[d] = a.nb[d];
+                F.nt[d] = a.nt[d];
+            }
+            F.tile0 = 0;
+            F.codes = a.codes;
+            F.counts = a.counts;
+            F.bflags = a.bflags;
+            F.consts = a.consts;
+            F.status = a.status;
+        } else {
+            int lo = 0, hi = a.nfields - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.fields[mid].tile0 <= t)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const FieldDesc &d = a.fields[lo];
+            F.src = FROM_P ? reinterpret_cast<const V *>(d.pfield) : reinterpret_cast<const V *>(d.x);
+            for (int k = 0; k < 3; ++k) {
+                F.n[k] = d.n[k];
+                F.nb[k] = d.nb[k];
+                F.nt[k] = d.nt[k];
+            }
+            F.tile0 = d.tile0;
+            F.codes = d.codes;
+            F.counts = d.counts;
+            F.bflags = d.bflags;
+            F.consts = d.consts;
+            F.status = d.status;
+        }
+        return F;
+    };
+    Fld F = field_of(0);
+    DevConsts c = *F.consts;
+    long long n0 = F.n[0], n1 = F.n[1], n2 = F.n[2];
+    bool w32 = c.w32 != 0;
 
     // LDS offsets of the neighbours, o = 1 .. 2^D-1
     int noff[8];
@@ -272,7 +329,7 @@ k_compress(CompressArgs a)
     const long long tend = std::min(a.ntiles, (long long)(xcd + 1) * chunk);
 
     // grid value (and bound check) of one point from its value
-    const V *src = FROM_P ? reinterpret_cast<const V *>(a.pfield) : reinterpret_cast<const V *>(a.x);
+    const V *src = F.src;
     auto point = [&](V v, bool verify, int &p, unsigned char &ok) {
         if constexpr (FROM_P) {
             const int e = (int)v;
@@ -292,26 +349,30 @@ k_compress(CompressArgs a)
     // origin, the linear index of entry (0, 0, 0), and the entry ranges that
     // lie inside the field.
     struct TileRef {
-        long long z0, y0, x0, base;
+        long long z0, y0, x0, base, n1, n2;
         int lo0, hi0, lo1, hi1, lo2, hi2;
     };
-    auto tile_ref = [&](long long t) {
+    // tile t (of the launch) of field G
+    auto tile_ref = [&](const Fld &G, long long t) {
         TileRef r;
-        r.z0 = t / (a.nt[1] * a.nt[2]) * T0;
-        r.y0 = (t / a.nt[2]) % a.nt[1] * T1;
-        r.x0 = t % a.nt[2] * T2;
+        const long long lt = t - G.tile0;
+        r.z0 = lt / (G.nt[1] * G.nt[2]) * T0;
+        r.y0 = (lt / G.nt[2]) % G.nt[1] * T1;
+        r.x0 = lt % G.nt[2] * T2;
         r.lo0 = (h0 && r.z0 == 0) ? 1 : 0;
         r.lo1 = (h1 && r.y0 == 0) ? 1 : 0;
         r.lo2 = r.x0 == 0 ? 1 : 0;
-        r.hi0 = (int)std::min((long long)E0, n0 - r.z0 + h0);
-        r.hi1 = (int)std::min((long long)E1, n1 - r.y0 + h1);
-        r.hi2 = (int)std::min((long long)E2, n2 - r.x0 + h2);
-        r.base = ((r.z0 - h0) * n1 + (r.y0 - h1)) * n2 + (r.x0 - h2);
+        r.hi0 = (int)std::min((long long)E0, G.n[0] - r.z0 + h0);
+        r.hi1 = (int)std::min((long long)E1, G.n[1] - r.y0 + h1);
+        r.hi2 = (int)std::min((long long)E2, G.n[2] - r.x0 + h2);
+        r.n1 = G.n[1];
+        r.n2 = G.n[2];
+        r.base = ((r.z0 - h0) * r.n1 + (r.y0 - h1)) * r.n2 + (r.x0 - h2);
         return r;
     };
     auto row_base = [&](const TileRef &r, int row) {
         const int e0 = row / E1, e1 = row - (row / E1) * E1;
-        return r.base + ((long long)e0 * n1 + e1) * n2;
+        return r.base + ((long long)e0 * r.n1 + e1) * r.n2;
     };
     auto row_in = [&](const TileRef &r, int row) {
         const int e0 = row / E1, e1 = row - (row / E1) * E1;
@@ -326,10 +387,11 @@ k_compress(CompressArgs a)
     constexpr bool PIPE = CT && (FROM_P || std::is_same<T, float>::value);
     constexpr int NEX = CT ? (S::T0 + h0) * (S::T1 + h1) * (S::T2 + h2) : 1;
     __shared__ unsigned xs[PIPE ? NEX : 1];
-    const unsigned *src32 = reinterpret_cast<const unsigned *>(src);
     const int lane = tid & 63, wave = tid >> 6;
     auto stage = [&](long long t) {
-        const TileRef r = tile_ref(t);
+        const Fld G = BATCH ? field_of(t) : F;
+        const unsigned *src32 = reinterpret_cast<const unsigned *>(G.src);
+        const TileRef r = tile_ref(G, t);
         for (int row = wave; row < nrows; row += NT / 64) {
             if (!row_in(r, row))
                 continue;  // uniform across the wave
@@ -358,7 +420,21 @@ k_compress(CompressArgs a)
     }
 
     for (; t < tend; t += nslot) {
-        const TileRef r = tile_ref(t);
+        if (BATCH && !(t >= F.tile0 && t < F.tile0 + F.nt[0] * F.nt[1] * F.nt[2])) {
+            // a tile of another field: its geometry, outputs and constants
+            if (err != kOk) {
+                set_status(F.status, err);
+                err = kOk;
+            }
+            F = field_of(t);
+            c = *F.consts;
+            n0 = F.n[0];
+            n1 = F.n[1];
+            n2 = F.n[2];
+            w32 = c.w32 != 0;
+            src = F.src;
+        }
+        const TileRef r = tile_ref(F, t);
         const long long g0z = r.z0, g0y = r.y0, g0x = r.x0;
         if constexpr (PIPE)
             wait_vmem();  // this wave's copies have landed
@@ -396,8 +472,8 @@ k_compress(CompressArgs a)
         for (int bt = tid; bt < nbt; bt += NT) {
             const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
             const long long bz = bz0 + btz, by = by0 + bty, bx = bx0 + btx;
-            if (bz < a.nb[0] && by < a.nb[1] && bx < a.nb[2]) {
-                const BlockGeo bg = block_geo3(bz, by, bx, a.n, bd0, bd1, bd2);
+            if (bz < F.nb[0] && by < F.nb[1] && bx < F.nb[2]) {
+                const BlockGeo bg = block_geo3(bz, by, bx, F.n, bd0, bd1, bd2);
                 bst[bt] = bg.start;
                 bext[bt] = (unsigned)bg.ex | ((unsigned)bg.ey << 16);
             }
@@ -531,7 +607,7 @@ k_compress(CompressArgs a)
                 }
                 if (!inside)
                     continue;
-                a.codes[pos0 + i] = code;
+                F.codes[pos0 + i] = code;
                 nzero += code == 0 ? 1u : 0u;
                 if (a.judge) {
                     if constexpr (PREC != 1)
@@ -644,7 +720,7 @@ k_compress(CompressArgs a)
                 const long long pos = bst[bt] + (long long)((lz * (int)(bext[bt] >> 16) + ly) *
                                                                 (int)(bext[bt] & 0xffffu) +
                                                             lx);
-                a.codes[pos] = (uint16_t)(jb[(cz * T1 + cy) * T2 + cx] >> 16);
+                F.codes[pos] = (uint16_t)(jb[(cz * T1 + cy) * T2 + cx] >> 16);
             }
             for (int bt = tid; bt < nbt; bt += NT) {
                 const bool use_n = jsum[2 * bt] > jsum[2 * bt + 1];
@@ -657,11 +733,11 @@ k_compress(CompressArgs a)
         for (int bt = tid; bt < nbt; bt += NT) {
             const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
             const long long bz = bz0 + btz, by = by0 + bty, bx = bx0 + btx;
-            if (bz < a.nb[0] && by < a.nb[1] && bx < a.nb[2]) {
-                const long long b = (bz * a.nb[1] + by) * a.nb[2] + bx;
-                a.counts[b] = cnt[bt];
-                if (a.bflags)
-                    a.bflags[b] = a.judge ? (jsum[2 * bt] > jsum[2 * bt + 1] ? 1 : 0)
+            if (bz < F.nb[0] && by < F.nb[1] && bx < F.nb[2]) {
+                const long long b = (bz * F.nb[1] + by) * F.nb[2] + bx;
+                F.counts[b] = cnt[bt];
+                if (F.bflags)
+                    F.bflags[b] = a.judge ? (jsum[2 * bt] > jsum[2 * bt + 1] ? 1 : 0)
                                           : (a.use_net ? 1 : 0);
             }
             cnt[bt] = 0u;
@@ -671,7 +747,7 @@ k_compress(CompressArgs a)
         // the next tile overwrites the LDS arrays only after this barrier
         __syncthreads();
     }
-    set_status(a.status, err);
+    set_status(F.status, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,20 +805,20 @@ bool tile_for(const Geom &g, Tile &tile)
     return true;
 }
 
-template <typename T, int D, int BB, int HP, bool FP, int PREC>
+template <typename T, int D, int BB, int HP, bool FP, int PREC, bool BATCH = false>
 static void go(const CompressArgs &a, unsigned num_cus, size_t lds, hipStream_t s)
 {
     // persistent grid: every workgroup that can be resident at once (a
     // multiple of 8 so that each XCD gets the same number), at most one per tile
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&k_compress<T, D, BB, HP, FP, PREC>), 256,
+            &per_cu, reinterpret_cast<const void *>(&k_compress<T, D, BB, HP, FP, PREC, BATCH>), 256,
             lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
     long long grid = std::min((long long)per_cu * num_cus, (a.ntiles + 7) / 8 * 8);
     grid = std::max(8LL, grid / 8 * 8);
-    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC>), dim3((unsigned)grid), dim3(256), lds,
-                       s, a);
+    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC, BATCH>), dim3((unsigned)grid), dim3(256),
+                       lds, s, a);
 }
 
 template <typename T, int D, int BB, bool FP>
@@ -784,6 +860,56 @@ static void by_shape(int D, int B, int HP, const CompressArgs &a, unsigned grid,
         by_hidden<T, 1, 0, FP>(HP, a, grid, lds, s);
 }
 
+template <typename T, int D, int BB>
+static void by_hidden_batch(int HP, const CompressArgs &a, unsigned grid, size_t lds, hipStream_t s)
+{
+    if (HP == 0)
+        go<T, D, BB, 8, true, 1, true>(a, grid, lds, s);
+    else if (HP == 8)
+        go<T, D, BB, 8, true, 0, true>(a, grid, lds, s);
+    else if (HP == 16)
+        go<T, D, BB, 16, true, 0, true>(a, grid, lds, s);
+    else
+        go<T, D, BB, 32, true, 0, true>(a, grid, lds, s);
+}
+
+bool batch_shape(int D, int B) { return (D == 3 && B == 8) || (D == 2 && B == 16); }
+
+// One persistent launch over every tile of nfields FP32 fields of one class
+// (dimensionality and block): d_fields (device) in tile order, each reading
+// its grid-value entries.
+hipError_t launch_compress_batch(const FieldDesc *d_fields, int nfields, long long ntiles,
+                                 const Geom &g, const Tile &tile, const pwrel_mlp *model,
+                                 const pwrel_options &opt, const long long *qtab, int num_cus,
+                                 hipStream_t s)
+{
+    if (!batch_shape(g.D, g.B) || g.dtype != PWREL_F32)
+        return hipErrorInvalidValue;
+    CompressArgs a{};
+    a.fields = d_fields;
+    a.nfields = nfields;
+    for (int d = 0; d < 3; ++d) {
+        a.bd[d] = g.bd[d];
+        a.t[d] = tile.t[d];
+    }
+    a.ntiles = ntiles;
+    a.use_net = opt.use_net;
+    a.judge = opt.judge;
+    a.independent = opt.independent_blocks;
+    a.entries = 1;
+    a.qtab = qtab;
+    a.mlp = pack_mlp(opt.use_net ? model : nullptr);
+    const bool mfma = opt.use_net && model && model->precision == 1;
+    const int HP = mfma ? 0 : hidden_pad(opt.use_net ? model : nullptr);
+    const size_t lds = compress_lds(g, tile.t, opt.judge != 0);
+    const unsigned grid = (unsigned)std::max(num_cus, 8);
+    if (g.D == 3)
+        by_hidden_batch<float, 3, 8>(HP, a, grid, lds, s);
+    else
+        by_hidden_batch<float, 2, 16>(HP, a, grid, lds, s);
+    return hipGetLastError();
+}
+
 // Grid value and bound check of every value of an FP32 field (the same
 // fast paths, fallbacks and order as the fused kernel's per-point step), one
 // entry per value: 2 p, plus 1 where the PW_REL bound check fails.  The fused
@@ -823,6 +949,40 @@ __global__ void __launch_bounds__(256) k_grid_entries(const float *__restrict__ 
     for (long long i = 4 * n4 + tid; i < n; i += stride)
         ent[i] = grid_entry(x[i], c, err);
     set_status(status, err);
+}
+
+// Grid entries of a batch: workgroup k takes chunk k - chunk0 of the field
+// whose chunk range holds k (binary search of the fields' first chunks).
+__global__ void __launch_bounds__(256) k_grid_entries_batch(const BatchField *fields, int nf)
+{
+    const long long k = blockIdx.x;
+    int lo = 0, hi = nf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fields[mid].echunk0 <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchField &f = fields[lo];
+    if (*f.status != kOk)
+        return;  // no barrier below: a per-thread exit is safe
+    const DevConsts c = *f.consts;
+    const float *x = static_cast<const float *>(f.x);
+    const long long b0 = (k - f.echunk0) * kEntryChunk, b1 = std::min(f.N, b0 + kEntryChunk);
+    int err = kOk;
+    for (long long i = b0 + threadIdx.x; i < b1; i += 256)
+        f.pgrid[i] = grid_entry(x[i], c, err);
+    set_status(f.status, err);
+}
+
+hipError_t launch_grid_entries_batch(const BatchField *d_fields, int nf, long long nchunks,
+                                     hipStream_t s)
+{
+    if (nchunks > 0)
+        hipLaunchKernelGGL(k_grid_entries_batch, dim3((unsigned)nchunks), dim3(256), 0, s,
+                           d_fields, nf);
+    return hipGetLastError();
 }
 
 hipError_t launch_grid_entries(const float *x, const Geom &g, Workspace &ws, int *ent,

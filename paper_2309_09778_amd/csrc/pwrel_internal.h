@@ -78,6 +78,73 @@ inline long long inv_table_size(const DevConsts &c)
     return (n > 0 && n <= kInvTable) ? n : 0;
 }
 
+// Field geometry as a kernel argument.
+struct GeoArgs {
+    long long n[3];
+    int bd[3];
+    long long nb[3];
+    long long nblocks;
+};
+
+// One field of a batched launch: its input, geometry, outputs and
+// constants; tiles tile0 .. tile0 + ntiles - 1 of the launch are its tiles.
+struct FieldDesc {
+    const void *x;
+    const int *pfield;
+    long long n[3];
+    long long nb[3];
+    long long nt[3];
+    long long tile0;
+    uint16_t *codes;
+    uint32_t *counts;
+    uint8_t *bflags;
+    const DevConsts *consts;
+    int *status;
+};
+
+// what the header kernel writes besides the device constants (host-built)
+constexpr int kHeaderGaps = 8;
+struct HeaderArgs {
+    int dtype, ndim, block, flags;
+    unsigned long long dims[3];
+    unsigned long long n, nblocks;
+    unsigned long long off_model, off_bflags, off_counts, off_codes, off_raw;
+    unsigned long long capacity;
+    int raw_size;
+    unsigned long long pad_lo[kHeaderGaps], pad_hi[kHeaderGaps];  // gaps between sections
+    // Huffman sections (0 without them)
+    unsigned long long off_huff, off_sizes, off_bits, n_bits;
+    unsigned n_sym, size_bytes;
+};
+// One field of pwrel_compress_batch for the batched statistics, constants,
+// grid entries, scan, raw scatter, model and header kernels (device table).
+struct BatchField {
+    const void *x;
+    int vec;                   // x 16-byte aligned
+    int pad0;
+    GeoArgs g;
+    long long N;
+    double eps;
+    long long part0, nparts;   // statistics records of the field
+    long long chunk0, nchunks; // scan chunks (kScanChunk blocks) of the field
+    long long blk0;            // first block in the batch's block numbering
+    long long echunk0;         // first grid-entry chunk (kEntryChunk values)
+    uint16_t *codes;
+    uint32_t *counts;
+    uint8_t *bflags;
+    void *raw;
+    unsigned long long raw_cap;
+    void *model_dst;           // the stream's model section, or nullptr
+    void *header;
+    unsigned long long *out_size;  // device: the stream's length (0 on error)
+    int *pgrid;                // grid entries of an FP32 field
+    DevConsts *consts;
+    int *status;
+    unsigned long long *n_raw;
+    HeaderArgs h;
+};
+constexpr long long kEntryChunk = 8192;
+
 constexpr int kQtab = 4097;
 
 constexpr int kScanChunk = 4096;
@@ -112,7 +179,8 @@ struct HuffLayout {
     uint64_t off_huff, off_sizes, off_bits, n_bits, table_bytes;
     uint32_t n_sym, size_bytes;
 };
-constexpr int kHeaderGaps = 8;
+HeaderArgs make_header_args(const Geom &g, int flags, const uint64_t *offs, uint64_t capacity,
+                            bool stream_gaps, const HuffLayout *hl);
 // stream_gaps: zero the alignment gaps between the sections that follow
 // d_header; hl: the Huffman sections (offs[3], the codes offset, unused)
 hipError_t launch_header(const Geom &g, int flags, const uint64_t *offs, Workspace &ws,
@@ -135,6 +203,24 @@ hipError_t launch_hist(const uint16_t *codes, long long n, unsigned long long *h
                        hipStream_t s);
 
 bool tile_for(const Geom &g, Tile &tile);
+
+// --- batched compression (pwrel_compress_batch) ------------------------------------
+bool batch_shape(int D, int B);  // classes the batched compressor is compiled for
+// reset, statistics (records: nparts), constants
+hipError_t launch_batch_front(const BatchField *d_fields, int nf, int dtype, long long nparts,
+                              DevStats *records, hipStream_t s);
+hipError_t launch_grid_entries_batch(const BatchField *d_fields, int nf, long long nchunks,
+                                     hipStream_t s);
+hipError_t launch_compress_batch(const FieldDesc *d_fields, int nfields, long long ntiles,
+                                 const Geom &g, const Tile &tile, const pwrel_mlp *model,
+                                 const pwrel_options &opt, const long long *qtab, int num_cus,
+                                 hipStream_t s);
+// scan, raw scatter, model (models: device, [3] by ndim - 1, or nullptr),
+// header of every field
+hipError_t launch_batch_back(const BatchField *d_fields, int nf, int dtype, long long nchunks,
+                             long long nblocks, unsigned long long *offsets,
+                             unsigned long long *partials, const pwrel_mlp *models,
+                             hipStream_t s);
 
 // --- host helpers shared by the entry points --------------------------------------
 constexpr uint64_t align256(uint64_t v) { return (v + 255u) & ~uint64_t(255u); }
@@ -255,6 +341,12 @@ int api_fail(pwrel_ctx *ctx, int code, const char *msg);
 int api_status(pwrel_ctx *ctx, int device_status);  // status of a finished call, with message
 int api_device(const pwrel_ctx *ctx);
 int api_num_cus(const pwrel_ctx *ctx);
+const long long *api_qtab(const pwrel_ctx *ctx);  // the judge's q(c) table
+// the context's batched-compression state (created on first use, released
+// by pwrel_destroy through batch_release)
+struct BatchState;
+BatchState *&api_batch_state(pwrel_ctx *ctx);
+void batch_release(BatchState *b);
 
 // static scratch of pwrel_compress_noalloc (pwrel_noalloc.hip): set up once
 // per device by pwrel_create, with that device current

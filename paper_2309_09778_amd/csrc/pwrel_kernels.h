@@ -209,13 +209,7 @@ inline bool known_shape(int D, int B, int *t)
     return false;
 }
 
-// Field geometry as a kernel argument.
-struct GeoArgs {
-    long long n[3];
-    int bd[3];
-    long long nb[3];
-    long long nblocks;
-};
+
 
 // Start of block (bz, by, bx) in the block-major stream and its extents.
 struct BlockGeo {

@@ -65,6 +65,11 @@ FAST_LOG2_ERR = 2.0 ** -20  # PWREL_FAST_LOG2_ERR
 FAST_EXP2_ERR = 2.0 ** -20  # PWREL_FAST_EXP2_ERR
 
 
+class FieldDesc(C.Structure):
+    _fields_ = [("d_field", C.c_void_p), ("dims", C.c_uint64 * 3), ("ndim", C.c_int32),
+                ("reserved", C.c_int32), ("d_out", C.c_void_p), ("out_capacity", C.c_uint64)]
+
+
 class TrainOptions(C.Structure):
     _fields_ = [("rho", C.c_double), ("seed", C.c_uint64), ("hidden", C.c_int32),
                 ("epochs", C.c_int32), ("batch", C.c_int32), ("n_lr", C.c_int32),
@@ -98,6 +103,9 @@ _SIGS = {
     "pwrel_compress_noalloc": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
                                          C.POINTER(Mlp), C.POINTER(Options), _P, C.c_uint64,
                                          C.POINTER(C.c_uint64), _P]),
+    "pwrel_compress_batch": (C.c_int, [_P, C.c_int, C.POINTER(FieldDesc), C.c_int, C.c_double,
+                                       _P, C.POINTER(C.POINTER(Mlp)), C.POINTER(Options), _P,
+                                       _P]),
     "pwrel_decompress": (C.c_int, [_P, _P, C.c_uint64, _P, _P, C.c_int, C.c_int, _P]),
     "pwrel_read_header": (C.c_int, [_P, C.c_uint64, C.POINTER(Header)]),
     "pwrel_compress_raw": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
@@ -388,6 +396,59 @@ class Context:
             C.c_void_p(out.data_ptr()), out.numel(), C.byref(size), _stream(stream))
         self._check(st, "compress_noalloc")
         return out[:size.value]
+
+    def compress_batch(self, xs, eps, models=None, use_net=True, judge=False,
+                       independent=False, blocks=None, outs=None, sizes=None, stream=None,
+                       views=True):
+        """pwrel_compress_batch over FP32 CUDA tensors xs (2-D or 3-D).
+        models: {ndim: network} for each dimensionality present (use_net);
+        blocks: {ndim: block edge} (defaults 16 for 2-D, 8 for 3-D).  outs
+        (one uint8 tensor per field) and sizes (int64 tensor of len(xs)) are
+        allocated when not given; keep passing the same ones (and the same
+        inputs) to repeat a request, e.g. under graph capture.  views=True:
+        synchronise and return the stream views; else (outs, sizes) with the
+        sizes still on the device."""
+        import torch
+        n = len(xs)
+        blocks = dict(blocks or {})
+        bs = (C.c_int * 3)(0, int(blocks.get(2, 16)), int(blocks.get(3, 8)))
+        if outs is None:
+            outs = []
+            for x in xs:
+                cap = compress_bound(x.shape, _dtype_code(x.dtype), bs[x.dim() - 1])
+                outs.append(torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device))
+        if sizes is None:
+            sizes = torch.zeros(n, dtype=torch.int64, device=xs[0].device)
+        descs = (FieldDesc * n)()
+        for i, (x, o) in enumerate(zip(xs, outs)):
+            assert x.is_cuda and x.is_contiguous()
+            d = descs[i]
+            d.d_field = x.data_ptr()
+            for k, s in enumerate(x.shape):
+                d.dims[k] = int(s)
+            d.ndim = x.dim()
+            d.d_out = o.data_ptr()
+            d.out_capacity = o.numel()
+        keep = {}
+        mptrs = (C.POINTER(Mlp) * 3)()
+        if use_net:
+            for nd, m in (models or {}).items():
+                keep[nd] = model_struct(m)
+                mptrs[nd - 1] = C.pointer(keep[nd])
+        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
+        dt = _dtype_code(xs[0].dtype) if n else F32
+        st = self._L.pwrel_compress_batch(self.h, n, descs, dt, float(eps), C.cast(bs, C.c_void_p),
+                                          mptrs, C.byref(opt), C.c_void_p(sizes.data_ptr()),
+                                          _stream(stream))
+        self._check(st, "compress_batch")
+        if not views:
+            return outs, sizes
+        if stream is not None:
+            stream.synchronize()
+        else:
+            torch.cuda.current_stream(xs[0].device).synchronize()
+        sz = sizes.cpu().tolist()
+        return [o[:s] for o, s in zip(outs, sz)]
 
     def decompress(self, stream_t, shape=None, dtype=None, out=None, stream=None):
         import torch
