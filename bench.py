@@ -260,6 +260,122 @@ def train_record(rep, wall_ms):
                                    2.0 ** 32 / max(rep["n_val"], 1), 4)}
 
 
+def batch_leg(ctx, n_fields, eps, steps, warmup, hidden, plain_hidden, rho, pwrel, synth, torch):
+    """Many uneven fields in one batched call: n_fields FP32 fields, even
+    index 2-D (sides uniform in 128..1024), odd 3-D (sides uniform in
+    32..256), each a log-normal k^-3 field of its own seed with 5% negative
+    regions; eps, independent blocks.  Two paths: the learned one (BF16
+    network of width `hidden` and the per-block judge) and the plain one
+    (FP32 network of width `plain_hidden`, no judge), each network trained on
+    the device on the first field of its dimensionality.  Per path: the
+    tile autotuner, eager calls, graph replays, and the same fields
+    compressed one call each (the unbatched baseline); a sample of fields
+    is checked byte for byte against single-field compression and decoded
+    against the bound."""
+    import numpy as np
+    shapes = synth.batch_shapes(n_fields, seed=3000)
+    t0 = time.perf_counter()
+    xs = []
+    for i, s in enumerate(shapes):
+        xs.append(synth.lognormal_grf_device(s, seed=3000 + i, decades=8.0, neg_frac=0.05,
+                                             zero_frac=0.005, pad_pow2=True))
+        if (i + 1) % 100 == 0:
+            log(f"batch fields generated: {i + 1}/{n_fields}")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    nvals = sum(x.numel() for x in xs)
+    gb = nvals * 4 / 1e9
+    i3 = next(i for i, s in enumerate(shapes) if len(s) == 3)
+    i2 = next(i for i, s in enumerate(shapes) if len(s) == 2)
+    outs = [torch.empty(pwrel.compress_bound(x.shape, pwrel.F32, 8 if x.dim() == 3 else 16),
+                        dtype=torch.uint8, device="cuda") for x in xs]
+    sizes = torch.zeros(len(xs), dtype=torch.int64, device="cuda")
+    rec = {"fields": n_fields, "values": nvals, "bytes": nvals * 4,
+           "fields_3d": sum(len(s) == 3 for s in shapes), "generate_s": round(gen_s, 2),
+           "workload": f"{n_fields} FP32 fields: even index 2-D (sides uniform 128..1024, block "
+                       f"16^2), odd 3-D (sides uniform 32..256, block 8^3); log-normal k^-3 "
+                       f"field per seed (drawn on the next power-of-two grid and cropped), 8 decades, 5% "
+                       f"negative regions, 0.5% zeros; eps "
+                       f"{eps:g}; independent blocks; 16-bit codes"}
+    sample = sorted(set([0, 1, 2, 3] + list(range(0, n_fields, max(1, n_fields // 16)))))
+    for name, H, prec, judge in (("learned", hidden, 1, True), ("plain", plain_hidden, 0, False)):
+        models, train_ms = {}, 0.0
+        for nd, i in ((3, i3), (2, i2)):
+            a = time.perf_counter()
+            m, _ = ctx.train(xs[i], eps, 8 if nd == 3 else 16, rho=rho, seed=3000 + i, hidden=H,
+                             precision=prec, independent=True)
+            train_ms += (time.perf_counter() - a) * 1e3
+            models[nd] = m
+        req = ctx.batch_request(xs, eps, models=models, judge=judge, independent=True, outs=outs,
+                                sizes=sizes)
+        variants, tune_ms = req.tune(reps=3)
+        for _ in range(warmup):
+            req.run()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(steps):
+            req.run()
+        torch.cuda.synchronize()
+        eager_ms = (time.perf_counter() - a) * 1e3 / steps
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                req.run(stream=side)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - a) * 1e3 / steps
+        views = req.views()
+        sz = [int(v.numel()) for v in views]
+        # the same fields one call each (each call synchronises once)
+        mst = {nd: pwrel.model_struct(m) for nd, m in models.items()}
+        a = time.perf_counter()
+        for x, o in zip(xs, outs):
+            ctx.compress(x, eps, 8 if x.dim() == 3 else 16, mst[x.dim()], judge=judge,
+                         independent=True, out=o)
+        torch.cuda.synchronize()
+        single_ms = (time.perf_counter() - a) * 1e3
+        # the batch again, then the sample: byte-identical to single calls, and decoded
+        req.run()
+        views = req.views()
+        same, bound = True, True
+        for i in sample:
+            x = xs[i]
+            s1 = ctx.compress(x, eps, 8 if x.dim() == 3 else 16, models[x.dim()], judge=judge,
+                              independent=True)
+            same = same and s1.numel() == views[i].numel() and bool(torch.equal(s1, views[i]))
+            xh = ctx.decompress(views[i])
+            bound = bound and bound_ok(x, xh, eps, torch)
+        shp = ctx.batch_tiles()[1]
+        rec[name] = {
+            "path": ("BF16 H=%d network + per-block judge" if judge else
+                     "FP32 H=%d network, no judge") % H,
+            "eager_ms": round(eager_ms, 3), "graph_ms": round(graph_ms, 3),
+            "eager_GBps": round(gb / (eager_ms * 1e-3), 2),
+            "graph_GBps": round(gb / (graph_ms * 1e-3), 2),
+            "unbatched_ms": round(single_ms, 2),
+            "speedup_vs_unbatched": round(single_ms / graph_ms, 2),
+            "ratio_16bit_codes": round(nvals * 4 / max(sum(sz), 1), 4),
+            "failed_fields": int(sum(1 for v in sz if v == 0)),
+            "tiles": {"variants_3d_2d": variants, "tile_3d": shp[0], "tile_2d": shp[1],
+                      "compress_ms_3d": [round(v, 3) for v in tune_ms[0]],
+                      "compress_ms_2d": [round(v, 3) for v in tune_ms[1]]},
+            "sample_fields": len(sample), "sample_equal_single": same,
+            "sample_bound_ok": bound, "train_ms": round(train_ms, 1)}
+        log(f"batch {name}: graph {graph_ms:.2f} ms, eager {eager_ms:.2f} ms, "
+            f"unbatched {single_ms:.1f} ms")
+        del g
+    del xs, outs
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +391,8 @@ def main():
     ap.add_argument("--only-timed", action="store_true",
                     help="the timed path only (no other paths, legs or CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-fields", type=int, default=2000,
+                    help="fields of the batched leg (0: no batched leg)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the codec has no multi-GPU path "
@@ -440,6 +558,13 @@ def main():
     res["zonal_2d"]["lorenzo_ratio_stream"] = stream_stats(ctx, Z0["stream"], x2.numel() * 4,
                                                            pwrel)["ratio_stream"]
     log("2-D field timed")
+
+    del x2, o2, h2, Z, Z0
+    torch.cuda.empty_cache()
+    if args.batch_fields > 0:
+        res["batch"] = batch_leg(ctx, args.batch_fields, eps, K, args.warmup, args.hidden,
+                                 args.plain_hidden, args.rho, pwrel, synth, torch)
+        log("batched leg timed")
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

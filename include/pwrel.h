@@ -286,6 +286,34 @@ int pwrel_compress_batch(pwrel_ctx *ctx, int n, const pwrel_field_desc *fields, 
                          uint64_t *d_out_sizes, void *stream);
 
 /*
+ * Tile shapes of the batched compression launch.  A tile is the group of
+ * whole blocks one workgroup predicts at a time; it schedules work only, so
+ * every shape gives the same streams.  Each class has PWREL_BATCH_TILES
+ * shapes (3-D block 8: 8x8x32, 8x16x16, 16x16x16; 2-D block 16: 16x128,
+ * 32x64, 16x256), variant 0 by default; the context keeps one per class.
+ *  pwrel_batch_set_tiles - variant[2] (host): 3-D class, then 2-D class;
+ *      PWREL_EINVAL outside 0 .. PWREL_BATCH_TILES - 1.
+ *  pwrel_batch_get_tiles - the context's variants into variant[2], and
+ *      their tile extents (z, y, x) into shapes[6] unless it is NULL.
+ *  pwrel_compress_batch_tune - the autotuner: runs the request (arguments
+ *      as pwrel_compress_batch) with each variant, `reps` timed runs after a
+ *      warm-up, times each class's compression launch with HIP events, and
+ *      keeps the variant of median-fastest time per class in the context
+ *      (variant_out[2], host, may be NULL; ms_out[2][PWREL_BATCH_TILES]
+ *      medians, host, may be NULL; 0 for an absent class).  Ends with the
+ *      request's outputs written by the chosen variants and the stream
+ *      synchronised.  Not under capture (PWREL_EINVAL).
+ */
+#define PWREL_BATCH_TILES 3
+int pwrel_batch_set_tiles(pwrel_ctx *ctx, const int *variant);
+int pwrel_batch_get_tiles(pwrel_ctx *ctx, int *variant, int *shapes);
+int pwrel_compress_batch_tune(pwrel_ctx *ctx, int n, const pwrel_field_desc *fields, int dtype,
+                              double rel_error_bound, const int *block_size,
+                              const pwrel_mlp *const *models, const pwrel_options *opt,
+                              uint64_t *d_out_sizes, int reps, int *variant_out, double *ms_out,
+                              void *stream);
+
+/*
  * A trained network kept for later fields (Sec. 5: the model trained in the
  * training phase is retained and used to compress; Sec. 4.3).  pwrel_mlp is a
  * plain value owned by the caller, so nothing is allocated or freed here.

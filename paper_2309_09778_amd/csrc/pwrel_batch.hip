@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "pwrel_internal.h"
+#include "pwrel_kernels.h"
 
 namespace pwrel {
 
@@ -78,11 +79,13 @@ struct Request {
     int has_model[3] = {};
     pwrel_options opt{};
     uint64_t *sizes = nullptr;
+    int variant[2] = {};  // tile shape variant of each class
 
     bool same(const Request &o) const
     {
         if (fields.size() != o.fields.size() || dtype != o.dtype || eps != o.eps ||
             sizes != o.sizes || std::memcmp(block, o.block, sizeof block) ||
+            std::memcmp(variant, o.variant, sizeof variant) ||
             std::memcmp(has_model, o.has_model, sizeof has_model) ||
             std::memcmp(&opt, &o.opt, sizeof opt))
             return false;
@@ -121,6 +124,9 @@ struct BatchState {
     hipEvent_t ev = nullptr;  // the last table copy
     hipStream_t prep_stream = nullptr;
     bool ready = false;
+    int variant[kClasses] = {};  // tile shape variant of each class (set or tuned)
+    hipEvent_t tev[kClasses][2] = {};  // around each class's compression launch (tuning)
+    bool timing = false;
     Request req;
     // the prepared launches
     int nf = 0;
@@ -145,6 +151,10 @@ void batch_release(BatchState *b)
         (void)hipHostFree(b->htab);
     if (b->ev)
         (void)hipEventDestroy(b->ev);
+    for (auto &pr : b->tev)
+        for (hipEvent_t e : pr)
+            if (e)
+                (void)hipEventDestroy(e);
     delete b;
 }
 
@@ -204,9 +214,15 @@ int prepare(pwrel_ctx *ctx, BatchState &b, const Request &r, hipStream_t s)
     for (int i = 0; i < nf; ++i) {
         const pwrel_field_desc &f = r.fields[(size_t)i];
         make_geom(f.dims, f.ndim, r.dtype, r.block[f.ndim - 1], geo[(size_t)i]);
-        if (!tile_for(geo[(size_t)i], til[(size_t)i]))
-            return api_fail(ctx, PWREL_EINVAL, "block too large for the LDS tile");
         const Geom &g = geo[(size_t)i];
+        Tile &t = til[(size_t)i];
+        if (!variant_shape(g.D, g.B, r.variant[class_of(f.ndim)], t.t))
+            return api_fail(ctx, PWREL_EINVAL, "no such batched tile shape");
+        t.ntiles = 1;
+        for (int d = 0; d < 3; ++d) {
+            t.nt[d] = (g.n[d] + t.t[d] - 1) / t.t[d];
+            t.ntiles *= t.nt[d];
+        }
         nparts += stat_parts(g.N);
         nechunks += (g.N + kEntryChunk - 1) / kEntryChunk;
         nchunks += (g.nblocks + kScanChunk - 1) / kScanChunk;
@@ -360,9 +376,13 @@ hipError_t launch_prepared(const BatchState &b, const Request &r, const long lon
             continue;
         const int d = b.geo[k].D - 1;
         const FieldDesc *fd = reinterpret_cast<const FieldDesc *>(b.dtab + b.off_fd[k]);
+        if (b.timing && (e = hipEventRecord(b.tev[k][0], s)) != hipSuccess)
+            return e;
         if ((e = launch_compress_batch(fd, b.nclass[k], b.ntiles[k], b.geo[k], b.tile[k],
-                                       r.opt.use_net ? &r.models[d] : nullptr, r.opt, qtab,
-                                       num_cus, s)) != hipSuccess)
+                                       r.variant[k], r.opt.use_net ? &r.models[d] : nullptr,
+                                       r.opt, qtab, num_cus, s)) != hipSuccess)
+            return e;
+        if (b.timing && (e = hipEventRecord(b.tev[k][1], s)) != hipSuccess)
             return e;
     }
     const pwrel_mlp *models =
@@ -373,6 +393,73 @@ hipError_t launch_prepared(const BatchState &b, const Request &r, const long lon
 
 }  // namespace
 
+}  // namespace pwrel
+
+namespace pwrel {
+namespace {
+
+// The request of a pwrel_compress_batch call (host copies of the arguments).
+Request make_request(const pwrel_field_desc *fields, int n, int dtype, double eps,
+                     const int *block_size, const pwrel_mlp *const *models,
+                     const pwrel_options *opt_in, uint64_t *d_out_sizes)
+{
+    Request r;
+    r.fields.assign(fields, fields + n);
+    r.dtype = dtype;
+    r.eps = eps;
+    r.block[0] = 0;
+    r.block[1] = block_size && block_size[1] ? block_size[1] : 16;
+    r.block[2] = block_size && block_size[2] ? block_size[2] : 8;
+    r.opt = opt_in ? *opt_in : pwrel_options{1, 0, 0, 0};
+    r.sizes = d_out_sizes;
+    for (int d = 1; d < 3; ++d)
+        if (r.opt.use_net && models && models[d]) {
+            r.models[d] = *models[d];
+            r.has_model[d] = 1;
+        }
+    return r;
+}
+
+BatchState *state_of(pwrel_ctx *ctx)
+{
+    BatchState *&b = api_batch_state(ctx);
+    if (!b)
+        b = new (std::nothrow) BatchState();
+    return b;
+}
+
+// One batched compression of request r (checked) with the context's tile
+// variants: the table is built unless r repeats the prepared request.
+int batch_call(pwrel_ctx *ctx, BatchState &b, Request &r, hipStream_t s)
+{
+    for (int k = 0; k < kClasses; ++k)
+        r.variant[k] = b.variant[k];
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess)
+        return api_fail(ctx, PWREL_EHIP, "stream capture query failed");
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    hipError_t e;
+    int st;
+    if (!(b.ready && b.req.same(r))) {
+        if (capturing)
+            return api_fail(ctx, PWREL_EINVAL,
+                            "a captured batch must repeat the request of an earlier call "
+                            "(the field table is built outside capture)");
+        if ((st = prepare(ctx, b, r, s)) != PWREL_OK) {
+            b.ready = false;
+            return st;
+        }
+    } else if (!capturing && s != b.prep_stream &&
+               (e = hipStreamWaitEvent(s, b.ev, 0)) != hipSuccess) {
+        return api_fail(ctx, PWREL_EHIP, "batch table wait");
+    }
+    if ((e = launch_prepared(b, b.req, api_qtab(ctx), api_num_cus(ctx), s)) != hipSuccess)
+        return api_fail(ctx, PWREL_EHIP,
+                        (std::string("batch launch: ") + hipGetErrorString(e)).c_str());
+    return PWREL_OK;
+}
+
+}  // namespace
 }  // namespace pwrel
 
 using namespace pwrel;
@@ -386,47 +473,131 @@ extern "C" int pwrel_compress_batch(pwrel_ctx *ctx, int n, const pwrel_field_des
         return PWREL_EINVAL;
     if (n < 1 || !fields)
         return api_fail(ctx, PWREL_EINVAL, "no fields");
-    Request r;
-    r.fields.assign(fields, fields + n);
-    r.dtype = dtype;
-    r.eps = rel_error_bound;
-    r.block[0] = 0;
-    r.block[1] = block_size && block_size[1] ? block_size[1] : 16;
-    r.block[2] = block_size && block_size[2] ? block_size[2] : 8;
-    r.opt = opt_in ? *opt_in : pwrel_options{1, 0, 0, 0};
-    r.sizes = d_out_sizes;
-    for (int d = 1; d < 3; ++d)
-        if (r.opt.use_net && models && models[d]) {
-            r.models[d] = *models[d];
-            r.has_model[d] = 1;
-        }
+    Request r = make_request(fields, n, dtype, rel_error_bound, block_size, models, opt_in,
+                             d_out_sizes);
+    int st = check_request(ctx, r);
+    if (st != PWREL_OK)
+        return st;
+    pwrel::DeviceGuard_ guard(api_device(ctx));
+    BatchState *b = state_of(ctx);
+    if (!b)
+        return api_fail(ctx, PWREL_ENOMEM, "batch state allocation failed");
+    return batch_call(ctx, *b, r, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int pwrel_batch_set_tiles(pwrel_ctx *ctx, const int *variant)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!variant)
+        return api_fail(ctx, PWREL_EINVAL, "NULL variant array");
+    for (int k = 0; k < kClasses; ++k)
+        if (variant[k] < 0 || variant[k] >= kTileVariants)
+            return api_fail(ctx, PWREL_EINVAL, "tile variant out of range");
+    BatchState *b = state_of(ctx);
+    if (!b)
+        return api_fail(ctx, PWREL_ENOMEM, "batch state allocation failed");
+    for (int k = 0; k < kClasses; ++k)
+        b->variant[k] = variant[k];
+    return PWREL_OK;
+}
+
+extern "C" int pwrel_batch_get_tiles(pwrel_ctx *ctx, int *variant, int *shapes)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!variant)
+        return api_fail(ctx, PWREL_EINVAL, "NULL variant array");
+    BatchState *b = state_of(ctx);
+    if (!b)
+        return api_fail(ctx, PWREL_ENOMEM, "batch state allocation failed");
+    static const int DB[kClasses][2] = {{3, 8}, {2, 16}};
+    for (int k = 0; k < kClasses; ++k) {
+        variant[k] = b->variant[k];
+        if (shapes)
+            variant_shape(DB[k][0], DB[k][1], b->variant[k], shapes + 3 * k);
+    }
+    return PWREL_OK;
+}
+
+extern "C" int pwrel_compress_batch_tune(pwrel_ctx *ctx, int n, const pwrel_field_desc *fields,
+                                         int dtype, double rel_error_bound,
+                                         const int *block_size, const pwrel_mlp *const *models,
+                                         const pwrel_options *opt_in, uint64_t *d_out_sizes,
+                                         int reps, int *variant_out, double *ms_out,
+                                         void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (n < 1 || !fields)
+        return api_fail(ctx, PWREL_EINVAL, "no fields");
+    if (reps < 1 || reps > 1000)
+        return api_fail(ctx, PWREL_EINVAL, "reps must be 1..1000");
+    Request r = make_request(fields, n, dtype, rel_error_bound, block_size, models, opt_in,
+                             d_out_sizes);
     int st = check_request(ctx, r);
     if (st != PWREL_OK)
         return st;
     pwrel::DeviceGuard_ guard(api_device(ctx));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess)
-        return api_fail(ctx, PWREL_EHIP, "stream capture query failed");
-    const bool capturing = cap != hipStreamCaptureStatusNone;
-    BatchState *&b = api_batch_state(ctx);
-    if (!b && !(b = new (std::nothrow) BatchState()))
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+        return api_fail(ctx, PWREL_EINVAL, "tuning times launches: not under capture");
+    BatchState *b = state_of(ctx);
+    if (!b)
         return api_fail(ctx, PWREL_ENOMEM, "batch state allocation failed");
     hipError_t e;
-    if (!(b->ready && b->req.same(r))) {
-        if (capturing)
-            return api_fail(ctx, PWREL_EINVAL,
-                            "a captured batch must repeat the request of an earlier call "
-                            "(the field table is built outside capture)");
-        if ((st = prepare(ctx, *b, r, s)) != PWREL_OK) {
-            b->ready = false;
-            return st;
+    for (auto &pr : b->tev)
+        for (hipEvent_t &ev : pr)
+            if (!ev && (e = hipEventCreate(&ev)) != hipSuccess)
+                return api_fail(ctx, PWREL_EHIP, "timing event creation failed");
+    double med[kClasses][kTileVariants] = {};
+    const int keep[kClasses] = {b->variant[0], b->variant[1]};
+    for (int v = 0; v < kTileVariants; ++v) {
+        for (int k = 0; k < kClasses; ++k)
+            b->variant[k] = v;
+        std::vector<double> t[kClasses];
+        for (int rep = 0; rep <= reps; ++rep) {  // rep 0 builds the table and warms up
+            b->timing = rep > 0;
+            st = batch_call(ctx, *b, r, s);
+            b->timing = false;
+            if (st == PWREL_OK && (e = hipStreamSynchronize(s)) != hipSuccess)
+                st = api_fail(ctx, PWREL_EHIP, "tuning synchronize");
+            if (st != PWREL_OK) {
+                for (int k = 0; k < kClasses; ++k)
+                    b->variant[k] = keep[k];
+                return st;
+            }
+            if (rep == 0)
+                continue;
+            for (int k = 0; k < kClasses; ++k) {
+                float ms = 0.0f;
+                if (b->nclass[k] &&
+                    hipEventElapsedTime(&ms, b->tev[k][0], b->tev[k][1]) == hipSuccess)
+                    t[k].push_back(ms);
+            }
         }
-    } else if (!capturing && s != b->prep_stream &&
-               (e = hipStreamWaitEvent(s, b->ev, 0)) != hipSuccess) {
-        return api_fail(ctx, PWREL_EHIP, "batch table wait");
+        for (int k = 0; k < kClasses; ++k) {
+            std::sort(t[k].begin(), t[k].end());
+            med[k][v] = t[k].empty() ? 0.0 : t[k][t[k].size() / 2];
+        }
     }
-    if ((e = launch_prepared(*b, b->req, api_qtab(ctx), api_num_cus(ctx), s)) != hipSuccess)
-        return api_fail(ctx, PWREL_EHIP, (std::string("batch launch: ") + hipGetErrorString(e)).c_str());
+    for (int k = 0; k < kClasses; ++k) {
+        int best = 0;
+        for (int v = 1; v < kTileVariants; ++v)
+            if (med[k][v] < med[k][best])
+                best = v;
+        b->variant[k] = best;
+        if (variant_out)
+            variant_out[k] = best;
+        if (ms_out)
+            for (int v = 0; v < kTileVariants; ++v)
+                ms_out[k * kTileVariants + v] = med[k][v];
+    }
+    // leave the outputs (and the prepared table) of the chosen variants
+    if ((st = batch_call(ctx, *b, r, s)) != PWREL_OK)
+        return st;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return api_fail(ctx, PWREL_EHIP, "tuning synchronize");
     return PWREL_OK;
 }

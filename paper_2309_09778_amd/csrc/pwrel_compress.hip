@@ -189,13 +189,13 @@ __device__ __forceinline__ void wait_vmem()
 // Occupancy bound (measured at 512^3): six waves per SIMD for the FP32 and
 // Lorenzo variants, four for the BF16 one; the registers the bound takes away
 // cost a few spills, far less than the latency the extra waves hide.
-template <typename T, int D, int BB, int HP, bool FROM_P, int PREC, bool BATCH>
+template <typename T, int D, int BB, int HP, bool FROM_P, int PREC, bool BATCH, int TV = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 4 : 6)))
 k_compress(CompressArgs a)
 {
     static_assert(FROM_P || !std::is_same<T, float>::value,
                   "FP32 values are read as entries (k_grid_entries)");
-    using S = ShapeOf<D, BB>;
+    using S = TileOf<D, BB, TV>;
     constexpr bool CT = S::known;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = 256;
@@ -295,7 +295,8 @@ k_compress(CompressArgs a)
                 else
                     hi = mid - 1;
             }
-            const FieldDesc &d = a.fields[lo];
+            // uniform across the workgroup: the field's words load as scalars
+            const FieldDesc &d = a.fields[__builtin_amdgcn_readfirstlane(lo)];
             F.src = FROM_P ? reinterpret_cast<const V *>(d.pfield) : reinterpret_cast<const V *>(d.x);
             for (int k = 0; k < 3; ++k) {
                 F.n[k] = d.n[k];
@@ -805,20 +806,20 @@ bool tile_for(const Geom &g, Tile &tile)
     return true;
 }
 
-template <typename T, int D, int BB, int HP, bool FP, int PREC, bool BATCH = false>
+template <typename T, int D, int BB, int HP, bool FP, int PREC, bool BATCH = false, int TV = 0>
 static void go(const CompressArgs &a, unsigned num_cus, size_t lds, hipStream_t s)
 {
     // persistent grid: every workgroup that can be resident at once (a
     // multiple of 8 so that each XCD gets the same number), at most one per tile
+    const void *fn = reinterpret_cast<const void *>(&k_compress<T, D, BB, HP, FP, PREC, BATCH, TV>);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&k_compress<T, D, BB, HP, FP, PREC, BATCH>), 256,
-            lds) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess ||
+        per_cu < 1)
         per_cu = 1;
     long long grid = std::min((long long)per_cu * num_cus, (a.ntiles + 7) / 8 * 8);
     grid = std::max(8LL, grid / 8 * 8);
-    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC, BATCH>), dim3((unsigned)grid), dim3(256),
-                       lds, s, a);
+    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC, BATCH, TV>), dim3((unsigned)grid),
+                       dim3(256), lds, s, a);
 }
 
 template <typename T, int D, int BB, bool FP>
@@ -860,30 +861,45 @@ static void by_shape(int D, int B, int HP, const CompressArgs &a, unsigned grid,
         by_hidden<T, 1, 0, FP>(HP, a, grid, lds, s);
 }
 
-template <typename T, int D, int BB>
+template <typename T, int D, int BB, int TV>
 static void by_hidden_batch(int HP, const CompressArgs &a, unsigned grid, size_t lds, hipStream_t s)
 {
     if (HP == 0)
-        go<T, D, BB, 8, true, 1, true>(a, grid, lds, s);
+        go<T, D, BB, 8, true, 1, true, TV>(a, grid, lds, s);
     else if (HP == 8)
-        go<T, D, BB, 8, true, 0, true>(a, grid, lds, s);
+        go<T, D, BB, 8, true, 0, true, TV>(a, grid, lds, s);
     else if (HP == 16)
-        go<T, D, BB, 16, true, 0, true>(a, grid, lds, s);
+        go<T, D, BB, 16, true, 0, true, TV>(a, grid, lds, s);
     else
-        go<T, D, BB, 32, true, 0, true>(a, grid, lds, s);
+        go<T, D, BB, 32, true, 0, true, TV>(a, grid, lds, s);
+}
+
+template <typename T, int D, int BB>
+static void by_variant_batch(int TV, int HP, const CompressArgs &a, unsigned grid, size_t lds,
+                             hipStream_t s)
+{
+    if (TV == 1)
+        by_hidden_batch<T, D, BB, 1>(HP, a, grid, lds, s);
+    else if (TV == 2)
+        by_hidden_batch<T, D, BB, 2>(HP, a, grid, lds, s);
+    else
+        by_hidden_batch<T, D, BB, 0>(HP, a, grid, lds, s);
 }
 
 bool batch_shape(int D, int B) { return (D == 3 && B == 8) || (D == 2 && B == 16); }
 
 // One persistent launch over every tile of nfields FP32 fields of one class
 // (dimensionality and block): d_fields (device) in tile order, each reading
-// its grid-value entries.
+// its grid-value entries; tiles of shape variant `variant` (tile.t).
 hipError_t launch_compress_batch(const FieldDesc *d_fields, int nfields, long long ntiles,
-                                 const Geom &g, const Tile &tile, const pwrel_mlp *model,
-                                 const pwrel_options &opt, const long long *qtab, int num_cus,
-                                 hipStream_t s)
+                                 const Geom &g, const Tile &tile, int variant,
+                                 const pwrel_mlp *model, const pwrel_options &opt,
+                                 const long long *qtab, int num_cus, hipStream_t s)
 {
-    if (!batch_shape(g.D, g.B) || g.dtype != PWREL_F32)
+    int vt[3];
+    if (!batch_shape(g.D, g.B) || g.dtype != PWREL_F32 || variant < 0 ||
+        variant >= kTileVariants || !variant_shape(g.D, g.B, variant, vt) ||
+        vt[0] != tile.t[0] || vt[1] != tile.t[1] || vt[2] != tile.t[2])
         return hipErrorInvalidValue;
     CompressArgs a{};
     a.fields = d_fields;
@@ -904,9 +920,9 @@ hipError_t launch_compress_batch(const FieldDesc *d_fields, int nfields, long lo
     const size_t lds = compress_lds(g, tile.t, opt.judge != 0);
     const unsigned grid = (unsigned)std::max(num_cus, 8);
     if (g.D == 3)
-        by_hidden_batch<float, 3, 8>(HP, a, grid, lds, s);
+        by_variant_batch<float, 3, 8>(variant, HP, a, grid, lds, s);
     else
-        by_hidden_batch<float, 2, 16>(HP, a, grid, lds, s);
+        by_variant_batch<float, 2, 16>(variant, HP, a, grid, lds, s);
     return hipGetLastError();
 }
 

@@ -212,9 +212,9 @@ hipError_t launch_batch_front(const BatchField *d_fields, int nf, int dtype, lon
 hipError_t launch_grid_entries_batch(const BatchField *d_fields, int nf, long long nchunks,
                                      hipStream_t s);
 hipError_t launch_compress_batch(const FieldDesc *d_fields, int nfields, long long ntiles,
-                                 const Geom &g, const Tile &tile, const pwrel_mlp *model,
-                                 const pwrel_options &opt, const long long *qtab, int num_cus,
-                                 hipStream_t s);
+                                 const Geom &g, const Tile &tile, int variant,
+                                 const pwrel_mlp *model, const pwrel_options &opt,
+                                 const long long *qtab, int num_cus, hipStream_t s);
 // scan, raw scatter, model (models: device, [3] by ndim - 1, or nullptr),
 // header of every field
 hipError_t launch_batch_back(const BatchField *d_fields, int nf, int dtype, long long nchunks,

@@ -211,6 +211,45 @@ inline bool known_shape(int D, int B, int *t)
 
 
 
+// Tile shapes of the batched launch: variant 0 is the shape above; variants
+// 1 and 2 group the same blocks otherwise (fewer halo entries per point, or
+// larger tiles at lower occupancy).  Tiles only schedule work: every variant
+// writes the same stream, so the batch autotuner may pick any by time.
+constexpr int kTileVariants = 3;
+template <int D, int BB, int TV> struct TileOf : ShapeOf<D, BB> {};
+#define PWREL_TILE(DD, BB_, V, A, Bv, Cv)                                                     \
+    template <> struct TileOf<DD, BB_, V> {                                                   \
+        static constexpr bool known = true;                                                   \
+        static constexpr int T0 = A, T1 = Bv, T2 = Cv;                                        \
+    };
+PWREL_TILE(3, 8, 1, 8, 16, 16)
+PWREL_TILE(3, 8, 2, 16, 16, 16)
+PWREL_TILE(2, 16, 1, 1, 32, 64)
+PWREL_TILE(2, 16, 2, 1, 16, 256)
+#undef PWREL_TILE
+
+// Host-side copy: the tile of variant v of the (D, B) shape.
+inline bool variant_shape(int D, int B, int v, int *t)
+{
+    if (v == 0)
+        return known_shape(D, B, t);
+    struct E {
+        int D, B, v, t0, t1, t2;
+    };
+    static const E tab[] = {{3, 8, 1, 8, 16, 16},
+                            {3, 8, 2, 16, 16, 16},
+                            {2, 16, 1, 1, 32, 64},
+                            {2, 16, 2, 1, 16, 256}};
+    for (const E &e : tab)
+        if (e.D == D && e.B == B && e.v == v) {
+            t[0] = e.t0;
+            t[1] = e.t1;
+            t[2] = e.t2;
+            return true;
+        }
+    return false;
+}
+
 // Start of block (bz, by, bx) in the block-major stream and its extents.
 struct BlockGeo {
     long long bz, by, bx;

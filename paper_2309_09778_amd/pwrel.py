@@ -21,6 +21,7 @@ F32, F64 = 0, 1
 OK, EINVAL, ERANGE, ENONFINITE, ENOSPC, ECORRUPT, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
 HF_NET, HF_JUDGE, HF_INDEPENDENT, HF_HUFFMAN = 1, 2, 4, 8
 HUFF_MAX_LEN = 32
+BATCH_TILES = 3
 HEADER_BYTES = 512
 MAXH, MAXK = 32, 6
 R = 32768
@@ -106,6 +107,11 @@ _SIGS = {
     "pwrel_compress_batch": (C.c_int, [_P, C.c_int, C.POINTER(FieldDesc), C.c_int, C.c_double,
                                        _P, C.POINTER(C.POINTER(Mlp)), C.POINTER(Options), _P,
                                        _P]),
+    "pwrel_batch_set_tiles": (C.c_int, [_P, _P]),
+    "pwrel_batch_get_tiles": (C.c_int, [_P, _P, _P]),
+    "pwrel_compress_batch_tune": (C.c_int, [_P, C.c_int, C.POINTER(FieldDesc), C.c_int,
+                                            C.c_double, _P, C.POINTER(C.POINTER(Mlp)),
+                                            C.POINTER(Options), _P, C.c_int, _P, _P, _P]),
     "pwrel_decompress": (C.c_int, [_P, _P, C.c_uint64, _P, _P, C.c_int, C.c_int, _P]),
     "pwrel_read_header": (C.c_int, [_P, C.c_uint64, C.POINTER(Header)]),
     "pwrel_compress_raw": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
@@ -397,58 +403,40 @@ class Context:
         self._check(st, "compress_noalloc")
         return out[:size.value]
 
+    def batch_request(self, xs, eps, models=None, use_net=True, judge=False,
+                      independent=False, blocks=None, outs=None, sizes=None):
+        """The marshalled arguments of one pwrel_compress_batch request over
+        FP32 CUDA tensors xs (2-D or 3-D); run() issues the call.  models:
+        {ndim: network} for each dimensionality present (use_net); blocks:
+        {ndim: block edge} (defaults 16 for 2-D, 8 for 3-D).  outs (one uint8
+        tensor per field) and sizes (an int64 tensor of len(xs), each
+        stream's length) are allocated when not given.  Running the same
+        request again repeats it for the library (same fields, outputs and
+        options), which is what a graph capture needs."""
+        return BatchRequest(self, xs, eps, models, use_net, judge, independent, blocks, outs,
+                            sizes)
+
+    def batch_tiles(self, variants=None):
+        """Set (variants = [3-D, 2-D]) and return the batched tile variants and
+        their tile extents."""
+        if variants is not None:
+            v = (C.c_int * 2)(*[int(x) for x in variants])
+            self._check(self._L.pwrel_batch_set_tiles(self.h, v), "batch_set_tiles")
+        v = (C.c_int * 2)()
+        sh = (C.c_int * 6)()
+        self._check(self._L.pwrel_batch_get_tiles(self.h, v, sh), "batch_get_tiles")
+        return list(v), [tuple(sh[0:3]), tuple(sh[3:6])]
+
     def compress_batch(self, xs, eps, models=None, use_net=True, judge=False,
                        independent=False, blocks=None, outs=None, sizes=None, stream=None,
                        views=True):
-        """pwrel_compress_batch over FP32 CUDA tensors xs (2-D or 3-D).
-        models: {ndim: network} for each dimensionality present (use_net);
-        blocks: {ndim: block edge} (defaults 16 for 2-D, 8 for 3-D).  outs
-        (one uint8 tensor per field) and sizes (int64 tensor of len(xs)) are
-        allocated when not given; keep passing the same ones (and the same
-        inputs) to repeat a request, e.g. under graph capture.  views=True:
-        synchronise and return the stream views; else (outs, sizes) with the
-        sizes still on the device."""
-        import torch
-        n = len(xs)
-        blocks = dict(blocks or {})
-        bs = (C.c_int * 3)(0, int(blocks.get(2, 16)), int(blocks.get(3, 8)))
-        if outs is None:
-            outs = []
-            for x in xs:
-                cap = compress_bound(x.shape, _dtype_code(x.dtype), bs[x.dim() - 1])
-                outs.append(torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device))
-        if sizes is None:
-            sizes = torch.zeros(n, dtype=torch.int64, device=xs[0].device)
-        descs = (FieldDesc * n)()
-        for i, (x, o) in enumerate(zip(xs, outs)):
-            assert x.is_cuda and x.is_contiguous()
-            d = descs[i]
-            d.d_field = x.data_ptr()
-            for k, s in enumerate(x.shape):
-                d.dims[k] = int(s)
-            d.ndim = x.dim()
-            d.d_out = o.data_ptr()
-            d.out_capacity = o.numel()
-        keep = {}
-        mptrs = (C.POINTER(Mlp) * 3)()
-        if use_net:
-            for nd, m in (models or {}).items():
-                keep[nd] = model_struct(m)
-                mptrs[nd - 1] = C.pointer(keep[nd])
-        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
-        dt = _dtype_code(xs[0].dtype) if n else F32
-        st = self._L.pwrel_compress_batch(self.h, n, descs, dt, float(eps), C.cast(bs, C.c_void_p),
-                                          mptrs, C.byref(opt), C.c_void_p(sizes.data_ptr()),
-                                          _stream(stream))
-        self._check(st, "compress_batch")
-        if not views:
-            return outs, sizes
-        if stream is not None:
-            stream.synchronize()
-        else:
-            torch.cuda.current_stream(xs[0].device).synchronize()
-        sz = sizes.cpu().tolist()
-        return [o[:s] for o, s in zip(outs, sz)]
+        """One pwrel_compress_batch call (see batch_request).  views=True:
+        synchronise and return each field's stream view; else (outs, sizes)
+        with the sizes still on the device."""
+        r = self.batch_request(xs, eps, models, use_net, judge, independent, blocks, outs,
+                               sizes)
+        r.run(stream)
+        return r.views(stream) if views else (r.outs, r.sizes)
 
     def decompress(self, stream_t, shape=None, dtype=None, out=None, stream=None):
         import torch
@@ -655,6 +643,75 @@ class Context:
 
 
 # --- stream inspection (host copies of the sections) ------------------------------
+
+class BatchRequest:
+    """Arguments of pwrel_compress_batch built once (field table, models,
+    options, outputs); run() passes them to the library."""
+
+    def __init__(self, ctx, xs, eps, models, use_net, judge, independent, blocks, outs, sizes):
+        import torch
+        n = len(xs)
+        self.ctx, self.xs, self.eps = ctx, list(xs), float(eps)
+        blocks = dict(blocks or {})
+        self.bs = (C.c_int * 3)(0, int(blocks.get(2, 16)), int(blocks.get(3, 8)))
+        if outs is None:
+            outs = []
+            for x in xs:
+                cap = compress_bound(x.shape, _dtype_code(x.dtype), self.bs[x.dim() - 1])
+                outs.append(torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device))
+        if sizes is None:
+            sizes = torch.zeros(n, dtype=torch.int64, device=xs[0].device)
+        self.outs, self.sizes = list(outs), sizes
+        self.descs = (FieldDesc * n)()
+        for i, (x, o) in enumerate(zip(xs, outs)):
+            assert x.is_cuda and x.is_contiguous()
+            d = self.descs[i]
+            d.d_field = x.data_ptr()
+            for k, s in enumerate(x.shape):
+                d.dims[k] = int(s)
+            d.ndim = x.dim()
+            d.d_out = o.data_ptr()
+            d.out_capacity = o.numel()
+        self.keep = {}
+        self.mptrs = (C.POINTER(Mlp) * 3)()
+        if use_net:
+            for nd, m in (models or {}).items():
+                self.keep[nd] = model_struct(m)
+                self.mptrs[nd - 1] = C.pointer(self.keep[nd])
+        self.opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
+        self.dt = _dtype_code(xs[0].dtype) if n else F32
+
+    def tune(self, reps=3, stream=None):
+        """pwrel_compress_batch_tune over this request: returns (variants
+        [3-D, 2-D], median ms [class][variant]); the context keeps them."""
+        c = self.ctx
+        var = (C.c_int * 2)()
+        ms = (C.c_double * (2 * BATCH_TILES))()
+        st = c._L.pwrel_compress_batch_tune(c.h, len(self.xs), self.descs, self.dt, self.eps,
+                                            C.cast(self.bs, C.c_void_p), self.mptrs,
+                                            C.byref(self.opt), C.c_void_p(self.sizes.data_ptr()),
+                                            int(reps), var, ms, _stream(stream))
+        c._check(st, "compress_batch_tune")
+        return list(var), [list(ms[k * BATCH_TILES:(k + 1) * BATCH_TILES]) for k in range(2)]
+
+    def run(self, stream=None):
+        c = self.ctx
+        st = c._L.pwrel_compress_batch(c.h, len(self.xs), self.descs, self.dt, self.eps,
+                                       C.cast(self.bs, C.c_void_p), self.mptrs,
+                                       C.byref(self.opt), C.c_void_p(self.sizes.data_ptr()),
+                                       _stream(stream))
+        c._check(st, "compress_batch")
+
+    def views(self, stream=None):
+        """Synchronise `stream` and return each field's stream (empty where
+        the field failed)."""
+        import torch
+        if stream is not None:
+            stream.synchronize()
+        else:
+            torch.cuda.current_stream(self.sizes.device).synchronize()
+        return [o[:s] for o, s in zip(self.outs, self.sizes.cpu().tolist())]
+
 
 def header(stream_t):
     """Parse and validate the header of a device stream tensor."""

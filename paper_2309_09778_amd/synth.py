@@ -130,25 +130,30 @@ def batch_shapes(n_fields=2000, seed=3000, lo2=128, hi2=1024, lo3=32, hi3=256):
 
 
 def lognormal_grf_device(shape, seed=0, decades=8.0, neg_frac=0.10, zero_frac=0.005, slope=3.0,
-                         dtype=None, device="cuda"):
+                         dtype=None, device="cuda", pad_pow2=False):
     """The lognormal_grf recipe drawn on the GPU with torch (for fields of
     gigabytes, where the host FFT would take minutes).  The numbers differ
     from lognormal_grf's (another generator) but follow the same recipe; the
     sign threshold is the (1 - neg_frac) quantile of a 2^24-value subsample of
-    its field.  Returns a torch tensor on `device`."""
+    its field.  pad_pow2: each Gaussian field is drawn on the grid of the
+    next powers of two and cropped to `shape` (one FFT plan per power-of-two
+    shape instead of one per shape, for batches of many uneven shapes).
+    Returns a torch tensor on `device`."""
     import torch
     dtype = torch.float32 if dtype is None else dtype
     shape = tuple(int(s) for s in shape)
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
 
+    gshape = tuple(1 << max(0, (n - 1).bit_length()) for n in shape) if pad_pow2 else shape
+
     def grf():
-        white = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+        white = torch.randn(gshape, generator=gen, device=device, dtype=torch.float64)
         spec = torch.fft.rfftn(white)
         del white
         k2 = None
-        for ax, n in enumerate(shape):
-            if ax == len(shape) - 1:
+        for ax, n in enumerate(gshape):
+            if ax == len(gshape) - 1:
                 f = torch.fft.rfftfreq(n, device=device, dtype=torch.float64) * n
             else:
                 f = torch.fft.fftfreq(n, device=device, dtype=torch.float64) * n
@@ -160,8 +165,10 @@ def lognormal_grf_device(shape, seed=0, decades=8.0, neg_frac=0.10, zero_frac=0.
                           torch.zeros((), dtype=torch.float64, device=device))
         spec *= amp
         del amp, k2
-        g = torch.fft.irfftn(spec, s=shape)
+        g = torch.fft.irfftn(spec, s=gshape)
         del spec
+        if gshape != shape:
+            g = g[tuple(slice(0, n) for n in shape)].contiguous()
         g -= g.mean()
         sd = g.std()
         if sd > 0:

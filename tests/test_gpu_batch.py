@@ -205,3 +205,31 @@ def test_batch_graph_replay(ctx):
         for i, w in enumerate(want):
             assert sz[i] == w.size, (rep, i)
             assert np.array_equal(outs[i][:sz[i]].cpu().numpy(), w), (rep, i)
+
+
+def test_batch_tile_variants_and_tuner(ctx):
+    """Every tile shape variant writes the same streams; the tuner keeps a
+    valid variant per class and leaves the request's outputs written."""
+    print("batch tile variants", flush=True)
+    models = make_models(CASES["bf16_judge"]["models"])
+    xs = fields(seed0=1300)
+    want = single(ctx, xs, 1e-2, models, judge=True)
+    try:
+        for v in range(pwrel.BATCH_TILES):
+            var, shapes = ctx.batch_tiles([v, v])
+            assert var == [v, v]
+            got = ctx.compress_batch(xs, 1e-2, models=models, judge=True)
+            for i, w in enumerate(want):
+                assert np.array_equal(got[i].cpu().numpy(), w), (v, i, shapes)
+        with pytest.raises(pwrel.PwrelError):
+            ctx.batch_tiles([pwrel.BATCH_TILES, 0])
+        req = ctx.batch_request(xs, 1e-2, models=models, judge=True)
+        var, ms = req.tune(reps=2)
+        assert all(0 <= v < pwrel.BATCH_TILES for v in var)
+        assert ctx.batch_tiles()[0] == var
+        assert all(m > 0 for m in ms[0]) and all(m > 0 for m in ms[1])
+        got = req.views()
+        for i, w in enumerate(want):
+            assert np.array_equal(got[i].cpu().numpy(), w), ("tuned", i)
+    finally:
+        ctx.batch_tiles([0, 0])
