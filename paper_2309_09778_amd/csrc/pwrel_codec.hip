@@ -987,23 +987,41 @@ __global__ void __launch_bounds__(1024) k_batch_scan_partials(const BatchField *
     scan_partials(partials + b.chunk0, b.nchunks, b.n_raw);
 }
 
-// raw values: one wave per block of the batch's block numbering
+// raw values: one wave per scan chunk (kScanChunk blocks) of the batch's
+// chunk numbering; a chunk without balance points (its exclusive offsets
+// equal the next chunk's) is skipped whole, and within a chunk only the
+// blocks with a non-zero count are walked.
 template <typename T>
 __global__ void __launch_bounds__(256) k_batch_scatter(const BatchField *f, int nf,
-                                                       long long nblocks,
+                                                       long long nchunks,
                                                        const unsigned long long *offs,
                                                        const unsigned long long *partials)
 {
-    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-    for (long long k = wave; k < nblocks; k += nwaves) {
-        const int i = batch_field_of(f, nf, k, [](const BatchField &b) { return b.blk0; });
-        const BatchField &b = f[i];
-        if (*b.status != kOk)
-            continue;  // wave-uniform
-        scatter_block<T>(static_cast<const T *>(b.x), b.g, b.codes, b.counts, offs + b.blk0,
-                         partials + b.chunk0, static_cast<T *>(b.raw), b.raw_cap, b.status,
-                         k - b.blk0);
+    const long long c = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (c >= nchunks)
+        return;  // wave-uniform
+    const int lane = threadIdx.x & 63;
+    const int i = __builtin_amdgcn_readfirstlane(
+        batch_field_of(f, nf, c, [](const BatchField &b) { return b.chunk0; }));
+    const BatchField &b = f[i];
+    if (*b.status != kOk)
+        return;  // wave-uniform
+    const long long lc = c - b.chunk0;
+    const unsigned long long hi = lc + 1 < b.nchunks ? partials[c + 1] : *b.n_raw;
+    if (hi == partials[c])
+        return;
+    const long long b0 = lc * kScanChunk, b1 = std::min(b.g.nblocks, b0 + kScanChunk);
+    for (long long k0 = b0; k0 < b1; k0 += 64) {
+        const long long k = k0 + lane;
+        const unsigned cnt = k < b1 ? b.counts[k] : 0u;
+        unsigned long long m = __ballot(cnt != 0u);
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1ULL;
+            scatter_block<T>(static_cast<const T *>(b.x), b.g, b.codes, b.counts, offs + b.blk0,
+                             partials + b.chunk0, static_cast<T *>(b.raw), b.raw_cap, b.status,
+                             k0 + j);
+        }
     }
 }
 
@@ -1035,13 +1053,14 @@ hipError_t launch_batch_back(const BatchField *d_fields, int nf, int dtype, long
     hipLaunchKernelGGL(k_batch_scan_local, dim3((unsigned)nchunks), dim3(256), 0, s, d_fields,
                        nf, offsets, partials);
     hipLaunchKernelGGL(k_batch_scan_partials, dim3(nf), dim3(1024), 0, s, d_fields, partials);
-    const unsigned grid = grid_for(nblocks, 4, 16384);
+    (void)nblocks;
+    const unsigned grid = (unsigned)((nchunks + 3) / 4);
     if (dtype == PWREL_F32)
         hipLaunchKernelGGL(k_batch_scatter<float>, dim3(grid), dim3(256), 0, s, d_fields, nf,
-                           nblocks, offsets, partials);
+                           nchunks, offsets, partials);
     else
         hipLaunchKernelGGL(k_batch_scatter<double>, dim3(grid), dim3(256), 0, s, d_fields, nf,
-                           nblocks, offsets, partials);
+                           nchunks, offsets, partials);
     if (models)
         hipLaunchKernelGGL(k_batch_model, dim3(nf), dim3(256), 0, s, d_fields, models);
     hipLaunchKernelGGL(k_batch_header, dim3(nf), dim3(256), 0, s, d_fields);

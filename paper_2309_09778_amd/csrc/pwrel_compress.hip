@@ -980,14 +980,24 @@ __global__ void __launch_bounds__(256) k_grid_entries_batch(const BatchField *fi
         else
             hi = mid - 1;
     }
-    const BatchField &f = fields[lo];
+    const BatchField &f = fields[__builtin_amdgcn_readfirstlane(lo)];
     if (*f.status != kOk)
         return;  // no barrier below: a per-thread exit is safe
     const DevConsts c = *f.consts;
     const float *x = static_cast<const float *>(f.x);
     const long long b0 = (k - f.echunk0) * kEntryChunk, b1 = std::min(f.N, b0 + kEntryChunk);
     int err = kOk;
-    for (long long i = b0 + threadIdx.x; i < b1; i += 256)
+    // four values per 16-byte load and store where the field is 16-byte
+    // aligned (chunk starts are multiples of 4 values, entry rows of 64)
+    const long long n4 = f.vec ? (b1 - b0) >> 2 : 0;
+    const float4 *x4 = reinterpret_cast<const float4 *>(x + b0);
+    int4 *e4 = reinterpret_cast<int4 *>(f.pgrid + b0);
+    for (long long i = threadIdx.x; i < n4; i += 256) {
+        const float4 v = x4[i];
+        e4[i] = make_int4(grid_entry(v.x, c, err), grid_entry(v.y, c, err),
+                          grid_entry(v.z, c, err), grid_entry(v.w, c, err));
+    }
+    for (long long i = b0 + 4 * n4 + threadIdx.x; i < b1; i += 256)
         f.pgrid[i] = grid_entry(x[i], c, err);
     set_status(f.status, err);
 }
