@@ -97,33 +97,20 @@ __device__ __forceinline__ void judge_hash_add(unsigned *tab, int hc, unsigned c
 }
 
 // The judge's scores of one block held by a wave: each 32-bit key carries the
-// network's code (low half) and Lorenzo's (high half) of one point; elements
-// i = k 64 + lane, k < EPL; nsent of them are stand-ins (0xFFFF in both
-// halves) for positions outside the field.  Returns, for each half, the sum
-// over its distinct codes of c q(c), c = the code's multiplicity.  Both
-// halves are sorted at once (wave_sort_pk16); stand-ins sort last and are
-// taken off the last run of each half.
+// network's code (low half) and Lorenzo's (high half) of one point, EPL keys
+// a lane in any order; nsent of them are stand-ins (0xFFFF in both halves)
+// for positions outside the field.  Returns, for each half, the sum over its
+// distinct codes of c q(c), c = the code's multiplicity.  Both halves are
+// sorted at once (wave_sort_lm); stand-ins sort last and are taken off the
+// last run of each half.
 template <int EPL>
 __device__ __forceinline__ void wave_multiset_score(unsigned (&a)[EPL], unsigned nsent,
                                                     const long long *qtab,
                                                     unsigned long long &s0,
                                                     unsigned long long &s1)
 {
-    wave_sort_pk16<EPL>(a);
-    unsigned long long J[2] = {0ULL, 0ULL};
-    wave_runs_pk16<EPL>(a, [&](int h, unsigned key, int c) {
-        if (key == 0xFFFFu)
-            c -= (int)nsent;
-        if (c > 0)
-            J[h] += (unsigned long long)c * (unsigned long long)qtab[c];
-    });
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        J[0] += (unsigned long long)__shfl_xor((long long)J[0], o, 64);
-        J[1] += (unsigned long long)__shfl_xor((long long)J[1], o, 64);
-    }
-    s0 = J[0];
-    s1 = J[1];
+    wave_sort_lm<EPL>(a);
+    wave_runs_lm<EPL>(a, nsent, qtab, s0, s1);
 }
 
 __device__ __forceinline__ int judge_bin(unsigned code)
