@@ -219,55 +219,91 @@ __device__ __forceinline__ float forward_pair(const float *th, int H, const floa
     return y - ts;
 }
 
-// gradient of parameter p over the minibatch held in LDS (gy = d loss / d y
-// per pair, z = hidden pre-activations); the leaky-ReLU slope at 0 is 1
+// Minibatch rows in LDS padded to an odd number of words, so that the
+// threads of a wave, one pair each, meet distinct banks
+constexpr int kUsRow = 9;   // scaled inputs (K <= 6)
+constexpr int kZzRow = 33;  // hidden pre-activations (H <= 32)
+
+// data part of the gradient of parameter p over pairs i0 .. i1 - 1 of the
+// minibatch held in LDS (gy = d loss / d y per pair, z = hidden
+// pre-activations); the leaky-ReLU slope at 0 is 1.  The regularisation term
+// is added by the caller.
 template <int K>
-__device__ __forceinline__ float grad_param(int p, int H, int nb, const float (*us)[8],
-                                            const float *gy, const float (*zz)[32],
-                                            const float *th, float alpha, float lambda)
+__device__ __forceinline__ float grad_part(int p, int H, int i0, int i1, const float (*us)[kUsRow],
+                                           const float *gy, const float (*zz)[kZzRow],
+                                           const float *th, float alpha)
 {
     float g = 0.0f;
     constexpr int KK = K > 0 ? K : 1;
     const float *v = th + H * K + H;
     if (p < H * K) {
         const int j = p / KK, k = p % KK;
-        for (int i = 0; i < nb; ++i) {
+#pragma unroll 4
+        for (int i = i0; i < i1; ++i) {
             const float gz = gy[i] * v[j] * (zz[i][j] < 0.0f ? alpha : 1.0f);
             g = __builtin_fmaf(gz, us[i][k], g);
         }
-        g = __builtin_fmaf(lambda, th[p], g);
     } else if (p < H * K + H) {
         const int j = p - H * K;
-        for (int i = 0; i < nb; ++i)
+#pragma unroll 4
+        for (int i = i0; i < i1; ++i)
             g += gy[i] * v[j] * (zz[i][j] < 0.0f ? alpha : 1.0f);
     } else if (p < H * K + 2 * H) {
         const int j = p - H * K - H;
-        for (int i = 0; i < nb; ++i) {
+#pragma unroll 4
+        for (int i = i0; i < i1; ++i) {
             const float z = zz[i][j];
             g = __builtin_fmaf(gy[i], z < 0.0f ? alpha * z : z, g);
         }
-        g = __builtin_fmaf(lambda, th[p], g);
     } else {
-        for (int i = 0; i < nb; ++i)
+#pragma unroll 4
+        for (int i = i0; i < i1; ++i)
             g += gy[i];
     }
     return g;
 }
 
+// whether parameter p carries the L2 term (first- and second-layer weights)
+__device__ __forceinline__ bool regularised(int p, int H, int K)
+{
+    return p < H * K || (p >= H * K + H && p < H * K + 2 * H);
+}
+
+// gradient of parameter p over the whole minibatch
+template <int K>
+__device__ __forceinline__ float grad_param(int p, int H, int nb, const float (*us)[kUsRow],
+                                            const float *gy, const float (*zz)[kZzRow],
+                                            const float *th, float alpha, float lambda)
+{
+    float g = grad_part<K>(p, H, 0, nb, us, gy, zz, th, alpha);
+    if (regularised(p, H, K))
+        g = __builtin_fmaf(lambda, th[p], g);
+    return g;
+}
+
 struct TrainSmem {
     float th[kMaxParams], m[kMaxParams], v[kMaxParams];
-    float us[256][8];
+    float us[256][kUsRow];
     float gy[256];
-    float zz[256][32];
+    float zz[256][kZzRow];
     float loss[256];
 };
 
+// One workgroup of kTrainThreads per candidate: a minibatch's forward pass
+// by one thread per pair, then each parameter's gradient by kGradSplit
+// threads over a share of the pairs each (their partial sums added in a
+// fixed order), then the Adam step.
+constexpr int kTrainThreads = 1024;
+constexpr int kGradSplit = 4;
+
 template <int HM, int K>
-__global__ void __launch_bounds__(256) k_train(TrainArgs a)
+__global__ void __launch_bounds__(kTrainThreads) k_train(TrainArgs a)
 {
     __shared__ TrainSmem sm;
     const int H = a.H, P = H * K + 2 * H + 1;
     const int tid = threadIdx.x, cand = blockIdx.x;
+    const int part = tid % kGradSplit, prow = tid / kGradSplit;
+    constexpr int PROWS = kTrainThreads / kGradSplit;
     const float lr = (float)a.lr[cand], lam = (float)a.lambda[cand];
     const float inv_sigma = (float)(1.0 / *a.sigma);
     for (int p = tid; p < P; p += blockDim.x) {
@@ -293,18 +329,37 @@ __global__ void __launch_bounds__(256) k_train(TrainArgs a)
             __syncthreads();
             ++step;
             const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
-            float gnew[2];
-            for (int p = tid, q = 0; p < P; p += blockDim.x, ++q)
-                gnew[q] = grad_param<K>(p, H, nb, sm.us, sm.gy, sm.zz, sm.th, a.alpha, lam);
+            // pairs of this thread's share (contiguous)
+            const int per = (nb + kGradSplit - 1) / kGradSplit;
+            const int i0 = part * per, i1 = i0 + per < nb ? i0 + per : nb;
+            float gnew[(kMaxParams + PROWS - 1) / PROWS];
+#pragma unroll
+            for (int q = 0; q < (kMaxParams + PROWS - 1) / PROWS; ++q) {
+                const int p = prow + q * PROWS;
+                float g = p < P ? grad_part<K>(p, H, i0, i1, sm.us, sm.gy, sm.zz, sm.th, a.alpha)
+                                : 0.0f;
+                // the kGradSplit shares sit in consecutive lanes: add them pairwise
+                g += __shfl_xor(g, 1, kGradSplit);
+                g += __shfl_xor(g, 2, kGradSplit);
+                if (p < P && regularised(p, H, K))
+                    g = __builtin_fmaf(lam, sm.th[p], g);
+                gnew[q] = g;
+            }
             // every gradient reads theta before any update writes it
             __syncthreads();
-            for (int p = tid, q = 0; p < P; p += blockDim.x, ++q) {
-                const float g = gnew[q];
-                const float mm = 0.9f * sm.m[p] + 0.1f * g;
-                const float vv = 0.999f * sm.v[p] + 0.001f * g * g;
-                sm.m[p] = mm;
-                sm.v[p] = vv;
-                sm.th[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
+            if (part == 0) {
+#pragma unroll
+                for (int q = 0; q < (kMaxParams + PROWS - 1) / PROWS; ++q) {
+                    const int p = prow + q * PROWS;
+                    if (p >= P)
+                        continue;
+                    const float g = gnew[q];
+                    const float mm = 0.9f * sm.m[p] + 0.1f * g;
+                    const float vv = 0.999f * sm.v[p] + 0.001f * g * g;
+                    sm.m[p] = mm;
+                    sm.v[p] = vv;
+                    sm.th[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
+                }
             }
             __syncthreads();
         }
@@ -509,11 +564,11 @@ template <int H>
 static void train_k(int K, const TrainArgs &a, int ncand, hipStream_t s)
 {
     if (K == 6)
-        hipLaunchKernelGGL((k_train<H, 6>), dim3(ncand), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_train<H, 6>), dim3(ncand), dim3(kTrainThreads), 0, s, a);
     else if (K == 2)
-        hipLaunchKernelGGL((k_train<H, 2>), dim3(ncand), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_train<H, 2>), dim3(ncand), dim3(kTrainThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_train<H, 0>), dim3(ncand), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_train<H, 0>), dim3(ncand), dim3(kTrainThreads), 0, s, a);
 }
 
 hipError_t launch_train(int H, int K, const TrainArgs &a, int ncand, hipStream_t s)
