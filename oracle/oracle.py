@@ -118,6 +118,16 @@ def lib():
         L.or_judge_j.argtypes = [P, C.c_int64]
         L.or_qlog.restype = C.c_int64
         L.or_qlog.argtypes = [C.c_int64]
+        L.or_tcoord.restype = C.c_double
+        L.or_tcoord.argtypes = [C.c_double, C.POINTER(_Consts)]
+        L.or_tinverse.restype = C.c_double
+        L.or_tinverse.argtypes = [C.c_double, C.POINTER(_Consts), C.c_int]
+        L.or_openloop_encode.argtypes = [P, P, C.c_int, C.c_int, C.c_double, C.c_int,
+                                         C.POINTER(_MLP), C.c_int, C.c_int, P, P, P,
+                                         C.POINTER(C.c_uint64), P, C.POINTER(_Consts)]
+        L.or_openloop_decode.argtypes = [P, P, C.c_uint64, C.POINTER(_Consts), P, C.c_int,
+                                         C.c_int, C.c_int, C.POINTER(_MLP), C.c_int, P, P]
+        L.or_openloop_choose_m.argtypes = [P, C.c_double]
         for fn in ("or_sizeof_mlp", "or_sizeof_consts", "or_sizeof_stats"):
             getattr(L, fn).restype = C.c_size_t
         assert L.or_sizeof_mlp() == C.sizeof(_MLP)
@@ -562,3 +572,78 @@ def train_rule(p, c, B, init, rho=0.10, seed=0, lrs=DEFAULT_LRS, lambdas=DEFAULT
     if st < 0:
         raise OracleError(st, "train_rule")
     return _from_c_mlp(out), st, ntr.value, nva.value
+
+
+# --- open-loop mode (the paper's literal data selection; Sec. 4.3, 4.4) ------------------------
+
+def tcoord(x, c):
+    """Continuous grid coordinate of each value of x (before rounding)."""
+    cs = _consts_struct(c)
+    xf = np.asarray(x, dtype=np.float64).ravel()
+    return np.array([lib().or_tcoord(float(v), C.byref(cs)) for v in xf]).reshape(np.shape(x))
+
+
+def tinverse(t, c, dtype):
+    cs = _consts_struct(c)
+    dc = 0 if np.dtype(dtype) == np.float32 else 1
+    tf = np.asarray(t, dtype=np.float64).ravel()
+    out = np.array([lib().or_tinverse(float(v), C.byref(cs), dc) for v in tf])
+    return out.astype(dtype).reshape(np.shape(t))
+
+
+def openloop_encode(x, eps, B, model=None, mbits=16, gap=0):
+    """Open-loop compression (independent blocks); returns dict(codes,
+    counts, raw, hist, consts)."""
+    x = np.ascontiguousarray(x)
+    dims = _dims(x.shape)
+    N, nb = x.size, nblocks(x.shape, B)
+    codes = np.zeros(N, dtype=np.uint16)
+    counts = np.zeros(nb, dtype=np.uint32)
+    raw = np.zeros(N, dtype=x.dtype)
+    hist = np.zeros(18, dtype=np.uint64)
+    nraw = C.c_uint64(0)
+    c = _Consts()
+    m = _to_c_mlp(model)
+    st = lib().or_openloop_encode(_ptr(x), _ptr(dims), x.ndim, _dtype_code(x), float(eps), B,
+                                  C.byref(m) if m is not None else None, int(mbits), int(gap),
+                                  _ptr(codes), _ptr(counts), _ptr(raw), C.byref(nraw),
+                                  _ptr(hist), C.byref(c))
+    _check(st, "openloop_encode")
+    return {"codes": codes, "counts": counts, "raw": raw[:nraw.value].copy(), "hist": hist,
+            "consts": {k: getattr(c, k) for k, _ in _Consts._fields_}}
+
+
+def openloop_decode(codes, raw, c, shape, dtype, B, model=None, mbits=16):
+    """Open-loop decompression; returns (x^, reconstructed coordinates)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    raw = np.ascontiguousarray(raw, dtype=dtype)
+    dims = _dims(shape)
+    xh = np.zeros(shape, dtype=dtype)
+    t = np.zeros(shape, dtype=np.float64)
+    cs = _consts_struct(c)
+    m = _to_c_mlp(model)
+    st = lib().or_openloop_decode(_ptr(codes), _ptr(raw), raw.size, C.byref(cs), _ptr(dims),
+                                  len(shape), _dtype_code(xh), B,
+                                  C.byref(m) if m is not None else None, int(mbits), _ptr(xh),
+                                  _ptr(t))
+    _check(st, "openloop_decode")
+    return xh, t
+
+
+def openloop_choose_m(hist, eps):
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    return int(lib().or_openloop_choose_m(_ptr(h), float(eps)))
+
+
+def openloop_report(x, xh, eps):
+    """Violations of the PW_REL bound (sign and zero included) and the
+    largest relative error over the non-zero values."""
+    xd, hd = np.asarray(x, np.float64).ravel(), np.asarray(xh, np.float64).ravel()
+    nz = xd != 0
+    bad = np.zeros(xd.size, dtype=bool)
+    bad[~nz] = hd[~nz] != 0
+    with np.errstate(invalid="ignore", over="ignore"):
+        rel = np.where(nz, np.abs(xd - hd) / np.where(nz, np.abs(xd), 1.0), 0.0)
+    bad[nz] = (np.signbit(xd[nz]) != np.signbit(hd[nz])) | (hd[nz] == 0) | \
+        ~(np.abs(xd[nz] - hd[nz]) <= eps * np.abs(xd[nz]))
+    return {"violations": int(bad.sum()), "max_rel": float(np.max(rel)) if rel.size else 0.0}

@@ -1653,3 +1653,223 @@ void or_mlp_eval_f64_many(const or_mlp *m, const float *u, int64_t n, double *y,
 size_t or_sizeof_mlp(void) { return sizeof(or_mlp); }
 size_t or_sizeof_consts(void) { return sizeof(or_consts); }
 size_t or_sizeof_stats(void) { return sizeof(or_stats); }
+
+/* ------------------------------------------------------------------------ */
+/* Open-loop mode: the paper's literal data selection (Sec. 4.4.1, 4.4.2).  */
+/* The compressor predicts every point from its neighbours' raw values in   */
+/* the log domain (continuous grid coordinates, before rounding), so all    */
+/* points are predicted independently; the decompressor can only predict   */
+/* from its own reconstructions, so reconstruction errors can accumulate.   */
+/* The controls the paper gives against that drift:                          */
+/*   - balance (equilibrium) points, stored raw and exact: codes out of the  */
+/*     m-bit range (Sec. 4.3, Sec. 5), the first point of every block (each  */
+/*     sub-block starts decompression from a balance point, Sec. 4.4.2), and */
+/*     deliberate ones: a point becomes one when `gap` points in a row of    */
+/*     its block carried none (Sec. 4.4.1(b); gap 0 = none inserted);        */
+/*   - m chosen by coverage, the share of points whose code is in range:    */
+/*     closest to 50% below a 1.5% bound, to 80% from 1.5% up (Sec. 4.3);   */
+/*   - a model is accepted if the decompressed error stays within 1.5 times */
+/*     the bound (Sec. 4.3).                                                 */
+/* Independent blocks only.  Codes: e = pred - t, c = rint(e); code c + 2^(m-1) */
+/* where |c| < 2^(m-1), else 0 (balance point).                              */
+/* ------------------------------------------------------------------------ */
+
+/* continuous grid coordinate of x (the grid value before rounding, Eq. 6, 7) */
+static double tcoord(double x, const or_consts *c)
+{
+    if (x == 0.0)
+        return (double)c->p_zero;
+    if (x > 0.0)
+        return (or_det_log2(x) + c->Lp) * c->r;
+    return (or_det_log2(-x) + c->Ln) * c->r + (double)c->delta;
+}
+
+/* inverse of a continuous coordinate: zero / positive / negative by its
+ * nearest grid value, magnitude from the coordinate itself */
+static double tinverse(double t, const or_consts *c, int dtype)
+{
+    double q = rint(t);
+    double v;
+    if (q <= (double)c->p_zero)
+        v = 0.0;
+    else if (q <= (double)c->b_sign)
+        v = or_det_exp2(t * c->w - c->Lp);
+    else
+        v = -or_det_exp2((t - (double)c->delta) * c->w - c->Ln);
+    return cast_t(v, dtype);
+}
+
+double or_tcoord(double x, const or_consts *c) { return tcoord(x, c); }
+double or_tinverse(double t, const or_consts *c, int dtype) { return tinverse(t, c, dtype); }
+
+/* prediction of point c from coordinates T of its block's neighbours:
+ * network (FP32 on u_k = float(t_{k+2} - t_1)) where every neighbour exists,
+ * else Lorenzo over the available ones, added in offset order */
+static double ol_predict(const geom *g, const double *T, const int64_t *c, const or_mlp *m)
+{
+    int no = (1 << g->D) - 1;
+    double nv[8];
+    int avail = 0, all = 1;
+    for (int o = 1; o <= no; ++o) {
+        int64_t q[3];
+        if (neighbour(g, c, o, 1, q)) {
+            nv[o] = T[lin(g, q)];
+            avail |= 1 << o;
+        } else {
+            nv[o] = 0.0;
+            all = 0;
+        }
+    }
+    if (m && all) {
+        float u[OR_MAXK];
+        for (int k = 0; k < m->inputs; ++k)
+            u[k] = (float)(nv[k + 2] - nv[1]);
+        return nv[1] + (double)mlp_eval_f32(m, u);
+    }
+    double s = 0.0;
+    for (int o = 1; o <= no; ++o)
+        if (avail & (1 << o))
+            s = lorenzo_coef(o) > 0 ? s + nv[o] : s - nv[o];
+    return s;
+}
+
+/* smallest m with |c| < 2^(m-1) (1 for c = 0), 17 when no m <= 16 covers it */
+static int m_needed(double c)
+{
+    double a = fabs(c);
+    for (int m = 1; m <= 16; ++m)
+        if (a < ldexp(1.0, m - 1))
+            return m;
+    return 17;
+}
+
+/* Open-loop compression.  Outputs (caller-allocated): codes[N] (stream
+ * order), counts[nblocks], raw (dtype, capacity N) and n_raw, hist[18]
+ * (hist[m] = points whose prediction error first fits m bits, before any
+ * balance point is forced), consts.  m: model or NULL (Lorenzo). */
+int or_openloop_encode(const void *x, const uint64_t *dims, int ndim, int dtype, double eps,
+                       int B, const or_mlp *m, int mbits, int gap, uint16_t *codes,
+                       uint32_t *counts, void *raw, uint64_t *n_raw, uint64_t *hist,
+                       or_consts *consts)
+{
+    geom g;
+    int st = geom_init(&g, dims, ndim, B);
+    if (st)
+        return st;
+    if ((dtype != OR_F32 && dtype != OR_F64) || mbits < 2 || mbits > 16 || gap < 0)
+        return OR_EINVAL;
+    if (m && (m->inputs != (1 << ndim) - 2 || m->hidden < 1 || m->hidden > OR_MAXH))
+        return OR_EINVAL;
+    or_stats sts;
+    st = or_stats_compute(x, (uint64_t)g.N, dtype, &sts);
+    if (st)
+        return st;
+    st = or_consts_compute(&sts, dtype, eps, consts);
+    if (st)
+        return st;
+    double *T = (double *)malloc((size_t)g.N * sizeof(double));
+    if (!T)
+        return OR_ENOMEM;
+    for (int64_t i = 0; i < g.N; ++i)
+        T[i] = tcoord(load_val(x, dtype, (uint64_t)i), consts);
+    for (int j = 0; j < 18; ++j)
+        hist[j] = 0;
+    const double half = ldexp(1.0, mbits - 1);
+    uint64_t nr = 0;
+    iter it;
+    it_init(&it, &g);
+    while (!it.done) {
+        int64_t b = it.block, since = 0, k = 0;
+        uint32_t cnt = 0;
+        do {
+            int64_t i = lin(&g, it.c);
+            double cq = rint(ol_predict(&g, T, it.c, m) - T[i]);
+            hist[m_needed(cq)]++;
+            int balance = !(fabs(cq) < half);
+            if (k == 0)
+                balance = 1; /* the block's starting point */
+            else if (!balance && gap > 0 && since + 1 >= gap)
+                balance = 1; /* deliberate */
+            since = balance ? 0 : since + 1;
+            uint16_t cd = balance ? 0 : (uint16_t)(cq + half);
+            codes[it.pos] = cd;
+            if (cd == 0) {
+                store_val(raw, dtype, nr++, load_val(x, dtype, (uint64_t)i));
+                cnt++;
+            }
+            k++;
+        } while (!it_next(&it));
+        counts[b] = cnt;
+    }
+    free(T);
+    *n_raw = nr;
+    return OR_OK;
+}
+
+/* Open-loop decompression: blocks and points in stream order, each point
+ * predicted from the reconstructed coordinates of its block. */
+int or_openloop_decode(const uint16_t *codes, const void *raw, uint64_t n_raw, const or_consts *c,
+                       const uint64_t *dims, int ndim, int dtype, int B, const or_mlp *m,
+                       int mbits, void *xh, double *t_out)
+{
+    geom g;
+    int st = geom_init(&g, dims, ndim, B);
+    if (st)
+        return st;
+    if (mbits < 2 || mbits > 16)
+        return OR_EINVAL;
+    double *T = t_out ? t_out : (double *)malloc((size_t)g.N * sizeof(double));
+    if (!T)
+        return OR_ENOMEM;
+    const double half = ldexp(1.0, mbits - 1);
+    uint64_t kr = 0;
+    iter it;
+    it_init(&it, &g);
+    int status = OR_OK;
+    while (!it.done && status == OR_OK) {
+        do {
+            int64_t i = lin(&g, it.c);
+            uint16_t cd = codes[it.pos];
+            if (cd == 0) {
+                if (kr >= n_raw) {
+                    status = OR_EINVAL;
+                    break;
+                }
+                double v = load_val(raw, dtype, kr++);
+                store_val(xh, dtype, (uint64_t)i, v);
+                T[i] = tcoord(v, c);
+            } else {
+                T[i] = ol_predict(&g, T, it.c, m) - ((double)cd - half);
+                store_val(xh, dtype, (uint64_t)i, tinverse(T[i], c, dtype));
+            }
+        } while (!it_next(&it));
+    }
+    if (!t_out)
+        free(T);
+    return status;
+}
+
+/* m whose coverage (share of points with |c| < 2^(m-1)) is closest to the
+ * target: 50% for eps below 1.5%, 80% from 1.5% up; ties to the smaller m */
+int or_openloop_choose_m(const uint64_t *hist, double eps)
+{
+    uint64_t n = 0;
+    for (int j = 0; j < 18; ++j)
+        n += hist[j];
+    double target = eps < 0.015 ? 0.5 : 0.8;
+    int best = 2;
+    double bestd = INFINITY;
+    uint64_t cum = 0;
+    for (int mm = 1; mm <= 16; ++mm) {
+        cum += hist[mm];
+        if (mm < 2)
+            continue;
+        double cov = n ? (double)cum / (double)n : 1.0;
+        double d = fabs(cov - target);
+        if (d < bestd) {
+            bestd = d;
+            best = mm;
+        }
+    }
+    return best;
+}

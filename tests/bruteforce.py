@@ -255,3 +255,90 @@ def decompress(codes, raw, c, shape, is_f32, B, model=None, independent=False):
 
 def f32_bits(v):
     return struct.unpack("<I", struct.pack("<f", v))[0]
+
+
+# --- open-loop mode (raw-coordinate prediction, drifting decoder) ----------------------
+
+def ol_coord(x, c):
+    """Continuous grid coordinate (before rounding)."""
+    if x == 0.0:
+        return float(c["p_zero"])
+    if x > 0:
+        return (det_log2(x) + c["Lp"]) * c["r"]
+    return (det_log2(-x) + c["Ln"]) * c["r"] + float(c["delta"])
+
+
+def ol_inverse(t, c, is_f32):
+    q = round(t)
+    if q <= c["p_zero"]:
+        v = 0.0
+    elif q <= c["b_sign"]:
+        v = det_exp2(t * c["w"] - c["Lp"])
+    else:
+        v = -det_exp2((t - float(c["delta"])) * c["w"] - c["Ln"])
+    return f32(v) if (is_f32 and math.isfinite(v)) else v
+
+
+def ol_predict(T, coord, shape, B, model):
+    D = len(shape)
+    nbr = {}
+    for o, step in offsets(D):
+        q = tuple(a - s for a, s in zip(coord, step))
+        if all(v >= 0 for v in q) and all(a // B == b // B for a, b in zip(q, coord)):
+            nbr[o] = T[q]
+    if model is not None and len(nbr) == (1 << D) - 1:
+        u = [f32(nbr[k + 2] - nbr[1]) for k in range((1 << D) - 2)]
+        return nbr[1] + net_value(model, u)
+    s = 0.0
+    for o, step in offsets(D):
+        if o in nbr:
+            s = s + nbr[o] if lorenzo_sign(step) > 0 else s - nbr[o]
+    return s
+
+
+def ol_compress(x, eps, B, model=None, mbits=16, gap=0):
+    """Returns codes, counts, raw, hist (hist[m] = errors first fitting m bits), consts."""
+    shape = x.shape
+    is_f32 = x.dtype.itemsize == 4
+    vals = {k: float(x[k]) for k in itertools.product(*[range(n) for n in shape])}
+    c = constants(list(vals.values()), is_f32, eps)
+    T = {k: ol_coord(v, c) for k, v in vals.items()}
+    half = 2 ** (mbits - 1)
+    nb = 1
+    for n in shape:
+        nb *= -(-n // B)
+    counts, codes, raw, hist = [0] * nb, [], [], [0] * 18
+    last_block, since = None, 0
+    for coord in stream_order(shape, B):
+        b = block_index(coord, shape, B)
+        cq = round(ol_predict(T, coord, shape, B, model) - T[coord])
+        need = next((m for m in range(1, 17) if abs(cq) < 2 ** (m - 1)), 17)
+        hist[need] += 1
+        first = b != last_block
+        last_block = b
+        balance = first or not abs(cq) < half
+        if not balance and gap > 0 and since + 1 >= gap:
+            balance = True
+        since = 0 if balance else since + 1
+        if balance:
+            codes.append(0)
+            raw.append(vals[coord])
+            counts[b] += 1
+        else:
+            codes.append(cq + half)
+    return codes, counts, raw, hist, c
+
+
+def ol_decompress(codes, raw, c, shape, is_f32, B, model=None, mbits=16):
+    half = 2 ** (mbits - 1)
+    T, xh = {}, {}
+    it = iter(raw)
+    for code, coord in zip(codes, stream_order(shape, B)):
+        if code:
+            T[coord] = ol_predict(T, coord, shape, B, model) - float(code - half)
+            xh[coord] = ol_inverse(T[coord], c, is_f32)
+        else:
+            v = next(it)
+            xh[coord] = v
+            T[coord] = ol_coord(v, c)
+    return xh, T
