@@ -304,6 +304,47 @@ int pwrel_compress_batch(pwrel_ctx *ctx, int n, const pwrel_field_desc *fields, 
  *      request's outputs written by the chosen variants and the stream
  *      synchronised.  Not under capture (PWREL_EINVAL).
  */
+/*
+ * pwrel_openloop: the paper's literal data selection (Sec. 4.4.1 and 4.4.2:
+ * predict from the neighbours' actual values), run as a measurement beside
+ * the codec.  The compressor predicts every point from its neighbours' raw
+ * log-domain values (the continuous grid coordinate (log2|x| + L) r, before
+ * rounding; Eq. 6, 7); the decompressor can only predict from its own
+ * reconstructions, so errors accumulate and the PW_REL bound can break.
+ * The paper's controls: balance points stored raw (Sec. 4.3, Sec. 5) at the
+ * first point of every block (Sec. 4.4.2), where a code leaves the m-bit
+ * range, and deliberately after `gap` points of a block without one
+ * (Sec. 4.4.1(b); gap 0 = none); m chosen by coverage (Sec. 4.3: closest to
+ * 50% below a 1.5% bound, to 80% from 1.5% up).  Independent blocks; the
+ * network (model, or NULL for Lorenzo) is evaluated in FP32 on
+ * u_k = float(t_{k+2} - t_1).  Codes: c = rint(prediction - t), code
+ * c + 2^(m-1) where |c| < 2^(m-1), 0 = balance point.
+ *   mbits        2..16, or 0: chosen by coverage (one more pass)
+ *   d_codes      uint16 [n] (device) block-major codes
+ *   d_counts     uint32 [nblocks] (device) balance points per block
+ *   d_raw        dtype [raw_capacity] (device) balance-point values, stream order
+ *   d_xhat       dtype [n] (device) the open-loop decoder's reconstruction
+ *   report       (host) n_raw, points violating the bound (sign and zero
+ *                included), the largest relative error, the histogram of the
+ *                bits the prediction errors need (hist[m]: first fitting m
+ *                bits, 17 = none), the m and gap used
+ * Synchronises `stream`.  PWREL_ENOSPC when raw_capacity is too small.
+ */
+typedef struct {
+    uint64_t n_raw;
+    uint64_t violations;
+    double max_rel_error;
+    uint64_t hist[18];
+    int32_t mbits;
+    int32_t gap;
+} pwrel_openloop_report;
+
+int pwrel_openloop(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                   int dtype, double rel_error_bound, int block_size, const pwrel_mlp *model,
+                   int mbits, int gap, uint16_t *d_codes, uint32_t *d_counts, void *d_raw,
+                   uint64_t raw_capacity, void *d_xhat, pwrel_openloop_report *report,
+                   void *stream);
+
 #define PWREL_BATCH_TILES 3
 int pwrel_batch_set_tiles(pwrel_ctx *ctx, const int *variant);
 int pwrel_batch_get_tiles(pwrel_ctx *ctx, int *variant, int *shapes);

@@ -45,6 +45,7 @@ struct pwrel_ctx {
     unsigned epoch = 0;
     void *hdr = nullptr;  // header of pwrel_compress_raw (PWREL_HEADER_BYTES)
     pwrel::BatchState *batch = nullptr;  // pwrel_compress_batch's workspace and table
+    pwrel::OlState *ol = nullptr;        // pwrel_openloop's scratch
 };
 
 namespace {
@@ -369,6 +370,7 @@ void pwrel_destroy(pwrel_ctx *ctx)
         for (hipEvent_t &e : ctx->ev)
             (void)hipEventDestroy(e);
     batch_release(ctx->batch);
+    ol_release(ctx->ol);
     delete ctx;
 }
 
@@ -426,6 +428,9 @@ int api_device(const pwrel_ctx *ctx) { return ctx->device; }
 int api_num_cus(const pwrel_ctx *ctx) { return ctx->num_cus; }
 const long long *api_qtab(const pwrel_ctx *ctx) { return ctx->ws.qtab; }
 BatchState *&api_batch_state(pwrel_ctx *ctx) { return ctx->batch; }
+OlState *&api_ol_state(pwrel_ctx *ctx) { return ctx->ol; }
+Workspace &api_ws(pwrel_ctx *ctx) { return ctx->ws; }
+int api_ensure_scan(pwrel_ctx *ctx, const Geom &g) { return ensure_scan(ctx, g); }
 
 // The compression launches (Algorithm 1): reset, statistics, constants, grid
 // values and bound checks (FP32), prediction / quantisation / judge, scan,

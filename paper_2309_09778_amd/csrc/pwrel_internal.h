@@ -347,6 +347,12 @@ const long long *api_qtab(const pwrel_ctx *ctx);  // the judge's q(c) table
 struct BatchState;
 BatchState *&api_batch_state(pwrel_ctx *ctx);
 void batch_release(BatchState *b);
+// the context's open-loop state (coordinate scratch, report counters)
+struct OlState;
+OlState *&api_ol_state(pwrel_ctx *ctx);
+void ol_release(OlState *o);
+Workspace &api_ws(pwrel_ctx *ctx);
+int api_ensure_scan(pwrel_ctx *ctx, const Geom &g);  // per-block scan buffers
 
 // static scratch of pwrel_compress_noalloc (pwrel_noalloc.hip): set up once
 // per device by pwrel_create, with that device current

@@ -71,6 +71,12 @@ class FieldDesc(C.Structure):
                 ("reserved", C.c_int32), ("d_out", C.c_void_p), ("out_capacity", C.c_uint64)]
 
 
+class OpenloopReport(C.Structure):
+    _fields_ = [("n_raw", C.c_uint64), ("violations", C.c_uint64),
+                ("max_rel_error", C.c_double), ("hist", C.c_uint64 * 18), ("mbits", C.c_int32),
+                ("gap", C.c_int32)]
+
+
 class TrainOptions(C.Structure):
     _fields_ = [("rho", C.c_double), ("seed", C.c_uint64), ("hidden", C.c_int32),
                 ("epochs", C.c_int32), ("batch", C.c_int32), ("n_lr", C.c_int32),
@@ -112,6 +118,9 @@ _SIGS = {
     "pwrel_compress_batch_tune": (C.c_int, [_P, C.c_int, C.POINTER(FieldDesc), C.c_int,
                                             C.c_double, _P, C.POINTER(C.POINTER(Mlp)),
                                             C.POINTER(Options), _P, C.c_int, _P, _P, _P]),
+    "pwrel_openloop": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
+                                 C.POINTER(Mlp), C.c_int, C.c_int, _P, _P, _P, C.c_uint64, _P,
+                                 C.POINTER(OpenloopReport), _P]),
     "pwrel_decompress": (C.c_int, [_P, _P, C.c_uint64, _P, _P, C.c_int, C.c_int, _P]),
     "pwrel_read_header": (C.c_int, [_P, C.c_uint64, C.POINTER(Header)]),
     "pwrel_compress_raw": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
@@ -437,6 +446,35 @@ class Context:
                                sizes)
         r.run(stream)
         return r.views(stream) if views else (r.outs, r.sizes)
+
+    def openloop(self, x, eps, block=8, model=None, mbits=0, gap=0, stream=None):
+        """pwrel_openloop (the paper's literal open-loop prediction, measured):
+        returns dict(codes, counts, raw, xhat, report) with device tensors and
+        the report as a dict."""
+        import torch
+        assert x.is_cuda and x.is_contiguous()
+        dt = _dtype_code(x.dtype)
+        nb = 1
+        for s in x.shape:
+            nb *= -(-int(s) // int(block))
+        codes = torch.empty(x.numel(), dtype=torch.int16, device=x.device)
+        counts = torch.empty(nb, dtype=torch.int32, device=x.device)
+        raw = torch.empty(max(x.numel(), 1), dtype=x.dtype, device=x.device)
+        xh = torch.empty_like(x)
+        m = model_struct(model)
+        rep = OpenloopReport()
+        st = self._L.pwrel_openloop(self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(), dt,
+                                    float(eps), int(block), C.byref(m) if m is not None else None,
+                                    int(mbits), int(gap), C.c_void_p(codes.data_ptr()),
+                                    C.c_void_p(counts.data_ptr()), C.c_void_p(raw.data_ptr()),
+                                    raw.numel(), C.c_void_p(xh.data_ptr()), C.byref(rep),
+                                    _stream(stream))
+        self._check(st, "openloop")
+        r = {"n_raw": rep.n_raw, "violations": rep.violations,
+             "max_rel_error": rep.max_rel_error, "hist": list(rep.hist), "mbits": rep.mbits,
+             "gap": rep.gap}
+        return {"codes": codes, "counts": counts, "raw": raw[:rep.n_raw], "xhat": xh,
+                "report": r}
 
     def decompress(self, stream_t, shape=None, dtype=None, out=None, stream=None):
         import torch
