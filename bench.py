@@ -376,6 +376,43 @@ def batch_leg(ctx, n_fields, eps, steps, warmup, hidden, plain_hidden, rho, pwre
     return rec
 
 
+def openloop_leg(ctx, side, eps, rho, plain_hidden, pwrel, synth, torch):
+    """The paper's literal open-loop prediction (raw neighbours, drifting
+    decoder) on a side^3 FP32 log-normal field, independent 8^3 blocks:
+    Lorenzo and a device-trained FP32 network; m by coverage and m = 16;
+    deliberate balance points every gap points (0 = none).  Reports points
+    breaking the bound, the largest relative error (in units of eps: the
+    paper accepts up to 1.5) and the balance-point share; the grid-snapped
+    codec on the same field breaks no bound."""
+    x = synth.lognormal_grf_device((side, side, side), seed=1005)
+    net, _ = ctx.train(x, eps, 8, rho=rho, seed=1005, hidden=plain_hidden, precision=0,
+                       independent=True)
+    out = {"field": f"{side}^3 FP32 log-normal k^-3 (8 decades, 10% negative, 0.5% zeros), "
+                    f"block 8^3 independent, eps {eps:g}", "runs": []}
+    N = x.numel()
+    for pred, m in (("lorenzo", None), ("fp32_net_H%d" % plain_hidden, net)):
+        for mbits, gap in ((0, 0), (16, 0), (0, 16), (16, 16), (0, 4)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.openloop(x, eps, 8, m, mbits, gap)
+            ms = (time.perf_counter() - t0) * 1e3
+            rep = r["report"]
+            out["runs"].append({
+                "predictor": pred, "mbits": rep["mbits"], "m_by_coverage": mbits == 0,
+                "gap": gap, "violation_frac": round(rep["violations"] / N, 6),
+                "max_rel_over_eps": round(rep["max_rel_error"] / eps, 3),
+                "accepted_1p5": rep["max_rel_error"] <= 1.5 * eps,
+                "balance_frac": round(rep["n_raw"] / N, 5),
+                "coverage_16": round(sum(rep["hist"][:17]) / N, 5), "ms": round(ms, 2)})
+            del r
+    s = ctx.compress(x, eps, 8, None, use_net=False, independent=True)
+    xh = ctx.decompress(s)
+    out["grid_snapped_bound_ok"] = bound_ok(x, xh, eps, torch)
+    del x, xh, s
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -561,6 +598,9 @@ def main():
 
     del x2, o2, h2, Z, Z0
     torch.cuda.empty_cache()
+    res["open_loop"] = openloop_leg(ctx, 256, eps, args.rho, args.plain_hidden, pwrel, synth,
+                                    torch)
+    log("open-loop leg measured")
     if args.batch_fields > 0:
         res["batch"] = batch_leg(ctx, args.batch_fields, eps, K, args.warmup, args.hidden,
                                  args.plain_hidden, args.rho, pwrel, synth, torch)
