@@ -430,6 +430,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-fields", type=int, default=2000,
                     help="fields of the batched leg (0: no batched leg)")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="the batched leg only (one JSON line with its record)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the codec has no multi-GPU path "
@@ -438,6 +440,13 @@ def main():
 
     import torch
     from paper_2309_09778_amd import pwrel, synth
+
+    if args.only_batch:
+        ctx = pwrel.Context(0)
+        rec = batch_leg(ctx, args.batch_fields, args.eps, args.steps, args.warmup, args.hidden,
+                        args.plain_hidden, args.rho, pwrel, synth, torch)
+        print(json.dumps({"batch": rec}), flush=True)
+        return
 
     S, eps, B = args.side, args.eps, args.block
     x = synth.lognormal_grf((S, S, S), seed=1001)
@@ -483,7 +492,7 @@ def main():
     c_ach = flops_pp * N / (c_ms * 1e-3) / 1e12
     c_bytes = N * 4 + N * 2 + nblocks * 5 + n_raw * 4  # field in; codes, counts, flags, raw out
     mfma_useful = 2 * (args.hidden * 6 + args.hidden) * N
-    roofline = {"kernel": "k_grid_entries + k_compress<float,3,8,8,true,1> (a3-a7, BF16 MFMA "
+    roofline = {"kernel": "k_grid_entries + k_compress<float,3,8,8,true,1,false,0> (a3-a7, BF16 MFMA "
                           "network, exact per-block judge)", "bound": "alu",
                 "achieved": round(c_ach, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
                 "unit": "TFLOP/s", "frac": round(c_ach / ALU_PEAK_TFLOPS, 4),
