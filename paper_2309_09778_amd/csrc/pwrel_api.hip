@@ -1071,7 +1071,7 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
         if ((e = launch_huff_decode(g, reinterpret_cast<const uint32_t *>(in + h.off_huff),
                                     reinterpret_cast<const uint32_t *>(in + h.off_bits),
                                     (h.n_bits + 31) / 32, in + h.off_sizes, ctx->ws.codes16,
-                                    ctx->ws, s)) != hipSuccess)
+                                    h.n_sym, ctx->ws, s)) != hipSuccess)
             return hip_fail(ctx, e, "Huffman decode");
         codes = ctx->ws.codes16;
     }

@@ -36,9 +36,10 @@ int huff_size_bytes(const Geom &g);
 hipError_t launch_huff_encode(const Geom &g, const uint16_t *codes, const uint32_t *d_tab,
                               void *d_sizes, uint32_t *d_bits, unsigned long long nwords,
                               Workspace &ws, hipStream_t s);
-// decoder: codes (block-major) from the table, words and per-block sizes
+// decoder: codes (block-major) from the table (nsym symbols), words and
+// per-block sizes
 hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32_t *d_bits,
                               unsigned long long nwords, const void *d_sizes, uint16_t *codes,
-                              Workspace &ws, hipStream_t s);
+                              unsigned nsym, Workspace &ws, hipStream_t s);
 
 }  // namespace pwrel

@@ -393,33 +393,69 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
 // decoder: one thread per block
 constexpr int kLutBits = 12;
 
+// Per-block decoder, one thread per block.  Codes of up to kLutBits bits come
+// from a lookup table of the next kLutBits bits; a longer code's length is
+// the number of canonical length limits its window reaches (a sum of
+// comparisons, no loop), and its symbol sits at index offset[len] + the
+// code.  The table and the symbols (up to kSymsLds of them) live in the
+// workgroup's LDS, so a step never waits on a global load.
+constexpr int kUnpackThreads = 1024;
+constexpr int kSymsLds = 32768;
+
 template <typename S>
-__global__ void __launch_bounds__(256) k_huff_unpack(const uint32_t *__restrict__ tab,
+__global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *__restrict__ tab,
                                                      const uint32_t *__restrict__ bits,
                                                      unsigned long long nwords, GeoArgs g,
                                                      const S *__restrict__ sizes,
                                                      const unsigned long long *__restrict__ boffs,
                                                      const unsigned long long *__restrict__ bparts,
-                                                     uint16_t *__restrict__ codes, int *status)
+                                                     uint16_t *__restrict__ codes, int *status,
+                                                     unsigned nsym)
 {
-    __shared__ uint32_t lut[1 << kLutBits];  // symbol | length << 16 (length 0: longer code)
+    extern __shared__ __align__(16) unsigned char hsm[];
+    uint32_t *lut = reinterpret_cast<uint32_t *>(hsm);  // symbol | length << 16 (0: longer)
+    uint16_t *ssyms = reinterpret_cast<uint16_t *>(lut + (1 << kLutBits));
     __shared__ Canon cs;
+    __shared__ int soff[kHuffMaxLen + 2];        // index[l] - first[l]
+    __shared__ unsigned slim[kHuffMaxLen + 2];   // left-aligned end of the length-l codes
+    __shared__ unsigned smax;                    // longest code length
     const uint32_t *cnt = tab;
     const uint16_t *syms = reinterpret_cast<const uint16_t *>(tab + kHuffMaxLen + 1);
-    if (threadIdx.x == 0)
+    const unsigned nlds = nsym < (unsigned)kSymsLds ? nsym : (unsigned)kSymsLds;
+    if (threadIdx.x == 0) {
         canon_from(cnt, cs);
+        unsigned mx = 0;
+        for (int l = 1; l <= kHuffMaxLen; ++l) {
+            soff[l] = (int)cs.index[l] - (int)cs.first[l];
+            // below the longest length the end stays under 2^32
+            const unsigned long long end = ((unsigned long long)cs.first[l] + cs.count[l])
+                                           << (32 - l);
+            slim[l] = end > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned)end;
+            if (cs.count[l])
+                mx = (unsigned)l;
+        }
+        smax = mx;
+    }
+    for (unsigned k = threadIdx.x; k < nlds; k += blockDim.x)
+        ssyms[k] = syms[k];
     __syncthreads();
     for (int e = threadIdx.x; e < (1 << kLutBits); e += blockDim.x) {
         uint32_t v = 0;
         for (int l = 1; l <= kLutBits; ++l) {
             const unsigned pre = (unsigned)e >> (kLutBits - l);
             if (pre - cs.first[l] < cs.count[l]) {
-                v = syms[cs.index[l] + (pre - cs.first[l])] | ((uint32_t)l << 16);
+                const unsigned ix = cs.index[l] + (pre - cs.first[l]);
+                v = (ix < nlds ? ssyms[ix] : syms[ix]) | ((uint32_t)l << 16);
                 break;
             }
         }
         lut[e] = v;
     }
+    unsigned lim[kHuffMaxLen];
+    const unsigned maxlen = smax;
+#pragma unroll
+    for (int l = kLutBits + 1; l < kHuffMaxLen; ++l)
+        lim[l] = slim[l];
     __syncthreads();
     const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= g.nblocks)
@@ -477,17 +513,20 @@ __global__ void __launch_bounds__(256) k_huff_unpack(const uint32_t *__restrict_
         const uint32_t e = lut[win >> (32 - kLutBits)];
         unsigned l = e >> 16, sym = e & 0xFFFFu;
         if (l == 0) {
-            for (l = kLutBits + 1; l <= kHuffMaxLen; ++l) {
-                const unsigned pre = win >> (32 - l);
-                if (pre - cs.first[l] < cs.count[l])
-                    break;
-            }
-            if (l > kHuffMaxLen) {
+            // a longer code: its length is kLutBits + 1 plus the number of
+            // length limits (below the longest length) the window reaches
+            unsigned len = kLutBits + 1;
+#pragma unroll
+            for (int q = kLutBits + 1; q < kHuffMaxLen; ++q)
+                len += ((unsigned)q < maxlen && win >= lim[q]) ? 1u : 0u;
+            const long long ix = (long long)soff[len] + (long long)(win >> (32 - len));
+            if (len > maxlen || ix < 0 || ix >= (long long)nsym) {
                 err = kECorrupt;
                 l = 1;
                 sym = 0;
             } else {
-                sym = syms[cs.index[l] + ((win >> (32 - l)) - cs.first[l])];
+                l = len;
+                sym = ix < (long long)nlds ? ssyms[ix] : syms[ix];
             }
         }
         buf <<= l;
@@ -595,25 +634,29 @@ hipError_t launch_huff_encode(const Geom &g, const uint16_t *codes, const uint32
 
 hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32_t *d_bits,
                               unsigned long long nwords, const void *d_sizes, uint16_t *codes,
-                              Workspace &ws, hipStream_t s)
+                              unsigned nsym, Workspace &ws, hipStream_t s)
 {
     const GeoArgs ga = geo_of(g);
-    const unsigned grid = (unsigned)((g.nblocks + 255) / 256);
+    const unsigned grid = (unsigned)((g.nblocks + kUnpackThreads - 1) / kUnpackThreads);
+    const unsigned nlds = nsym < (unsigned)kSymsLds ? nsym : (unsigned)kSymsLds;
+    const size_t lds = (size_t)(1 << kLutBits) * sizeof(uint32_t) + (size_t)nlds * sizeof(uint16_t);
     hipError_t e;
     if (huff_size_bytes(g) == 2) {
         const uint16_t *sz = static_cast<const uint16_t *>(d_sizes);
         if ((e = launch_scan_sizes(sz, 2, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
                                    s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_huff_unpack<uint16_t>, dim3(grid), dim3(256), 0, s, d_tab, d_bits,
-                           nwords, ga, sz, ws.boffsets, ws.bpartials, codes, ws.status);
+        hipLaunchKernelGGL(k_huff_unpack<uint16_t>, dim3(grid), dim3(kUnpackThreads), lds, s,
+                           d_tab, d_bits, nwords, ga, sz, ws.boffsets, ws.bpartials, codes,
+                           ws.status, nsym);
     } else {
         const uint32_t *sz = static_cast<const uint32_t *>(d_sizes);
         if ((e = launch_scan_sizes(sz, 4, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
                                    s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_huff_unpack<uint32_t>, dim3(grid), dim3(256), 0, s, d_tab, d_bits,
-                           nwords, ga, sz, ws.boffsets, ws.bpartials, codes, ws.status);
+        hipLaunchKernelGGL(k_huff_unpack<uint32_t>, dim3(grid), dim3(kUnpackThreads), lds, s,
+                           d_tab, d_bits, nwords, ga, sz, ws.boffsets, ws.bpartials, codes,
+                           ws.status, nsym);
     }
     return hipGetLastError();
 }
