@@ -176,7 +176,12 @@ __device__ __forceinline__ void wait_vmem()
 // Occupancy bound (measured at 512^3): six waves per SIMD for the FP32 and
 // Lorenzo variants, four for the BF16 one; the registers the bound takes away
 // cost a few spills, far less than the latency the extra waves hide.
-template <typename T, int D, int BB, int HP, bool FROM_P, int PREC, bool BATCH, int TV = 0>
+// W32 (compiled tiles of grid entries only): the variant for fields whose grid
+// values span less than 2^27, with one branch-free prediction loop; a launch
+// of the other variant pairs with it and each returns at once on the other's
+// fields, so neither carries the other's code.
+template <typename T, int D, int BB, int HP, bool FROM_P, int PREC, bool BATCH, int TV = 0,
+          bool W32 = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 4 : 6)))
 k_compress(CompressArgs a)
 {
@@ -303,6 +308,11 @@ k_compress(CompressArgs a)
     DevConsts c = *F.consts;
     long long n0 = F.n[0], n1 = F.n[1], n2 = F.n[2];
     bool w32 = c.w32 != 0;
+    constexpr bool SPLIT = CT && FROM_P && !BATCH;  // launched as a W32 / generic pair
+    if constexpr (SPLIT) {
+        if (w32 != W32)
+            return;  // the pair's other kernel takes this field (uniform)
+    }
 
     // LDS offsets of the neighbours, o = 1 .. 2^D-1
     int noff[8];
@@ -375,7 +385,8 @@ k_compress(CompressArgs a)
     constexpr bool PIPE = CT && (FROM_P || std::is_same<T, float>::value);
     constexpr int NEX = CT ? (S::T0 + h0) * (S::T1 + h1) * (S::T2 + h2) : 1;
     __shared__ unsigned xs[PIPE ? NEX : 1];
-    const int lane = tid & 63, wave = tid >> 6;
+    // the wave index, provably uniform: the staging loop's row arithmetic is scalar
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     auto stage = [&](long long t) {
         const Fld G = BATCH ? field_of(t) : F;
         const unsigned *src32 = reinterpret_cast<const unsigned *>(G.src);
@@ -489,6 +500,113 @@ k_compress(CompressArgs a)
         const int edge = a.independent ? 7 : first;
         constexpr int NO = (1 << D) - 1;
         const int DZ = E1 * E2, DY = E2;
+        if constexpr (W32) {
+            // Branch-free loop (grid values spanning less than 2^27): a missing
+            // axis zeroes its neighbours (the Lorenzo predictor counts them as
+            // zero; e = sum of signed neighbours - p wraps exactly in 32 bits),
+            // points outside the field are computed and dropped, codes leave
+            // four at a time where a group lies in the field.
+            static_assert(CT && FROM_P, "the 32-bit loop reads compiled tiles of entries");
+            constexpr int S8 = BB < 8 ? BB : 8;
+            const bool vec = (reinterpret_cast<uintptr_t>(F.codes) & 7) == 0;
+#pragma unroll 1
+            for (int u0 = 0; u0 < nunits; u0 += NT) {
+                const int u = u0 + tid;
+                const int uu = u < nunits ? u : 0;
+                const int seg = uu % nseg, row = uu / nseg;
+                const int ly = row % bd1, lz = (row / bd1) % bd0, bt = row / (bd1 * bd0);
+                const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
+                const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx0 = btx * bd2 + seg * S8;
+                const bool urow = u < nunits && cz < limz && cy < limy;
+                const int pz = a.independent ? lz : cz, py = a.independent ? ly : cy;
+                const int my = (D >= 2 && (py != 0 || !(edge & 2))) ? -1 : 0;
+                const int mz = (D >= 3 && (pz != 0 || !(edge & 4))) ? -1 : 0;
+                const bool yz_full = (D < 2 || my != 0) && (D < 3 || mz != 0);
+                const int px0 = a.independent ? seg * S8 : cx0;
+                const bool x0 = px0 != 0 || !(edge & 1);  // x - 1 of the first point available
+                const int nin = urow ? limx - cx0 : 0;    // points of the segment in the field: min(nin, S8)
+                const int eb = ((cz + h0) * E1 + (cy + h1)) * E2 + (cx0 + h2);
+                const int ex = (int)(bext[bt] & 0xffffu), ey = (int)(bext[bt] >> 16);
+                const long long pos0 = bst[bt] + (long long)((lz * ey + ly) * ex + seg * S8);
+                const int okr = (cz * T1 + cy) * T2 + cx0;
+                uint16_t *dst = F.codes + pos0;
+                int q0 = ptile[eb - 1];
+                int q2 = D >= 2 ? ptile[eb - 1 - DY] : 0;
+                int q4 = D >= 3 ? ptile[eb - 1 - DZ] : 0;
+                int q6 = D >= 3 ? ptile[eb - 1 - DZ - DY] : 0;
+                unsigned long long cacc = 0ULL;
+                unsigned nz = 0;
+#pragma unroll 1
+                for (int i = 0; i < S8; ++i) {
+                    const bool inside = i < nin;
+                    const int p = ptile[eb + i];
+                    const int c2 = D >= 2 ? ptile[eb + i - DY] : 0;
+                    const int c4 = D >= 3 ? ptile[eb + i - DZ] : 0;
+                    const int c6 = D >= 3 ? ptile[eb + i - DZ - DY] : 0;
+                    const bool xa = i > 0 || x0;
+                    const int mx = xa ? -1 : 0;
+                    const int n1 = q0 & mx;
+                    int el;
+                    if constexpr (D == 1) {
+                        el = n1 - p;
+                    } else if constexpr (D == 2) {
+                        el = (n1 + (c2 & my)) - ((q2 & my & mx) + p);
+                    } else {
+                        const int n2 = c2 & my, n3 = q2 & my & mx;
+                        const int n4 = c4 & mz, n5 = q4 & mz & mx;
+                        const int n6 = c6 & mz & my, n7 = q6 & mz & my & mx;
+                        el = ((n1 + n2) + (n4 + n7)) - ((n3 + n5) + (n6 + p));
+                    }
+                    const bool use = a.use_net != 0 && inside && xa && yz_full;
+                    const bool okp = okb[okr + i] != 0;
+                    int e = el;
+                    if constexpr (PREC == 1) {
+                        constexpr int K = (1 << D) - 2;
+                        const int nvr[6] = {c2, q2, c4, q4, c6, q6};
+                        float uin[6];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            uin[k] = (k < K && use)
+                                         ? (float)(int)((unsigned)nvr[k] - (unsigned)q0)
+                                         : 0.0f;
+                        const float y = net_bf16(net16, uin);  // every lane takes part
+                        if (use) {
+                            const int nv2[8] = {p, q0, 0, 0, 0, 0, 0, 0};
+                            e = net_err32(y, nv2);
+                        }
+                    } else {
+                        if (use) {
+                            const int nv[8] = {p, q0, c2, q2, c4, q4, c6, q6};
+                            e = net_err32(net_f32<D, HP>(nv, WeightsLds{wl}, b2, alpha), nv);
+                        }
+                    }
+                    const unsigned code = code32(e, okp);
+                    if (inside) {
+                        nz += code == 0u ? 1u : 0u;
+                        if (a.judge)
+                            jb[okr + i] = code | ((unsigned)code32(el, okp) << 16);
+                    }
+                    cacc |= (unsigned long long)code << (16 * (i & 3));
+                    if ((i & 3) == 3 || i == S8 - 1) {  // uniform: every lane is at step i
+                        const int i0 = i & ~3;
+                        if (vec && i0 + 3 < nin && ((pos0 + i0) & 3) == 0) {
+                            *reinterpret_cast<unsigned long long *>(dst + i0) = cacc;
+                        } else {
+                            for (int k = 0; k <= (i & 3); ++k)
+                                if (i0 + k < nin)
+                                    dst[i0 + k] = (uint16_t)(cacc >> (16 * k));
+                        }
+                        cacc = 0ULL;
+                    }
+                    q0 = p;
+                    q2 = c2;
+                    q4 = c4;
+                    q6 = c6;
+                }
+                if (!a.judge && nz)
+                    atomicAdd(&cnt[bt], nz);
+            }
+        } else {
 #pragma unroll 1
         for (int u0 = 0; u0 < nunits; u0 += NT) {
             const int u = u0 + tid;
@@ -606,6 +724,7 @@ k_compress(CompressArgs a)
             }
             if (!a.judge && nzero)
                 atomicAdd(&cnt[bt], nzero);
+        }
         }
         __syncthreads();
 
@@ -793,20 +912,31 @@ bool tile_for(const Geom &g, Tile &tile)
     return true;
 }
 
-template <typename T, int D, int BB, int HP, bool FP, int PREC, bool BATCH = false, int TV = 0>
-static void go(const CompressArgs &a, unsigned num_cus, size_t lds, hipStream_t s)
+template <typename T, int D, int BB, int HP, bool FP, int PREC, bool BATCH, int TV, bool W32>
+static void go_one(const CompressArgs &a, unsigned num_cus, size_t lds, hipStream_t s)
 {
     // persistent grid: every workgroup that can be resident at once (a
     // multiple of 8 so that each XCD gets the same number), at most one per tile
-    const void *fn = reinterpret_cast<const void *>(&k_compress<T, D, BB, HP, FP, PREC, BATCH, TV>);
+    const void *fn =
+        reinterpret_cast<const void *>(&k_compress<T, D, BB, HP, FP, PREC, BATCH, TV, W32>);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     long long grid = std::min((long long)per_cu * num_cus, (a.ntiles + 7) / 8 * 8);
     grid = std::max(8LL, grid / 8 * 8);
-    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC, BATCH, TV>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((k_compress<T, D, BB, HP, FP, PREC, BATCH, TV, W32>), dim3((unsigned)grid),
                        dim3(256), lds, s, a);
+}
+
+template <typename T, int D, int BB, int HP, bool FP, int PREC, bool BATCH = false, int TV = 0>
+static void go(const CompressArgs &a, unsigned num_cus, size_t lds, hipStream_t s)
+{
+    // compiled tiles of grid entries: the 32-bit variant and the generic one,
+    // each returning at once on the other's fields
+    if constexpr (ShapeOf<D, BB>::known && FP && !BATCH)
+        go_one<T, D, BB, HP, FP, PREC, BATCH, TV, true>(a, num_cus, lds, s);
+    go_one<T, D, BB, HP, FP, PREC, BATCH, TV, false>(a, num_cus, lds, s);
 }
 
 template <typename T, int D, int BB, bool FP>

@@ -186,6 +186,20 @@ def _case(name):
         x = synth.lognormal_grf((20, 24, 30), seed=12, decades=75, neg_frac=0.3, zero_frac=0.01)
         x = (x * (8.0 if name.endswith("hi") else 2.0 ** -6)).astype(np.float32)
         return x, 1e-2, 8, random_model(3, 16, 12), False
+    if name.startswith("wide_span"):
+        # a smooth field plus a few magnitudes near both ends of the FP32
+        # range: at a bound of 5e-7 the grid values span more than 2^27, so the
+        # kernels take their 64-bit (generic) branch; about a fifth of the
+        # points end raw
+        rng = np.random.default_rng(14)
+        x = synth.lognormal_grf((20, 24, 30), seed=14, decades=0.05, neg_frac=0.05,
+                                zero_frac=0.002).astype(np.float64)
+        f = x.reshape(-1)
+        idx = rng.choice(f.size, 6, replace=False)
+        f[idx[:3]] = np.sign(f[idx[:3]] + 1e-30) * 2.0 ** -124
+        f[idx[3:]] = np.sign(f[idx[3:]] + 1e-30) * 2.0 ** 125
+        model = None if name.endswith("lorenzo") else random_model(3, 16, 14)
+        return x.astype(np.float32), 5e-7, 8, model, name.endswith("indep")
     if name.startswith("pencil_"):
         # halo-mode pencil decoder edges: one pencil row (n0 < 8), short y,
         # long pencils with a ragged last block, one block column
@@ -237,6 +251,7 @@ CASES = ["config0_bumps64", "grf_ragged_1e-3", "grf_ragged_indep", "grf_B4_H32",
          "grf_B5", "zonal_2d", "grf_2d_B64", "grf_1d_halo", "grf_1d_indep", "f64_1e-4",
          "lorenzo_only", "single_point", "all_zero", "tiny_1d", "sign_gap_delta",
          "f32_range_ends_1e-2", "f32_smooth_range_hi", "f32_smooth_range_lo",
+         "wide_span_halo", "wide_span_indep", "wide_span_lorenzo",
          "pencil_thin_z", "pencil_thin_y", "pencil_long", "pencil_single_x",
          "flow_96cubed_B16", "flow_B4_1320_blocks", "lanes_f32_B8", "lanes_B4_ragged",
          "lanes_2d_B16", "lanes_f64", "lanes_lorenzo"]
@@ -249,6 +264,8 @@ def test_codec_bit_exact_vs_oracle(ctx, name):
     mode = O.MODE_PLAIN if use_net else O.MODE_LORENZO
     stream = ctx.compress(dev(x), eps, B, model, use_net=use_net, independent=indep)
     g = host_sections(stream)
+    if name.startswith("wide_span"):
+        assert g["h"]["p_max"] - g["h"]["p_zero"] >= 2 ** 27
     ref = O.compress(x, eps, B, model, mode, independent=indep)
     for k in CONST_KEYS:
         assert g["h"][k] == ref["consts"][k], k

@@ -32,6 +32,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as O
 from paper_2309_09778_amd import pwrel, synth
+from tests.test_gpu_codec import _case as codec_case
 
 pytestmark = pytest.mark.gpu
 
@@ -340,10 +341,14 @@ def _judge_case(name):
     if name == "zonal_2d":
         return synth.zonal_bands_2d((150, 301), seed=14), 1e-2, 16, random_model(2, 16, 14, 0.1), \
             False
+    if name.startswith("wide_span"):  # grid values spanning more than 2^27: 64-bit branch
+        x, eps, B, _, indep = codec_case(name)
+        return x, eps, B, random_model(3, 16, 12, 0.15), indep
     raise KeyError(name)
 
 
-JUDGE_CASES = ["grf_random", "grf_random_indep", "grf_thin", "grf_B4", "zonal_2d"]
+JUDGE_CASES = ["grf_random", "grf_random_indep", "grf_thin", "grf_B4", "zonal_2d",
+               "wide_span_halo", "wide_span_indep"]
 
 
 @pytest.mark.parametrize("name", JUDGE_CASES)
