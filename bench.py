@@ -492,8 +492,8 @@ def main():
     c_ach = flops_pp * N / (c_ms * 1e-3) / 1e12
     c_bytes = N * 4 + N * 2 + nblocks * 5 + n_raw * 4  # field in; codes, counts, flags, raw out
     mfma_useful = 2 * (args.hidden * 6 + args.hidden) * N
-    roofline = {"kernel": "k_grid_entries + k_compress<float,3,8,8,true,1,false,0> (a3-a7, BF16 MFMA "
-                          "network, exact per-block judge)", "bound": "alu",
+    roofline = {"kernel": "k_grid_entries + k_compress<float,3,8,8,true,1,false,0,W32> pair (a3-a7, "
+                          "BF16 MFMA network, exact per-block judge)", "bound": "alu",
                 "achieved": round(c_ach, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
                 "unit": "TFLOP/s", "frac": round(c_ach / ALU_PEAK_TFLOPS, 4),
                 "traffic": profiled_traffic(COMPRESS_PROFILE, COMPRESS_SOURCES),
