@@ -110,6 +110,12 @@ def lib():
         L.or_huff_encode.argtypes = [P, C.c_int64, P, P, P]
         L.or_huff_decode.restype = C.c_int64
         L.or_huff_decode.argtypes = [P, C.c_int64, C.c_int64, P, C.c_int, C.c_int, P]
+        L.or_huff_trained_lengths.argtypes = [P, P]
+        L.or_huff_encode_esc.restype = C.c_int64
+        L.or_huff_encode_esc.argtypes = [P, C.c_int64, P, P, P]
+        L.or_huff_decode_esc.restype = C.c_int64
+        L.or_huff_decode_esc.argtypes = [P, C.c_int64, C.c_int64, P, C.c_int, P]
+        L.or_val_codes.argtypes = [C.POINTER(_MLP), P, P, C.c_int64, P]
         L.or_bf16_rne.restype = C.c_float
         L.or_bf16_rne.argtypes = [C.c_float]
         L.or_entropy_j.restype = C.c_int64
@@ -275,6 +281,74 @@ def huff_decode(words, n, lengths, start=0, lmax=HUFF_LMAX):
     if end < 0:
         raise OracleError(-5, "huff_decode")
     return out[:n], end
+
+
+# --- the codebook of the training phase (Sec. 4.3) ----------------------------
+
+ESC = 65536  # alphabet index of the escape symbol
+
+
+def huff_trained_lengths(hist):
+    """Lengths of the codebook built once from validation code counts: an
+    array of 65,537 (the 65,536 codes, then the escape), and the escape's
+    length (0 when every code was seen)."""
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    assert hist.size == 65536
+    ln = np.zeros(ESC + 1, dtype=np.uint8)
+    esc = lib().or_huff_trained_lengths(_ptr(hist), _ptr(ln))
+    if esc < 0:
+        raise OracleError(esc, "huff_trained_lengths")
+    return ln, int(esc)
+
+
+def huff_encode_esc(codes, lengths):
+    """Bitstream of the codes under a trained codebook (lengths of 65,537);
+    returns (words, bit count)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    ln = np.ascontiguousarray(lengths, dtype=np.uint8)
+    assert ln.size == ESC + 1
+    cw = huff_canonical(ln, 32)
+    per = np.where(ln[codes] > 0, ln[codes].astype(np.int64), int(ln[ESC]) + 16)
+    nbits = int(per.sum())
+    words = np.zeros(max((nbits + 31) // 32, 1), dtype=np.uint32)
+    got = lib().or_huff_encode_esc(_ptr(codes), codes.size, _ptr(ln), _ptr(cw), _ptr(words))
+    if got < 0:
+        raise OracleError(int(got), "huff_encode_esc")
+    assert got == nbits
+    return words, nbits
+
+
+def huff_decode_esc(words, n, lengths, start=0):
+    """n codes decoded under a trained codebook from bit `start`; returns
+    (codes, end bit)."""
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    ln = np.ascontiguousarray(lengths, dtype=np.uint8)
+    assert ln.size == ESC + 1
+    out = np.zeros(max(int(n), 1), dtype=np.uint16)
+    end = lib().or_huff_decode_esc(_ptr(words), int(start), int(n), _ptr(ln), 32, _ptr(out))
+    if end < 0:
+        raise OracleError(-5, "huff_decode_esc")
+    return out[:n], end
+
+
+def huff_book(lengths):
+    """The stream form of a codebook: count[0..32] (codewords per length) and
+    the symbols in canonical order (by length, then value); the escape, the
+    last symbol of its length, is listed as 0."""
+    ln = np.asarray(lengths)
+    count = np.bincount(ln[ln > 0], minlength=33).astype(np.uint32)
+    syms = [s for L in range(1, 33) for s in np.flatnonzero(ln == L)]
+    return count, np.array([0 if s == ESC else s for s in syms], dtype=np.uint16)
+
+
+def val_codes(model, u, t):
+    """Codes of an FP32 network on validation pairs (u: [n][K], t: [n])."""
+    u = np.ascontiguousarray(u, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int32)
+    out = np.zeros(max(t.size, 1), dtype=np.uint16)
+    m = _to_c_mlp(model)
+    lib().or_val_codes(C.byref(m), _ptr(u), _ptr(t), t.size, _ptr(out))
+    return out[:t.size]
 
 
 # --- deterministic math -------------------------------------------------------

@@ -25,6 +25,8 @@
  *   decompression ................ Sec. 5 (decompression paragraph)
  *   training ..................... Sec. 4.3 (10% uniform sample, 8:2 split, L2,
  *                                  one round, several lr/lambda sets, pick best)
+ *   Huffman stage ................ Sec. 4.1 coding stage, Algorithm 1, Sec. 5
+ *   trained codebook ............. Sec. 4.3 (validation code frequencies)
  *
  * Readings where the paper is silent or inconsistent (each is listed in the
  * design notes of the repository):
@@ -41,6 +43,9 @@
  *   - the network predicts the difference to the previous point along the
  *     fastest axis from the other neighbours' differences, Lorenzo at init.
  *   - m = 16: codes 1..65535, code 0 = balance point (raw input value kept).
+ *   - the trained codebook gives codes unseen in validation an escape
+ *     codeword plus their 16 bits (the paper does not say what happens to
+ *     them).
  */
 #include <math.h>
 #include <stdint.h>
@@ -1638,6 +1643,150 @@ int64_t or_huff_decode(const uint32_t *words, int64_t start, int64_t n, const ui
     }
     free(sorted);
     return pos;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The codebook of the training phase (Sec. 4.3): one table built once from  */
+/* the code frequencies of the validation blocks and reused for every block  */
+/* of the compression.  The paper averages the counts per block; an average  */
+/* is the total over the validation set divided by the number of blocks, a   */
+/* common factor, so the totals give the same lengths.  A code the           */
+/* validation never produced has no codeword of its own: the escape symbol   */
+/* (alphabet index 65536) stands for every such code and is followed in the  */
+/* stream by the code's 16 bits, most significant first.  The escape weighs  */
+/* the number of codes seen exactly once, at least 1 (Good-Turing estimate   */
+/* of the probability of an unseen code).  With an escape in the alphabet no */
+/* codeword is longer than 16 bits, so an escaped code takes at most 32;     */
+/* without one (every code seen) the limit is 32.                            */
+/* ------------------------------------------------------------------------ */
+
+#define OR_ESC 65536
+
+/* len[0..65536]: the lengths of the 65,536 codes and of the escape (0 when
+ * unused).  Returns the escape's length (0: no escape), or -1. */
+int or_huff_trained_lengths(const uint64_t *hist, uint8_t *len)
+{
+    uint64_t *w = (uint64_t *)malloc((OR_ESC + 1) * sizeof(uint64_t));
+    if (!w)
+        return -1;
+    uint64_t ones = 0;
+    int unseen = 0;
+    for (int s = 0; s < OR_ESC; ++s) {
+        w[s] = hist[s];
+        ones += hist[s] == 1;
+        unseen |= hist[s] == 0;
+    }
+    w[OR_ESC] = unseen ? (ones > 0 ? ones : 1) : 0;
+    int st = or_huff_lengths(w, OR_ESC + 1, unseen ? 16 : 32, len);
+    free(w);
+    if (st)
+        return -1;
+    return len[OR_ESC];
+}
+
+/* The bitstream of n codes with the escape: a code with a codeword takes
+ * it; any other code takes the escape's codeword, then its own 16 bits.
+ * len/code have 65,537 entries.  words must hold enough zeroed words.
+ * Returns the bit count, or -1 for a code with no codeword and no escape. */
+int64_t or_huff_encode_esc(const uint16_t *codes, int64_t n, const uint8_t *len,
+                           const uint32_t *code, uint32_t *words)
+{
+    int64_t pos = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int s = codes[i];
+        int nb;
+        uint64_t v;
+        if (len[s]) {
+            nb = len[s];
+            v = code[s];
+        } else if (len[OR_ESC]) {
+            nb = len[OR_ESC] + 16;
+            v = ((uint64_t)code[OR_ESC] << 16) | (uint64_t)s;
+        } else {
+            return -1;
+        }
+        for (int k = nb - 1; k >= 0; --k) {
+            if ((v >> k) & 1u)
+                words[pos >> 5] |= 1u << (31 - (pos & 31));
+            pos++;
+        }
+    }
+    return pos;
+}
+
+/* Decode n codes from bit `start`, bit by bit down the canonical code of the
+ * 65,537-symbol alphabet; the escape symbol is followed by the code's 16
+ * bits.  Returns the bit position after the last code, or -1 if the bits
+ * match no codeword. */
+int64_t or_huff_decode_esc(const uint32_t *words, int64_t start, int64_t n, const uint8_t *len,
+                           int Lmax, uint16_t *out)
+{
+    const int nsym = OR_ESC + 1;
+    uint32_t bl_count[64] = {0}, first[64] = {0};
+    int32_t index[64] = {0};
+    for (int s = 0; s < nsym; ++s)
+        if (len[s])
+            bl_count[len[s]]++;
+    int32_t *sorted = (int32_t *)malloc((size_t)nsym * sizeof(int32_t));
+    if (!sorted)
+        return -1;
+    int m = 0;
+    uint32_t c = 0;
+    for (int b = 1; b <= Lmax; ++b) {
+        c = (c + bl_count[b - 1]) << 1;
+        first[b] = c;
+        index[b] = m;
+        for (int s = 0; s < nsym; ++s)
+            if (len[s] == b)
+                sorted[m++] = s;
+    }
+    int64_t pos = start;
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t v = 0;
+        int b = 0, sym = -1;
+        while (b < Lmax) {
+            v = (v << 1) | ((words[pos >> 5] >> (31 - (pos & 31))) & 1u);
+            pos++;
+            b++;
+            if (v - first[b] < bl_count[b]) {
+                sym = sorted[index[b] + (int32_t)(v - first[b])];
+                break;
+            }
+        }
+        if (sym < 0) {
+            free(sorted);
+            return -1;
+        }
+        if (sym == OR_ESC) {
+            uint32_t r = 0;
+            for (int k = 0; k < 16; ++k) {
+                r = (r << 1) | ((words[pos >> 5] >> (31 - (pos & 31))) & 1u);
+                pos++;
+            }
+            sym = (int)r;
+        }
+        out[i] = (uint16_t)sym;
+    }
+    free(sorted);
+    return pos;
+}
+
+/* The codes an FP32 network gives on validation pairs (the values whose
+ * histogram the validation scores and the trained codebook use). */
+void or_val_codes(const or_mlp *m, const int32_t *u, const int32_t *t, int64_t n, uint16_t *out)
+{
+    int K = m->inputs;
+    for (int64_t i = 0; i < n; ++i) {
+        float uf[OR_MAXK];
+        for (int k = 0; k < K; ++k)
+            uf[k] = (float)u[i * K + k];
+        float y = mlp_eval_f32(m, uf);
+        if (y > 0x1p30f)
+            y = 0x1p30f;
+        if (!(y >= -0x1p30f))
+            y = -0x1p30f;
+        out[i] = code_of((int64_t)rintf(y), (int64_t)t[i], 1);
+    }
 }
 
 /* FP64 value of the network and the BF16 error bound of mlp_bf16_bound. */

@@ -10,6 +10,22 @@ to decode), CPU only:
 - with a binding limit, the cost equals the optimum found by brute force over
   every admissible length vector on tiny alphabets, and no length exceeds it;
 - the bitstream decodes back to the codes, bit positions included.
+
+The codebook of the training phase (Sec. 4.3: one table from validation code
+frequencies, reused for every block), with its escape for codes the
+validation never produced:
+
+- a worked example derived by hand (weights 3, 1 and an escape of weight 1:
+  lengths 1, 2, 2; the stream of three codes written out bit by bit);
+- the escape weighs the number of codes seen exactly once (a case where a
+  weight of 1 would give another escape length) and sits last among the
+  codewords of its length;
+- with an escape the lengths stop at 16 bits (a case where the unlimited code
+  goes beyond), without one (every code seen) they equal the 32-bit limited
+  code of the counts; the code stays complete (Kraft sum 1);
+- costs equal the textbook Huffman construction of the augmented weights
+  when the limit does not bind;
+- escaped and coded codes decode back, bit counts and positions included.
 """
 import heapq
 import itertools
@@ -97,3 +113,119 @@ def test_bitstream_round_trip_and_positions():
     cw = O.huff_canonical(ln)
     l0 = int(ln[codes[0]])
     assert int(words[0]) >> (32 - l0) == int(cw[codes[0]])
+
+
+# --- the trained codebook (Sec. 4.3) ----------------------------------------------------------
+
+def _hist(d):
+    h = np.zeros(65536, dtype=np.uint64)
+    for s, c in d.items():
+        h[s] = c
+    return h
+
+
+def _bits(words, nbits):
+    return "".join(format(int(w), "032b") for w in words)[:nbits]
+
+
+def test_trained_codebook_worked_example():
+    # weights: code 5 -> 3, code 7 -> 1, escape -> 1 (one code seen once).
+    # Huffman: merge 7 and the escape (2), then with 5: lengths 1, 2, 2.
+    # Canonical: 5 -> "0"; 7 -> "10", escape -> "11" (last of length 2).
+    ln, esc = O.huff_trained_lengths(_hist({5: 3, 7: 1}))
+    assert esc == 2 and ln[5] == 1 and ln[7] == 2 and ln[O.ESC] == 2
+    assert int((ln > 0).sum()) == 3
+    words, nbits = O.huff_encode_esc(np.array([5, 7, 9], dtype=np.uint16), ln)
+    # "0" + "10" + "11" + the 16 bits of 9
+    assert nbits == 21
+    assert _bits(words, nbits) == "0" + "10" + "11" + "0000000000001001"
+    assert int(words[0]) == 0x58004800
+    back, end = O.huff_decode_esc(words, 3, ln)
+    assert end == 21 and list(back) == [5, 7, 9]
+    count, syms = O.huff_book(ln)
+    assert list(count[:3]) == [0, 1, 2] and list(syms) == [5, 7, 0]
+
+
+def test_escape_weight_is_the_singleton_count():
+    # counts 100, 1, 1, 1: three codes seen once -> escape weight 3.
+    # weights 100, 1, 1, 1, 3: merges 1+1, 1+2, 3+3, 6+100, so the escape
+    # gets 2 bits.  A weight of 1 instead would make four equal leaves of
+    # 3 bits under the heavy symbol.
+    ln, esc = O.huff_trained_lengths(_hist({1: 100, 2: 1, 3: 1, 4: 1}))
+    assert esc == 2
+    assert [int(ln[s]) for s in (1, 2, 3, 4)] == [1, 4, 4, 3]
+    # no code seen once: weight 1
+    ln, esc = O.huff_trained_lengths(_hist({1: 10, 2: 4, 3: 4}))
+    w = [10, 4, 4, 1]
+    assert int(sum(a * b for a, b in zip(w, [ln[1], ln[2], ln[3], ln[O.ESC]]))) == \
+        huffman_cost(w)
+    assert esc == 3
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_trained_cost_equals_textbook_huffman_of_augmented_weights(seed):
+    rng = np.random.default_rng(50 + seed)
+    used = rng.choice(65536, size=[3, 40, 900, 3000][seed], replace=False)
+    h = np.zeros(65536, dtype=np.uint64)
+    h[used] = (rng.pareto(2.5, used.size) * 30 + 1).astype(np.uint64)
+    ln, esc = O.huff_trained_lengths(h)
+    ones = int((h == 1).sum())
+    wesc = max(1, ones)
+    # the 16-bit limit does not bind on these counts
+    assert O.huff_lengths(np.append(h, np.uint64(wesc)), 62).max() <= 16
+    assert ln.max() <= 16
+    cost = int((h * ln[:65536]).sum()) + wesc * esc
+    assert cost == huffman_cost(list(h[h > 0]) + [wesc])
+    kraft = sum(2.0 ** -int(v) for v in ln[ln > 0])
+    assert kraft == pytest.approx(1.0, abs=1e-12)
+    # the escape is the last codeword of its length
+    count, syms = O.huff_book(ln)
+    first = int(count[:esc].sum())
+    assert syms[first + int(count[esc]) - 1] == 0
+    assert int((ln[:65536] == esc).sum()) == int(count[esc]) - 1
+
+
+def test_trained_lengths_stop_at_16_bits_with_an_escape():
+    # counts 2, 4, ..., 2^25 and the escape's 1: the unlimited code is 25 deep
+    h = _hist({100 + i: 2 ** i for i in range(1, 26)})
+    free = O.huff_lengths(np.append(h, np.uint64(1)), 62)
+    assert free.max() == 25
+    ln, esc = O.huff_trained_lengths(h)
+    assert 0 < esc <= 16 and ln.max() == 16
+    kraft = sum(2.0 ** -int(v) for v in ln[ln > 0])
+    assert kraft == pytest.approx(1.0, abs=1e-12)
+
+
+def test_every_code_seen_means_no_escape():
+    rng = np.random.default_rng(8)
+    h = (rng.pareto(1.1, 65536) * 3 + 1).astype(np.uint64)
+    ln, esc = O.huff_trained_lengths(h)
+    assert esc == 0 and ln[O.ESC] == 0
+    assert np.array_equal(ln[:65536], O.huff_lengths(h, 32))
+
+
+def test_empty_validation_escapes_everything():
+    ln, esc = O.huff_trained_lengths(np.zeros(65536, dtype=np.uint64))
+    assert esc == 1 and int((ln > 0).sum()) == 1
+    words, nbits = O.huff_encode_esc(np.array([3, 65535], dtype=np.uint16), ln)
+    assert nbits == 34
+    assert _bits(words, nbits) == "0" + format(3, "016b") + "0" + format(65535, "016b")
+
+
+def test_trained_stream_round_trip_with_escapes():
+    rng = np.random.default_rng(12)
+    val = np.clip(np.round(rng.laplace(32768, 30, 30000)), 1, 65535).astype(np.uint16)
+    ln, esc = O.huff_trained_lengths(np.bincount(val, minlength=65536).astype(np.uint64))
+    assert esc > 0
+    codes = np.clip(np.round(rng.laplace(32768, 60, 20000)), 0, 65535).astype(np.uint16)
+    codes[::101] = 0
+    per = np.array([int(ln[c]) if ln[c] else esc + 16 for c in codes])
+    assert (ln[codes] == 0).sum() > 100  # escapes happen
+    words, nbits = O.huff_encode_esc(codes, ln)
+    assert nbits == int(per.sum())
+    back, end = O.huff_decode_esc(words, codes.size, ln)
+    assert end == nbits and np.array_equal(back, codes)
+    off = int(per[:7000].sum())
+    part, end2 = O.huff_decode_esc(words, 5000, ln, start=off)
+    assert np.array_equal(part, codes[7000:12000])
+    assert end2 == off + int(per[7000:12000].sum())
