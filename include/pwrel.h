@@ -78,6 +78,23 @@ typedef struct {
     int32_t precision; /* 0 = FP32 vector ALU, 1 = BF16 matrix cores */
 } pwrel_mlp;
 
+/*
+ * A Huffman codebook built once by the training phase (Sec. 4.3: one table
+ * from the code frequencies of the validation blocks, reused for every block
+ * of the compression; Sec. 5 rebuilds it to decode).  Codes the validation
+ * never produced share an escape codeword, followed in the stream by the
+ * code's own 16 bits (most significant first); with an escape no codeword is
+ * longer than 16 bits.  Filled by pwrel_train_codebook or
+ * pwrel_huffman_trained_codebook; host memory, owned by the caller.
+ */
+typedef struct {
+    uint32_t count[33];   /* count[l] = codewords of l bits, the escape included; count[0] = 0 */
+    uint32_t n_sym;       /* entries of syms (the sum of count) */
+    uint32_t esc_len;     /* bits of the escape codeword; 0 = no escape (every code listed) */
+    uint16_t syms[65536]; /* the symbols in canonical order (by length, then value); the
+                             escape is the last of its length and is stored as 0 */
+} pwrel_codebook;
+
 /* Compression options; pass NULL for the defaults (all zero except use_net = 1). */
 typedef struct {
     int32_t use_net;            /* 0: one-layer Lorenzo everywhere; 1: network where all
@@ -98,6 +115,11 @@ typedef struct {
                                    histogram, canonical codewords); where the codebook would
                                    cost more than it saves, the stream keeps the 16-bit codes
                                    (no PWREL_HF_HUFFMAN flag).  pwrel_compress only */
+    const pwrel_codebook *codebook; /* entropy = 1 only (else ignored): NULL = the codebook of
+                                   this field's histogram, as above; else this trained codebook
+                                   (host memory, read during the call), no histogram pass; where
+                                   its coded size is not below the 16-bit codes, the stream
+                                   keeps them */
 } pwrel_options;
 
 /*
@@ -147,7 +169,8 @@ typedef struct {
     double abs_min, abs_max;
     uint64_t n_zero, n_neg;
     int32_t status; /* device-side status of the producing call (0 = ok) */
-    int32_t pad0;
+    uint32_t esc_len; /* PWREL_HF_HUFFMAN: bits of the escape codeword (0 = none), see
+                         pwrel_codebook */
     /* Huffman sections (PWREL_HF_HUFFMAN; else all 0) */
     uint64_t off_huff, off_sizes, off_bits;
     uint64_t n_bits;      /* coded bits of all blocks */
@@ -418,6 +441,19 @@ int pwrel_huffman_codebook(const uint64_t *hist65536, uint32_t *count33, uint16_
                            uint32_t *n_sym, uint64_t *n_bits);
 
 /*
+ * The trained codebook of a validation code histogram (host only; Sec. 4.3):
+ * the paper averages the counts per validation block, a common factor, so
+ * the totals give the same table.  Leaves: every code with a non-zero count,
+ * and, when some code has none, the escape, weighted by the number of codes
+ * seen exactly once (at least 1).  Lengths: the optimal prefix code of the
+ * leaves with no codeword longer than 16 bits (32 when every code was seen),
+ * by package-merge; ties between equal weights go to the smaller code, the
+ * escape after every code.  Returns PWREL_OK, or PWREL_EINVAL for a NULL
+ * argument.
+ */
+int pwrel_huffman_trained_codebook(const uint64_t *hist65536, pwrel_codebook *out);
+
+/*
  * Device time per phase of the last pwrel_compress / pwrel_decompress on this
  * context, in milliseconds, from HIP events recorded on the caller's stream
  * while profiling is enabled (off by default; enabling adds no host sync).
@@ -491,6 +527,16 @@ typedef struct {
 int pwrel_train(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim, int dtype,
                 double rel_error_bound, int block_size, const pwrel_train_options *opt,
                 const pwrel_mlp *init, pwrel_mlp *out, pwrel_train_report *report, void *stream);
+
+/*
+ * The Huffman codebook of the context's last successful pwrel_train (Sec.
+ * 4.3: built once, from the validation codes of the chosen network; FP32
+ * network, the codes its validation score counts), as
+ * pwrel_huffman_trained_codebook builds it from their histogram.  *out
+ * (host) receives it; pass it as pwrel_options.codebook.  Synchronizes the
+ * stream.  PWREL_EINVAL when the context has not trained.
+ */
+int pwrel_train_codebook(pwrel_ctx *ctx, pwrel_codebook *out, void *stream);
 
 /*
  * Training pieces on their own (same kernels as pwrel_train), for checking.

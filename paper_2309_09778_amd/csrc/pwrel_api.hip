@@ -35,6 +35,7 @@ struct pwrel_ctx {
     MlpW *nets = nullptr;    // [1 + candidates]
     unsigned long long *vhist = nullptr;  // [1 + candidates][65536]
     size_t vhist_cap = 0;
+    int train_best = -1;  // the last pwrel_train's chosen candidate (-1: none)
     double *scal = nullptr;  // sigma, partial sums (256), loss
     long long *scores = nullptr;
     // halo-mode decoder: block order of the last geometry, flag epoch
@@ -487,6 +488,145 @@ namespace {
 
 void mark_cb(void *ctx, int i, hipStream_t s) { mark(static_cast<pwrel_ctx *>(ctx), i, s); }
 
+// The end of a Huffman-stage compression whose codebook would not pay: the
+// 16-bit codes (in the context's code buffer, balance-point counts scanned)
+// go into the stream as pwrel_compress writes them without the stage.
+int finish_codes16(pwrel_ctx *ctx, const void *d_field, const Geom &g, const pwrel_mlp *model,
+                   const pwrel_options &opt, unsigned char *out, uint64_t out_capacity,
+                   uint64_t *out_size, hipStream_t s)
+{
+    Workspace &ws = ctx->ws;
+    const int pflags = flags_of(opt) & ~PWREL_HF_HUFFMAN;
+    const Layout L = layout_for(g, pflags);
+    const uint64_t tsize = g.dtype == PWREL_F32 ? 4u : 8u;
+    const uint32_t *counts = reinterpret_cast<const uint32_t *>(out + L.off[2]);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(out + L.off[3], ws.codes16, 2ull * (uint64_t)g.N,
+                            hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = launch_scatter(d_field, g, ws.codes16, counts, ws, out + L.off[4],
+                            (out_capacity - L.off[4]) / tsize, s)) != hipSuccess ||
+        (opt.use_net && (e = launch_write_model(*model, out + L.off[0], s)) != hipSuccess) ||
+        (e = launch_header(g, pflags, L.off, ws, out, out_capacity, true, s)) != hipSuccess)
+        return hip_fail(ctx, e, "compress (16-bit codes)");
+    mark(ctx, 3, s);
+    pwrel_header h;
+    if ((e = hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    static const int spans16[3][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}};
+    collect(ctx, spans16, 3);
+    if (h.status != PWREL_OK)
+        return finish_status(ctx, h.status);
+    *out_size = h.total_size;
+    return PWREL_OK;
+}
+
+// A caller's trained codebook (Sec. 4.3) is a valid canonical table: counts
+// that sum to n_sym within the Kraft bound, an escape of at most 16 bits
+// that has a slot, and every listed code once.
+bool codebook_ok(const pwrel_codebook &cb)
+{
+    uint64_t nsym = 0, kraft = 0;
+    for (int l = 1; l <= kHuffMaxLen; ++l) {
+        nsym += cb.count[l];
+        kraft += (uint64_t)cb.count[l] << (kHuffMaxLen - l);
+    }
+    if (cb.count[0] != 0 || nsym == 0 || nsym > 65536 || nsym != cb.n_sym ||
+        kraft > (uint64_t(1) << kHuffMaxLen) || cb.esc_len > 16 ||
+        (cb.esc_len != 0 && cb.count[cb.esc_len] == 0))
+        return false;
+    uint64_t esc_ix = ~0ull;
+    if (cb.esc_len) {
+        uint64_t idx = 0;
+        for (uint32_t l = 1; l <= cb.esc_len; ++l)
+            idx += cb.count[l];
+        esc_ix = idx - 1;
+    }
+    std::vector<uint64_t> seen(1024, 0);
+    for (uint64_t i = 0; i < nsym; ++i) {
+        if (i == esc_ix)
+            continue;
+        const uint32_t v = cb.syms[i];
+        if (seen[v >> 6] & (1ull << (v & 63)))
+            return false;
+        seen[v >> 6] |= 1ull << (v & 63);
+    }
+    return true;
+}
+
+// The Huffman stage with a trained codebook: the table is known before any
+// code is, so the per-block sizes and their scan follow the compression
+// kernels directly; one small copy (balance points, status, coded bits)
+// then lays the stream out.
+int huffman_trained_tail(pwrel_ctx *ctx, const void *d_field, const Geom &g,
+                         const pwrel_mlp *model, const pwrel_options &opt, unsigned char *out,
+                         uint64_t out_capacity, uint64_t *out_size, hipStream_t s)
+{
+    Workspace &ws = ctx->ws;
+    const pwrel_codebook &cb = *opt.codebook;
+    const int flags = flags_of(opt);
+    const Layout L = layout_for(g, flags);
+    const uint64_t tsize = g.dtype == PWREL_F32 ? 4u : 8u;
+    const uint32_t *counts = reinterpret_cast<const uint32_t *>(out + L.off[2]);
+    hipError_t e;
+    if ((e = launch_scan(counts, g, ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "compress (scan)");
+    uint64_t total = 0;
+    HuffLayout hl = huff_layout(g, L, cb.n_sym, 0, 0, tsize, total);
+    if (hl.off_bits > out_capacity)  // table and sizes alone outgrow the output
+        return finish_codes16(ctx, d_field, g, model, opt, out, out_capacity, out_size, s);
+    uint32_t *d_tab = reinterpret_cast<uint32_t *>(out + hl.off_huff);
+    struct {
+        unsigned long long n_raw, bits;
+        int status;
+    } got{};
+    if ((e = hipMemcpyAsync(d_tab, cb.count, sizeof cb.count, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(d_tab + kHuffMaxLen + 1, cb.syms, 2ull * cb.n_sym,
+                            hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_huff_sizes(g, ws.codes16, d_tab, cb.esc_len, out + hl.off_sizes, ws, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&got.n_raw, ws.n_raw, sizeof got.n_raw, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&got.bits, ws.bits_total, sizeof got.bits, hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&got.status, ws.status, sizeof got.status, hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "compress (Huffman sizes)");
+    if (got.status == PWREL_ECORRUPT)
+        return fail(ctx, PWREL_EINVAL, "the codebook has no codeword and no escape for a code");
+    if (got.status != PWREL_OK)
+        return finish_status(ctx, got.status);
+    hl = huff_layout(g, L, cb.n_sym, got.bits, got.n_raw, tsize, total);
+    hl.esc_len = cb.esc_len;
+    if (total >= L.off[4] + got.n_raw * tsize)
+        return finish_codes16(ctx, d_field, g, model, opt, out, out_capacity, out_size, s);
+    if (total > out_capacity)
+        return fail(ctx, PWREL_ENOSPC, "output capacity too small");
+    const uint64_t off_raw = align256(hl.off_bits + 4ull * ((hl.n_bits + 31) / 32));
+    const uint64_t offs[5] = {L.off[0], L.off[1], L.off[2], 0, off_raw};
+    if ((e = launch_scatter(d_field, g, ws.codes16, counts, ws, out + off_raw,
+                            (out_capacity - off_raw) / tsize, s)) != hipSuccess ||
+        (e = launch_huff_pack(g, ws.codes16, out + hl.off_sizes,
+                              reinterpret_cast<uint32_t *>(out + hl.off_bits),
+                              (hl.n_bits + 31) / 32, ws, s)) != hipSuccess ||
+        (opt.use_net && (e = launch_write_model(*model, out + L.off[0], s)) != hipSuccess) ||
+        (e = launch_header(g, flags, offs, ws, out, out_capacity, true, s, &hl)) != hipSuccess)
+        return hip_fail(ctx, e, "compress (Huffman stage)");
+    mark(ctx, 3, s);
+    pwrel_header h;
+    if ((e = hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    static const int spans[3][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}};
+    collect(ctx, spans, 3);
+    if (h.status != PWREL_OK)
+        return finish_status(ctx, h.status);
+    *out_size = h.total_size;
+    return PWREL_OK;
+}
+
 // pwrel_compress with the Huffman stage (Sec. 4.1 coding stage; Algorithm 1
 // writes the Huffman codes).  Pass 1 on the device: statistics, constants,
 // grid values, prediction and quantisation into the context's 16-bit code
@@ -524,6 +664,8 @@ int compress_huffman(pwrel_ctx *ctx, const void *d_field, const Geom &g, const T
         return hip_fail(ctx, e, "compress");
     }
     mark(ctx, 2, s);
+    if (opt.codebook)
+        return huffman_trained_tail(ctx, d_field, g, model, opt, out, out_capacity, out_size, s);
     std::vector<uint64_t> hist(65536);
     unsigned long long n_raw = 0;
     int dst = 0;
@@ -545,29 +687,10 @@ int compress_huffman(pwrel_ctx *ctx, const void *d_field, const Geom &g, const T
         return fail(ctx, PWREL_EHIP, "internal: Huffman code longer than the 16-bit codes");
     uint64_t total = 0;
     const HuffLayout hl = huff_layout(g, L, t.syms.size(), t.n_bits, n_raw, tsize, total);
-    if (total >= L.off[4] + n_raw * tsize) {
+    if (total >= L.off[4] + n_raw * tsize)
         // the codebook costs more than it saves (codes spread over many
         // values in a small field): the stream keeps the 16-bit codes
-        const int pflags = flags & ~PWREL_HF_HUFFMAN;
-        if ((e = hipMemcpyAsync(out + L.off[3], ws.codes16, 2ull * (uint64_t)g.N,
-                                hipMemcpyDeviceToDevice, s)) != hipSuccess ||
-            (e = launch_scatter(d_field, g, ws.codes16, counts, ws, out + L.off[4],
-                                (out_capacity - L.off[4]) / tsize, s)) != hipSuccess ||
-            (opt.use_net && (e = launch_write_model(*model, out + L.off[0], s)) != hipSuccess) ||
-            (e = launch_header(g, pflags, L.off, ws, out, out_capacity, true, s)) != hipSuccess)
-            return hip_fail(ctx, e, "compress (16-bit codes)");
-        mark(ctx, 3, s);
-        pwrel_header h;
-        if ((e = hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return hip_fail(ctx, e, "header copy");
-        static const int spans16[3][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}};
-        collect(ctx, spans16, 3);
-        if (h.status != PWREL_OK)
-            return finish_status(ctx, h.status);
-        *out_size = h.total_size;
-        return PWREL_OK;
-    }
+        return finish_codes16(ctx, d_field, g, model, opt, out, out_capacity, out_size, s);
     if (total > out_capacity)
         return fail(ctx, PWREL_ENOSPC, "output capacity too small");
     // codebook section: count[0..32], then the symbols in canonical order
@@ -643,6 +766,8 @@ int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, in
         (e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N)) != hipSuccess)
         return fail(ctx, PWREL_ENOMEM, "grid field allocation failed");
     unsigned char *out = static_cast<unsigned char *>(d_out);
+    if (opt.entropy && opt.codebook && !codebook_ok(*opt.codebook))
+        return fail(ctx, PWREL_EINVAL, "the codebook is not a valid canonical table");
     if (opt.entropy)
         return compress_huffman(ctx, d_field, g, tile, eps, model, opt, out, out_capacity,
                                 out_size, s);
@@ -909,7 +1034,7 @@ int pwrel_read_header(const void *buf, uint64_t size, pwrel_header *out)
         return PWREL_ECORRUPT;
     if (h.flags & PWREL_HF_HUFFMAN) {
         if (h.off_codes != 0 || h.n_sym < 1 || h.n_sym > 65536 || h.n_bits > 16ull * h.n ||
-            h.size_bytes != (uint32_t)huff_size_bytes(g))
+            h.size_bytes != (uint32_t)huff_size_bytes(g) || h.esc_len > 16)
             return PWREL_ECORRUPT;
         uint64_t total = 0;
         const HuffLayout hl = huff_layout(g, L, h.n_sym, h.n_bits, h.n_raw, tsize, total);
@@ -918,7 +1043,7 @@ int pwrel_read_header(const void *buf, uint64_t size, pwrel_header *out)
             return PWREL_ECORRUPT;
     } else {
         if (h.off_codes != L.off[3] || h.off_raw != L.off[4] || h.off_huff || h.off_sizes ||
-            h.off_bits || h.n_bits || h.n_sym || h.size_bytes)
+            h.off_bits || h.n_bits || h.n_sym || h.size_bytes || h.esc_len)
             return PWREL_ECORRUPT;
     }
     if (h.total_size != h.off_raw + h.n_raw * tsize || h.total_size > size)
@@ -1064,14 +1189,15 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
             nsym += cnt[l];
             kraft += (uint64_t)cnt[l] << (kHuffMaxLen - l);
         }
-        if (cnt[0] != 0 || nsym != h.n_sym || kraft > (uint64_t(1) << kHuffMaxLen))
+        if (cnt[0] != 0 || nsym != h.n_sym || kraft > (uint64_t(1) << kHuffMaxLen) ||
+            (h.esc_len != 0 && cnt[h.esc_len] == 0))
             return fail(ctx, PWREL_ECORRUPT, "stream codebook is corrupt");
         if ((st = ensure_huffman(ctx, g)) != PWREL_OK)
             return st;
         if ((e = launch_huff_decode(g, reinterpret_cast<const uint32_t *>(in + h.off_huff),
                                     reinterpret_cast<const uint32_t *>(in + h.off_bits),
                                     (h.n_bits + 31) / 32, in + h.off_sizes, ctx->ws.codes16,
-                                    h.n_sym, ctx->ws, s)) != hipSuccess)
+                                    h.n_sym, h.esc_len, ctx->ws, s)) != hipSuccess)
             return hip_fail(ctx, e, "Huffman decode");
         codes = ctx->ws.codes16;
     }
@@ -1293,6 +1419,22 @@ int pwrel_huffman_codebook(const uint64_t *hist, uint32_t *count33, uint16_t *sy
     return PWREL_OK;
 }
 
+int pwrel_huffman_trained_codebook(const uint64_t *hist, pwrel_codebook *out)
+{
+    if (!hist || !out)
+        return PWREL_EINVAL;
+    HuffTable t;
+    uint32_t esc = 0;
+    if (!huff_build_trained(hist, t, esc))
+        return PWREL_EHIP;
+    std::memset(out, 0, sizeof *out);
+    std::memcpy(out->count, t.count.data(), (kHuffMaxLen + 1) * sizeof(uint32_t));
+    std::memcpy(out->syms, t.syms.data(), t.syms.size() * sizeof(uint16_t));
+    out->n_sym = (uint32_t)t.syms.size();
+    out->esc_len = esc;
+    return PWREL_OK;
+}
+
 uint64_t pwrel_huffman_bits(const uint64_t *hist, uint32_t *max_len_out)
 {
     // Huffman code lengths by repeated merging of the two lightest subtrees;
@@ -1469,6 +1611,7 @@ int pwrel_train(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int n
 {
     if (!ctx)
         return PWREL_EINVAL;
+    ctx->train_best = -1;
     if (pwrel_check_args(dims, ndim, dtype, eps, block_size) != PWREL_OK || !d_field || !opt ||
         !out)
         return fail(ctx, PWREL_EINVAL, "bad dims/ndim/dtype/bound/block size or NULL pointer");
@@ -1642,6 +1785,29 @@ int pwrel_train(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int n
     }
     cleanup();
     *out = res;
+    ctx->train_best = best;
+    return PWREL_OK;
+}
+
+int pwrel_train_codebook(pwrel_ctx *ctx, pwrel_codebook *out, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!out)
+        return fail(ctx, PWREL_EINVAL, "NULL codebook");
+    if (ctx->train_best < 0 || !ctx->vhist)
+        return fail(ctx, PWREL_EINVAL, "the context has not trained a network");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::vector<uint64_t> hist(65536);
+    hipError_t e = hipMemcpyAsync(hist.data(), ctx->vhist + (size_t)ctx->train_best * 65536,
+                                  65536 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "validation histogram copy");
+    if (pwrel_huffman_trained_codebook(hist.data(), out) != PWREL_OK)
+        return fail(ctx, PWREL_EHIP, "internal: trained codebook construction failed");
     return PWREL_OK;
 }
 

@@ -514,6 +514,7 @@ __device__ __forceinline__ void write_header(const HeaderArgs &h, const DevConst
     o.n_bits = h.n_bits;
     o.n_sym = h.n_sym;
     o.size_bytes = h.size_bytes;
+    o.esc_len = h.esc_len;
     int st = *status;
     if (st == kOk && o.total_size > h.capacity)
         st = kENoSpc;
@@ -828,6 +829,7 @@ HeaderArgs make_header_args(const Geom &g, int flags, const uint64_t *offs, uint
         h.n_bits = hl->n_bits;
         h.n_sym = hl->n_sym;
         h.size_bytes = hl->size_bytes;
+        h.esc_len = hl->esc_len;
         gap(offs[2] + 4ull * (unsigned long long)g.nblocks, hl->off_huff);
         gap(hl->off_huff + hl->table_bytes, hl->off_sizes);
         gap(hl->off_sizes + (unsigned long long)hl->size_bytes * g.nblocks, hl->off_bits);

@@ -27,6 +27,13 @@ inline uint64_t huff_table_bytes(uint64_t n_sym) { return 4ull * (kHuffMaxLen + 
 // histogram)
 bool huff_build(const uint64_t *hist, HuffTable &t);
 
+// the escape symbol of a trained codebook (an index past the 16-bit codes)
+constexpr uint32_t kHuffEsc = 65536;
+// the trained codebook (lengths of at most 16 bits with an escape, 32
+// without) from validation code counts; esc_len = the escape's length (0 =
+// none); the escape is listed as 0, last among the symbols of its length
+bool huff_build_trained(const uint64_t *hist, HuffTable &t, uint32_t &esc_len);
+
 // bytes per block bit size in the stream (2 when every block fits 65,535 bits)
 int huff_size_bytes(const Geom &g);
 
@@ -36,10 +43,18 @@ int huff_size_bytes(const Geom &g);
 hipError_t launch_huff_encode(const Geom &g, const uint16_t *codes, const uint32_t *d_tab,
                               void *d_sizes, uint32_t *d_bits, unsigned long long nwords,
                               Workspace &ws, hipStream_t s);
-// decoder: codes (block-major) from the table (nsym symbols), words and
-// per-block sizes
+// the encoder's two halves: encoder tables (esc_len: the table's escape
+// length, 0 = none), per-block sizes and their scan (total in ws.bits_total);
+// then the zeroed bit section and the packing
+hipError_t launch_huff_sizes(const Geom &g, const uint16_t *codes, const uint32_t *d_tab,
+                             unsigned esc_len, void *d_sizes, Workspace &ws, hipStream_t s);
+hipError_t launch_huff_pack(const Geom &g, const uint16_t *codes, const void *d_sizes,
+                            uint32_t *d_bits, unsigned long long nwords, Workspace &ws,
+                            hipStream_t s);
+// decoder: codes (block-major) from the table (nsym symbols, escape of
+// esc_len bits or none), words and per-block sizes
 hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32_t *d_bits,
                               unsigned long long nwords, const void *d_sizes, uint16_t *codes,
-                              unsigned nsym, Workspace &ws, hipStream_t s);
+                              unsigned nsym, unsigned esc_len, Workspace &ws, hipStream_t s);
 
 }  // namespace pwrel

@@ -162,6 +162,120 @@ bool huff_build(const uint64_t *hist, HuffTable &t)
     return kraft <= (uint64_t(1) << kHuffMaxLen);
 }
 
+// The codebook of the training phase (Sec. 4.3: one table from the
+// validation set's code frequencies, reused for every block).  The leaves
+// are the codes with a non-zero count and, when some code was never seen,
+// the escape (alphabet index 65536, weight = the number of codes seen once,
+// at least 1), which stands for every unseen code and is followed in the
+// stream by the code's 16 bits.  Lengths: the optimal prefix code with no
+// codeword longer than 16 bits (32 without an escape), by package-merge
+// (Larmore and Hirschberg 1990).  Row r holds the leaves merged with the
+// pairs of row r - 1 (a leaf goes before a pair of equal weight); the last
+// row's 2n - 2 lightest items are selected, and every selected prefix of a
+// row asks for twice its pairs from the row before.  Only each row's leaf
+// positions are kept (a bit per item): the selected prefix of a row holds
+// the lightest m_r leaves, and a leaf's length is the number of rows whose
+// m_r passes it.
+bool huff_build_trained(const uint64_t *hist, HuffTable &t, uint32_t &esc_len)
+{
+    struct Leaf {
+        uint64_t w;
+        uint32_t s;
+    };
+    std::vector<Leaf> leaves;
+    uint64_t ones = 0;
+    bool unseen = false;
+    for (uint32_t s = 0; s < 65536u; ++s) {
+        if (hist[s])
+            leaves.push_back({hist[s], s});
+        ones += hist[s] == 1;
+        unseen |= hist[s] == 0;
+    }
+    if (unseen)
+        leaves.push_back({std::max<uint64_t>(ones, 1), kHuffEsc});
+    std::stable_sort(leaves.begin(), leaves.end(),
+                     [](const Leaf &a, const Leaf &b) { return a.w < b.w; });
+    const size_t n = leaves.size();
+    const uint32_t lmax = unseen ? 16u : (uint32_t)kHuffMaxLen;
+    std::vector<uint32_t> len(n, 0);
+    if (n == 1) {
+        len[0] = 1;
+    } else {
+        if (n > ((size_t)1 << lmax))
+            return false;
+        // forward: each row's item weights (to pair them into the next row)
+        // and leaf flags (to count the selected leaves on the way back)
+        std::vector<std::vector<uint64_t>> isleaf(lmax);
+        std::vector<uint64_t> prev, cur;
+        std::vector<size_t> rows(lmax);
+        for (uint32_t r = 0; r < lmax; ++r) {
+            const size_t np = r == 0 ? 0 : prev.size() / 2;
+            cur.clear();
+            cur.reserve(n + np);
+            isleaf[r].assign((n + np + 63) / 64, 0ull);
+            size_t i = 0, j = 0;
+            while (i < n || j < np) {
+                const uint64_t pw = j < np ? prev[2 * j] + prev[2 * j + 1] : 0;
+                if (j >= np || (i < n && leaves[i].w <= pw)) {
+                    isleaf[r][cur.size() >> 6] |= 1ull << (cur.size() & 63);
+                    cur.push_back(leaves[i++].w);
+                } else {
+                    cur.push_back(pw);
+                    ++j;
+                }
+            }
+            rows[r] = cur.size();
+            prev.swap(cur);
+        }
+        size_t take = 2 * n - 2;
+        if (rows[lmax - 1] < take)
+            return false;
+        // backward: selected leaves of each row, then the pairs it takes
+        std::vector<int64_t> diff(n + 1, 0);
+        for (uint32_t r = lmax; r-- > 0;) {
+            size_t m = 0;
+            for (size_t k = 0; k < take / 64; ++k)
+                m += (size_t)__builtin_popcountll(isleaf[r][k]);
+            if (take & 63)
+                m += (size_t)__builtin_popcountll(isleaf[r][take / 64] &
+                                                  ((1ull << (take & 63)) - 1));
+            diff[0] += 1;
+            diff[m] -= 1;
+            take = 2 * (take - m);
+        }
+        if (take != 0)
+            return false;
+        int64_t acc = 0;
+        for (size_t i = 0; i < n; ++i) {
+            acc += diff[i];
+            len[i] = (uint32_t)acc;
+        }
+    }
+    // canonical order: by length, then symbol (the escape last of its length)
+    t.count.assign(kHuffMaxLen + 1, 0);
+    t.n_bits = 0;
+    t.max_len = 0;
+    esc_len = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> ord(n);
+    for (size_t i = 0; i < n; ++i) {
+        if (len[i] < 1 || len[i] > lmax)
+            return false;
+        t.count[len[i]]++;
+        t.max_len = std::max(t.max_len, len[i]);
+        if (leaves[i].s == kHuffEsc)
+            esc_len = len[i];
+        ord[i] = {len[i], leaves[i].s};
+    }
+    std::sort(ord.begin(), ord.end());
+    t.syms.resize(n);
+    for (size_t i = 0; i < n; ++i)
+        t.syms[i] = ord[i].second == kHuffEsc ? (uint16_t)0 : (uint16_t)ord[i].second;
+    uint64_t kraft = 0;
+    for (uint32_t l = 1; l <= (uint32_t)kHuffMaxLen; ++l)
+        kraft += (uint64_t)t.count[l] << (kHuffMaxLen - l);
+    return kraft <= (uint64_t(1) << kHuffMaxLen);
+}
+
 // ---------------------------------------------------------------------------
 // device
 // ---------------------------------------------------------------------------
@@ -197,9 +311,43 @@ __global__ void k_fill_u32(uint32_t *p, unsigned long long n, uint32_t v)
         p[i] = v;
 }
 
-// encoder table: length and codeword of every symbol (0 = unused)
-__global__ void k_huff_enc(const uint32_t *__restrict__ tab, uint8_t *__restrict__ enc_len,
-                           uint32_t *__restrict__ enc_code)
+// canonical index and codeword of the escape (the last symbol of length
+// esc_len); ~0u when there is none
+__device__ __forceinline__ void esc_of(const uint32_t *cnt, unsigned esc_len, unsigned &ix,
+                                       unsigned &code)
+{
+    ix = ~0u;
+    code = 0;
+    if (esc_len == 0 || esc_len > (unsigned)kHuffMaxLen || cnt[esc_len] == 0)
+        return;
+    unsigned c = 0, idx = 0, prev = 0;
+    for (unsigned l = 1; l <= esc_len; ++l) {
+        c = (c + prev) << 1;
+        prev = cnt[l];
+        idx += l < esc_len ? cnt[l] : 0u;
+    }
+    ix = idx + cnt[esc_len] - 1;
+    code = c + cnt[esc_len] - 1;
+}
+
+// encoder table before k_huff_enc: every code unused (esc_len = 0), or
+// every code the escape codeword followed by its own 16 bits
+__global__ void k_huff_enc_init(const uint32_t *__restrict__ tab, unsigned esc_len,
+                                uint8_t *__restrict__ enc_len, uint32_t *__restrict__ enc_code)
+{
+    unsigned ix, ecode;
+    esc_of(tab, esc_len, ix, ecode);
+    for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < 65536u;
+         s += gridDim.x * blockDim.x) {
+        enc_len[s] = ix == ~0u ? (uint8_t)0 : (uint8_t)(esc_len + 16);
+        enc_code[s] = ix == ~0u ? 0u : (ecode << 16) | s;
+    }
+}
+
+// encoder table: length and codeword of every symbol the table lists (the
+// escape's slot excepted)
+__global__ void k_huff_enc(const uint32_t *__restrict__ tab, unsigned esc_len,
+                           uint8_t *__restrict__ enc_len, uint32_t *__restrict__ enc_code)
 {
     const uint32_t *cnt = tab;
     const uint16_t *syms = reinterpret_cast<const uint16_t *>(tab + kHuffMaxLen + 1);
@@ -207,7 +355,9 @@ __global__ void k_huff_enc(const uint32_t *__restrict__ tab, uint8_t *__restrict
     for (int l = 1; l <= kHuffMaxLen; ++l)
         nsym += cnt[l];
     const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsym)
+    unsigned eix, ecode;
+    esc_of(cnt, esc_len, eix, ecode);
+    if (i >= nsym || i == eix)
         return;
     unsigned code = 0, idx = 0, prev = 0;
     for (int l = 1; l <= kHuffMaxLen; ++l) {
@@ -410,7 +560,7 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
                                                      const unsigned long long *__restrict__ boffs,
                                                      const unsigned long long *__restrict__ bparts,
                                                      uint16_t *__restrict__ codes, int *status,
-                                                     unsigned nsym)
+                                                     unsigned nsym, unsigned esc_len)
 {
     extern __shared__ __align__(16) unsigned char hsm[];
     uint32_t *lut = reinterpret_cast<uint32_t *>(hsm);  // symbol | length << 16 (0: longer)
@@ -419,6 +569,7 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
     __shared__ int soff[kHuffMaxLen + 2];        // index[l] - first[l]
     __shared__ unsigned slim[kHuffMaxLen + 2];   // left-aligned end of the length-l codes
     __shared__ unsigned smax;                    // longest code length
+    __shared__ unsigned sesc;                    // canonical index of the escape (~0u: none)
     const uint32_t *cnt = tab;
     const uint16_t *syms = reinterpret_cast<const uint16_t *>(tab + kHuffMaxLen + 1);
     const unsigned nlds = nsym < (unsigned)kSymsLds ? nsym : (unsigned)kSymsLds;
@@ -435,6 +586,8 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
                 mx = (unsigned)l;
         }
         smax = mx;
+        unsigned ecode;
+        esc_of(cnt, esc_len, sesc, ecode);
     }
     for (unsigned k = threadIdx.x; k < nlds; k += blockDim.x)
         ssyms[k] = syms[k];
@@ -445,7 +598,8 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
             const unsigned pre = (unsigned)e >> (kLutBits - l);
             if (pre - cs.first[l] < cs.count[l]) {
                 const unsigned ix = cs.index[l] + (pre - cs.first[l]);
-                v = (ix < nlds ? ssyms[ix] : syms[ix]) | ((uint32_t)l << 16);
+                v = ix == sesc ? 0x80000000u | ((uint32_t)l << 16)
+                               : (ix < nlds ? ssyms[ix] : syms[ix]) | ((uint32_t)l << 16);
                 break;
             }
         }
@@ -453,6 +607,7 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
     }
     unsigned lim[kHuffMaxLen];
     const unsigned maxlen = smax;
+    const unsigned esc_ix = sesc;
 #pragma unroll
     for (int l = kLutBits + 1; l < kHuffMaxLen; ++l)
         lim[l] = slim[l];
@@ -511,7 +666,8 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
         refill();
         const unsigned win = (unsigned)(buf >> 32);
         const uint32_t e = lut[win >> (32 - kLutBits)];
-        unsigned l = e >> 16, sym = e & 0xFFFFu;
+        unsigned l = (e >> 16) & 0xFFu, sym = e & 0xFFFFu;
+        bool esc = (e >> 31) != 0;
         if (l == 0) {
             // a longer code: its length is kLutBits + 1 plus the number of
             // length limits (below the longest length) the window reaches
@@ -526,12 +682,21 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
                 sym = 0;
             } else {
                 l = len;
+                esc = ix == (long long)esc_ix;
                 sym = ix < (long long)nlds ? ssyms[ix] : syms[ix];
             }
         }
         buf <<= l;
         nb -= (int)l;
         used += l;
+        if (esc) {
+            // the escaped code's own 16 bits follow (the escape has at most
+            // 16 bits, so the refilled buffer still holds them)
+            sym = (unsigned)(buf >> 48);
+            buf <<= 16;
+            nb -= 16;
+            used += 16;
+        }
         return sym;
     };
     uint16_t *dst = codes + q.start;
@@ -587,15 +752,35 @@ int huff_size_bytes(const Geom &g)
     return bv * kHuffMaxLen <= 65535 ? 2 : 4;
 }
 
-hipError_t launch_huff_encode(const Geom &g, const uint16_t *codes, const uint32_t *d_tab,
-                              void *d_sizes, uint32_t *d_bits, unsigned long long nwords,
-                              Workspace &ws, hipStream_t s)
+hipError_t launch_huff_sizes(const Geom &g, const uint16_t *codes, const uint32_t *d_tab,
+                             unsigned esc_len, void *d_sizes, Workspace &ws, hipStream_t s)
 {
     const GeoArgs ga = geo_of(g);
-    hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, s,
-                       reinterpret_cast<uint32_t *>(ws.enc_len), 65536ull / 4, 0u);
-    hipLaunchKernelGGL(k_huff_enc, dim3(256), dim3(256), 0, s, d_tab, ws.enc_len, ws.enc_code);
+    hipLaunchKernelGGL(k_huff_enc_init, dim3(64), dim3(256), 0, s, d_tab, esc_len, ws.enc_len,
+                       ws.enc_code);
+    hipLaunchKernelGGL(k_huff_enc, dim3(256), dim3(256), 0, s, d_tab, esc_len, ws.enc_len,
+                       ws.enc_code);
     const unsigned grid = wave_grid(g.nblocks);
+    hipError_t e;
+    if (huff_size_bytes(g) == 2) {
+        uint16_t *sz = static_cast<uint16_t *>(d_sizes);
+        hipLaunchKernelGGL(k_huff_sizes<uint16_t>, dim3(grid), dim3(256), 0, s, codes, ga,
+                           ws.enc_len, sz, ws.status);
+        e = launch_scan_sizes(sz, 2, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total, s);
+    } else {
+        uint32_t *sz = static_cast<uint32_t *>(d_sizes);
+        hipLaunchKernelGGL(k_huff_sizes<uint32_t>, dim3(grid), dim3(256), 0, s, codes, ga,
+                           ws.enc_len, sz, ws.status);
+        e = launch_scan_sizes(sz, 4, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total, s);
+    }
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_huff_pack(const Geom &g, const uint16_t *codes, const void *d_sizes,
+                            uint32_t *d_bits, unsigned long long nwords, Workspace &ws,
+                            hipStream_t s)
+{
+    const GeoArgs ga = geo_of(g);
     const long long bv = (long long)g.bd[0] * g.bd[1] * g.bd[2];
     const int wave_words = (int)((bv * kHuffMaxLen + 31) / 32 + 2);
     // waves per workgroup of the packer: each holds its block's words in LDS
@@ -606,35 +791,30 @@ hipError_t launch_huff_encode(const Geom &g, const uint16_t *codes, const uint32
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<unsigned long long>(
                                        std::max<unsigned long long>(1, (nwords + 255) / 256), 8192)),
                        dim3(256), 0, s, d_bits, nwords, 0u);
-    if (huff_size_bytes(g) == 2) {
-        uint16_t *sz = static_cast<uint16_t *>(d_sizes);
-        hipLaunchKernelGGL(k_huff_sizes<uint16_t>, dim3(grid), dim3(256), 0, s, codes, ga,
-                           ws.enc_len, sz, ws.status);
-        hipError_t e = launch_scan_sizes(sz, 2, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
-                                         s);
-        if (e != hipSuccess)
-            return e;
+    if (huff_size_bytes(g) == 2)
         hipLaunchKernelGGL(k_huff_pack<uint16_t>, dim3(pgrid), dim3(64 * wpg), lds, s, codes, ga,
-                           ws.enc_len, ws.enc_code, sz, ws.boffsets, ws.bpartials, d_bits,
-                           wave_words, ws.status);
-    } else {
-        uint32_t *sz = static_cast<uint32_t *>(d_sizes);
-        hipLaunchKernelGGL(k_huff_sizes<uint32_t>, dim3(grid), dim3(256), 0, s, codes, ga,
-                           ws.enc_len, sz, ws.status);
-        hipError_t e = launch_scan_sizes(sz, 4, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
-                                         s);
-        if (e != hipSuccess)
-            return e;
+                           ws.enc_len, ws.enc_code, static_cast<const uint16_t *>(d_sizes),
+                           ws.boffsets, ws.bpartials, d_bits, wave_words, ws.status);
+    else
         hipLaunchKernelGGL(k_huff_pack<uint32_t>, dim3(pgrid), dim3(64 * wpg), lds, s, codes, ga,
-                           ws.enc_len, ws.enc_code, sz, ws.boffsets, ws.bpartials, d_bits,
-                           wave_words, ws.status);
-    }
+                           ws.enc_len, ws.enc_code, static_cast<const uint32_t *>(d_sizes),
+                           ws.boffsets, ws.bpartials, d_bits, wave_words, ws.status);
     return hipGetLastError();
+}
+
+hipError_t launch_huff_encode(const Geom &g, const uint16_t *codes, const uint32_t *d_tab,
+                              void *d_sizes, uint32_t *d_bits, unsigned long long nwords,
+                              Workspace &ws, hipStream_t s)
+{
+    hipError_t e = launch_huff_sizes(g, codes, d_tab, 0, d_sizes, ws, s);
+    if (e != hipSuccess)
+        return e;
+    return launch_huff_pack(g, codes, d_sizes, d_bits, nwords, ws, s);
 }
 
 hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32_t *d_bits,
                               unsigned long long nwords, const void *d_sizes, uint16_t *codes,
-                              unsigned nsym, Workspace &ws, hipStream_t s)
+                              unsigned nsym, unsigned esc_len, Workspace &ws, hipStream_t s)
 {
     const GeoArgs ga = geo_of(g);
     const unsigned grid = (unsigned)((g.nblocks + kUnpackThreads - 1) / kUnpackThreads);
@@ -648,7 +828,7 @@ hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32
             return e;
         hipLaunchKernelGGL(k_huff_unpack<uint16_t>, dim3(grid), dim3(kUnpackThreads), lds, s,
                            d_tab, d_bits, nwords, ga, sz, ws.boffsets, ws.bpartials, codes,
-                           ws.status, nsym);
+                           ws.status, nsym, esc_len);
     } else {
         const uint32_t *sz = static_cast<const uint32_t *>(d_sizes);
         if ((e = launch_scan_sizes(sz, 4, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
@@ -656,7 +836,7 @@ hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32
             return e;
         hipLaunchKernelGGL(k_huff_unpack<uint32_t>, dim3(grid), dim3(kUnpackThreads), lds, s,
                            d_tab, d_bits, nwords, ga, sz, ws.boffsets, ws.bpartials, codes,
-                           ws.status, nsym);
+                           ws.status, nsym, esc_len);
     }
     return hipGetLastError();
 }

@@ -114,7 +114,7 @@ struct HeaderArgs {
     unsigned long long pad_lo[kHeaderGaps], pad_hi[kHeaderGaps];  // gaps between sections
     // Huffman sections (0 without them)
     unsigned long long off_huff, off_sizes, off_bits, n_bits;
-    unsigned n_sym, size_bytes;
+    unsigned n_sym, size_bytes, esc_len;
 };
 // One field of pwrel_compress_batch for the batched statistics, constants,
 // grid entries, scan, raw scatter, model and header kernels (device table).
@@ -177,7 +177,7 @@ hipError_t launch_scatter(const void *x, const Geom &g, const uint16_t *codes,
 // Placement of the Huffman sections of a stream (host-computed)
 struct HuffLayout {
     uint64_t off_huff, off_sizes, off_bits, n_bits, table_bytes;
-    uint32_t n_sym, size_bytes;
+    uint32_t n_sym, size_bytes, esc_len;
 };
 HeaderArgs make_header_args(const Geom &g, int flags, const uint64_t *offs, uint64_t capacity,
                             bool stream_gaps, const HuffLayout *hl);

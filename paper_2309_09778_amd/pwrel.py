@@ -39,9 +39,23 @@ class Mlp(C.Structure):
                 ("v", C.c_float * MAXH), ("b2", C.c_float), ("precision", C.c_int32)]
 
 
+class Codebook(C.Structure):
+    """pwrel_codebook: a trained Huffman codebook (count[l] per length, the
+    symbols in canonical order, the escape's length or 0)."""
+    _fields_ = [("count", C.c_uint32 * 33), ("n_sym", C.c_uint32), ("esc_len", C.c_uint32),
+                ("syms", C.c_uint16 * 65536)]
+
+    def arrays(self):
+        """(count[33], syms[n_sym], esc_len) as numpy arrays."""
+        cnt = np.frombuffer(self.count, dtype=np.uint32).copy()
+        syms = np.frombuffer(self.syms, dtype=np.uint16)[:self.n_sym].copy()
+        return cnt, syms, int(self.esc_len)
+
+
 class Options(C.Structure):
     _fields_ = [("use_net", C.c_int32), ("judge", C.c_int32),
-                ("independent_blocks", C.c_int32), ("entropy", C.c_int32)]
+                ("independent_blocks", C.c_int32), ("entropy", C.c_int32),
+                ("codebook", C.POINTER(Codebook))]
 
 
 class Header(C.Structure):
@@ -56,7 +70,7 @@ class Header(C.Structure):
                 ("off_counts", C.c_uint64), ("off_codes", C.c_uint64), ("off_raw", C.c_uint64),
                 ("total_size", C.c_uint64), ("abs_min", C.c_double), ("abs_max", C.c_double),
                 ("n_zero", C.c_uint64), ("n_neg", C.c_uint64), ("status", C.c_int32),
-                ("pad0", C.c_int32), ("off_huff", C.c_uint64), ("off_sizes", C.c_uint64),
+                ("esc_len", C.c_uint32), ("off_huff", C.c_uint64), ("off_sizes", C.c_uint64),
                 ("off_bits", C.c_uint64), ("n_bits", C.c_uint64), ("n_sym", C.c_uint32),
                 ("size_bytes", C.c_uint32), ("p_max", C.c_int64)]
 
@@ -138,6 +152,8 @@ _SIGS = {
     "pwrel_huffman_bits": (C.c_uint64, [_P, C.POINTER(C.c_uint32)]),
     "pwrel_huffman_codebook": (C.c_int, [_P, _P, _P, C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_uint64)]),
+    "pwrel_huffman_trained_codebook": (C.c_int, [_P, C.POINTER(Codebook)]),
+    "pwrel_train_codebook": (C.c_int, [_P, C.POINTER(Codebook), _P]),
     "pwrel_mlp_init": (C.c_int, [C.POINTER(Mlp), C.c_int, C.c_int, C.c_float, C.c_uint64]),
     "pwrel_set_profiling": (C.c_int, [_P, C.c_int]),
     "pwrel_phase_times": (C.c_int, [_P, _P, C.c_int]),
@@ -324,6 +340,18 @@ def huffman_codebook(hist):
     return cnt, syms[:ns.value].copy(), int(nb.value)
 
 
+def huffman_trained_codebook(hist):
+    """The library's trained codebook (Sec. 4.3) of a 65,536-bin validation
+    code histogram, as a Codebook."""
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    assert hist.size == 65536
+    cb = Codebook()
+    st = lib().pwrel_huffman_trained_codebook(hist.ctypes.data_as(_P), C.byref(cb))
+    if st:
+        raise PwrelError(st, "huffman_trained_codebook")
+    return cb
+
+
 def codebook_lengths(count, syms):
     """Per-symbol codeword lengths (65,536 entries, 0 = unused) of a codebook
     given as length counts and canonical-order symbols."""
@@ -368,9 +396,11 @@ class Context:
 
     # codec -------------------------------------------------------------------
     def compress(self, x, eps, block=8, model=None, use_net=True, judge=False,
-                 independent=False, entropy=False, out=None, stream=None):
+                 independent=False, entropy=False, out=None, stream=None, codebook=None):
         """Compress a contiguous CUDA tensor; returns a uint8 CUDA tensor view.
-        entropy=True: the codes are Huffman coded in the stream."""
+        entropy=True: the codes are Huffman coded in the stream; codebook (a
+        Codebook, implies entropy): that trained table instead of one built
+        from the field's histogram."""
         import torch
         assert x.is_cuda and x.is_contiguous()
         dt = _dtype_code(x.dtype)
@@ -381,7 +411,9 @@ class Context:
             out = torch.empty(cap, dtype=torch.uint8, device=x.device)
         m = model_struct(model) if use_net else None
         opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)),
-                      int(bool(entropy)))
+                      int(bool(entropy) or codebook is not None))
+        if codebook is not None:
+            opt.codebook = C.pointer(codebook)
         size = C.c_uint64(0)
         st = self._L.pwrel_compress(self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), x.dim(),
                                     dt, float(eps), int(block),
@@ -566,6 +598,14 @@ class Context:
              "ms_sample": rep.ms_sample, "ms_train": rep.ms_train,
              "ms_select": rep.ms_select}
         return model_dict(out), r
+
+    def train_codebook(self, stream=None):
+        """The trained codebook of the last train() (Sec. 4.3: from the chosen
+        network's validation codes), as a Codebook."""
+        cb = Codebook()
+        self._check(self._L.pwrel_train_codebook(self.h, C.byref(cb), _stream(stream)),
+                    "train_codebook")
+        return cb
 
     def sample(self, x, eps, block=8, independent=False, rho=0.01, seed=0, stream=None):
         """Training/validation pairs of x in ascending point order:

@@ -349,8 +349,63 @@ def test_huffman_header_validation():
         with pytest.raises(pwrel.PwrelError) as e:
             pwrel.read_header_bytes(_bytes(hh), size=h.total_size + 4096)
         assert e.value.status == pwrel.ECORRUPT, field
+    # an escape of up to 16 bits is valid, a longer one corrupt
+    hh = pwrel.Header.from_buffer_copy(bytes(h))
+    hh.esc_len = 16
+    assert pwrel.read_header_bytes(_bytes(hh), size=h.total_size)["esc_len"] == 16
+    hh.esc_len = 17
+    with pytest.raises(pwrel.PwrelError):
+        pwrel.read_header_bytes(_bytes(hh), size=h.total_size)
     # Huffman fields in a 16-bit-code stream are corrupt too
     hh = _valid_header(n=n, block=block, n_raw=nraw)
     hh.n_sym = 5
     with pytest.raises(pwrel.PwrelError):
         pwrel.read_header_bytes(_bytes(hh), size=hh.total_size)
+    hh = _valid_header(n=n, block=block, n_raw=nraw)
+    hh.esc_len = 3
+    with pytest.raises(pwrel.PwrelError):
+        pwrel.read_header_bytes(_bytes(hh), size=hh.total_size)
+
+
+def _trained_hist(kind, rng):
+    h = np.zeros(65536, dtype=np.uint64)
+    if kind == "laplace":          # codes of a validation sample: a peak with tails
+        c = np.clip(np.round(rng.laplace(32768, 25, 200000)), 0, 65535).astype(np.int64)
+        h += np.bincount(c, minlength=65536).astype(np.uint64)
+    elif kind == "deep":           # the 16-bit limit binds
+        h[100:126] = 2 ** np.arange(1, 27, dtype=np.uint64)
+    elif kind == "all_seen":       # no escape: the 32-bit limit
+        h[:] = (rng.pareto(1.1, 65536) * 3 + 1).astype(np.uint64)
+    elif kind == "one_unseen":     # 65,535 codes plus the escape: every length 16
+        h[:] = rng.integers(1, 4, 65536).astype(np.uint64)
+        h[777] = 0
+    elif kind == "single":
+        h[32768] = 99
+    elif kind == "empty":
+        pass
+    else:                          # a few heavy codes and many seen once
+        idx = rng.choice(65536, 4000, replace=False)
+        h[idx] = 1
+        h[idx[:20]] = rng.integers(1000, 100000, 20).astype(np.uint64)
+    return h
+
+
+@pytest.mark.parametrize("kind", ["laplace", "deep", "all_seen", "one_unseen", "single", "empty",
+                                  "singletons"])
+def test_library_trained_codebook_equals_oracle(kind):
+    """The trained codebook of the library (Sec. 4.3: built once from
+    validation code counts, an escape for unseen codes) is the oracle's:
+    the same length counts, canonical symbols and escape length, bit for
+    bit."""
+    rng = np.random.default_rng(sum(map(ord, kind)))
+    h = _trained_hist(kind, rng)
+    cnt, syms, esc = pwrel.huffman_trained_codebook(h).arrays()
+    ln, oesc = O.huff_trained_lengths(h)
+    ocnt, osyms = O.huff_book(ln)
+    assert esc == oesc
+    assert np.array_equal(cnt, ocnt)
+    assert np.array_equal(syms, osyms)
+    if kind == "all_seen":
+        assert esc == 0 and int(cnt.sum()) == 65536
+    if kind in ("deep", "one_unseen"):
+        assert esc > 0 and max(l for l in range(33) if cnt[l]) == 16

@@ -1,0 +1,260 @@
+"""GPU parity of the Huffman stage with the codebook of the training phase
+(Sec. 4.3: one table built once from validation code frequencies and reused
+for every block; Algorithm 1 looks codes up in it; Sec. 5 rebuilds it to
+decode).  Codes the validation never produced take the escape codeword and
+their own 16 bits.
+
+- streams coded with a given trained codebook: the bit section equals, word
+  for word, the oracle's encoding of the oracle's codes under that codebook
+  (escapes included); per-block sizes, the stored table, the escape length,
+  counts and raw values are the oracle's; the reconstruction equals the
+  oracle's bit for bit.  Where the table would not pay, the stream is the
+  16-bit stream byte for byte;
+- the codebook of a training call equals the oracle's construction on the
+  histogram of the oracle's validation codes of the chosen network (same
+  sample), and a learned BF16 stream with the per-block judge coded with it
+  holds the bits of the oracle's encoding of that call's own codes;
+- invalid codebooks are refused before any GPU work; a table that lacks a
+  code and has no escape is refused; a stream whose escape has no slot is
+  corrupt.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2309_09778_amd import pwrel, synth
+from tests.test_gpu_codec import _case, assert_bound, dev, random_model
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pwrel.Context(0)
+    yield c
+    c.close()
+
+
+def _lengths(cb):
+    """Per-symbol lengths (65,537 entries: the codes, then the escape) of a
+    Codebook."""
+    cnt, syms, esc = cb.arrays()
+    ln = np.zeros(O.ESC + 1, dtype=np.uint8)
+    i = 0
+    for L in range(1, 33):
+        c = int(cnt[L])
+        for k in range(c):
+            is_esc = esc == L and k == c - 1
+            ln[O.ESC if is_esc else int(syms[i + k])] = L
+        i += c
+    return ln
+
+
+def _block_bits(codes, shape, B, ln):
+    per = np.where(ln[codes] > 0, ln[codes].astype(np.int64), int(ln[O.ESC]) + 16)
+    nb = [-(-s // B) for s in shape]
+    sizes, pos = [], 0
+    for bi in np.ndindex(*nb):
+        n = int(np.prod([min(B, s - b * B) for s, b in zip(shape, bi)]))
+        sizes.append(int(per[pos:pos + n].sum()))
+        pos += n
+    return np.array(sizes, dtype=np.int64)
+
+
+def _check_trained_stream(stream, cb, codes_ref, shape, B):
+    sec = pwrel.sections(stream)
+    h = sec["header"]
+    cnt, syms, esc = cb.arrays()
+    assert h["flags"] & pwrel.HF_HUFFMAN and h["esc_len"] == esc and h["n_sym"] == syms.size
+    assert np.array_equal(sec["huff_count"].cpu().numpy().view(np.uint32), cnt)
+    assert np.array_equal(sec["huff_syms"].cpu().numpy().view(np.uint16), syms)
+    ln = _lengths(cb)
+    words_ref, nbits = O.huff_encode_esc(codes_ref, ln)
+    assert h["n_bits"] == nbits
+    bits = sec["bits"].cpu().numpy().view(np.uint32)
+    assert np.array_equal(bits, words_ref[:bits.size])
+    dec, end = O.huff_decode_esc(bits, codes_ref.size, ln)
+    assert end == nbits and np.array_equal(dec, codes_ref)
+    sizes = sec["sizes"].cpu().numpy()
+    sizes = sizes.view(np.uint16 if h["size_bytes"] == 2 else np.uint32).astype(np.int64)
+    assert np.array_equal(sizes, _block_bits(codes_ref, shape, B, ln))
+    return sec
+
+
+def _tcase(name):
+    if name == "grf_64_lorenzo":
+        return synth.lognormal_grf((64, 64, 64), seed=31), 1e-2, 8, None, False
+    if name == "grf_64_net_indep":
+        return synth.lognormal_grf((64, 64, 64), seed=32), 1e-2, 8, random_model(3, 16, 32), \
+            True
+    if name == "grf_2d_B16":
+        return synth.lognormal_grf((300, 257), seed=33), 1e-2, 16, random_model(2, 16, 33), \
+            False
+    return _case(name)
+
+
+TRAINED_CASES = ["grf_64_lorenzo", "grf_64_net_indep", "grf_2d_B16", "config0_bumps64",
+                 "grf_B4_H32", "grf_1d_halo", "pencil_long", "f64_1e-4", "wide_span_halo",
+                 "tiny_1d"]
+
+
+@pytest.mark.parametrize("name", TRAINED_CASES)
+def test_trained_codebook_stream_vs_oracle(ctx, name):
+    x, eps, B, model, indep = _tcase(name)
+    print(f"[trained codebook] {name} {x.shape} B={B}", flush=True)
+    use_net = model is not None
+    mode = O.MODE_PLAIN if use_net else O.MODE_LORENZO
+    ref = O.compress(x, eps, B, model, mode, independent=indep)
+    # the table of a 1-in-7 subsample of the codes: the others include codes
+    # the table has never seen, which take the escape
+    hval = np.bincount(ref["codes"][::7], minlength=65536).astype(np.uint64)
+    cb = pwrel.huffman_trained_codebook(hval)
+    ln, oesc = O.huff_trained_lengths(hval)
+    assert np.array_equal(_lengths(cb), ln) and cb.esc_len == oesc
+    stream = ctx.compress(dev(x), eps, B, model, use_net=use_net, independent=indep,
+                          codebook=cb)
+    plain = ctx.compress(dev(x), eps, B, model, use_net=use_net, independent=indep)
+    h = pwrel.header(stream)
+    if not h["flags"] & pwrel.HF_HUFFMAN:
+        # the table costs more than it saves: the 16-bit stream, byte for byte
+        assert name in ("tiny_1d", "f64_1e-4", "wide_span_halo"), name
+        assert np.array_equal(stream.cpu().numpy(), plain.cpu().numpy())
+        return
+    assert stream.numel() < plain.numel()
+    if name != "grf_1d_halo":
+        assert int((ln[ref["codes"]] == 0).sum()) > 0  # escapes were coded
+    sec = _check_trained_stream(stream, cb, ref["codes"], x.shape, B)
+    assert np.array_equal(sec["counts"].cpu().numpy().view(np.uint32), ref["counts"])
+    assert np.array_equal(sec["raw"].cpu().numpy().view(np.uint8), ref["raw"].view(np.uint8))
+    xh = ctx.decompress(stream).cpu().numpy()
+    ref_xh, _ = O.decompress(ref["codes"], ref["raw"], ref["consts"], x.shape, x.dtype, B, model,
+                             mode, independent=indep)
+    assert np.array_equal(xh.view(np.uint8), ref_xh.view(np.uint8))
+    assert_bound(x, xh, eps)
+
+
+def test_codebook_without_escape(ctx):
+    """A table from a histogram where every code was seen (no escape, 32-bit
+    limit) codes the field exactly as the oracle does (a field large enough
+    for the 65,536-symbol table to pay)."""
+    x = synth.lognormal_grf((96, 96, 96), seed=41)
+    ref = O.compress(x, 1e-2, 8, None, O.MODE_LORENZO)
+    hval = np.bincount(ref["codes"], minlength=65536).astype(np.uint64) * 50 + 1
+    cb = pwrel.huffman_trained_codebook(hval)
+    assert cb.esc_len == 0 and cb.n_sym == 65536
+    stream = ctx.compress(dev(x), 1e-2, 8, None, use_net=False, codebook=cb)
+    _check_trained_stream(stream, cb, ref["codes"], x.shape, 8)
+    assert pwrel.header(stream)["esc_len"] == 0
+    xh = ctx.decompress(stream).cpu().numpy()
+    ref_xh, _ = O.decompress(ref["codes"], ref["raw"], ref["consts"], x.shape, x.dtype, 8, None,
+                             O.MODE_LORENZO)
+    assert np.array_equal(xh.view(np.uint8), ref_xh.view(np.uint8))
+
+
+@pytest.fixture(scope="module")
+def grf64():
+    return synth.lognormal_grf((64, 64, 64), seed=1001, decades=8, neg_frac=0.1, zero_frac=0.005)
+
+
+@pytest.mark.parametrize("indep", [False, True])
+def test_training_codebook_equals_oracle_and_codes_the_field(ctx, grf64, indep):
+    x = grf64
+    init = O.mlp_init(3, 32, seed=7)
+    print(f"[trained codebook] training indep={indep}", flush=True)
+    model, rep = ctx.train(dev(x), 1e-2, 8, init=init, rho=0.1, seed=99, precision=1,
+                           independent=indep)
+    cb = ctx.train_codebook()
+    c = O.consts(x, 1e-2)
+    s = O.sample(O.transform_field(x, c), c, 8, 0.1, 99, independent=indep)
+    uv, tv = s["u"][s["is_val"]], s["t"][s["is_val"]]
+    vc = O.val_codes(dict(model, precision=0), uv, tv)
+    hval = np.bincount(vc, minlength=65536).astype(np.uint64)
+    assert rep["val_score"][rep["chosen"]] == O.val_score(dict(model, precision=0), uv, tv)
+    ln, oesc = O.huff_trained_lengths(hval)
+    ocnt, osyms = O.huff_book(ln)
+    cnt, syms, esc = cb.arrays()
+    assert esc == oesc and np.array_equal(cnt, ocnt) and np.array_equal(syms, osyms)
+    # the learned BF16 path with the judge, coded with the table
+    xd = dev(x)
+    plain = ctx.compress(xd, 1e-2, 8, model, judge=True, independent=indep)
+    coded = ctx.compress(xd, 1e-2, 8, model, judge=True, independent=indep, codebook=cb)
+    assert pwrel.header(coded)["flags"] & pwrel.HF_HUFFMAN
+    codes = pwrel.sections(plain)["codes"].cpu().numpy().view(np.uint16)
+    sec = _check_trained_stream(coded, cb, codes, x.shape, 8)
+    assert np.array_equal(sec["bflags"].cpu().numpy(),
+                          pwrel.sections(plain)["bflags"].cpu().numpy())
+    a = ctx.decompress(plain).cpu().numpy()
+    b = ctx.decompress(coded).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert_bound(x, b, 1e-2)
+    # the table of the field's own histogram codes these codes in no more
+    # bits (it is optimal for them).  The trained one comes from about 5,000
+    # validation codes here (a 64^3 field, 10 % sample, 2 in 10 kept for
+    # validation) for a code distribution of about 10 bits of entropy, so
+    # many codes take the escape: it stays within a third.
+    own = ctx.compress(xd, 1e-2, 8, model, judge=True, independent=indep, entropy=True)
+    nb_own, nb_cb = pwrel.header(own)["n_bits"], pwrel.header(coded)["n_bits"]
+    print(f"bits: own table {nb_own}, trained table {nb_cb}", flush=True)
+    assert nb_own <= nb_cb <= 1.34 * nb_own
+
+
+def test_codebook_errors(ctx):
+    x = synth.lognormal_grf((24, 24, 24), seed=5)
+    xd = dev(x)
+    ref = O.compress(x, 1e-2, 8, None, O.MODE_LORENZO)
+    hval = np.bincount(ref["codes"][::3], minlength=65536).astype(np.uint64)
+    good = pwrel.huffman_trained_codebook(hval)
+    assert good.esc_len > 0
+
+    def bad(edit):
+        cb = pwrel.Codebook.from_buffer_copy(bytes(good))
+        edit(cb)
+        with pytest.raises(pwrel.PwrelError) as e:
+            ctx.compress(xd, 1e-2, 8, None, use_net=False, codebook=cb)
+        assert e.value.status == pwrel.EINVAL
+    bad(lambda cb: setattr(cb, "n_sym", cb.n_sym + 1))           # counts do not sum to n_sym
+    bad(lambda cb: setattr(cb, "esc_len", 17))                    # escape too long
+    esc_ix = int(np.asarray(good.count)[1:good.esc_len + 1].sum()) - 1
+    i, j = [k for k in range(4) if k != esc_ix][:2]
+    bad(lambda cb: cb.syms.__setitem__(j, cb.syms[i]))            # a code listed twice
+    bad(lambda cb: cb.count.__setitem__(0, 1))                    # count[0] must be 0
+
+    def over(cb):                                                 # Kraft sum above 1
+        cb.count[1] += 2
+        cb.n_sym += 2
+    bad(over)
+    # no escape and a code of the field missing from the table
+    noesc = pwrel.huffman_trained_codebook(
+        np.bincount(ref["codes"][::3], minlength=65536).astype(np.uint64) + 1)
+    cnt, syms, _ = noesc.arrays()
+    drop = pwrel.Codebook.from_buffer_copy(bytes(noesc))
+    # drop a symbol that the field uses, and shrink its length's count
+    used = set(np.unique(ref["codes"]).tolist())
+    k = next(i for i in range(syms.size) if int(syms[i]) in used)
+    L = int(np.searchsorted(np.cumsum(cnt), k, side="right"))
+    rest = np.delete(syms, k)
+    drop.count[L] -= 1
+    drop.n_sym -= 1
+    for i, v in enumerate(rest):
+        drop.syms[i] = int(v)
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.compress(xd, 1e-2, 8, None, use_net=False, codebook=drop)
+    assert e.value.status == pwrel.EINVAL
+    # a stream whose escape length names a length with no codeword is corrupt
+    s = ctx.compress(xd, 1e-2, 8, None, use_net=False, codebook=good).clone()
+    h = pwrel.header(s)
+    assert h["flags"] & pwrel.HF_HUFFMAN
+    empty = next(l for l in range(1, 17) if good.count[l] == 0)
+    raw = bytearray(s[:pwrel.HEADER_BYTES].cpu().numpy().tobytes())
+    hh = pwrel.Header.from_buffer_copy(bytes(raw[:C_SIZE]))
+    hh.esc_len = empty
+    raw[:C_SIZE] = bytes(hh)
+    s[:pwrel.HEADER_BYTES] = torch.tensor(list(raw), dtype=torch.uint8, device=s.device)
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.decompress(s)
+    assert e.value.status == pwrel.ECORRUPT
+
+
+C_SIZE = __import__("ctypes").sizeof(pwrel.Header)
