@@ -115,7 +115,8 @@ def lib():
         L.or_huff_encode_esc.argtypes = [P, C.c_int64, P, P, P]
         L.or_huff_decode_esc.restype = C.c_int64
         L.or_huff_decode_esc.argtypes = [P, C.c_int64, C.c_int64, P, C.c_int, P]
-        L.or_val_codes.argtypes = [C.POINTER(_MLP), P, P, C.c_int64, P]
+        L.or_table_hist.restype = C.c_int64
+        L.or_table_hist.argtypes = [P, P, C.c_int, C.c_int, C.c_double, C.c_uint64, P]
         L.or_bf16_rne.restype = C.c_float
         L.or_bf16_rne.argtypes = [C.c_float]
         L.or_entropy_j.restype = C.c_int64
@@ -341,14 +342,19 @@ def huff_book(lengths):
     return count, np.array([0 if s == ESC else s for s in syms], dtype=np.uint16)
 
 
-def val_codes(model, u, t):
-    """Codes of an FP32 network on validation pairs (u: [n][K], t: [n])."""
-    u = np.ascontiguousarray(u, dtype=np.int32)
-    t = np.ascontiguousarray(t, dtype=np.int32)
-    out = np.zeros(max(t.size, 1), dtype=np.uint16)
-    m = _to_c_mlp(model)
-    lib().or_val_codes(C.byref(m), _ptr(u), _ptr(t), t.size, _ptr(out))
-    return out[:t.size]
+def table_hist(codes, shape, B, frac, seed):
+    """Code counts of the table's validation blocks (Sec. 4.3): block b of
+    the stream order is one iff u01(splitmix64(seed ^ b)) < frac; codes of
+    the whole field in stream order.  Returns (hist[65536], number of
+    blocks)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    dims = _dims(shape)
+    hist = np.zeros(65536, dtype=np.uint64)
+    nsel = lib().or_table_hist(_ptr(codes), _ptr(dims), len(shape), int(B), float(frac),
+                               int(seed), _ptr(hist))
+    if nsel < 0:
+        raise OracleError(-1, "table_hist")
+    return hist, int(nsel)
 
 
 # --- deterministic math -------------------------------------------------------

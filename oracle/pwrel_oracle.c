@@ -26,7 +26,7 @@
  *   training ..................... Sec. 4.3 (10% uniform sample, 8:2 split, L2,
  *                                  one round, several lr/lambda sets, pick best)
  *   Huffman stage ................ Sec. 4.1 coding stage, Algorithm 1, Sec. 5
- *   trained codebook ............. Sec. 4.3 (validation code frequencies)
+ *   trained codebook ............. Sec. 4.3 (code frequencies of validation blocks)
  *
  * Readings where the paper is silent or inconsistent (each is listed in the
  * design notes of the repository):
@@ -1771,22 +1771,38 @@ int64_t or_huff_decode_esc(const uint32_t *words, int64_t start, int64_t n, cons
     return pos;
 }
 
-/* The codes an FP32 network gives on validation pairs (the values whose
- * histogram the validation scores and the trained codebook use). */
-void or_val_codes(const or_mlp *m, const int32_t *u, const int32_t *t, int64_t n, uint16_t *out)
+/* The table's validation set (Sec. 4.3: the table comes from the code
+ * frequencies of the validation blocks, on which the compression is
+ * simulated): block b (stream order) belongs to it iff
+ * u01(splitmix64(seed ^ b)) < frac.  hist[65536] receives the counts of
+ * their codes, given the codes of the whole field in stream order (blocks in
+ * raster order, each block's points contiguous).  The paper averages the
+ * counts per block; the totals give the same table.  Returns the number of
+ * blocks in the set, or -1 for a bad geometry. */
+int64_t or_table_hist(const uint16_t *codes, const uint64_t *dims, int ndim, int B, double frac,
+                      uint64_t seed, uint64_t *hist)
 {
-    int K = m->inputs;
-    for (int64_t i = 0; i < n; ++i) {
-        float uf[OR_MAXK];
-        for (int k = 0; k < K; ++k)
-            uf[k] = (float)u[i * K + k];
-        float y = mlp_eval_f32(m, uf);
-        if (y > 0x1p30f)
-            y = 0x1p30f;
-        if (!(y >= -0x1p30f))
-            y = -0x1p30f;
-        out[i] = code_of((int64_t)rintf(y), (int64_t)t[i], 1);
+    geom g;
+    if (geom_init(&g, dims, ndim, B))
+        return -1;
+    memset(hist, 0, 65536 * sizeof(uint64_t));
+    int64_t pos = 0, nsel = 0;
+    for (int64_t b = 0; b < g.nblocks; ++b) {
+        int64_t rem = b, size = 1;
+        for (int d = g.D - 1; d >= 0; --d) {
+            const int64_t bc = rem % g.nb[d];
+            rem /= g.nb[d];
+            const int64_t e = g.n[d] - bc * g.B;
+            size *= e < g.B ? e : g.B;
+        }
+        if (u01(or_splitmix64(seed ^ (uint64_t)b)) < frac) {
+            nsel++;
+            for (int64_t k = 0; k < size; ++k)
+                hist[codes[pos + k]]++;
+        }
+        pos += size;
     }
+    return nsel;
 }
 
 /* FP64 value of the network and the BF16 error bound of mlp_bf16_bound. */

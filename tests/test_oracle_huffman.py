@@ -25,7 +25,12 @@ validation never produced:
   code of the counts; the code stays complete (Kraft sum 1);
 - costs equal the textbook Huffman construction of the augmented weights
   when the limit does not bind;
-- escaped and coded codes decode back, bit counts and positions included.
+- escaped and coded codes decode back, bit counts and positions included;
+- the table's validation blocks (the compression simulated on a uniform
+  sample of whole blocks): their code counts equal the counts recomputed
+  here block by block, with splitmix64 written out from its published
+  definition; every block at frac 1, none at frac 0, and about frac of them
+  otherwise.
 """
 import heapq
 import itertools
@@ -229,3 +234,45 @@ def test_trained_stream_round_trip_with_escapes():
     part, end2 = O.huff_decode_esc(words, 5000, ln, start=off)
     assert np.array_equal(part, codes[7000:12000])
     assert end2 == off + int(per[7000:12000].sum())
+
+
+# --- the table's validation blocks -------------------------------------------------------------
+
+def _splitmix64(state):
+    m = (1 << 64) - 1
+    z = (state + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def _blocks_in_stream_order(shape, B):
+    nb = [-(-s // B) for s in shape]
+    for bi in np.ndindex(*nb):
+        yield int(np.prod([min(B, s - b * B) for s, b in zip(shape, bi)]))
+
+
+@pytest.mark.parametrize("shape,B", [((37, 20, 19), 8), ((130, 71), 16), ((1001,), 64),
+                                     ((9, 9, 9), 4)])
+def test_table_hist_is_the_selected_blocks_codes(shape, B):
+    rng = np.random.default_rng(len(shape) * 7 + B)
+    n = int(np.prod(shape))
+    codes = np.clip(np.round(rng.laplace(32768, 40, n)), 0, 65535).astype(np.uint16)
+    seed, frac = 0x5EED + B, 0.3
+    hist, nsel = O.table_hist(codes, shape, B, frac, seed)
+    want = np.zeros(65536, dtype=np.uint64)
+    pos = k = 0
+    for b, size in enumerate(_blocks_in_stream_order(shape, B)):
+        u = (_splitmix64(seed ^ b) >> 11) * 2.0 ** -53
+        if u < frac:
+            k += 1
+            want += np.bincount(codes[pos:pos + size], minlength=65536).astype(np.uint64)
+        pos += size
+    assert pos == n and nsel == k and np.array_equal(hist, want)
+    nblocks = sum(1 for _ in _blocks_in_stream_order(shape, B))
+    assert abs(nsel - frac * nblocks) <= 4 * np.sqrt(frac * (1 - frac) * nblocks) + 1
+    full, nall = O.table_hist(codes, shape, B, 1.0, seed)
+    assert nall == nblocks
+    assert np.array_equal(full, np.bincount(codes, minlength=65536).astype(np.uint64))
+    none, nz = O.table_hist(codes, shape, B, 0.0, seed)
+    assert nz == 0 and not none.any()
