@@ -147,12 +147,15 @@ def copy_bandwidth(xd, torch, reps=10):
     return round(2 * xd.numel() * xd.element_size() / (ms * 1e-3) / 1e9, 1)
 
 
-def run_path(ctx, xd, eps, B, model, judge, ind, entropy, out, xh, steps, warmup, pwrel, torch):
+def run_path(ctx, xd, eps, B, model, judge, ind, entropy, out, xh, steps, warmup, pwrel, torch,
+             codebook=None):
     """Warm up, then time `steps` round trips (compress + decompress) of one
-    path; returns wall times, per-phase device times and the last stream."""
+    path; returns wall times, per-phase device times and the last stream.
+    codebook: a trained Huffman table (else the field's own when entropy)."""
     model = pwrel.model_struct(model) if model is not None else None
     use_net = model is not None
-    kw = dict(use_net=use_net, judge=judge, independent=ind, entropy=entropy, out=out)
+    kw = dict(use_net=use_net, judge=judge, independent=ind, entropy=entropy, out=out,
+              codebook=codebook)
     for _ in range(warmup):
         s = ctx.compress(xd, eps, B, model, **kw)
         ctx.decompress(s, out=xh)
@@ -465,14 +468,21 @@ def main():
     t0 = time.perf_counter()
     learned, rep = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.hidden,
                              precision=1, independent=True)
+    # the Huffman table of the training phase: the compression simulated on
+    # a 2 % share of the blocks (the paper's validation share)
+    table = ctx.train_codebook(xd, eps, B, learned, judge=True, independent=True, frac=0.02,
+                               seed=1001)
     train_ms = (time.perf_counter() - t0) * 1e3
     log(f"trained: chosen {rep['chosen']}, {rep['n_train']} pairs, {train_ms:.1f} ms")
 
-    # timed: the learned path, independent blocks, judge, Huffman-coded stream
+    # timed: the learned path, independent blocks, judge, the codes Huffman
+    # coded with the table of the training phase
     L = run_path(ctx, xd, eps, B, learned, True, True, True, out, xh, K, args.warmup, pwrel,
-                 torch)
-    rec_l = path_record("learned BF16 H=%d, judge, independent blocks, Huffman" % args.hidden,
-                        L, ctx, xd, xh, eps, gb, K, pwrel, torch)
+                 torch, codebook=table)
+    rec_l = path_record("learned BF16 H=%d, judge, independent blocks, Huffman table of the "
+                        "training phase (%d symbols, %d-bit escape)"
+                        % (args.hidden, table.n_sym, table.esc_len), L, ctx, xd, xh, eps, gb, K,
+                        pwrel, torch)
     ms_step = L["wall_s"] * 1e3 / K
     value = gb / (L["wall_s"] / K)
     # the same call's codes as 16 bits (for the prediction error and the ratio estimate)
@@ -519,7 +529,8 @@ def main():
                                f"0.5% zeros), block {B}^3, eps {eps:g}, learned path: network "
                                f"H={args.hidden} trained on the device ({args.rho:g} sample), "
                                f"BF16 matrix cores, per-block Lorenzo judge, independent blocks, "
-                               f"Huffman-coded stream", "field_bytes": x.nbytes},
+                               f"Huffman table of the training phase (2 % of the blocks)",
+                   "field_bytes": x.nbytes},
         "compress_GBps": rec_l["compress_GBps"], "decompress_GBps": rec_l["decompress_GBps"],
         "compress_frac_hbm": round(rec_l["compress_GBps"] / HBM_PEAK_GBPS, 4),
         "decompress_frac_hbm": round(rec_l["decompress_GBps"] / HBM_PEAK_GBPS, 4),
@@ -536,32 +547,48 @@ def main():
         "copy_GBps_measured": copy_gbps,
         "learned": rec_l,
     }
+    # the same path with a table built in the call from the field's own
+    # code histogram (optimal for the field; a histogram pass and a host
+    # build inside every call)
+    T = run_path(ctx, xd, eps, B, learned, True, True, True, out, xh, K, args.warmup, pwrel,
+                 torch)
+    res["learned_own_table"] = path_record(
+        "learned BF16 H=%d, judge, independent blocks, Huffman table of the field's own "
+        "histogram" % args.hidden, T, ctx, xd, xh, eps, gb, K, pwrel, torch)
+    log("learned path with the field's own table timed")
     if args.only_timed:
         print(json.dumps(res), flush=True)
         return
 
     # the learned path with halo prediction
     lh, rep_h = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.hidden, precision=1)
-    H_ = run_path(ctx, xd, eps, B, lh, True, False, True, out, xh, K, args.warmup, pwrel, torch)
-    res["learned_halo"] = path_record("learned BF16 H=%d, judge, halo prediction, Huffman"
-                                      % args.hidden, H_, ctx, xd, xh, eps, gb, K, pwrel, torch)
+    th = ctx.train_codebook(xd, eps, B, lh, judge=True, frac=0.02, seed=1001)
+    H_ = run_path(ctx, xd, eps, B, lh, True, False, True, out, xh, K, args.warmup, pwrel, torch,
+                  codebook=th)
+    res["learned_halo"] = path_record("learned BF16 H=%d, judge, halo prediction, Huffman table "
+                                      "of the training phase" % args.hidden, H_, ctx, xd, xh, eps,
+                                      gb, K, pwrel, torch)
     log("learned halo path timed")
 
     # the plain path: FP32 network of width 16 trained by the same device trainer
     pm, rep_p = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.plain_hidden,
                           precision=0, independent=True)
-    P = run_path(ctx, xd, eps, B, pm, False, True, True, out, xh, K, args.warmup, pwrel, torch)
+    tp = ctx.train_codebook(xd, eps, B, pm, independent=True, frac=0.02, seed=1001)
+    P = run_path(ctx, xd, eps, B, pm, False, True, True, out, xh, K, args.warmup, pwrel, torch,
+                 codebook=tp)
     res["plain"] = path_record("plain FP32 H=%d (trained on the device, no judge), independent "
-                               "blocks, Huffman" % args.plain_hidden, P, ctx, xd, xh, eps, gb, K,
-                               pwrel, torch)
+                               "blocks, Huffman table of the training phase" % args.plain_hidden,
+                               P, ctx, xd, xh, eps, gb, K, pwrel, torch)
     res["plain"]["training"] = train_record(rep_p, rep_p["ms_sample"] + rep_p["ms_train"])
     s16 = ctx.compress(xd, eps, B, pm, independent=True, out=out)
     res["plain"]["pred_error_rms"] = pred_error_rms(ctx, pwrel.sections(s16)["codes"], pwrel)
-    Ph = run_path(ctx, xd, eps, B, pwrel.mlp_init(3, args.plain_hidden, 0.01, 1001), False,
-                  False, True, out, xh, K, args.warmup, pwrel, torch)
+    m0 = pwrel.mlp_init(3, args.plain_hidden, 0.01, 1001)
+    t0h = ctx.train_codebook(xd, eps, B, m0, frac=0.02, seed=1001)
+    Ph = run_path(ctx, xd, eps, B, m0, False, False, True, out, xh, K, args.warmup, pwrel, torch,
+                  codebook=t0h)
     res["lorenzo_halo"] = path_record("untrained network (= one-layer Lorenzo), halo "
-                                      "prediction, Huffman", Ph, ctx, xd, xh, eps, gb, K, pwrel,
-                                      torch)
+                                      "prediction, Huffman table of the training phase", Ph, ctx,
+                                      xd, xh, eps, gb, K, pwrel, torch)
     log("plain paths timed")
     res["learned_vs_plain_size"] = round(rec_l["stream_bytes"] / res["plain"]["stream_bytes"], 4)
     cpu_model = learned
@@ -577,10 +604,14 @@ def main():
     t0 = time.perf_counter()
     m64, rep64 = ctx.train(x64, 1e-4, 8, rho=0.002, seed=1004, hidden=args.hidden, precision=1,
                            independent=True)
+    t64tab = ctx.train_codebook(x64, 1e-4, 8, m64, judge=True, independent=True, frac=0.02,
+                                seed=1004)
     t64 = (time.perf_counter() - t0) * 1e3
-    F = run_path(ctx, x64, 1e-4, 8, m64, True, True, True, o64, h64, 3, 1, pwrel, torch)
+    F = run_path(ctx, x64, 1e-4, 8, m64, True, True, True, o64, h64, 3, 1, pwrel, torch,
+                 codebook=t64tab)
     res["fp64_volume"] = path_record("FP64 1024x1024x512 (12 decades, 10% negative, 1% zeros), "
-                                     "eps 1e-4, learned BF16, judge, independent blocks, Huffman",
+                                     "eps 1e-4, learned BF16, judge, independent blocks, Huffman "
+                                     "table of the training phase",
                                      F, ctx, x64, h64, 1e-4, x64.numel() * 8 / 1e9, 3, pwrel,
                                      torch)
     res["fp64_volume"]["training"] = train_record(rep64, t64)
@@ -595,12 +626,17 @@ def main():
     h2 = torch.empty_like(x2)
     m2, rep2 = ctx.train(x2, eps, 16, rho=args.rho, seed=1002, hidden=args.hidden, precision=1,
                          independent=True)
-    Z = run_path(ctx, x2, eps, 16, m2, True, True, True, o2, h2, K, args.warmup, pwrel, torch)
+    t2 = ctx.train_codebook(x2, eps, 16, m2, judge=True, independent=True, frac=0.02, seed=1002)
+    Z = run_path(ctx, x2, eps, 16, m2, True, True, True, o2, h2, K, args.warmup, pwrel, torch,
+                 codebook=t2)
     res["zonal_2d"] = path_record("2-D 1800x3600 zonal bands + k^-2 noise, block 16^2, learned "
-                                  "BF16, judge, independent blocks, Huffman", Z, ctx, x2, h2, eps,
-                                  x2.numel() * 4 / 1e9, K, pwrel, torch)
-    Z0 = run_path(ctx, x2, eps, 16, pwrel.mlp_init(2, args.plain_hidden, 0.01, 1002), False, True,
-                  True, o2, h2, K, args.warmup, pwrel, torch)
+                                  "BF16, judge, independent blocks, Huffman table of the training "
+                                  "phase", Z, ctx, x2, h2, eps, x2.numel() * 4 / 1e9, K, pwrel,
+                                  torch)
+    m20 = pwrel.mlp_init(2, args.plain_hidden, 0.01, 1002)
+    t20 = ctx.train_codebook(x2, eps, 16, m20, independent=True, frac=0.02, seed=1002)
+    Z0 = run_path(ctx, x2, eps, 16, m20, False, True, True, o2, h2, K, args.warmup, pwrel, torch,
+                  codebook=t20)
     res["zonal_2d"]["lorenzo_ratio_stream"] = stream_stats(ctx, Z0["stream"], x2.numel() * 4,
                                                            pwrel)["ratio_stream"]
     log("2-D field timed")

@@ -529,14 +529,24 @@ int pwrel_train(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int n
                 const pwrel_mlp *init, pwrel_mlp *out, pwrel_train_report *report, void *stream);
 
 /*
- * The Huffman codebook of the context's last successful pwrel_train (Sec.
- * 4.3: built once, from the validation codes of the chosen network; FP32
- * network, the codes its validation score counts), as
- * pwrel_huffman_trained_codebook builds it from their histogram.  *out
- * (host) receives it; pass it as pwrel_options.codebook.  Synchronizes the
- * stream.  PWREL_EINVAL when the context has not trained.
+ * The Huffman table of the training phase (Sec. 4.3: the compression is
+ * simulated on the validation set, each code's frequency is averaged per
+ * block, and one table built from them serves every block of the
+ * compression).  The field is compressed with `model` and *opt (use_net,
+ * judge, independent_blocks; entropy and codebook ignored) into the
+ * context's workspace; the validation set is the blocks b (raster order of
+ * the blocks) with u01(splitmix64(seed ^ b)) < frac, u01 = the top 53 bits
+ * scaled to [0, 1); their codes' counts give the table as
+ * pwrel_huffman_trained_codebook builds it.  frac in (0, 1]; the paper's
+ * validation share is 0.02 (a 10 % sample split 8:2).  *out (host) receives
+ * the table; pass it as pwrel_options.codebook, for this field or for others
+ * like it.  Synchronizes the stream.  Errors as pwrel_compress, and
+ * PWREL_EINVAL for a NULL out or frac outside (0, 1].
  */
-int pwrel_train_codebook(pwrel_ctx *ctx, pwrel_codebook *out, void *stream);
+int pwrel_train_codebook(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                         int dtype, double rel_error_bound, int block_size, const pwrel_mlp *model,
+                         const pwrel_options *opt, double frac, uint64_t seed,
+                         pwrel_codebook *out, void *stream);
 
 /*
  * Training pieces on their own (same kernels as pwrel_train), for checking.

@@ -19,6 +19,8 @@ struct pwrel_ctx {
     Workspace ws;
     uint32_t *counts_scratch = nullptr;  // per-block counts for pwrel_encode_grid
     size_t counts_scratch_cap = 0;
+    uint8_t *bflags_scratch = nullptr;   // per-block judge flags for pwrel_train_codebook
+    size_t bflags_scratch_cap = 0;
     std::string err;
     int profiling = 0;
     hipEvent_t ev[10] = {};
@@ -35,7 +37,6 @@ struct pwrel_ctx {
     MlpW *nets = nullptr;    // [1 + candidates]
     unsigned long long *vhist = nullptr;  // [1 + candidates][65536]
     size_t vhist_cap = 0;
-    int train_best = -1;  // the last pwrel_train's chosen candidate (-1: none)
     double *scal = nullptr;  // sigma, partial sums (256), loss
     long long *scores = nullptr;
     // halo-mode decoder: block order of the last geometry, flag epoch
@@ -363,7 +364,7 @@ void pwrel_destroy(pwrel_ctx *ctx)
                     ctx->vhist,     ctx->scal,      ctx->scores,   ws.done,        ws.ticket,
                     ctx->order,     ws.praw,        ws.zf,         ws.yf,          ctx->hdr,
                     ws.codes16,     ws.enc_len,     ws.enc_code,   ws.boffsets,    ws.bpartials,
-                    ws.bits_total,  ws.invtab};
+                    ws.bits_total,  ws.invtab,     ctx->bflags_scratch};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -627,6 +628,34 @@ int huffman_trained_tail(pwrel_ctx *ctx, const void *d_field, const Geom &g,
     return PWREL_OK;
 }
 
+// Statistics, constants, grid values, prediction and quantisation of a field
+// into the context's 16-bit code buffer (block-major), per-block counts and
+// judge flags into the given buffers; phase marks 0 to 2.
+int codes_pass(pwrel_ctx *ctx, const void *d_field, const Geom &g, const Tile &tile, double eps,
+               const pwrel_mlp *model, const pwrel_options &opt, uint32_t *counts,
+               uint8_t *bflags, hipStream_t s)
+{
+    Workspace &ws = ctx->ws;
+    hipError_t e;
+    mark(ctx, 0, s);
+    if ((e = launch_reset(ws, s)) != hipSuccess || (e = launch_stats(d_field, g, ws, s)) != hipSuccess ||
+        (e = launch_consts(g, eps, ws, s)) != hipSuccess)
+        return hip_fail(ctx, e, "compress (statistics)");
+    mark(ctx, 1, s);
+    if (g.dtype == PWREL_F32) {
+        if ((e = launch_grid_entries(static_cast<const float *>(d_field), g, ws, ws.pgrid, s)) !=
+                hipSuccess ||
+            (e = launch_compress(d_field, ws.pgrid, g, tile, model, opt, ws, ws.codes16, counts,
+                                 bflags, ctx->num_cus, s, true)) != hipSuccess)
+            return hip_fail(ctx, e, "compress");
+    } else if ((e = launch_compress(d_field, nullptr, g, tile, model, opt, ws, ws.codes16, counts,
+                                    bflags, ctx->num_cus, s)) != hipSuccess) {
+        return hip_fail(ctx, e, "compress");
+    }
+    mark(ctx, 2, s);
+    return PWREL_OK;
+}
+
 // pwrel_compress with the Huffman stage (Sec. 4.1 coding stage; Algorithm 1
 // writes the Huffman codes).  Pass 1 on the device: statistics, constants,
 // grid values, prediction and quantisation into the context's 16-bit code
@@ -648,22 +677,8 @@ int compress_huffman(pwrel_ctx *ctx, const void *d_field, const Geom &g, const T
     uint32_t *counts = reinterpret_cast<uint32_t *>(out + L.off[2]);
     uint8_t *bflags = (flags & PWREL_HF_JUDGE) ? out + L.off[1] : nullptr;
     hipError_t e;
-    mark(ctx, 0, s);
-    if ((e = launch_reset(ws, s)) != hipSuccess || (e = launch_stats(d_field, g, ws, s)) != hipSuccess ||
-        (e = launch_consts(g, eps, ws, s)) != hipSuccess)
-        return hip_fail(ctx, e, "compress (statistics)");
-    mark(ctx, 1, s);
-    if (g.dtype == PWREL_F32) {
-        if ((e = launch_grid_entries(static_cast<const float *>(d_field), g, ws, ws.pgrid, s)) !=
-                hipSuccess ||
-            (e = launch_compress(d_field, ws.pgrid, g, tile, model, opt, ws, ws.codes16, counts,
-                                 bflags, ctx->num_cus, s, true)) != hipSuccess)
-            return hip_fail(ctx, e, "compress");
-    } else if ((e = launch_compress(d_field, nullptr, g, tile, model, opt, ws, ws.codes16, counts,
-                                    bflags, ctx->num_cus, s)) != hipSuccess) {
-        return hip_fail(ctx, e, "compress");
-    }
-    mark(ctx, 2, s);
+    if ((st = codes_pass(ctx, d_field, g, tile, eps, model, opt, counts, bflags, s)) != PWREL_OK)
+        return st;
     if (opt.codebook)
         return huffman_trained_tail(ctx, d_field, g, model, opt, out, out_capacity, out_size, s);
     std::vector<uint64_t> hist(65536);
@@ -1611,7 +1626,6 @@ int pwrel_train(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int n
 {
     if (!ctx)
         return PWREL_EINVAL;
-    ctx->train_best = -1;
     if (pwrel_check_args(dims, ndim, dtype, eps, block_size) != PWREL_OK || !d_field || !opt ||
         !out)
         return fail(ctx, PWREL_EINVAL, "bad dims/ndim/dtype/bound/block size or NULL pointer");
@@ -1785,27 +1799,56 @@ int pwrel_train(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int n
     }
     cleanup();
     *out = res;
-    ctx->train_best = best;
     return PWREL_OK;
 }
 
-int pwrel_train_codebook(pwrel_ctx *ctx, pwrel_codebook *out, void *stream)
+int pwrel_train_codebook(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
+                         int dtype, double eps, int block_size, const pwrel_mlp *model,
+                         const pwrel_options *opt_in, double frac, uint64_t seed,
+                         pwrel_codebook *out, void *stream)
 {
     if (!ctx)
         return PWREL_EINVAL;
     if (!out)
         return fail(ctx, PWREL_EINVAL, "NULL codebook");
-    if (ctx->train_best < 0 || !ctx->vhist)
-        return fail(ctx, PWREL_EINVAL, "the context has not trained a network");
+    if (!(frac > 0.0 && frac <= 1.0))
+        return fail(ctx, PWREL_EINVAL, "the validation fraction must lie in (0, 1]");
+    pwrel_options opt{1, 0, 0, 0, nullptr};
+    if (opt_in)
+        opt = *opt_in;
+    Geom g;
+    Tile tile;
+    int st;
+    if (!check_compress_args(ctx, d_field, dims, ndim, dtype, eps, block_size, model, opt, g,
+                             tile, st))
+        return st;
     DeviceGuard guard(ctx->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::vector<uint64_t> hist(65536);
-    hipError_t e = hipMemcpyAsync(hist.data(), ctx->vhist + (size_t)ctx->train_best * 65536,
-                                  65536 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if ((st = ensure_scan(ctx, g)) != PWREL_OK || (st = ensure_huffman(ctx, g)) != PWREL_OK)
+        return st;
+    hipError_t e = hipSuccess;
+    if (g.dtype == PWREL_F32)
+        e = grow(ctx->ws.pgrid, ctx->ws.pgrid_cap, (size_t)g.N);
     if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
+        e = grow(ctx->counts_scratch, ctx->counts_scratch_cap, (size_t)g.nblocks);
+    if (e == hipSuccess && opt.judge)
+        e = grow(ctx->bflags_scratch, ctx->bflags_scratch_cap, (size_t)g.nblocks);
     if (e != hipSuccess)
-        return hip_fail(ctx, e, "validation histogram copy");
+        return fail(ctx, PWREL_ENOMEM, "scratch allocation failed");
+    if ((st = codes_pass(ctx, d_field, g, tile, eps, model, opt, ctx->counts_scratch,
+                         opt.judge ? ctx->bflags_scratch : nullptr, s)) != PWREL_OK)
+        return st;
+    std::vector<uint64_t> hist(65536);
+    int dst = 0;
+    if ((e = launch_table_hist(ctx->ws.codes16, g, frac, seed, ctx->ws.hist, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(hist.data(), ctx->ws.hist, 65536 * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&dst, ctx->ws.status, sizeof dst, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "validation block histogram");
+    if (dst != PWREL_OK)
+        return finish_status(ctx, dst);
     if (pwrel_huffman_trained_codebook(hist.data(), out) != PWREL_OK)
         return fail(ctx, PWREL_EHIP, "internal: trained codebook construction failed");
     return PWREL_OK;

@@ -83,5 +83,8 @@ hipError_t launch_qtable(long long *q, int n, hipStream_t s);
 hipError_t launch_fold(const FoldArgs &a, hipStream_t s);
 
 __global__ void k_zero_u64_n(unsigned long long *p, long long n);
+// code counts of the trained table's validation blocks (codes block-major)
+hipError_t launch_table_hist(const uint16_t *codes, const Geom &g, double frac, uint64_t seed,
+                             unsigned long long *hist, hipStream_t s);
 
 }  // namespace pwrel

@@ -648,6 +648,67 @@ hipError_t launch_qtable(long long *q, int n, hipStream_t s)
 }  // namespace pwrel
 
 namespace pwrel {
+// ---------------------------------------------------------------------------
+// The trained Huffman table's input (Sec. 4.3: the code frequencies of the
+// validation blocks, on which the compression is simulated): block b of the
+// stream order is a validation block iff u01(splitmix64(seed ^ b)) < frac.
+// One wave per block adds the block's codes (block-major) to a 4096-bin LDS
+// window around the zero-error code, the rest to global bins; each
+// workgroup flushes its window once.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_table_hist(const uint16_t *__restrict__ codes, GeoArgs g,
+                                                    double frac, unsigned long long seed,
+                                                    unsigned long long *__restrict__ hist)
+{
+    constexpr int WIN = 4096;
+    __shared__ unsigned win[WIN];
+    for (int i = threadIdx.x; i < WIN; i += blockDim.x)
+        win[i] = 0u;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    const int lo = kR - WIN / 2;
+    for (long long b = wave; b < g.nblocks; b += nwaves) {
+        const double U = (double)(mix64(seed ^ (unsigned long long)b) >> 11) * 0x1p-53;
+        if (!(U < frac))
+            continue;
+        const long long bx = b % g.nb[2], by = (b / g.nb[2]) % g.nb[1],
+                        bz = b / (g.nb[1] * g.nb[2]);
+        const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
+        const long long bsize = (long long)q.ez * q.ey * q.ex;
+        for (long long i = lane; i < bsize; i += 64) {
+            const int code = codes[q.start + i];
+            const int k = code - lo;
+            if (k >= 0 && k < WIN)
+                atomicAdd(&win[k], 1u);
+            else
+                atomicAdd(&hist[code], 1ULL);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < WIN; i += blockDim.x)
+        if (win[i])
+            atomicAdd(&hist[lo + i], (unsigned long long)win[i]);
+}
+
+hipError_t launch_table_hist(const uint16_t *codes, const Geom &g, double frac, uint64_t seed,
+                             unsigned long long *hist, hipStream_t s)
+{
+    GeoArgs a{};
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = g.n[d];
+        a.bd[d] = g.bd[d];
+        a.nb[d] = g.nb[d];
+    }
+    a.nblocks = g.nblocks;
+    hipLaunchKernelGGL(k_zero_u64_n, dim3(256), dim3(256), 0, s, hist, 65536LL);
+    const long long wg = std::max<long long>(1, std::min<long long>((g.nblocks + 3) / 4, 2048));
+    hipLaunchKernelGGL(k_table_hist, dim3((unsigned)wg), dim3(256), 0, s, codes, a, frac,
+                       (unsigned long long)seed, hist);
+    return hipGetLastError();
+}
+
 __global__ void k_zero_u64_n(unsigned long long *p, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;

@@ -153,7 +153,9 @@ _SIGS = {
     "pwrel_huffman_codebook": (C.c_int, [_P, _P, _P, C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_uint64)]),
     "pwrel_huffman_trained_codebook": (C.c_int, [_P, C.POINTER(Codebook)]),
-    "pwrel_train_codebook": (C.c_int, [_P, C.POINTER(Codebook), _P]),
+    "pwrel_train_codebook": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
+                                       C.POINTER(Mlp), C.POINTER(Options), C.c_double,
+                                       C.c_uint64, C.POINTER(Codebook), _P]),
     "pwrel_mlp_init": (C.c_int, [C.POINTER(Mlp), C.c_int, C.c_int, C.c_float, C.c_uint64]),
     "pwrel_set_profiling": (C.c_int, [_P, C.c_int]),
     "pwrel_phase_times": (C.c_int, [_P, _P, C.c_int]),
@@ -599,12 +601,21 @@ class Context:
              "ms_select": rep.ms_select}
         return model_dict(out), r
 
-    def train_codebook(self, stream=None):
-        """The trained codebook of the last train() (Sec. 4.3: from the chosen
-        network's validation codes), as a Codebook."""
+    def train_codebook(self, x, eps, block=8, model=None, use_net=True, judge=False,
+                       independent=False, frac=0.02, seed=0, stream=None):
+        """The Huffman table of the training phase (Sec. 4.3): the field
+        compressed with these options, the code counts of its validation
+        blocks (a `frac` share, drawn with `seed`), one table from them; a
+        Codebook for compress(codebook=...)."""
+        assert x.is_cuda and x.is_contiguous()
+        m = model_struct(model) if use_net else None
+        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
         cb = Codebook()
-        self._check(self._L.pwrel_train_codebook(self.h, C.byref(cb), _stream(stream)),
-                    "train_codebook")
+        st = self._L.pwrel_train_codebook(self.h, C.c_void_p(x.data_ptr()), _dims(x.shape),
+                                          x.dim(), _dtype_code(x.dtype), float(eps), int(block),
+                                          C.byref(m) if m is not None else None, C.byref(opt),
+                                          float(frac), int(seed), C.byref(cb), _stream(stream))
+        self._check(st, "train_codebook")
         return cb
 
     def sample(self, x, eps, block=8, independent=False, rho=0.01, seed=0, stream=None):
