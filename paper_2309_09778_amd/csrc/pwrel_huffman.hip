@@ -541,18 +541,29 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
 }
 
 // decoder: one thread per block
-constexpr int kLutBits = 12;
+constexpr int kLutBits = 14;
 
 // Per-block decoder, one thread per block.  Codes of up to kLutBits bits come
-// from a lookup table of the next kLutBits bits; a longer code's length is
-// the number of canonical length limits its window reaches (a sum of
-// comparisons, no loop), and its symbol sits at index offset[len] + the
-// code.  The table and the symbols (up to kSymsLds of them) live in the
-// workgroup's LDS, so a step never waits on a global load.
+// from a lookup table of the next kLutBits bits (the escape flagged in it); for
+// a longer code the table gives the shortest and longest length under its
+// prefix, and the length is the shortest plus the canonical length limits (in
+// LDS) between the two that its window reaches; its symbol sits at index
+// offset[len] + the code.  The table and the
+// symbols (all of them when ALL_LDS, else the first kSymsLds) live in the
+// workgroup's LDS, so a step waits on no global load.  Each thread's bits
+// come a 128-byte line at a time into registers (the next line in flight),
+// four words at a time from there through a queue that shifts by one word
+// per refill; one refill of 32 bits per symbol keeps at least 33 bits in the
+// buffer (no codeword, escape and its 16 bits included, is longer than 32).
 constexpr int kUnpackThreads = 1024;
 constexpr int kSymsLds = 32768;
+// lookup-table entries: symbol | length << 16 for a code of at most kLutBits
+// bits (kLutEsc: the escape); kLutLong | shortest << 16 | longest << 8 for a
+// prefix of longer codes; 0 for bits no codeword starts with
+constexpr uint32_t kLutEsc = 0x80000000u;
+constexpr uint32_t kLutLong = 0x40000000u;
 
-template <typename S>
+template <typename S, bool ALL_LDS>
 __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *__restrict__ tab,
                                                      const uint32_t *__restrict__ bits,
                                                      unsigned long long nwords, GeoArgs g,
@@ -598,19 +609,27 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
             const unsigned pre = (unsigned)e >> (kLutBits - l);
             if (pre - cs.first[l] < cs.count[l]) {
                 const unsigned ix = cs.index[l] + (pre - cs.first[l]);
-                v = ix == sesc ? 0x80000000u | ((uint32_t)l << 16)
+                v = ix == sesc ? kLutEsc | ((uint32_t)l << 16)
                                : (ix < nlds ? ssyms[ix] : syms[ix]) | ((uint32_t)l << 16);
                 break;
             }
         }
+        if (v == 0 && smax > (unsigned)kLutBits) {
+            // longer codes under this prefix: the lengths of its first and last
+            // windows bound theirs
+            const unsigned lo = (unsigned)e << (32 - kLutBits);
+            const unsigned hi = lo | ((1u << (32 - kLutBits)) - 1u);
+            unsigned a = kLutBits + 1, b = kLutBits + 1;
+            for (unsigned qq = kLutBits + 1; qq < smax; ++qq) {
+                a += lo >= slim[qq] ? 1u : 0u;
+                b += hi >= slim[qq] ? 1u : 0u;
+            }
+            v = kLutLong | (a << 16) | (b << 8);
+        }
         lut[e] = v;
     }
-    unsigned lim[kHuffMaxLen];
-    const unsigned maxlen = smax;
-    const unsigned esc_ix = sesc;
-#pragma unroll
-    for (int l = kLutBits + 1; l < kHuffMaxLen; ++l)
-        lim[l] = slim[l];
+    const unsigned maxlen = __builtin_amdgcn_readfirstlane(smax);
+    const unsigned esc_ix = __builtin_amdgcn_readfirstlane(sesc);
     __syncthreads();
     const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= g.nblocks)
@@ -619,79 +638,126 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
     const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
     const long long bsize = (long long)q.ez * q.ey * q.ex;
     const unsigned long long start = boffs[b] + bparts[b / kScanChunk];
-    const unsigned long long end = start + (unsigned long long)sizes[b];
+    const unsigned nbits_block = (unsigned)sizes[b];
     int err = kOk;
-    if (end > nwords * 32ull) {
+    if (start + nbits_block > nwords * 32ull) {
         set_status(status, kECorrupt);
         return;
     }
-    // the stream's words come four at a time (16-byte aligned loads, the next
-    // group in flight); buf holds the next nb bits left-aligned
+    // The bit queue.  A thread's bits stream through registers one 128-byte
+    // line at a time (eight 16-byte groups, the next line in flight): all
+    // 262,144 block streams of a 512^3 field are resident at once, and a
+    // line fetched 16 bytes at a time would leave L2 between two of a
+    // thread's reads.  cur holds the words of the current group not yet
+    // taken, shifted to the front.
+    // A line holding any word of the section is read whole: the section
+    // starts 256-byte aligned and the next section starts at the next 256-byte
+    // boundary after it (the gap zeroed), so the line stays inside the stream;
+    // lines past the section read as zeros.
     const uint4 *w4 = reinterpret_cast<const uint4 *>(bits);
-    const unsigned long long n4 = nwords >> 2;
-    unsigned long long gi = (start >> 5) >> 2;  // current group
-    auto load4 = [&](unsigned long long k) -> uint4 {
-        if (k < n4)
-            return w4[k];
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        const unsigned long long w = 4 * k;
-        if (w < nwords) v.x = bits[w];
-        if (w + 1 < nwords) v.y = bits[w + 1];
-        if (w + 2 < nwords) v.z = bits[w + 2];
-        return v;
-    };
-    uint4 cur = load4(gi), nxt = load4(gi + 1);
-    int wk = (int)((start >> 5) & 3u);  // next word of cur
-    unsigned long long buf = 0;
-    int nb = 0;
-    auto refill = [&]() {
-        while (nb <= 32) {
-            const uint32_t v = wk == 0 ? cur.x : wk == 1 ? cur.y : wk == 2 ? cur.z : cur.w;
-            buf |= (unsigned long long)v << (32 - nb);
-            nb += 32;
-            if (++wk == 4) {
-                wk = 0;
-                cur = nxt;
-                ++gi;
-                nxt = load4(gi + 1);
-            }
+    auto load_line = [&](uint4 (&dstl)[8], unsigned long long ln) {
+        if (32 * ln < nwords) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                dstl[k] = w4[8 * ln + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                dstl[k] = make_uint4(0u, 0u, 0u, 0u);
         }
     };
-    refill();
+    unsigned long long line = (start >> 5) >> 5;  // 32 words per line
+    uint4 L[8], N[8];
+    load_line(L, line);
+    load_line(N, line + 1);
+    // L[0] is the current group: the line's groups shift down as they are
+    // used (fixed register indices only), the next line follows at its end
+    int gq = (int)(((start >> 5) >> 2) & 7u);  // groups of the line used before L[0]
+    for (int k = 0; k < gq; ++k) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            L[j] = L[j + 1];
+    }
+    uint4 cur = L[0];
+    int left = 4 - (int)((start >> 5) & 3u);  // words of cur not yet taken
+    // drop the words of cur before the block's first word
+    for (int k = 0; k < 4 - left; ++k) {
+        cur.x = cur.y;
+        cur.y = cur.z;
+        cur.z = cur.w;
+    }
+    unsigned long long buf = 0;
+    int nb = 0;
+    auto take = [&]() {
+        buf |= (unsigned long long)cur.x << (32 - nb);
+        nb += 32;
+        cur.x = cur.y;
+        cur.y = cur.z;
+        cur.z = cur.w;
+        if (--left == 0) {
+            left = 4;
+            if (++gq == 8) {
+                gq = 0;
+                ++line;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    L[k] = N[k];
+                load_line(N, line + 1);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 7; ++j)
+                    L[j] = L[j + 1];
+            }
+            cur = L[0];
+        }
+    };
+    take();
+    take();
     const unsigned sk = (unsigned)(start & 31u);
     buf <<= sk;
     nb -= (int)sk;
-    unsigned long long used = 0;
+    unsigned used = 0;
     auto next_sym = [&]() -> unsigned {
-        refill();
+        if (nb <= 32)
+            take();
         const unsigned win = (unsigned)(buf >> 32);
         const uint32_t e = lut[win >> (32 - kLutBits)];
         unsigned l = (e >> 16) & 0xFFu, sym = e & 0xFFFFu;
-        bool esc = (e >> 31) != 0;
-        if (l == 0) {
-            // a longer code: its length is kLutBits + 1 plus the number of
-            // length limits (below the longest length) the window reaches
-            unsigned len = kLutBits + 1;
-#pragma unroll
-            for (int q = kLutBits + 1; q < kHuffMaxLen; ++q)
-                len += ((unsigned)q < maxlen && win >= lim[q]) ? 1u : 0u;
-            const long long ix = (long long)soff[len] + (long long)(win >> (32 - len));
-            if (len > maxlen || ix < 0 || ix >= (long long)nsym) {
+        bool esc = (e & kLutEsc) != 0;
+        if (e & kLutLong) {
+            // a longer code: its length lies between the bounds of its prefix;
+            // add the length limits between them that the window reaches
+            unsigned len = l;
+            const unsigned lmax = (e >> 8) & 0xFFu;
+            for (unsigned qq = l; qq < lmax; ++qq)
+                len += win >= slim[qq] ? 1u : 0u;
+            // index[len] + (code - first[len]), in wrapping 32-bit arithmetic
+            // (exact: the true index is below 2^16)
+            const unsigned ix = (unsigned)soff[len] + (win >> (32 - len));
+            if (len > maxlen || ix >= nsym) {
                 err = kECorrupt;
                 l = 1;
                 sym = 0;
+                esc = false;
             } else {
                 l = len;
-                esc = ix == (long long)esc_ix;
-                sym = ix < (long long)nlds ? ssyms[ix] : syms[ix];
+                esc = ix == esc_ix;
+                if constexpr (ALL_LDS)
+                    sym = ssyms[ix];
+                else
+                    sym = ix < nlds ? ssyms[ix] : syms[ix];
             }
+        }
+        if (l == 0) {  // the bits match no codeword
+            err = kECorrupt;
+            l = 1;
         }
         buf <<= l;
         nb -= (int)l;
         used += l;
         if (esc) {
             // the escaped code's own 16 bits follow (the escape has at most
-            // 16 bits, so the refilled buffer still holds them)
+            // 16 bits, so the buffer still holds them)
             sym = (unsigned)(buf >> 48);
             buf <<= 16;
             nb -= 16;
@@ -702,21 +768,24 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
     uint16_t *dst = codes + q.start;
     long long i = 0;
     if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-        // eight codes per 16-byte store
+        // eight codes per 16-byte store, two per step into a shifting word queue
         for (; i + 8 <= bsize && err == kOk; i += 8) {
-            unsigned wv[4];
-#pragma unroll
+            uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll 1
             for (int k = 0; k < 4; ++k) {
                 const unsigned lo = next_sym();
                 const unsigned hi = next_sym();
-                wv[k] = lo | (hi << 16);
+                acc.x = acc.y;
+                acc.y = acc.z;
+                acc.z = acc.w;
+                acc.w = lo | (hi << 16);
             }
-            *reinterpret_cast<uint4 *>(dst + i) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+            *reinterpret_cast<uint4 *>(dst + i) = acc;
         }
     }
     for (; i < bsize && err == kOk; ++i)
         dst[i] = (uint16_t)next_sym();
-    if (used != end - start)
+    if (used != nbits_block)
         err = kECorrupt;
     set_status(status, err);
 }
@@ -818,25 +887,30 @@ hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32
 {
     const GeoArgs ga = geo_of(g);
     const unsigned grid = (unsigned)((g.nblocks + kUnpackThreads - 1) / kUnpackThreads);
-    const unsigned nlds = nsym < (unsigned)kSymsLds ? nsym : (unsigned)kSymsLds;
+    const bool all = nsym <= (unsigned)kSymsLds;
+    const unsigned nlds = all ? nsym : (unsigned)kSymsLds;
     const size_t lds = (size_t)(1 << kLutBits) * sizeof(uint32_t) + (size_t)nlds * sizeof(uint16_t);
-    hipError_t e;
-    if (huff_size_bytes(g) == 2) {
+    const int sb = huff_size_bytes(g);
+    hipError_t e = launch_scan_sizes(d_sizes, sb, g.nblocks, ws.boffsets, ws.bpartials,
+                                     ws.bits_total, s);
+    if (e != hipSuccess)
+        return e;
+    auto go = [&](auto kern, const auto *sz) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kUnpackThreads), lds, s, d_tab, d_bits, nwords,
+                           ga, sz, ws.boffsets, ws.bpartials, codes, ws.status, nsym, esc_len);
+    };
+    if (sb == 2) {
         const uint16_t *sz = static_cast<const uint16_t *>(d_sizes);
-        if ((e = launch_scan_sizes(sz, 2, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
-                                   s)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_huff_unpack<uint16_t>, dim3(grid), dim3(kUnpackThreads), lds, s,
-                           d_tab, d_bits, nwords, ga, sz, ws.boffsets, ws.bpartials, codes,
-                           ws.status, nsym, esc_len);
+        if (all)
+            go(k_huff_unpack<uint16_t, true>, sz);
+        else
+            go(k_huff_unpack<uint16_t, false>, sz);
     } else {
         const uint32_t *sz = static_cast<const uint32_t *>(d_sizes);
-        if ((e = launch_scan_sizes(sz, 4, g.nblocks, ws.boffsets, ws.bpartials, ws.bits_total,
-                                   s)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_huff_unpack<uint32_t>, dim3(grid), dim3(kUnpackThreads), lds, s,
-                           d_tab, d_bits, nwords, ga, sz, ws.boffsets, ws.bpartials, codes,
-                           ws.status, nsym, esc_len);
+        if (all)
+            go(k_huff_unpack<uint32_t, true>, sz);
+        else
+            go(k_huff_unpack<uint32_t, false>, sz);
     }
     return hipGetLastError();
 }
