@@ -126,7 +126,7 @@ int ensure_huffman(pwrel_ctx *ctx, const Geom &g)
     if (e == hipSuccess && !ws.enc_len)
         e = hipMalloc(reinterpret_cast<void **>(&ws.enc_len), 65536);
     if (e == hipSuccess && !ws.enc_code)
-        e = hipMalloc(reinterpret_cast<void **>(&ws.enc_code), 65536 * sizeof(uint32_t));
+        e = hipMalloc(reinterpret_cast<void **>(&ws.enc_code), 65536 * sizeof(unsigned long long));
     if (e == hipSuccess && !ws.bits_total)
         e = hipMalloc(reinterpret_cast<void **>(&ws.bits_total), 256);
     if (e != hipSuccess)
@@ -1193,20 +1193,8 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
     const uint32_t *counts = reinterpret_cast<const uint32_t *>(in + h.off_counts);
     const uint16_t *codes = reinterpret_cast<const uint16_t *>(in + h.off_codes);
     if (h.flags & PWREL_HF_HUFFMAN) {
-        // the codebook's length counts must describe a prefix code of n_sym symbols
-        uint32_t cnt[kHuffMaxLen + 1];
-        if ((e = hipMemcpyAsync(cnt, in + h.off_huff, sizeof cnt, hipMemcpyDeviceToHost, s)) !=
-                hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return hip_fail(ctx, e, "codebook copy");
-        uint64_t nsym = 0, kraft = 0;
-        for (int l = 1; l <= kHuffMaxLen; ++l) {
-            nsym += cnt[l];
-            kraft += (uint64_t)cnt[l] << (kHuffMaxLen - l);
-        }
-        if (cnt[0] != 0 || nsym != h.n_sym || kraft > (uint64_t(1) << kHuffMaxLen) ||
-            (h.esc_len != 0 && cnt[h.esc_len] == 0))
-            return fail(ctx, PWREL_ECORRUPT, "stream codebook is corrupt");
+        // the decoding kernel checks the codebook's length counts (a prefix
+        // code of n_sym symbols) before it reads the table
         if ((st = ensure_huffman(ctx, g)) != PWREL_OK)
             return st;
         if ((e = launch_huff_decode(g, reinterpret_cast<const uint32_t *>(in + h.off_huff),

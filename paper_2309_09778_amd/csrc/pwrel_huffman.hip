@@ -333,21 +333,24 @@ __device__ __forceinline__ void esc_of(const uint32_t *cnt, unsigned esc_len, un
 // encoder table before k_huff_enc: every code unused (esc_len = 0), or
 // every code the escape codeword followed by its own 16 bits
 __global__ void k_huff_enc_init(const uint32_t *__restrict__ tab, unsigned esc_len,
-                                uint8_t *__restrict__ enc_len, uint32_t *__restrict__ enc_code)
+                                uint8_t *__restrict__ enc_len,
+                                unsigned long long *__restrict__ enc_code)
 {
     unsigned ix, ecode;
     esc_of(tab, esc_len, ix, ecode);
     for (unsigned s = blockIdx.x * blockDim.x + threadIdx.x; s < 65536u;
          s += gridDim.x * blockDim.x) {
-        enc_len[s] = ix == ~0u ? (uint8_t)0 : (uint8_t)(esc_len + 16);
-        enc_code[s] = ix == ~0u ? 0u : (ecode << 16) | s;
+        const unsigned l = ix == ~0u ? 0u : esc_len + 16;
+        enc_len[s] = (uint8_t)l;
+        enc_code[s] = ix == ~0u ? 0ull
+                                : ((unsigned long long)l << 32) | ((ecode << 16) | s);
     }
 }
 
 // encoder table: length and codeword of every symbol the table lists (the
 // escape's slot excepted)
 __global__ void k_huff_enc(const uint32_t *__restrict__ tab, unsigned esc_len,
-                           uint8_t *__restrict__ enc_len, uint32_t *__restrict__ enc_code)
+                           uint8_t *__restrict__ enc_len, unsigned long long *__restrict__ enc_code)
 {
     const uint32_t *cnt = tab;
     const uint16_t *syms = reinterpret_cast<const uint16_t *>(tab + kHuffMaxLen + 1);
@@ -366,7 +369,7 @@ __global__ void k_huff_enc(const uint32_t *__restrict__ tab, unsigned esc_len,
         if (i < idx + cnt[l]) {
             const unsigned s = syms[i];
             enc_len[s] = (uint8_t)l;
-            enc_code[s] = code + (i - idx);
+            enc_code[s] = ((unsigned long long)l << 32) | (code + (i - idx));
             return;
         }
         idx += cnt[l];
@@ -428,8 +431,7 @@ __global__ void __launch_bounds__(256) k_huff_sizes(const uint16_t *__restrict__
 // (shared with the neighbouring blocks) by atomic OR into the zeroed section.
 template <typename S>
 __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ codes, GeoArgs g,
-                                                   const uint8_t *__restrict__ enc_len,
-                                                   const uint32_t *__restrict__ enc_code,
+                                                   const unsigned long long *__restrict__ enc,
                                                    const S *__restrict__ sizes,
                                                    const unsigned long long *__restrict__ boffs,
                                                    const unsigned long long *__restrict__ bparts,
@@ -490,8 +492,9 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const unsigned sym = (cw[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-                    l[j] = enc_len[sym];
-                    c[j] = enc_code[sym];
+                    const unsigned long long ec = enc[sym];  // one gather per code
+                    l[j] = (unsigned)(ec >> 32);
+                    c[j] = (unsigned)ec;
                     t += l[j];
                 }
                 unsigned incl = t;
@@ -509,9 +512,9 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
             const long long i = c0 + lane;
             unsigned l = 0, cw = 0;
             if (i < bsize) {
-                const unsigned sym = src[i];
-                l = enc_len[sym];
-                cw = enc_code[sym];
+                const unsigned long long ec = enc[src[i]];
+                l = (unsigned)(ec >> 32);
+                cw = (unsigned)ec;
             }
             unsigned incl = l;
 #pragma unroll
@@ -581,10 +584,21 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
     __shared__ unsigned slim[kHuffMaxLen + 2];   // left-aligned end of the length-l codes
     __shared__ unsigned smax;                    // longest code length
     __shared__ unsigned sesc;                    // canonical index of the escape (~0u: none)
+    __shared__ int sok;                          // the stream's length counts are valid
     const uint32_t *cnt = tab;
     const uint16_t *syms = reinterpret_cast<const uint16_t *>(tab + kHuffMaxLen + 1);
     const unsigned nlds = nsym < (unsigned)kSymsLds ? nsym : (unsigned)kSymsLds;
     if (threadIdx.x == 0) {
+        // the length counts must describe a prefix code of the nsym stored
+        // symbols (Kraft sum at most 1) whose escape, if any, has a slot;
+        // checked here so no thread indexes the table before they are
+        unsigned long long ns = 0, kraft = 0;
+        for (int l = 1; l <= kHuffMaxLen; ++l) {
+            ns += cnt[l];
+            kraft += (unsigned long long)cnt[l] << (kHuffMaxLen - l);
+        }
+        sok = cnt[0] == 0 && ns == nsym && kraft <= (1ull << kHuffMaxLen) &&
+              (esc_len == 0 || (esc_len <= 16u && cnt[esc_len] != 0));
         canon_from(cnt, cs);
         unsigned mx = 0;
         for (int l = 1; l <= kHuffMaxLen; ++l) {
@@ -603,6 +617,11 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
     for (unsigned k = threadIdx.x; k < nlds; k += blockDim.x)
         ssyms[k] = syms[k];
     __syncthreads();
+    if (!sok) {
+        if (threadIdx.x == 0)
+            set_status(status, kECorrupt);
+        return;
+    }
     for (int e = threadIdx.x; e < (1 << kLutBits); e += blockDim.x) {
         uint32_t v = 0;
         for (int l = 1; l <= kLutBits; ++l) {
@@ -862,11 +881,11 @@ hipError_t launch_huff_pack(const Geom &g, const uint16_t *codes, const void *d_
                        dim3(256), 0, s, d_bits, nwords, 0u);
     if (huff_size_bytes(g) == 2)
         hipLaunchKernelGGL(k_huff_pack<uint16_t>, dim3(pgrid), dim3(64 * wpg), lds, s, codes, ga,
-                           ws.enc_len, ws.enc_code, static_cast<const uint16_t *>(d_sizes),
+                           ws.enc_code, static_cast<const uint16_t *>(d_sizes),
                            ws.boffsets, ws.bpartials, d_bits, wave_words, ws.status);
     else
         hipLaunchKernelGGL(k_huff_pack<uint32_t>, dim3(pgrid), dim3(64 * wpg), lds, s, codes, ga,
-                           ws.enc_len, ws.enc_code, static_cast<const uint32_t *>(d_sizes),
+                           ws.enc_code, static_cast<const uint32_t *>(d_sizes),
                            ws.boffsets, ws.bpartials, d_bits, wave_words, ws.status);
     return hipGetLastError();
 }

@@ -61,7 +61,7 @@ struct Workspace {
     uint16_t *codes16 = nullptr;
     size_t codes16_cap = 0;
     uint8_t *enc_len = nullptr;
-    uint32_t *enc_code = nullptr;
+    unsigned long long *enc_code = nullptr;  // codeword | length << 32
     unsigned long long *boffsets = nullptr, *bpartials = nullptr;
     size_t boffsets_cap = 0, bpartials_cap = 0;
     unsigned long long *bits_total = nullptr;
