@@ -93,10 +93,17 @@ def _tcase(name):
     if name == "grf_2d_B16":
         return synth.lognormal_grf((300, 257), seed=33), 1e-2, 16, random_model(2, 16, 33), \
             False
+    if name == "grf_2d_whole_indep":  # whole 16^2 blocks, 315 of them (a partial last group of 64)
+        return synth.lognormal_grf((240, 336), seed=34), 1e-2, 16, random_model(2, 16, 34), \
+            True
+    if name == "grf_3d_whole_indep":  # whole 8^3 blocks, 270 of them
+        return synth.lognormal_grf((40, 48, 72), seed=35), 1e-2, 8, random_model(3, 16, 35), \
+            True
     return _case(name)
 
 
-TRAINED_CASES = ["grf_64_lorenzo", "grf_64_net_indep", "grf_2d_B16", "config0_bumps64",
+TRAINED_CASES = ["grf_64_lorenzo", "grf_64_net_indep", "grf_2d_B16", "grf_2d_whole_indep",
+                 "grf_3d_whole_indep", "config0_bumps64",
                  "grf_B4_H32", "grf_1d_halo", "pencil_long", "f64_1e-4", "wide_span_halo",
                  "tiny_1d"]
 
