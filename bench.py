@@ -233,6 +233,24 @@ def stream_stats(ctx, s, x_nbytes, pwrel, plain_codes=None):
     return out
 
 
+def bf16_vs_fp32(ctx, xd, eps, B, model, out, pwrel, torch):
+    """The same trained network on the matrix cores (BF16 operands) and on the
+    vector ALU (FP32), no judge: where both code a point, the codes differ by
+    the difference of the two rounded predictions (grid units).  Returns the
+    largest difference and the share of points where they differ."""
+    a = ctx.compress(xd, eps, B, dict(model, precision=1), independent=True, out=out)
+    ca = pwrel.sections(a)["codes"].clone()
+    b = ctx.compress(xd, eps, B, dict(model, precision=0), independent=True, out=out)
+    cb = pwrel.sections(b)["codes"]
+    ia = ca.view(torch.int16).to(torch.int32) & 0xFFFF
+    ib = cb.view(torch.int16).to(torch.int32) & 0xFFFF
+    both = (ia != 0) & (ib != 0)
+    d = (ia - ib).abs()[both]
+    return {"max_code_diff": int(d.max().item()) if d.numel() else 0,
+            "frac_points_differ": round(float((d != 0).float().mean().item()), 6),
+            "points_compared": int(d.numel())}
+
+
 def pred_error_rms(ctx, codes_t, pwrel):
     import numpy as np
     hist = ctx.histogram(codes_t).astype(np.float64)
@@ -490,6 +508,7 @@ def main():
     rec_l["pred_error_rms"] = pred_error_rms(ctx, pwrel.sections(s16)["codes"], pwrel)
     hist = ctx.histogram(pwrel.sections(s16)["codes"])
     rec_l["huffman_bits_estimate"] = pwrel.huffman_bits(hist)[0]
+    rec_l["bf16_vs_fp32_network"] = bf16_vs_fp32(ctx, xd, eps, B, learned, out, pwrel, torch)
     log("learned path timed")
 
     ph = L["phase_ms"]

@@ -439,8 +439,7 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
                                                    const int *status)
 {
     extern __shared__ uint32_t lw[];
-    if (*status != kOk)
-        return;
+    const int st0 = *status;
     const int lane = threadIdx.x & 63;
     uint32_t *w = lw + (threadIdx.x >> 6) * wave_words;
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -469,14 +468,40 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
         if (nacc > 0)
             atomicOr(&w[wp], (uint32_t)(acc >> 32));
     };
-    for (long long b = wave; b < g.nblocks; b += nwaves) {
+    // A wave packs several blocks in turn; each block's geometry, bit offset,
+    // bit size and first 16-byte load of codes are fetched while the block
+    // before it is packed, so their round trips overlap that work.
+    struct Ahead {
+        BlockGeo q;
+        unsigned long long start;
+        unsigned nbits;
+        uint4 v;
+    };
+    auto fetch = [&](long long b, Ahead &p) {
         const long long bx = b % g.nb[2], by = (b / g.nb[2]) % g.nb[1],
                         bz = b / (g.nb[1] * g.nb[2]);
-        const BlockGeo q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
+        p.q = block_geo3(bz, by, bx, g.n, g.bd[0], g.bd[1], g.bd[2]);
+        p.start = boffs[b] + bparts[b / kScanChunk];
+        p.nbits = (unsigned)sizes[b];
+        const uint16_t *src = codes + p.q.start;
+        const long long bsize = (long long)p.q.ez * p.q.ey * p.q.ex;
+        p.v = ((reinterpret_cast<uintptr_t>(src) & 15) == 0 && bsize >= 512)
+                  ? reinterpret_cast<const uint4 *>(src)[lane]
+                  : make_uint4(0u, 0u, 0u, 0u);
+    };
+    Ahead cur{}, nxt{};
+    if (wave < g.nblocks)
+        fetch(wave, cur);
+    if (st0 != kOk)
+        return;
+    for (long long b = wave; b < g.nblocks; b += nwaves) {
+        if (b + nwaves < g.nblocks)
+            fetch(b + nwaves, nxt);
+        const BlockGeo q = cur.q;
         const long long bsize = (long long)q.ez * q.ey * q.ex;
-        const unsigned long long start = boffs[b] + bparts[b / kScanChunk];
+        const unsigned long long start = cur.start;
         const unsigned s0 = (unsigned)(start & 31u);
-        const unsigned nbits = (unsigned)sizes[b];
+        const unsigned nbits = cur.nbits;
         const int nw = (int)((s0 + nbits + 31u) >> 5);
         for (int k = lane; k < nw; k += 64)
             w[k] = 0u;
@@ -486,7 +511,7 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
         long long i0 = 0;
         if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
             for (; i0 + 512 <= bsize; i0 += 512) {
-                const uint4 v = reinterpret_cast<const uint4 *>(src + i0)[lane];
+                const uint4 v = i0 == 0 ? cur.v : reinterpret_cast<const uint4 *>(src + i0)[lane];
                 const unsigned cw[4] = {v.x, v.y, v.z, v.w};
                 unsigned l[8], c[8], t = 0;
 #pragma unroll
@@ -540,6 +565,7 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
                 bits[w0 + k] = w[k];
         }
         __builtin_amdgcn_wave_barrier();
+        cur = nxt;
     }
 }
 
