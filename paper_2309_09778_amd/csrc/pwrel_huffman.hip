@@ -592,6 +592,70 @@ constexpr int kSymsLds = 32768;
 constexpr uint32_t kLutEsc = 0x80000000u;
 constexpr uint32_t kLutLong = 0x40000000u;
 
+// The decoder's lookup table, built once per call (kLutBits-bit windows, one
+// entry per thread): a codeword of at most kLutBits bits gives its symbol and
+// length (kLutEsc: the escape); a prefix of longer codes gives the shortest
+// and longest length under it (kLutLong); 0 where no codeword starts.  Length
+// counts that describe no prefix code of nsym symbols leave the table
+// unwritten (the decoder checks them too, and stops).
+__global__ void __launch_bounds__(256) k_huff_lut(const uint32_t *__restrict__ tab, unsigned nsym,
+                                                  unsigned esc_len, uint32_t *__restrict__ lut)
+{
+    __shared__ Canon cs;
+    __shared__ unsigned slim[kHuffMaxLen + 2];
+    __shared__ unsigned smax, sesc;
+    __shared__ int sok;
+    const uint32_t *cnt = tab;
+    const uint16_t *syms = reinterpret_cast<const uint16_t *>(tab + kHuffMaxLen + 1);
+    if (threadIdx.x == 0) {
+        unsigned long long ns = 0, kraft = 0;
+        for (int l = 1; l <= kHuffMaxLen; ++l) {
+            ns += cnt[l];
+            kraft += (unsigned long long)cnt[l] << (kHuffMaxLen - l);
+        }
+        sok = cnt[0] == 0 && ns == nsym && kraft <= (1ull << kHuffMaxLen) &&
+              (esc_len == 0 || (esc_len <= 16u && cnt[esc_len] != 0));
+        canon_from(cnt, cs);
+        unsigned mx = 0;
+        for (int l = 1; l <= kHuffMaxLen; ++l) {
+            const unsigned long long end = ((unsigned long long)cs.first[l] + cs.count[l])
+                                           << (32 - l);
+            slim[l] = end > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned)end;
+            if (cs.count[l])
+                mx = (unsigned)l;
+        }
+        smax = mx;
+        unsigned ecode;
+        esc_of(cnt, esc_len, sesc, ecode);
+    }
+    __syncthreads();
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!sok || e >= (1 << kLutBits))
+        return;
+    uint32_t v = 0;
+    for (int l = 1; l <= kLutBits; ++l) {
+        const unsigned pre = (unsigned)e >> (kLutBits - l);
+        if (pre - cs.first[l] < cs.count[l]) {
+            const unsigned ix = cs.index[l] + (pre - cs.first[l]);
+            v = ix == sesc ? kLutEsc | ((uint32_t)l << 16) : syms[ix] | ((uint32_t)l << 16);
+            break;
+        }
+    }
+    if (v == 0 && smax > (unsigned)kLutBits) {
+        // longer codes under this prefix: the lengths of its first and last
+        // windows bound theirs
+        const unsigned lo = (unsigned)e << (32 - kLutBits);
+        const unsigned hi = lo | ((1u << (32 - kLutBits)) - 1u);
+        unsigned a = kLutBits + 1, b = kLutBits + 1;
+        for (unsigned qq = kLutBits + 1; qq < smax; ++qq) {
+            a += lo >= slim[qq] ? 1u : 0u;
+            b += hi >= slim[qq] ? 1u : 0u;
+        }
+        v = kLutLong | (a << 16) | (b << 8);
+    }
+    lut[e] = v;
+}
+
 template <typename S, bool ALL_LDS>
 __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *__restrict__ tab,
                                                      const uint32_t *__restrict__ bits,
@@ -600,7 +664,8 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
                                                      const unsigned long long *__restrict__ boffs,
                                                      const unsigned long long *__restrict__ bparts,
                                                      uint16_t *__restrict__ codes, int *status,
-                                                     unsigned nsym, unsigned esc_len)
+                                                     unsigned nsym, unsigned esc_len,
+                                                     const uint32_t *__restrict__ glut)
 {
     extern __shared__ __align__(16) unsigned char hsm[];
     uint32_t *lut = reinterpret_cast<uint32_t *>(hsm);  // symbol | length << 16 (0: longer)
@@ -648,31 +713,9 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
             set_status(status, kECorrupt);
         return;
     }
-    for (int e = threadIdx.x; e < (1 << kLutBits); e += blockDim.x) {
-        uint32_t v = 0;
-        for (int l = 1; l <= kLutBits; ++l) {
-            const unsigned pre = (unsigned)e >> (kLutBits - l);
-            if (pre - cs.first[l] < cs.count[l]) {
-                const unsigned ix = cs.index[l] + (pre - cs.first[l]);
-                v = ix == sesc ? kLutEsc | ((uint32_t)l << 16)
-                               : (ix < nlds ? ssyms[ix] : syms[ix]) | ((uint32_t)l << 16);
-                break;
-            }
-        }
-        if (v == 0 && smax > (unsigned)kLutBits) {
-            // longer codes under this prefix: the lengths of its first and last
-            // windows bound theirs
-            const unsigned lo = (unsigned)e << (32 - kLutBits);
-            const unsigned hi = lo | ((1u << (32 - kLutBits)) - 1u);
-            unsigned a = kLutBits + 1, b = kLutBits + 1;
-            for (unsigned qq = kLutBits + 1; qq < smax; ++qq) {
-                a += lo >= slim[qq] ? 1u : 0u;
-                b += hi >= slim[qq] ? 1u : 0u;
-            }
-            v = kLutLong | (a << 16) | (b << 8);
-        }
-        lut[e] = v;
-    }
+    // the lookup table, built once per call by k_huff_lut
+    for (int e = threadIdx.x; e < (1 << kLutBits) / 4; e += blockDim.x)
+        reinterpret_cast<uint4 *>(lut)[e] = reinterpret_cast<const uint4 *>(glut)[e];
     const unsigned maxlen = __builtin_amdgcn_readfirstlane(smax);
     const unsigned esc_ix = __builtin_amdgcn_readfirstlane(sesc);
     __syncthreads();
@@ -931,7 +974,19 @@ hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32
                               unsigned nsym, unsigned esc_len, Workspace &ws, hipStream_t s)
 {
     const GeoArgs ga = geo_of(g);
-    const unsigned grid = (unsigned)((g.nblocks + kUnpackThreads - 1) / kUnpackThreads);
+    // one thread per block: workgroups of 1024 threads where the blocks fill
+    // every CU that way, smaller ones (down to one wave) for fewer blocks, so
+    // that a small field still spreads over all CUs
+    long long want = (g.nblocks + 255) / 256;
+    unsigned threads = 64;
+    while ((long long)threads < want && threads < (unsigned)kUnpackThreads)
+        threads <<= 1;
+    const unsigned grid = (unsigned)((g.nblocks + threads - 1) / threads);
+    // the lookup table goes through the encoder's codeword buffer (unused
+    // while decoding)
+    uint32_t *glut = reinterpret_cast<uint32_t *>(ws.enc_code);
+    hipLaunchKernelGGL(k_huff_lut, dim3((1 << kLutBits) / 256), dim3(256), 0, s, d_tab, nsym,
+                       esc_len, glut);
     const bool all = nsym <= (unsigned)kSymsLds;
     const unsigned nlds = all ? nsym : (unsigned)kSymsLds;
     const size_t lds = (size_t)(1 << kLutBits) * sizeof(uint32_t) + (size_t)nlds * sizeof(uint16_t);
@@ -941,8 +996,8 @@ hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32
     if (e != hipSuccess)
         return e;
     auto go = [&](auto kern, const auto *sz) {
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(kUnpackThreads), lds, s, d_tab, d_bits, nwords,
-                           ga, sz, ws.boffsets, ws.bpartials, codes, ws.status, nsym, esc_len);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, d_tab, d_bits, nwords, ga,
+                           sz, ws.boffsets, ws.bpartials, codes, ws.status, nsym, esc_len, glut);
     };
     if (sb == 2) {
         const uint16_t *sz = static_cast<const uint16_t *>(d_sizes);

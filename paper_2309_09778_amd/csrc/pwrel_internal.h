@@ -61,7 +61,8 @@ struct Workspace {
     uint16_t *codes16 = nullptr;
     size_t codes16_cap = 0;
     uint8_t *enc_len = nullptr;
-    unsigned long long *enc_code = nullptr;  // codeword | length << 32
+    unsigned long long *enc_code = nullptr;  // codeword | length << 32; while decoding, the
+                                             // decoder's lookup table
     unsigned long long *boffsets = nullptr, *bpartials = nullptr;
     size_t boffsets_cap = 0, bpartials_cap = 0;
     unsigned long long *bits_total = nullptr;
