@@ -46,6 +46,7 @@ struct pwrel_ctx {
     int order_pen = -1;  // the cached order is of pencils (1) or of blocks (0)
     unsigned epoch = 0;
     void *hdr = nullptr;  // header of pwrel_compress_raw (PWREL_HEADER_BYTES)
+    void *hstage = nullptr;  // pinned host staging of a caller's codebook (its upload stays async)
     pwrel::BatchState *batch = nullptr;  // pwrel_compress_batch's workspace and table
     pwrel::OlState *ol = nullptr;        // pwrel_openloop's scratch
 };
@@ -373,6 +374,8 @@ void pwrel_destroy(pwrel_ctx *ctx)
             (void)hipEventDestroy(e);
     batch_release(ctx->batch);
     ol_release(ctx->ol);
+    if (ctx->hstage)
+        (void)hipHostFree(ctx->hstage);
     delete ctx;
 }
 
@@ -581,10 +584,20 @@ int huffman_trained_tail(pwrel_ctx *ctx, const void *d_field, const Geom &g,
         unsigned long long n_raw, bits;
         int status;
     } got{};
-    if ((e = hipMemcpyAsync(d_tab, cb.count, sizeof cb.count, hipMemcpyHostToDevice, s)) !=
+    // the table goes through pinned staging, so its upload does not hold the
+    // host while the compression kernels run (every call ends synchronised,
+    // so the staging is free again at the next)
+    const size_t tbytes = sizeof cb.count + 2ull * cb.n_sym;
+    if (!ctx->hstage &&
+        (e = hipHostMalloc(&ctx->hstage, sizeof cb.count + sizeof cb.syms, 0)) != hipSuccess) {
+        ctx->hstage = nullptr;
+        return fail(ctx, PWREL_ENOMEM, "codebook staging allocation failed");
+    }
+    std::memcpy(ctx->hstage, cb.count, sizeof cb.count);
+    std::memcpy(static_cast<unsigned char *>(ctx->hstage) + sizeof cb.count, cb.syms,
+                2ull * cb.n_sym);
+    if ((e = hipMemcpyAsync(d_tab, ctx->hstage, tbytes, hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
-        (e = hipMemcpyAsync(d_tab + kHuffMaxLen + 1, cb.syms, 2ull * cb.n_sym,
-                            hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = launch_huff_sizes(g, ws.codes16, d_tab, cb.esc_len, out + hl.off_sizes, ws, s)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(&got.n_raw, ws.n_raw, sizeof got.n_raw, hipMemcpyDeviceToHost, s)) !=
