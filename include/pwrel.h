@@ -201,8 +201,9 @@ uint64_t pwrel_compress_bound(const uint64_t *dims, int ndim, int dtype, int blo
  * 2^16-code quantizer with balance points).  Every point of the result
  * decompresses to x^ with |x - x^| <= eps |x|, the sign of x, and x^ = 0
  * exactly where x = 0.  model may be NULL when opt->use_net = 0.  Writes the
- * stream to d_out (capacity out_capacity bytes) and its length to *out_size;
- * synchronises `stream` once to learn that length.
+ * stream to d_out (capacity out_capacity bytes, 16-byte aligned, as every
+ * device allocation is) and its length to *out_size; synchronises `stream`
+ * once to learn that length.  PWREL_EINVAL for an unaligned d_out.
  */
 int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
                    int dtype, double rel_error_bound, int block_size, const pwrel_mlp *model,
@@ -213,8 +214,9 @@ int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, in
  * Decompress a stream (Sec. 5): blocks in dependency order (block levels in
  * halo mode, all at once with independent blocks), grid values rebuilt from the
  * same prediction, x^ = exact inverse transform rounded to dtype; code-0 points
- * take their raw value.  dims/ndim/dtype must match the header.  Synchronises
- * `stream` once to read the header.
+ * take their raw value.  dims/ndim/dtype must match the header; d_in must start
+ * 16-byte aligned (PWREL_EINVAL otherwise).  Synchronises `stream` to read the
+ * header and, at the end, the decoders' status.
  */
 int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d_field,
                      const uint64_t *dims, int ndim, int dtype, void *stream);
@@ -276,8 +278,9 @@ int pwrel_compress_noalloc(pwrel_ctx *ctx, const void *d_field, const uint64_t *
  * over a field table.  Classes: 3-D fields with block 8 and 2-D fields with
  * block 16 (the compiled batched tile shapes).
  *   fields[i]       (host) d_field (device, C order), dims/ndim (2 or 3),
- *                   reserved = 0, d_out (device, out_capacity bytes; at
- *                   least the header + codes part, else PWREL_ENOSPC)
+ *                   reserved = 0, d_out (device, out_capacity bytes,
+ *                   16-byte aligned; at least the header + codes part, else
+ *                   PWREL_ENOSPC)
  *   block_size[3]   (host, or NULL) block edge by ndim - 1; 0 = default
  *                   (16 for 2-D, 8 for 3-D); others give PWREL_EINVAL
  *   models[3]       (host, or NULL) network by ndim - 1, needed for every

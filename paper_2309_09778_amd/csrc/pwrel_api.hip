@@ -781,6 +781,8 @@ int pwrel_compress(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, in
         return st;
     if (!d_out || !out_size)
         return fail(ctx, PWREL_EINVAL, "NULL output or size pointer");
+    if (reinterpret_cast<uintptr_t>(d_out) & 15)
+        return fail(ctx, PWREL_EINVAL, "the output must start 16-byte aligned");
     const int flags = flags_of(opt);
     const Layout L = layout_for(g, flags);
     if (out_capacity < L.off[4])
@@ -1091,6 +1093,8 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
         return PWREL_EINVAL;
     if (!d_in || !d_field || !dims)
         return fail(ctx, PWREL_EINVAL, "NULL stream, field or dims");
+    if (reinterpret_cast<uintptr_t>(d_in) & 15)
+        return fail(ctx, PWREL_EINVAL, "the stream must start 16-byte aligned");
     if (in_size < PWREL_HEADER_BYTES)
         return fail(ctx, PWREL_ECORRUPT, "stream shorter than its header");
     DeviceGuard guard(ctx->device);

@@ -185,6 +185,8 @@ int check_request(pwrel_ctx *ctx, const Request &r)
             return api_fail(ctx, PWREL_EINVAL, (at + "bad dims or bound").c_str());
         if (!f.d_field || !f.d_out)
             return api_fail(ctx, PWREL_EINVAL, (at + "NULL field or output").c_str());
+        if (reinterpret_cast<uintptr_t>(f.d_out) & 15)
+            return api_fail(ctx, PWREL_EINVAL, (at + "output not 16-byte aligned").c_str());
         Geom g;
         make_geom(f.dims, f.ndim, r.dtype, B, g);
         const Layout L = layout_for(g, flags_of(r.opt));

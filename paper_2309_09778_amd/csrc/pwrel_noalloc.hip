@@ -131,6 +131,8 @@ extern "C" int pwrel_compress_noalloc(pwrel_ctx *ctx, const void *d_field, const
         return st;
     if (!d_out || !out_size)
         return api_fail(ctx, PWREL_EINVAL, "NULL output or size pointer");
+    if (reinterpret_cast<uintptr_t>(d_out) & 15)
+        return api_fail(ctx, PWREL_EINVAL, "the output must start 16-byte aligned");
     if (opt.entropy)
         return api_fail(ctx, PWREL_EINVAL, "pwrel_compress_noalloc stores 16-bit codes (entropy = 0)");
     if ((uint64_t)g.N > kNoAllocMaxValues || (uint64_t)g.nblocks > kNoAllocMaxBlocks)

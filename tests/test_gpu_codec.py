@@ -519,3 +519,29 @@ def test_stream_model_and_saved_model_compress_alike(ctx):
     with pytest.raises(pwrel.PwrelError) as e:
         ctx.stream_model(ctx.compress(dev(x), 1e-2, 8, None, use_net=False))
     assert e.value.status == pwrel.EINVAL
+
+
+def test_unaligned_stream_buffers_are_refused(ctx):
+    """Stream buffers must start 16-byte aligned (the kernels move them in
+    16-byte vectors and update shared words atomically): an output or a stream
+    starting one byte in is refused before any GPU work, by every entry point
+    that writes or reads a stream."""
+    x = dev(synth.lognormal_grf((16, 16, 16), seed=41))
+    cap = pwrel.compress_bound(tuple(x.shape), pwrel.F32, 8)
+    buf = torch.empty(cap + 16, dtype=torch.uint8, device="cuda")
+    for fn in (ctx.compress, ctx.compress_noalloc):
+        with pytest.raises(pwrel.PwrelError) as e:
+            fn(x, 1e-2, 8, None, use_net=False, out=buf[1:1 + cap])
+        assert e.value.status == pwrel.EINVAL
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.compress_batch([x], 1e-2, use_net=False, outs=[buf[1:1 + cap]])
+    assert e.value.status == pwrel.EINVAL
+    s = ctx.compress(x, 1e-2, 8, None, use_net=False)
+    moved = torch.empty(s.numel() + 16, dtype=torch.uint8, device="cuda")
+    moved[1:1 + s.numel()].copy_(s)
+    with pytest.raises(pwrel.PwrelError) as e:
+        ctx.decompress(moved[1:1 + s.numel()], shape=tuple(x.shape), dtype=torch.float32)
+    assert e.value.status == pwrel.EINVAL
+    # the same bytes at an aligned address decode
+    xh = ctx.decompress(moved[1:1 + s.numel()].clone())
+    assert xh.shape == x.shape
