@@ -312,6 +312,37 @@ int pwrel_compress_batch(pwrel_ctx *ctx, int n, const pwrel_field_desc *fields, 
                          uint64_t *d_out_sizes, void *stream);
 
 /*
+ * Data blocks (Sec. 5: a stream carries factor_pos and factor_neg for its data
+ * block; Algorithm 1 computes them from the extreme values of its input).  A
+ * 3-D FP32 field (dims[3], C order, device) is split into data blocks: its
+ * sub-volumes of edge `sub` (a positive multiple of 8; the last along an
+ * axis clipped), in raster order.  Each is compressed into its own stream
+ * with its own statistics, factors and constants, byte for byte the stream
+ * pwrel_compress writes for that sub-volume alone (block 8, 16-bit codes,
+ * `model` and *opt as there; entropy must be 0).
+ *  pwrel_compress_datablocks - stream i goes to d_out + i * out_stride
+ *      (device; out_stride a multiple of 256 of at least the header + codes of
+ *      a data block, d_out 16-byte aligned), its length to d_sizes[i] (device,
+ *      0 for a failed data block, as pwrel_compress_batch); *n_sub_out (host)
+ *      receives the number of data blocks.  One gather kernel copies the
+ *      sub-volumes contiguous into the context's staging (grown to the field),
+ *      then one batched compression runs; synchronises the stream once
+ *      before the gather (the data-block table).
+ *  pwrel_decompress_datablocks - the field back from those streams: sizes
+ *      (host, the n_sub lengths), d_in / in_stride as written; each stream is
+ *      decoded (pwrel_decompress, with its checks) and one scatter kernel puts
+ *      the sub-volumes in place.  Errors: PWREL_EINVAL for bad arguments, the
+ *      errors of the per-stream calls.
+ */
+int pwrel_compress_datablocks(pwrel_ctx *ctx, const float *d_field, const uint64_t *dims,
+                              double rel_error_bound, int sub, const pwrel_mlp *model,
+                              const pwrel_options *opt, void *d_out, uint64_t out_stride,
+                              uint64_t *d_sizes, uint64_t *n_sub_out, void *stream);
+int pwrel_decompress_datablocks(pwrel_ctx *ctx, const void *d_in, uint64_t in_stride,
+                                const uint64_t *sizes, float *d_field, const uint64_t *dims,
+                                int sub, void *stream);
+
+/*
  * Tile shapes of the batched compression launch.  A tile is the group of
  * whole blocks one workgroup predicts at a time; it schedules work only, so
  * every shape gives the same streams.  Each class has PWREL_BATCH_TILES

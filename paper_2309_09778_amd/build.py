@@ -10,7 +10,7 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pwrel_codec.hip", "pwrel_com
                                                    "pwrel_decode.hip", "pwrel_train.hip",
                                                    "pwrel_api.hip", "pwrel_noalloc.hip",
                                                    "pwrel_huffman.hip", "pwrel_decode_lanes.hip",
-                                                   "pwrel_batch.hip", "pwrel_openloop.hip")]
+                                                   "pwrel_batch.hip", "pwrel_openloop.hip", "pwrel_datablocks.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("pwrel_device.h", "pwrel_internal.h",
                                                    "pwrel_kernels.h", "pwrel_bf16.h",
                                                    "pwrel_train.h", "pwrel_huffman.h",

@@ -47,6 +47,10 @@ struct pwrel_ctx {
     unsigned epoch = 0;
     void *hdr = nullptr;  // header of pwrel_compress_raw (PWREL_HEADER_BYTES)
     void *hstage = nullptr;  // pinned host staging of a caller's codebook (its upload stays async)
+    float *dstage = nullptr;  // data blocks gathered contiguous (pwrel_*_datablocks)
+    size_t dstage_cap = 0;
+    unsigned long long *doffs = nullptr;  // their offsets in dstage
+    size_t doffs_cap = 0;
     pwrel::BatchState *batch = nullptr;  // pwrel_compress_batch's workspace and table
     pwrel::OlState *ol = nullptr;        // pwrel_openloop's scratch
 };
@@ -365,7 +369,7 @@ void pwrel_destroy(pwrel_ctx *ctx)
                     ctx->vhist,     ctx->scal,      ctx->scores,   ws.done,        ws.ticket,
                     ctx->order,     ws.praw,        ws.zf,         ws.yf,          ctx->hdr,
                     ws.codes16,     ws.enc_len,     ws.enc_code,   ws.boffsets,    ws.bpartials,
-                    ws.bits_total,  ws.invtab,     ctx->bflags_scratch};
+                    ws.bits_total,  ws.invtab,     ctx->bflags_scratch, ctx->dstage, ctx->doffs};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -435,6 +439,16 @@ const long long *api_qtab(const pwrel_ctx *ctx) { return ctx->ws.qtab; }
 BatchState *&api_batch_state(pwrel_ctx *ctx) { return ctx->batch; }
 OlState *&api_ol_state(pwrel_ctx *ctx) { return ctx->ol; }
 Workspace &api_ws(pwrel_ctx *ctx) { return ctx->ws; }
+hipError_t api_dstage(pwrel_ctx *ctx, size_t n, size_t nsub, float **stage,
+                      unsigned long long **offs)
+{
+    hipError_t e = grow(ctx->dstage, ctx->dstage_cap, std::max<size_t>(n, 1));
+    if (e == hipSuccess)
+        e = grow(ctx->doffs, ctx->doffs_cap, std::max<size_t>(nsub, 1));
+    *stage = ctx->dstage;
+    *offs = ctx->doffs;
+    return e;
+}
 int api_ensure_scan(pwrel_ctx *ctx, const Geom &g) { return ensure_scan(ctx, g); }
 
 // The compression launches (Algorithm 1): reset, statistics, constants, grid

@@ -353,6 +353,9 @@ struct OlState;
 OlState *&api_ol_state(pwrel_ctx *ctx);
 void ol_release(OlState *o);
 Workspace &api_ws(pwrel_ctx *ctx);
+// the context's data-block staging: n floats and nsub offsets (grown on demand)
+hipError_t api_dstage(pwrel_ctx *ctx, size_t n, size_t nsub, float **stage,
+                      unsigned long long **offs);
 int api_ensure_scan(pwrel_ctx *ctx, const Geom &g);  // per-block scan buffers
 
 // static scratch of pwrel_compress_noalloc (pwrel_noalloc.hip): set up once

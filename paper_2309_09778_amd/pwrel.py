@@ -153,6 +153,10 @@ _SIGS = {
     "pwrel_huffman_codebook": (C.c_int, [_P, _P, _P, C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_uint64)]),
     "pwrel_huffman_trained_codebook": (C.c_int, [_P, C.POINTER(Codebook)]),
+    "pwrel_compress_datablocks": (C.c_int, [_P, _P, _P, C.c_double, C.c_int, C.POINTER(Mlp),
+                                            C.POINTER(Options), _P, C.c_uint64, _P,
+                                            C.POINTER(C.c_uint64), _P]),
+    "pwrel_decompress_datablocks": (C.c_int, [_P, _P, C.c_uint64, _P, _P, _P, C.c_int, _P]),
     "pwrel_train_codebook": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_double, C.c_int,
                                        C.POINTER(Mlp), C.POINTER(Options), C.c_double,
                                        C.c_uint64, C.POINTER(Codebook), _P]),
@@ -600,6 +604,49 @@ class Context:
              "ms_sample": rep.ms_sample, "ms_train": rep.ms_train,
              "ms_select": rep.ms_select}
         return model_dict(out), r
+
+    def compress_datablocks(self, x, eps, sub, model=None, use_net=True, judge=False,
+                            independent=False, stride=None, stream=None):
+        """pwrel_compress_datablocks: a 3-D FP32 field split into data blocks of
+        edge `sub`, each its own stream with its own factors (Sec. 5).  Returns
+        (streams uint8 [n_sub, stride], sizes uint64 [n_sub]) as CUDA tensors."""
+        import torch
+        assert x.is_cuda and x.is_contiguous() and x.dim() == 3 and x.dtype == torch.float32
+        if stride is None:
+            e = max(int(sub), 1)
+            stride = compress_bound((min(e, x.shape[0]), min(e, x.shape[1]),
+                                     min(e, x.shape[2])), F32, 8)
+            stride = (stride + 255) // 256 * 256
+        nsub = 1
+        for d in x.shape:
+            nsub *= -(-int(d) // max(int(sub), 1))  # the library refuses a bad edge
+        outs = torch.empty((nsub, stride), dtype=torch.uint8, device=x.device)
+        sizes = torch.zeros(nsub, dtype=torch.int64, device=x.device)
+        m = model_struct(model) if use_net else None
+        opt = Options(int(bool(use_net)), int(bool(judge)), int(bool(independent)), 0)
+        n = C.c_uint64(0)
+        st = self._L.pwrel_compress_datablocks(
+            self.h, C.c_void_p(x.data_ptr()), _dims(x.shape), float(eps), int(sub),
+            C.byref(m) if m is not None else None, C.byref(opt), C.c_void_p(outs.data_ptr()),
+            int(stride), C.c_void_p(sizes.data_ptr()), C.byref(n), _stream(stream))
+        self._check(st, "compress_datablocks")
+        assert n.value == nsub
+        return outs, sizes
+
+    def decompress_datablocks(self, streams, sizes, shape, sub, out=None, stream=None):
+        """pwrel_decompress_datablocks: the field back from compress_datablocks'
+        streams ([n_sub, stride] uint8) and sizes (host or device)."""
+        import torch
+        hs = np.ascontiguousarray(np.asarray(sizes.cpu() if hasattr(sizes, "cpu") else sizes,
+                                             dtype=np.uint64))
+        if out is None:
+            out = torch.empty(tuple(shape), dtype=torch.float32, device=streams.device)
+        st = self._L.pwrel_decompress_datablocks(
+            self.h, C.c_void_p(streams.data_ptr()), int(streams.shape[1]),
+            hs.ctypes.data_as(_P), C.c_void_p(out.data_ptr()), _dims(shape), int(sub),
+            _stream(stream))
+        self._check(st, "decompress_datablocks")
+        return out
 
     def train_codebook(self, x, eps, block=8, model=None, use_net=True, judge=False,
                        independent=False, frac=0.02, seed=0, stream=None):
