@@ -233,6 +233,46 @@ def stream_stats(ctx, s, x_nbytes, pwrel, plain_codes=None):
     return out
 
 
+def datablocks_leg(ctx, xd, eps, model, steps, warmup, pwrel, torch):
+    """The field split into data blocks (sub-volumes) of edge 128 and 64, each
+    its own stream with its own factors (Sec. 5), learned BF16 network with
+    the judge, independent blocks, 16-bit codes: compress (gather + one
+    batched compression) and decompress (per-stream decoding + scatter)
+    times, the streams' total size against one stream of the whole field, and
+    the bound on every point."""
+    gb = xd.numel() * 4 / 1e9
+    one = ctx.compress(xd, eps, 8, model, judge=True, independent=True).numel()
+    rec = {}
+    for sub in (128, 64):
+        for _ in range(warmup):
+            outs, sizes = ctx.compress_datablocks(xd, eps, sub, model, judge=True,
+                                                  independent=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            outs, sizes = ctx.compress_datablocks(xd, eps, sub, model, judge=True,
+                                                  independent=True)
+        torch.cuda.synchronize()
+        tc = (time.perf_counter() - t0) / steps
+        hs = sizes.cpu()
+        back = ctx.decompress_datablocks(outs, hs, tuple(xd.shape), sub)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            back = ctx.decompress_datablocks(outs, hs, tuple(xd.shape), sub, out=back)
+        torch.cuda.synchronize()
+        td = (time.perf_counter() - t0) / steps
+        total = int(hs.sum().item())
+        rec[f"edge_{sub}"] = {"data_blocks": int(outs.shape[0]),
+                              "compress_GBps": round(gb / tc, 3),
+                              "decompress_GBps": round(gb / td, 3),
+                              "ratio_16bit_codes": round(xd.numel() * 4 / total, 4),
+                              "size_vs_one_stream": round(total / one, 4),
+                              "bound_ok_every_point": bound_ok(xd, back, eps, torch)}
+        del outs, back
+    return rec
+
+
 def bf16_vs_fp32(ctx, xd, eps, B, model, out, pwrel, torch):
     """The same trained network on the matrix cores (BF16 operands) and on the
     vector ALU (FP32), no judge: where both code a point, the codes differ by
@@ -578,6 +618,9 @@ def main():
     if args.only_timed:
         print(json.dumps(res), flush=True)
         return
+
+    res["data_blocks"] = datablocks_leg(ctx, xd, eps, learned, K, args.warmup, pwrel, torch)
+    log("data-block leg timed")
 
     # the learned path with halo prediction
     lh, rep_h = ctx.train(xd, eps, B, rho=args.rho, seed=1001, hidden=args.hidden, precision=1)

@@ -329,10 +329,13 @@ int pwrel_compress_batch(pwrel_ctx *ctx, int n, const pwrel_field_desc *fields, 
  *      then one batched compression runs; synchronises the stream once
  *      before the gather (the data-block table).
  *  pwrel_decompress_datablocks - the field back from those streams: sizes
- *      (host, the n_sub lengths), d_in / in_stride as written; each stream is
- *      decoded (pwrel_decompress, with its checks) and one scatter kernel puts
- *      the sub-volumes in place.  Errors: PWREL_EINVAL for bad arguments, the
- *      errors of the per-stream calls.
+ *      (host, the n_sub lengths), d_in / in_stride as written.  One strided
+ *      copy brings every header up; each stream is checked and decoded as
+ *      pwrel_decompress does, all of them queued back to back; one scatter
+ *      kernel puts the sub-volumes in place; the first failing stream's
+ *      status is returned (two host synchronisations in all).  Errors:
+ *      PWREL_EINVAL for bad arguments, PWREL_ECORRUPT for a length outside
+ *      the stride or a damaged stream.
  */
 int pwrel_compress_datablocks(pwrel_ctx *ctx, const float *d_field, const uint64_t *dims,
                               double rel_error_bound, int sub, const pwrel_mlp *model,

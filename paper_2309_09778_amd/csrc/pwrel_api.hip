@@ -51,6 +51,8 @@ struct pwrel_ctx {
     size_t dstage_cap = 0;
     unsigned long long *doffs = nullptr;  // their offsets in dstage
     size_t doffs_cap = 0;
+    int *mstatus = nullptr;  // status of a call that decodes several streams
+    size_t mstatus_cap = 0;
     pwrel::BatchState *batch = nullptr;  // pwrel_compress_batch's workspace and table
     pwrel::OlState *ol = nullptr;        // pwrel_openloop's scratch
 };
@@ -369,7 +371,8 @@ void pwrel_destroy(pwrel_ctx *ctx)
                     ctx->vhist,     ctx->scal,      ctx->scores,   ws.done,        ws.ticket,
                     ctx->order,     ws.praw,        ws.zf,         ws.yf,          ctx->hdr,
                     ws.codes16,     ws.enc_len,     ws.enc_code,   ws.boffsets,    ws.bpartials,
-                    ws.bits_total,  ws.invtab,     ctx->bflags_scratch, ctx->dstage, ctx->doffs};
+                    ws.bits_total,  ws.invtab,     ctx->bflags_scratch, ctx->dstage, ctx->doffs,
+                    ctx->mstatus};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -1100,32 +1103,28 @@ int pwrel_read_header(const void *buf, uint64_t size, pwrel_header *out)
     return PWREL_OK;
 }
 
-int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d_field,
-                     const uint64_t *dims, int ndim, int dtype, void *stream)
+}  // extern "C"
+
+namespace {
+
+// what a decompression reads of a stream before its kernels: the header and
+// the model that may follow it
+struct StreamHead {
+    pwrel_header h;
+    unsigned char pad[PWREL_HEADER_BYTES - sizeof(pwrel_header)];
+    pwrel_mlp m;
+};
+static_assert(sizeof(pwrel_header) <= PWREL_HEADER_BYTES, "header too large");
+
+// Check a stream's header (held in host memory: `want` bytes of it were
+// read) against the caller's field, then queue every decoding kernel on s.
+// Leaves the stream's status in ws.status and its decoded balance points in
+// ws.n_raw; *hout receives the checked header.
+int decompress_launch(pwrel_ctx *ctx, const StreamHead &head, uint64_t want, const void *d_in,
+                      uint64_t in_size, void *d_field, const uint64_t *dims, int ndim, int dtype,
+                      hipStream_t s, pwrel_header *hout)
 {
-    if (!ctx)
-        return PWREL_EINVAL;
-    if (!d_in || !d_field || !dims)
-        return fail(ctx, PWREL_EINVAL, "NULL stream, field or dims");
-    if (reinterpret_cast<uintptr_t>(d_in) & 15)
-        return fail(ctx, PWREL_EINVAL, "the stream must start 16-byte aligned");
-    if (in_size < PWREL_HEADER_BYTES)
-        return fail(ctx, PWREL_ECORRUPT, "stream shorter than its header");
-    DeviceGuard guard(ctx->device);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    struct {
-        pwrel_header h;
-        unsigned char pad[PWREL_HEADER_BYTES - sizeof(pwrel_header)];
-        pwrel_mlp m;
-    } head;
-    static_assert(sizeof(pwrel_header) <= PWREL_HEADER_BYTES, "header too large");
-    const uint64_t want = std::min<uint64_t>(in_size, sizeof head);
-    std::memset(&head, 0, sizeof head);
-    hipError_t e = hipMemcpyAsync(&head, d_in, want, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
-    if (e != hipSuccess)
-        return hip_fail(ctx, e, "header copy");
+    hipError_t e;
     pwrel_header h;
     if (pwrel_read_header(&head.h, in_size, &h) != PWREL_OK)
         return fail(ctx, PWREL_ECORRUPT, "stream header is corrupt or truncated");
@@ -1251,6 +1250,58 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
         (e = launch_inverse(g, c, ctx->ws, d_field, s)) != hipSuccess)
         return hip_fail(ctx, e, "inverse");
     mark(ctx, 8, s);
+    *hout = h;
+    return PWREL_OK;
+}
+
+__global__ void k_fill_i32(int *p, int n, int v)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        p[i] = v;
+}
+
+// one thread: a decoded stream's status and balance-point count into the
+// status of a call that decodes several streams (the first error stays)
+__global__ void k_accum_status(const int *status, const unsigned long long *n_raw,
+                               unsigned long long want, int *acc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0 || *acc != PWREL_OK)
+        return;
+    if (*status != PWREL_OK)
+        *acc = *status;
+    else if (*n_raw != want)
+        *acc = PWREL_ECORRUPT;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d_field,
+                     const uint64_t *dims, int ndim, int dtype, void *stream)
+{
+    if (!ctx)
+        return PWREL_EINVAL;
+    if (!d_in || !d_field || !dims)
+        return fail(ctx, PWREL_EINVAL, "NULL stream, field or dims");
+    if (reinterpret_cast<uintptr_t>(d_in) & 15)
+        return fail(ctx, PWREL_EINVAL, "the stream must start 16-byte aligned");
+    if (in_size < PWREL_HEADER_BYTES)
+        return fail(ctx, PWREL_ECORRUPT, "stream shorter than its header");
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    StreamHead head;
+    const uint64_t want = std::min<uint64_t>(in_size, sizeof head);
+    std::memset(&head, 0, sizeof head);
+    hipError_t e = hipMemcpyAsync(&head, d_in, want, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    pwrel_header h;
+    int st = decompress_launch(ctx, head, want, d_in, in_size, d_field, dims, ndim, dtype, s, &h);
+    if (st != PWREL_OK)
+        return st;
     int dst = 0;
     unsigned long long nr = 0;
     if ((e = hipMemcpyAsync(&dst, ctx->ws.status, sizeof dst, hipMemcpyDeviceToHost, s)) !=
@@ -1265,6 +1316,56 @@ int pwrel_decompress(pwrel_ctx *ctx, const void *d_in, uint64_t in_size, void *d
     collect(ctx, spans, 4);
     return finish_status(ctx, dst);
 }
+
+}  // extern "C"
+
+namespace pwrel {
+
+// Several streams decoded in stream order with two host synchronisations in
+// all: one strided copy brings every header (and model) up, the streams'
+// kernels are queued one stream after the other, each stream's status and
+// balance-point count folded into one word, read at the end.
+int api_decompress_many(pwrel_ctx *ctx, const unsigned char *d_in, uint64_t stride,
+                        const uint64_t *sizes, size_t n, float *const *outs,
+                        const uint64_t (*dims)[3], hipStream_t s)
+{
+    DeviceGuard guard(ctx->device);
+    if (n == 0)
+        return PWREL_OK;
+    std::vector<StreamHead> heads(n);
+    std::memset(heads.data(), 0, n * sizeof(StreamHead));
+    hipError_t e;
+    if ((e = grow(ctx->mstatus, ctx->mstatus_cap, 1)) != hipSuccess)
+        return fail(ctx, PWREL_ENOMEM, "status allocation failed");
+    const size_t want = std::min<uint64_t>(stride, sizeof(StreamHead));
+    if ((e = hipMemcpy2DAsync(heads.data(), sizeof(StreamHead), d_in, stride, want, n,
+                              hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "header copy");
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, ctx->mstatus, 1, PWREL_OK);
+    for (size_t i = 0; i < n; ++i) {
+        if (sizes[i] < PWREL_HEADER_BYTES || sizes[i] > stride)
+            return fail(ctx, PWREL_ECORRUPT, "a stream's length is invalid");
+        pwrel_header h;
+        const int st = decompress_launch(ctx, heads[i], std::min<uint64_t>(sizes[i], want),
+                                         d_in + i * stride, sizes[i], outs[i], dims[i], 3,
+                                         PWREL_F32, s, &h);
+        if (st != PWREL_OK)
+            return st;
+        hipLaunchKernelGGL(k_accum_status, dim3(1), dim3(64), 0, s, ctx->ws.status,
+                           ctx->ws.n_raw, (unsigned long long)h.n_raw, ctx->mstatus);
+    }
+    int dst = 0;
+    if ((e = hipMemcpyAsync(&dst, ctx->mstatus, sizeof dst, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(ctx, e, "status copy");
+    return finish_status(ctx, dst);
+}
+
+}  // namespace pwrel
+
+extern "C" {
 
 int pwrel_transform(pwrel_ctx *ctx, const void *d_field, const uint64_t *dims, int ndim,
                     int dtype, double eps, int32_t *d_p, pwrel_header *hdr_out, void *stream)

@@ -201,14 +201,15 @@ extern "C" int pwrel_decompress_datablocks(pwrel_ctx *ctx, const void *d_in, uin
                             hipMemcpyHostToDevice, s)) != hipSuccess)
         return api_fail(ctx, PWREL_EHIP, "data-block offsets copy");
     const unsigned char *in = static_cast<const unsigned char *>(d_in);
-    for (size_t i = 0; i < nsub; ++i) {
-        if (sizes[i] == 0 || sizes[i] > in_stride)
-            return api_fail(ctx, PWREL_ECORRUPT, "a data block's stream length is invalid");
-        const int st = pwrel_decompress(ctx, in + i * in_stride, sizes[i], stage + p.offs[i],
-                                        p.dims[i].data(), 3, PWREL_F32, stream);
-        if (st != PWREL_OK)
-            return st;
-    }
+    std::vector<float *> outs(nsub);
+    std::vector<std::array<uint64_t, 3>> dd(p.dims);
+    for (size_t i = 0; i < nsub; ++i)
+        outs[i] = stage + p.offs[i];
+    // every stream's kernels queued back to back (one header copy, one status read)
+    const int st = api_decompress_many(ctx, in, in_stride, sizes, nsub, outs.data(),
+                                       reinterpret_cast<const uint64_t(*)[3]>(dd.data()), s);
+    if (st != PWREL_OK)
+        return st;
     hipLaunchKernelGGL(k_scatter_sub, dim3(grid_of(p.n)), dim3(256), 0, s, stage, p.g, d_offs,
                        d_field, p.n);
     if ((e = hipGetLastError()) != hipSuccess)

@@ -353,6 +353,11 @@ struct OlState;
 OlState *&api_ol_state(pwrel_ctx *ctx);
 void ol_release(OlState *o);
 Workspace &api_ws(pwrel_ctx *ctx);
+// n FP32 3-D streams at d_in + i * stride (lengths sizes[i], host) decoded
+// into outs[i] (dims[i]) in stream order, with two host synchronisations
+int api_decompress_many(pwrel_ctx *ctx, const unsigned char *d_in, uint64_t stride,
+                        const uint64_t *sizes, size_t n, float *const *outs,
+                        const uint64_t (*dims)[3], hipStream_t s);
 // the context's data-block staging: n floats and nsub offsets (grown on demand)
 hipError_t api_dstage(pwrel_ctx *ctx, size_t n, size_t nsub, float **stage,
                       unsigned long long **offs);
