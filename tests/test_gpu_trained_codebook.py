@@ -286,3 +286,31 @@ def test_codebook_errors(ctx):
 
 
 C_SIZE = __import__("ctypes").sizeof(pwrel.Header)
+
+
+@pytest.mark.parametrize("name", ["grf_1d_halo", "zonal_2d", "f64_1e-4", "grf_B5"])
+def test_training_table_other_shapes(ctx, name):
+    """The table of the training phase for 1-D, 2-D, FP64 and odd-block
+    fields: the validation blocks' counts of the oracle's codes give the
+    same table (Lorenzo where the case has no network, else the FP32 net)."""
+    x, eps, B, model, indep = _case(name)
+    use_net = model is not None
+    if use_net:
+        model = dict(model, precision=0)
+    mode = O.MODE_PLAIN if use_net else O.MODE_LORENZO
+    frac, seed = 0.3, 5
+    cb = ctx.train_codebook(dev(x), eps, B, model, use_net=use_net, independent=indep,
+                            frac=frac, seed=seed)
+    ref = O.compress(x, eps, B, model, mode, independent=indep)
+    hval, nsel = O.table_hist(ref["codes"], x.shape, B, frac, seed)
+    assert nsel > 0
+    ln, oesc = O.huff_trained_lengths(hval)
+    ocnt, osyms = O.huff_book(ln)
+    cnt, syms, esc = cb.arrays()
+    assert esc == oesc and np.array_equal(cnt, ocnt) and np.array_equal(syms, osyms)
+    # the field coded with it decodes exactly
+    s = ctx.compress(dev(x), eps, B, model, use_net=use_net, independent=indep, codebook=cb)
+    xh = ctx.decompress(s).cpu().numpy()
+    ref_xh, _ = O.decompress(ref["codes"], ref["raw"], ref["consts"], x.shape, x.dtype, B, model,
+                             mode, independent=indep)
+    assert np.array_equal(xh.view(np.uint8), ref_xh.view(np.uint8))
