@@ -165,6 +165,17 @@ __device__ __forceinline__ int net_err32(float y, const int (&nv)[8])
     return (nv[1] - nv[0]) + (int)__builtin_rintf(y);
 }
 
+// Workgroup barrier that orders LDS accesses only: global stores stay in
+// flight across it (no thread reads global memory that another thread of the
+// workgroup wrote in the same launch; the staged tile copies are waited for
+// explicitly).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // s_waitcnt vmcnt(0): this wave's outstanding global loads and stores are done
 __device__ __forceinline__ void wait_vmem()
 {
@@ -219,6 +230,16 @@ k_compress(CompressArgs a)
     constexpr int BVc = BB * (D >= 2 ? BB : 1) * (D >= 3 ? BB : 1);  // 0: runtime shape
     constexpr bool JS = judge_sorts(CT, BVc);
     constexpr int JEPL = JS ? judge_epl(BVc) : 1;
+    // 8^3 blocks: the sort whose stages all run inside a lane (layouts moved
+    // through the grid tile's LDS once the tile is predicted)
+    constexpr bool JL = JS && D == 3 && BB == 8;
+    if constexpr (JL) {
+        static_assert(JEPL == 8, "512 points a block");
+        static_assert((S::T0 + 1) * (S::T1 + 1) * (S::T2 + 1) >= (NT / 64) * kSortLdsWords,
+                      "the grid tile holds every wave's sort words");
+        static_assert((S::T0 / 8) * (S::T1 / 8) * (S::T2 / 8) % 4 == 0,
+                      "the grid tile starts 16-byte aligned (28 bytes a block before it)");
+    }
     const int HC = judge_slots(BV);
     const bool jwin = a.judge && !JS;
     unsigned *jb = jh + (jwin ? nbt * kJudgeWin : 0);
@@ -230,6 +251,15 @@ k_compress(CompressArgs a)
 
     __shared__ int s_status;
     __shared__ float4 wl[kWlds];
+    // the judge's q-table in LDS (sorted path, blocks of up to 512 points)
+    constexpr bool JQ = JS && BVc <= 512;
+    __shared__ long long sq[JQ ? BVc + 1 : 1];
+    if constexpr (JQ) {
+        if (a.judge)
+            for (int i = tid; i <= BVc; i += NT)
+                sq[i] = a.qtab[i];
+    }
+    const long long *qt = JQ ? sq : a.qtab;
     stage_weights<HP>(wl, a.mlp);
     const float b2 = a.mlp.b2, alpha = a.mlp.alpha;
     NetBf16 net16;
@@ -437,7 +467,7 @@ k_compress(CompressArgs a)
         const long long g0z = r.z0, g0y = r.y0, g0x = r.x0;
         if constexpr (PIPE)
             wait_vmem();  // this wave's copies have landed
-        __syncthreads();  // ... and every other wave's
+        lds_barrier();    // ... and every other wave's
 
         // --- grid values of the extended tile; bound check of the tile points --
         for (int it = tid; it < nrows * nch; it += NT) {
@@ -477,7 +507,7 @@ k_compress(CompressArgs a)
                 bext[bt] = (unsigned)bg.ex | ((unsigned)bg.ey << 16);
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         // the next tile's copies are in flight during this tile's prediction
         // (issued after the barrier: a barrier waits for outstanding copies)
@@ -726,7 +756,7 @@ k_compress(CompressArgs a)
                 atomicAdd(&cnt[bt], nzero);
         }
         }
-        __syncthreads();
+        lds_barrier();
 
         if (a.judge) {
             // --- per-block judge: keep the network iff the entropy of its codes
@@ -738,7 +768,30 @@ k_compress(CompressArgs a)
                 const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
                 unsigned long long s0 = 0ULL, s1 = 0ULL;
                 unsigned z0 = 0, z1 = 0;
-                if constexpr (JS) {
+                if constexpr (JL) {
+                    // element k + 8 lane = point (lane >> 3, lane & 7, k) of the
+                    // block; the sort's LDS is the wave's share of the grid
+                    // tile, which nothing reads again before the next tile
+                    const int cz = btz * 8 + (lane >> 3), cy = bty * 8 + (lane & 7);
+                    const int cx0 = btx * 8;
+                    const bool rin = cz < limz && cy < limy;
+                    const unsigned *src = jb + (cz * T1 + cy) * T2 + cx0;
+                    unsigned kv[8];
+                    unsigned nsent = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const bool pt = rin && cx0 + k < limx;
+                        const unsigned v = pt ? src[k] : 0xFFFFFFFFu;
+                        kv[k] = v;
+                        nsent += (unsigned)__popcll(__ballot(!pt));
+                        z0 += (unsigned)__popcll(__ballot(pt && (v & 0xffffu) == 0u));
+                        z1 += (unsigned)__popcll(__ballot(pt && (v >> 16) == 0u));
+                    }
+                    unsigned *scr = reinterpret_cast<unsigned *>(ptile) +
+                                    __builtin_amdgcn_readfirstlane(tid >> 6) * kSortLdsWords;
+                    wave_sort_lds8(kv, static_cast<unsigned *>(__builtin_assume_aligned(scr, 16)));
+                    wave_runs_lm<8>(kv, nsent, qt, s0, s1);
+                } else if constexpr (JS) {
                     unsigned kv[JEPL];
                     unsigned nsent = 0;
 #pragma unroll
@@ -753,7 +806,7 @@ k_compress(CompressArgs a)
                         z0 += (unsigned)__popcll(__ballot(pt && (v & 0xffffu) == 0u));
                         z1 += (unsigned)__popcll(__ballot(pt && (v >> 16) == 0u));
                     }
-                    wave_multiset_score<JEPL>(kv, nsent, a.qtab, s0, s1);
+                    wave_multiset_score<JEPL>(kv, nsent, qt, s0, s1);
                 } else {
                     unsigned *hb = jh + bt * kJudgeWin;
                     unsigned *t0 = jht + (2 * bt) * HC, *t1 = t0 + HC;
@@ -811,29 +864,35 @@ k_compress(CompressArgs a)
                     jz[2 * bt + 1] = z1;
                 }
             }
-            __syncthreads();
-            // blocks where Lorenzo wins: overwrite the network codes written above
-            // with the Lorenzo codes noted in the prediction loop
-            for (int q = tid; q < nbt * BV; q += NT) {
-                const int bt = q / BV;
+            lds_barrier();
+            // blocks where Lorenzo wins: each thread overwrites the network codes
+            // it stored in the prediction loop (the same units, so its earlier
+            // stores to these addresses are ordered before these) with the
+            // Lorenzo codes noted there
+            for (int u0 = 0; u0 < nunits; u0 += NT) {
+                const int u = u0 + tid;
+                if (u >= nunits)
+                    break;
+                const int seg = u % nseg, row = u / nseg;
+                const int ly = row % bd1, lz = (row / bd1) % bd0, bt = row / (bd1 * bd0);
                 if (jsum[2 * bt] > jsum[2 * bt + 1])
                     continue;
-                const int li = q - bt * BV;
                 const int btx = bt % nbt2, bty = (bt / nbt2) % nbt1, btz = bt / (nbt1 * nbt2);
-                const int lx = li % bd2, ly = (li / bd2) % bd1, lz = li / (bd1 * bd2);
-                const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx = btx * bd2 + lx;
-                if (!(cz < limz && cy < limy && cx < limx))
+                const int cz = btz * bd0 + lz, cy = bty * bd1 + ly, cx0 = btx * bd2 + seg * SEG;
+                if (!(cz < limz && cy < limy))
                     continue;
-                const long long pos = bst[bt] + (long long)((lz * (int)(bext[bt] >> 16) + ly) *
-                                                                (int)(bext[bt] & 0xffffu) +
-                                                            lx);
-                F.codes[pos] = (uint16_t)(jb[(cz * T1 + cy) * T2 + cx] >> 16);
+                const int ex = (int)(bext[bt] & 0xffffu), ey = (int)(bext[bt] >> 16);
+                const long long pos0 = bst[bt] + (long long)((lz * ey + ly) * ex + seg * SEG);
+                const int okr = (cz * T1 + cy) * T2 + cx0;
+                for (int i = 0; i < SEG; ++i)
+                    if (cx0 + i < limx)
+                        F.codes[pos0 + i] = (uint16_t)(jb[okr + i] >> 16);
             }
             for (int bt = tid; bt < nbt; bt += NT) {
                 const bool use_n = jsum[2 * bt] > jsum[2 * bt + 1];
                 cnt[bt] = use_n ? jz[2 * bt] : jz[2 * bt + 1];  // balance points of the winner
             }
-            __syncthreads();
+            lds_barrier();
         }
 
         // --- per-block balance-point counts ------------------------------------
@@ -852,7 +911,7 @@ k_compress(CompressArgs a)
                 jsum[2 * bt] = jsum[2 * bt + 1] = 0ULL;
         }
         // the next tile overwrites the LDS arrays only after this barrier
-        __syncthreads();
+        lds_barrier();
     }
     set_status(F.status, err);
 }

@@ -145,6 +145,136 @@ template <int EPL> __device__ __forceinline__ void wave_sort_lm(unsigned (&a)[EP
     lm_levels<EPL, 2>(a);
 }
 
+// Sorting 512 elements (8 a lane) with every compare-exchange inside a lane.
+// Bitonic sort with directions: merge s (blocks of 2^s elements) runs its
+// stages on index bits s - 1 .. 0, and a block whose bit s is set sorts
+// descending.  Elements of descending blocks are held complemented (the
+// minimum of complements is the complement of the maximum), so every stage
+// keeps the minimum at the lower index and the direction costs one XOR per
+// element at each change of merge.  An element index has 9 bits; three
+// layouts put three of them in a lane's registers: layout 0 bits 0-2
+// (element 8 lane + k, lane-major), layout 1 bits 3-5, layout 2 bits 6-8.
+// Between layouts the wave moves its elements through 568 words of LDS that
+// it alone uses: element i sits in word i + 8 (i >> 6), so the words that
+// layouts 1 and 2 access at one register index fall in 64 different banks.
+constexpr int kSortLdsWords = 568;
+
+template <int M> __device__ __forceinline__ int ls_base(int l)
+{
+    if constexpr (M == 0)
+        return 8 * l + 8 * (l >> 3);
+    else if constexpr (M == 1)
+        return (l & 7) + 72 * (l >> 3);
+    else
+        return l;
+}
+template <int M> __host__ __device__ constexpr int ls_off(int k)
+{
+    return M == 0 ? k : (M == 1 ? 8 * k : 72 * k);
+}
+
+// the wave's LDS accesses before this point are ordered before those after
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int FROM, int TO>
+__device__ __forceinline__ void ls_move(unsigned (&a)[8], unsigned *scr, int lane)
+{
+    unsigned *w = scr + ls_base<FROM>(lane);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        w[ls_off<FROM>(k)] = a[k];
+    wave_lds_sync();
+    const unsigned *r = scr + ls_base<TO>(lane);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        a[k] = r[ls_off<TO>(k)];
+    wave_lds_sync();
+}
+
+// the stage on the index bit held by register bit R: pairs k, k | 2^R
+template <int R> __device__ __forceinline__ void ls_stage(unsigned (&a)[8])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k & (1 << R))
+            continue;
+        const unsigned x = a[k], y = a[k | (1 << R)];
+        a[k] = pk_min16(x, y);
+        a[k | (1 << R)] = pk_max16(x, y);
+    }
+}
+
+// merge S >= 4, entered and left in layout 0
+template <int S>
+__device__ __forceinline__ void ls_merge(unsigned (&a)[8], unsigned *scr, int lane)
+{
+    // direction: bit S - 1 (lane bit S - 4) out, bit S (lane bit S - 3; none for S = 9) in
+    const unsigned m = (((lane >> (S - 4)) ^ (lane >> (S - 3))) & 1) ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        a[k] ^= m;
+    if constexpr (S >= 7) {
+        ls_move<0, 2>(a, scr, lane);
+        if constexpr (S >= 9)
+            ls_stage<2>(a);
+        if constexpr (S >= 8)
+            ls_stage<1>(a);
+        ls_stage<0>(a);
+        ls_move<2, 1>(a, scr, lane);
+    } else {
+        ls_move<0, 1>(a, scr, lane);
+    }
+    if constexpr (S >= 6)
+        ls_stage<2>(a);
+    if constexpr (S >= 5)
+        ls_stage<1>(a);
+    ls_stage<0>(a);
+    ls_move<1, 0>(a, scr, lane);
+    ls_stage<2>(a);
+    ls_stage<1>(a);
+    ls_stage<0>(a);
+}
+
+// Sorts the wave's 512 elements (8 a lane, lane-major on return), both
+// 16-bit halves as separate sequences; scr: kSortLdsWords words of LDS,
+// 16-byte aligned, used by this wave only.
+__device__ __forceinline__ void wave_sort_lds8(unsigned (&a)[8], unsigned *scr)
+{
+    const int lane = threadIdx.x & 63;
+    // merges 1-3 inside the lane (layout 0); merge s complements where bit s is set
+    a[2] = ~a[2];
+    a[3] = ~a[3];
+    a[6] = ~a[6];
+    a[7] = ~a[7];
+    ls_stage<0>(a);
+    a[2] = ~a[2];
+    a[3] = ~a[3];
+    a[4] = ~a[4];
+    a[5] = ~a[5];
+    ls_stage<1>(a);
+    ls_stage<0>(a);
+    {
+        const unsigned m = (lane & 1) ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            a[k] ^= (k & 4) ? ~m : m;
+    }
+    ls_stage<2>(a);
+    ls_stage<1>(a);
+    ls_stage<0>(a);
+    ls_merge<4>(a, scr, lane);
+    ls_merge<5>(a, scr, lane);
+    ls_merge<6>(a, scr, lane);
+    ls_merge<7>(a, scr, lane);
+    ls_merge<8>(a, scr, lane);
+    ls_merge<9>(a, scr, lane);
+}
+
 // Multiset scores of both halves of lane-major sorted elements:
 // J_h = sum over the runs of equal keys of c q(c), c the run's length (the
 // run of key 0xFFFF less `nsent` stand-ins).  A run starts where the key
@@ -190,21 +320,19 @@ __device__ __forceinline__ void wave_runs_lm(const unsigned (&a)[EPL], unsigned 
         const unsigned m = startmask(k);
         st = ((pos1 | (pos1 << 16)) & m) | (st & ~m);
         const unsigned y = a[k] ^ (k + 1 < EPL ? a[k + 1 < EPL ? k + 1 : k] : next);
+        // a run ends here: its length (0 otherwise, which adds 0 q(0) = 0);
+        // the lookups take no branch, so they are issued back to back
         const bool tail = k == EPL - 1 && lane == 63;
-        if (tail || (y & 0xFFFFu)) {
-            int c = (int)pos1 - (int)(st & 0xFFFFu) + 1;
-            if ((a[k] & 0xFFFFu) == 0xFFFFu)
-                c -= (int)nsent;
-            if (c > 0)
-                s0 += (unsigned long long)c * (unsigned long long)qtab[c];
-        }
-        if (tail || (y >> 16)) {
-            int c = (int)pos1 - (int)(st >> 16) + 1;
-            if ((a[k] >> 16) == 0xFFFFu)
-                c -= (int)nsent;
-            if (c > 0)
-                s1 += (unsigned long long)c * (unsigned long long)qtab[c];
-        }
+        int c0 = (int)pos1 - (int)(st & 0xFFFFu) + 1;
+        if ((a[k] & 0xFFFFu) == 0xFFFFu)
+            c0 -= (int)nsent;
+        const unsigned e0 = ((tail || (y & 0xFFFFu)) && c0 > 0) ? (unsigned)c0 : 0u;
+        int c1 = (int)pos1 - (int)(st >> 16) + 1;
+        if ((a[k] >> 16) == 0xFFFFu)
+            c1 -= (int)nsent;
+        const unsigned e1 = ((tail || (y >> 16)) && c1 > 0) ? (unsigned)c1 : 0u;
+        s0 += (unsigned long long)e0 * (unsigned long long)qtab[e0];
+        s1 += (unsigned long long)e1 * (unsigned long long)qtab[e1];
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
