@@ -193,7 +193,7 @@ __device__ __forceinline__ void wait_vmem()
 // fields, so neither carries the other's code.
 template <typename T, int D, int BB, int HP, bool FROM_P, int PREC, bool BATCH, int TV = 0,
           bool W32 = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 4 : 6)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 6)))
 k_compress(CompressArgs a)
 {
     static_assert(FROM_P || !std::is_same<T, float>::value,
