@@ -580,12 +580,14 @@ constexpr int kLutBits = 14;
 // offset[len] + the code.  The table and the
 // symbols (all of them when ALL_LDS, else the first kSymsLds) live in the
 // workgroup's LDS, so a step waits on no global load.  Each thread's bits
-// come a 128-byte line at a time into registers (the next line in flight),
-// four words at a time from there through a queue that shifts by one word
-// per refill; one refill of 32 bits per symbol keeps at least 33 bits in the
-// buffer (no codeword, escape and its 16 bits included, is longer than 32).
+// come half a 128-byte line at a time: the half being read sits in the
+// thread's own LDS slot, the next half is in flight in registers; one refill
+// of 32 bits per symbol (a word read from the slot at the thread's own index)
+// keeps at least 33 bits in the buffer (no codeword, escape and its 16 bits
+// included, is longer than 32).  LDS: the table (64 KiB), the slots (64 bytes
+// a thread) and the symbols (at most kSymsLds) fit in 160 KiB.
 constexpr int kUnpackThreads = 1024;
-constexpr int kSymsLds = 32768;
+constexpr int kSymsLds = 15360;
 // lookup-table entries: symbol | length << 16 for a code of at most kLutBits
 // bits (kLutEsc: the escape); kLutLong | shortest << 16 | longest << 8 for a
 // prefix of longer codes; 0 for bits no codeword starts with
@@ -669,7 +671,9 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
 {
     extern __shared__ __align__(16) unsigned char hsm[];
     uint32_t *lut = reinterpret_cast<uint32_t *>(hsm);  // symbol | length << 16 (0: longer)
-    uint16_t *ssyms = reinterpret_cast<uint16_t *>(lut + (1 << kLutBits));
+    // the threads' half lines: group k (16 bytes) of thread t at lines[k * blockDim.x + t]
+    uint4 *lines = reinterpret_cast<uint4 *>(lut + (1 << kLutBits));
+    uint16_t *ssyms = reinterpret_cast<uint16_t *>(lines + 4 * blockDim.x);
     __shared__ Canon cs;
     __shared__ int soff[kHuffMaxLen + 2];        // index[l] - first[l]
     __shared__ unsigned slim[kHuffMaxLen + 2];   // left-aligned end of the length-l codes
@@ -732,72 +736,56 @@ __global__ void __launch_bounds__(kUnpackThreads) k_huff_unpack(const uint32_t *
         set_status(status, kECorrupt);
         return;
     }
-    // The bit queue.  A thread's bits stream through registers one 128-byte
-    // line at a time (eight 16-byte groups, the next line in flight): all
-    // 262,144 block streams of a 512^3 field are resident at once, and a
-    // line fetched 16 bytes at a time would leave L2 between two of a
-    // thread's reads.  cur holds the words of the current group not yet
-    // taken, shifted to the front.
-    // A line holding any word of the section is read whole: the section
+    // The bit queue.  All 262,144 block streams of a 512^3 field are read at
+    // once, and a stream read 16 bytes at a time would see its line leave L2
+    // between two of its reads; a thread therefore fetches 64 bytes at a
+    // time.  The half line in use sits in the thread's LDS slot (a word is
+    // taken at the thread's own index: no register shuffling, which a wave
+    // would pay whenever any of its threads needed it), the next half is in
+    // flight in registers.
+    // A half line holding any word of the section is read whole: the section
     // starts 256-byte aligned and the next section starts at the next 256-byte
-    // boundary after it (the gap zeroed), so the line stays inside the stream;
-    // lines past the section read as zeros.
+    // boundary after it (the gap zeroed), so the half stays inside the stream;
+    // halves past the section read as zeros.
     const uint4 *w4 = reinterpret_cast<const uint4 *>(bits);
-    auto load_line = [&](uint4 (&dstl)[8], unsigned long long ln) {
-        if (32 * ln < nwords) {
+    auto load_half = [&](uint4 (&d)[4], unsigned long long h) {
+        if (16 * h < nwords) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                dstl[k] = w4[8 * ln + k];
+            for (int k = 0; k < 4; ++k)
+                d[k] = w4[4 * h + k];
         } else {
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                dstl[k] = make_uint4(0u, 0u, 0u, 0u);
+            for (int k = 0; k < 4; ++k)
+                d[k] = make_uint4(0u, 0u, 0u, 0u);
         }
     };
-    unsigned long long line = (start >> 5) >> 5;  // 32 words per line
-    uint4 L[8], N[8];
-    load_line(L, line);
-    load_line(N, line + 1);
-    // L[0] is the current group: the line's groups shift down as they are
-    // used (fixed register indices only), the next line follows at its end
-    int gq = (int)(((start >> 5) >> 2) & 7u);  // groups of the line used before L[0]
-    for (int k = 0; k < gq; ++k) {
+    uint4 *slot = lines + threadIdx.x;
+    const unsigned stride = blockDim.x;
+    auto put_half = [&](const uint4 (&d)[4]) {
 #pragma unroll
-        for (int j = 0; j < 7; ++j)
-            L[j] = L[j + 1];
-    }
-    uint4 cur = L[0];
-    int left = 4 - (int)((start >> 5) & 3u);  // words of cur not yet taken
-    // drop the words of cur before the block's first word
-    for (int k = 0; k < 4 - left; ++k) {
-        cur.x = cur.y;
-        cur.y = cur.z;
-        cur.z = cur.w;
-    }
+        for (int k = 0; k < 4; ++k)
+            slot[k * stride] = d[k];
+    };
+    unsigned long long half = (start >> 5) >> 4;  // 16 words a half
+    uint4 N[4];
+    load_half(N, half);
+    put_half(N);
+    load_half(N, half + 1);
+    unsigned widx = (unsigned)((start >> 5) & 15u);  // next word of the half in the slot
     unsigned long long buf = 0;
     int nb = 0;
     auto take = [&]() {
-        buf |= (unsigned long long)cur.x << (32 - nb);
-        nb += 32;
-        cur.x = cur.y;
-        cur.y = cur.z;
-        cur.z = cur.w;
-        if (--left == 0) {
-            left = 4;
-            if (++gq == 8) {
-                gq = 0;
-                ++line;
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    L[k] = N[k];
-                load_line(N, line + 1);
-            } else {
-#pragma unroll
-                for (int j = 0; j < 7; ++j)
-                    L[j] = L[j + 1];
-            }
-            cur = L[0];
+        if (widx == 16) {
+            put_half(N);
+            ++half;
+            widx = 0;
+            load_half(N, half + 1);
         }
+        const unsigned w =
+            reinterpret_cast<const unsigned *>(slot + (widx >> 2) * stride)[widx & 3u];
+        ++widx;
+        buf |= (unsigned long long)w << (32 - nb);
+        nb += 32;
     };
     take();
     take();
@@ -989,7 +977,8 @@ hipError_t launch_huff_decode(const Geom &g, const uint32_t *d_tab, const uint32
                        esc_len, glut);
     const bool all = nsym <= (unsigned)kSymsLds;
     const unsigned nlds = all ? nsym : (unsigned)kSymsLds;
-    const size_t lds = (size_t)(1 << kLutBits) * sizeof(uint32_t) + (size_t)nlds * sizeof(uint16_t);
+    const size_t lds = (size_t)(1 << kLutBits) * sizeof(uint32_t) + (size_t)threads * 64 +
+                       (size_t)nlds * sizeof(uint16_t);
     const int sb = huff_size_bytes(g);
     hipError_t e = launch_scan_sizes(d_sizes, sb, g.nblocks, ws.boffsets, ws.bpartials,
                                      ws.bits_total, s);
