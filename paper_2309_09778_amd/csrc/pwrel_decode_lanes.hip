@@ -9,8 +9,8 @@
 // every lane busy (a lane whose block keeps Lorenzo by the judge takes the
 // Lorenzo value).  A lane walks its block row by row along x: the codes of a
 // row are one 16-byte load (8^3 blocks), the previous row of the plane stays in
-// registers, the two rows of the previous plane come from an LDS ring of B + 1
-// rows per lane, and x^ of the row is written as one contiguous run (64 lanes
+// registers, row y of the previous plane comes from an LDS ring of B rows per
+// lane (its row y - 1 is the one read for the row before), and x^ of the row is written as one contiguous run (64 lanes
 // = 64 neighbouring blocks = one coalesced stretch of the field).
 //
 // Only whole blocks go here, of fields whose grid values span less than 2^27
@@ -107,9 +107,9 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_decode_lanes(DecodeArgs a)
 {
     constexpr int NO = (1 << D) - 1;
     constexpr int K = (1 << D) - 2;
-    constexpr int RW = D == 3 ? B + 1 : 1;  // ring rows: the previous plane and one more
+    constexpr int RW = D == 3 ? B : 1;  // ring rows: the previous plane
     __shared__ int ring[kLaneWaves][RW][B][64];
-    __shared__ float4 wl[kWlds];
+    __shared__ float4 wl[PREC == 0 ? kWlds : 1];
     if constexpr (PREC == 0)
         stage_weights<HP>(wl, a.mlp);
     __syncthreads();
@@ -143,9 +143,10 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_decode_lanes(DecodeArgs a)
     const DevConsts c = a.c;
     unsigned zc = 0;
     int prev[B];  // the previous row of this plane
+    int zrp[B];   // the previous plane's row y - 1 (read for the row before)
 #pragma unroll
     for (int k = 0; k < B; ++k)
-        prev[k] = 0;
+        prev[k] = zrp[k] = 0;
     const int nz = D == 3 ? B : 1;
     for (int lz = 0; lz < nz; ++lz) {
         for (int ly = 0; ly < B; ++ly) {
@@ -157,14 +158,16 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_decode_lanes(DecodeArgs a)
 #pragma unroll
                 for (int k = 0; k < B / 2; ++k)
                     rc.w[k] = (uint32_t)kR | ((uint32_t)kR << 16);
-            // the previous plane's rows y and y - 1 (ring slots of rows r - B and r - B - 1)
+            // the previous plane's rows y (ring slot of row r - B, which row r
+            // then takes) and y - 1 (read for the row before)
             int zr[B], zry[B];
             if (D == 3 && lz > 0) {
-                const int s0 = (r - B) % RW, s1 = (r - B - 1 + RW) % RW;
+                const int s0 = r % RW;
 #pragma unroll
                 for (int k = 0; k < B; ++k) {
                     zr[k] = ring[wv][s0][k][lane];
-                    zry[k] = ly > 0 ? ring[wv][s1][k][lane] : 0;
+                    zry[k] = ly > 0 ? zrp[k] : 0;
+                    zrp[k] = zr[k];
                 }
             } else {
 #pragma unroll
