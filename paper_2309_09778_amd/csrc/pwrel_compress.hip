@@ -251,13 +251,15 @@ k_compress(CompressArgs a)
 
     __shared__ int s_status;
     __shared__ float4 wl[kWlds];
-    // the judge's q-table in LDS (sorted path, blocks of up to 512 points)
+    // the judge's q-table in LDS (sorted path, blocks of up to 512 points);
+    // for 8^3 blocks it holds c q(c), the term a run of c equal codes adds
     constexpr bool JQ = JS && BVc <= 512;
     __shared__ long long sq[JQ ? BVc + 1 : 1];
     if constexpr (JQ) {
         if (a.judge)
             for (int i = tid; i <= BVc; i += NT)
-                sq[i] = a.qtab[i];
+                sq[i] = JL ? (long long)((unsigned long long)i * (unsigned long long)a.qtab[i])
+                           : a.qtab[i];
     }
     const long long *qt = JQ ? sq : a.qtab;
     stage_weights<HP>(wl, a.mlp);
@@ -790,7 +792,7 @@ k_compress(CompressArgs a)
                     unsigned *scr = reinterpret_cast<unsigned *>(ptile) +
                                     __builtin_amdgcn_readfirstlane(tid >> 6) * kSortLdsWords;
                     wave_sort_lds8(kv, static_cast<unsigned *>(__builtin_assume_aligned(scr, 16)));
-                    wave_runs_lm<8>(kv, nsent, qt, s0, s1);
+                    wave_runs_lm<8, true>(kv, nsent, qt, s0, s1);
                 } else if constexpr (JS) {
                     unsigned kv[JEPL];
                     unsigned nsent = 0;

@@ -281,7 +281,8 @@ __device__ __forceinline__ void wave_sort_lds8(unsigned (&a)[8], unsigned *scr)
 // differs from its predecessor; its start is found by the lane itself or,
 // for a run entering from lower lanes, by an exclusive prefix maximum of the
 // lanes' last starts.  Positions are kept + 1 (0 = none) in packed halves.
-template <int EPL>
+// (CQ: qtab[c] already holds c q(c))
+template <int EPL, bool CQ = false>
 __device__ __forceinline__ void wave_runs_lm(const unsigned (&a)[EPL], unsigned nsent,
                                              const long long *qtab, unsigned long long &J0,
                                              unsigned long long &J1)
@@ -331,8 +332,13 @@ __device__ __forceinline__ void wave_runs_lm(const unsigned (&a)[EPL], unsigned 
         if ((a[k] >> 16) == 0xFFFFu)
             c1 -= (int)nsent;
         const unsigned e1 = ((tail || (y >> 16)) && c1 > 0) ? (unsigned)c1 : 0u;
-        s0 += (unsigned long long)e0 * (unsigned long long)qtab[e0];
-        s1 += (unsigned long long)e1 * (unsigned long long)qtab[e1];
+        if constexpr (CQ) {
+            s0 += (unsigned long long)qtab[e0];
+            s1 += (unsigned long long)qtab[e1];
+        } else {
+            s0 += (unsigned long long)e0 * (unsigned long long)qtab[e0];
+            s1 += (unsigned long long)e1 * (unsigned long long)qtab[e1];
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
