@@ -56,7 +56,9 @@ struct CompressArgs {
 // same code, q(c) = rint(2^32 log2 c); n q(n) - J is 2^32 times the entropy in
 // bits.  One wave per block.  Blocks of up to 1,024 points of the compiled
 // shapes: the wave sorts the block's codes of each predictor (a bitonic network
-// in registers and lane exchanges) and reads the multiplicities off the runs.
+// in registers and lane exchanges; for 8^3 blocks with every stage inside a
+// lane, the register layouts exchanged through LDS) and reads the
+// multiplicities off the runs.
 // Other blocks: codes within a window of errors are counted in a histogram
 // (kJudgeWin bins: bin 0 = code 0, the balance point; bin e + kJudgeHalf for
 // |e| < kJudgeHalf), the others in a per-block hash table of each predictor

@@ -1,8 +1,9 @@
 // Sorting and run counting of 16-bit keys held by a wave, on the vector ALU
 // (DPP row/quad moves and the gfx950 lane swaps; the run scan shuffles
-// through the LDS crossbar).  Every 32-bit element carries two keys (low and
-// high half) that are sorted as two separate sequences by one bitonic network
-// on packed 16-bit minima/maxima.
+// through the LDS crossbar; the 512-element sort moves its register layouts
+// through LDS instead).  Every 32-bit element carries two keys (low and high
+// half) that are sorted as two separate sequences by one bitonic network on
+// packed 16-bit minima/maxima.
 #pragma once
 
 #include <hip/hip_runtime.h>
