@@ -423,6 +423,35 @@ __global__ void __launch_bounds__(256) k_huff_sizes(const uint16_t *__restrict__
     set_status(status, err);
 }
 
+// append n codes (lengths l[], codewords c[]) at bit `pos` of the LDS words w:
+// whole words by plain stores, the first and last (shared with the lanes on
+// either side) by atomic OR
+__device__ __forceinline__ void pack_emit(uint32_t *w, unsigned pos, const unsigned *l,
+                                          const unsigned *c, int n)
+{
+    unsigned long long acc = 0;
+    int nacc = (int)(pos & 31u);
+    unsigned wp = pos >> 5;
+    bool first = true;
+    for (int j = 0; j < n; ++j) {
+        acc |= (unsigned long long)c[j] << (64 - nacc - (int)l[j]);
+        nacc += (int)l[j];
+        if (nacc >= 32) {
+            const uint32_t word = (uint32_t)(acc >> 32);
+            if (first)
+                atomicOr(&w[wp], word);
+            else
+                w[wp] = word;
+            first = false;
+            ++wp;
+            acc <<= 32;
+            nacc -= 32;
+        }
+    }
+    if (nacc > 0)
+        atomicOr(&w[wp], (uint32_t)(acc >> 32));
+}
+
 // Bit packing: one wave per block, the block's words assembled in LDS.  Each
 // lane packs a run of consecutive codes (eight, from one 16-byte load, where
 // aligned; else one) into its own bit span: whole words by plain LDS stores,
@@ -444,29 +473,8 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
     uint32_t *w = lw + (threadIdx.x >> 6) * wave_words;
     const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-    // append n codes (lengths l[], codewords c[]) at bit `pos` of w
     auto emit = [&](unsigned pos, const unsigned *l, const unsigned *c, int n) {
-        unsigned long long acc = 0;
-        int nacc = (int)(pos & 31u);
-        unsigned wp = pos >> 5;
-        bool first = true;
-        for (int j = 0; j < n; ++j) {
-            acc |= (unsigned long long)c[j] << (64 - nacc - (int)l[j]);
-            nacc += (int)l[j];
-            if (nacc >= 32) {
-                const uint32_t word = (uint32_t)(acc >> 32);
-                if (first)
-                    atomicOr(&w[wp], word);
-                else
-                    w[wp] = word;
-                first = false;
-                ++wp;
-                acc <<= 32;
-                nacc -= 32;
-            }
-        }
-        if (nacc > 0)
-            atomicOr(&w[wp], (uint32_t)(acc >> 32));
+        pack_emit(w, pos, l, c, n);
     };
     // A wave packs several blocks in turn; each block's geometry, bit offset,
     // bit size and first 16-byte load of codes are fetched while the block
@@ -566,6 +574,118 @@ __global__ void __launch_bounds__(256) k_huff_pack(const uint16_t *__restrict__ 
         }
         __builtin_amdgcn_wave_barrier();
         cur = nxt;
+    }
+}
+
+// Bit packing of a 3-D field of whole 8^3 blocks (every side a multiple of
+// 8; block b's 512 codes at b * 512): k_huff_pack's packing, pipelined so
+// that a wave's stores never drain before its next block.  One counter tracks
+// a wave's loads and stores in issue order, so a wait for a load also waits
+// for every store issued before that load.  Here the loads a block waits for
+// (its table gathers, issued one block ahead, from codes read two blocks
+// ahead) come before the previous block's stores; every block issues the same
+// vector memory instructions (its words through a buffer range that drops
+// the lanes past them; offsets and sizes as scalar loads), so each wait counts
+// only what came after its load.
+constexpr int kWholeStoreRounds = 9;  // 64-lane rounds of a block's at most 514 words
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_huff_pack_whole(const uint16_t *__restrict__ codes,
+                                                         long long nblocks,
+                                                         const unsigned long long *__restrict__ enc,
+                                                         const S *__restrict__ sizes,
+                                                         const unsigned long long *__restrict__ boffs,
+                                                         const unsigned long long *__restrict__ bparts,
+                                                         uint32_t *__restrict__ bits, int wave_words,
+                                                         const int *status)
+{
+    extern __shared__ uint32_t lw[];
+    if (*status != kOk)
+        return;
+    const int lane = threadIdx.x & 63;
+    uint32_t *w = lw + (threadIdx.x >> 6) * wave_words;
+    const long long wave =
+        __builtin_amdgcn_readfirstlane((int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    if (wave >= nblocks)
+        return;
+    const long long last = nblocks - 1;
+    auto codes_of = [&](long long b) {
+        return reinterpret_cast<const uint4 *>(codes + b * 512)[lane];
+    };
+    auto gather = [&](const uint4 &v, unsigned (&l)[8], unsigned (&c)[8]) {
+        const unsigned cw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const unsigned long long ec = enc[(cw[j >> 1] >> (16 * (j & 1))) & 0xFFFFu];
+            l[j] = (unsigned)(ec >> 32);
+            c[j] = (unsigned)ec;
+        }
+    };
+    unsigned l[8], c[8];
+    uint4 vn = codes_of(wave);
+    gather(vn, l, c);
+    vn = codes_of(std::min(wave + nwaves, last));
+    for (long long b = wave; b < nblocks; b += nwaves) {
+        // the next block's gathers (its codes arrived during this block's
+        // predecessor), then the codes of the block after it
+        unsigned ln[8], cn[8];
+        gather(vn, ln, cn);
+        vn = codes_of(std::min(b + 2 * nwaves, last));
+        const unsigned long long start = boffs[b] + bparts[b / kScanChunk];
+        // the block's size through a scalar load (a 16-bit size from the
+        // aligned word that holds it)
+        unsigned nbits;
+        if constexpr (sizeof(S) == 2) {
+            const unsigned sw = reinterpret_cast<const unsigned *>(sizes)[b >> 1];
+            nbits = (b & 1) ? sw >> 16 : sw & 0xFFFFu;
+        } else {
+            nbits = (unsigned)sizes[b];
+        }
+        const unsigned s0 = (unsigned)(start & 31u);
+        const int nw = (int)((s0 + nbits + 31u) >> 5);
+        for (int k = lane; k < nw; k += 64)
+            w[k] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        unsigned t = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            t += l[j];
+        unsigned incl = t;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned o = __shfl_up(incl, d, 64);
+            if (lane >= d)
+                incl += o;
+        }
+        pack_emit(w, s0 + incl - t, l, c, 8);
+        // this wave's LDS writes above are complete before its reads below
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long w0 = start >> 5;
+        const bool part_lo = s0 != 0, part_hi = ((s0 + nbits) & 31u) != 0;
+        // words shared with a neighbouring block, by atomic OR below; the
+        // others by plain stores (lanes past the block's words fall outside
+        // the range and store nothing)
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(bits + w0, 0, nw * 4, 0x00020000);
+#pragma unroll
+        for (int q = 0; q < kWholeStoreRounds; ++q) {
+            const int k = lane + 64 * q;
+            const bool shared = (k == 0 && part_lo) || (k == nw - 1 && part_hi);
+            const uint32_t v = w[k < wave_words ? k : 0];
+            __builtin_amdgcn_raw_buffer_store_b32(v, r, (k < nw && !shared) ? 4 * k : 4 * nw, 0, 0);
+        }
+        if (lane == 0 && part_lo)
+            atomicOr(&bits[w0], w[0]);
+        if (lane == 1 && part_hi)
+            atomicOr(&bits[w0 + nw - 1], w[nw - 1]);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            l[j] = ln[j];
+            c[j] = cn[j];
+        }
     }
 }
 
@@ -936,6 +1056,25 @@ hipError_t launch_huff_pack(const Geom &g, const uint16_t *codes, const void *d_
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<unsigned long long>(
                                        std::max<unsigned long long>(1, (nwords + 255) / 256), 8192)),
                        dim3(256), 0, s, d_bits, nwords, 0u);
+    // whole 8^3 blocks (every side a multiple of 8), codes 16-byte aligned: the
+    // pipelined packer
+    const bool whole = g.D == 3 && g.bd[0] == 8 && g.bd[1] == 8 && g.bd[2] == 8 &&
+                       g.n[0] % 8 == 0 && g.n[1] % 8 == 0 && g.n[2] % 8 == 0 &&
+                       (reinterpret_cast<uintptr_t>(codes) & 15) == 0 &&
+                       wave_words <= 64 * kWholeStoreRounds;
+    if (whole) {
+        if (huff_size_bytes(g) == 2)
+            hipLaunchKernelGGL(k_huff_pack_whole<uint16_t>, dim3(pgrid), dim3(64 * wpg), lds, s,
+                               codes, g.nblocks, ws.enc_code,
+                               static_cast<const uint16_t *>(d_sizes), ws.boffsets, ws.bpartials,
+                               d_bits, wave_words, ws.status);
+        else
+            hipLaunchKernelGGL(k_huff_pack_whole<uint32_t>, dim3(pgrid), dim3(64 * wpg), lds, s,
+                               codes, g.nblocks, ws.enc_code,
+                               static_cast<const uint32_t *>(d_sizes), ws.boffsets, ws.bpartials,
+                               d_bits, wave_words, ws.status);
+        return hipGetLastError();
+    }
     if (huff_size_bytes(g) == 2)
         hipLaunchKernelGGL(k_huff_pack<uint16_t>, dim3(pgrid), dim3(64 * wpg), lds, s, codes, ga,
                            ws.enc_code, static_cast<const uint16_t *>(d_sizes),
