@@ -148,16 +148,24 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_decode_lanes(DecodeArgs a)
     for (int k = 0; k < B; ++k)
         prev[k] = zrp[k] = 0;
     const int nz = D == 3 ? B : 1;
+    // a row's codes are loaded one row ahead, before the previous row's
+    // stores: one counter tracks a wave's loads and stores in issue order, so
+    // a load issued after them would make each row wait for both
+    auto row_codes = [&](RowCodes<B> &rc, int r) {
+        if (have && r < nz * B)
+            rc.load(a.codes + q.start + (long long)r * B);
+        else
+#pragma unroll
+            for (int k = 0; k < B / 2; ++k)
+                rc.w[k] = (uint32_t)kR | ((uint32_t)kR << 16);
+    };
+    RowCodes<B> rc;
+    row_codes(rc, 0);
     for (int lz = 0; lz < nz; ++lz) {
         for (int ly = 0; ly < B; ++ly) {
             const int r = lz * B + ly;
-            RowCodes<B> rc;
-            if (have)
-                rc.load(a.codes + q.start + (long long)r * B);
-            else
-#pragma unroll
-                for (int k = 0; k < B / 2; ++k)
-                    rc.w[k] = (uint32_t)kR | ((uint32_t)kR << 16);
+            RowCodes<B> rn;
+            row_codes(rn, r + 1);
             // the previous plane's rows y (ring slot of row r - B, which row r
             // then takes) and y - 1 (read for the row before)
             int zr[B], zry[B];
@@ -217,10 +225,14 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_decode_lanes(DecodeArgs a)
                     }
                     x = inverse_of<T>(p, a);
                 } else {
-                    // balance point: its raw value and that value's grid value
+                    // balance point: its raw value and that value's grid value,
+                    // waited for here (s_waitcnt vmcnt(0)), in this rare branch:
+                    // otherwise the common path, where p merges with this load,
+                    // would wait at every point for every earlier load and store
                     if (zc < nzero) {
                         p = a.praw[roff + zc];
                         x = raw[roff + zc];
+                        __builtin_amdgcn_s_waitcnt(0x0F70);
                     } else {
                         err = kECorrupt;
                         p = 0;
@@ -243,6 +255,7 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_decode_lanes(DecodeArgs a)
 #pragma unroll
             for (int k = 0; k < B; ++k)
                 prev[k] = cur[k];
+            rc = rn;
         }
         if constexpr (D == 3) {
 #pragma unroll
