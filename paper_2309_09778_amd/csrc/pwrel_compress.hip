@@ -204,6 +204,13 @@ k_compress(CompressArgs a)
     constexpr bool CT = S::known;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = 256;
+    constexpr bool SPLIT = CT && FROM_P && !BATCH;  // launched as a W32 / generic pair
+    if constexpr (SPLIT) {
+        // the pair's other kernel takes this field: return before any set-up
+        // (uniform: one field, every thread reads the same constant)
+        if ((a.consts->w32 != 0) != W32)
+            return;
+    }
     const int tid = threadIdx.x;
     constexpr int h0 = D >= 3 ? 1 : 0, h1 = D >= 2 ? 1 : 0, h2 = 1;
     const int B = CT ? BB : a.bd[2];
@@ -342,11 +349,6 @@ k_compress(CompressArgs a)
     DevConsts c = *F.consts;
     long long n0 = F.n[0], n1 = F.n[1], n2 = F.n[2];
     bool w32 = c.w32 != 0;
-    constexpr bool SPLIT = CT && FROM_P && !BATCH;  // launched as a W32 / generic pair
-    if constexpr (SPLIT) {
-        if (w32 != W32)
-            return;  // the pair's other kernel takes this field (uniform)
-    }
 
     // LDS offsets of the neighbours, o = 1 .. 2^D-1
     int noff[8];
